@@ -1,0 +1,187 @@
+/*
+ * fem_heat.h -- C ABI of the MI355X (gfx950) assembly-free transient heat solver.
+ *
+ * The method is that of Loeb & Earls, arXiv:1905.07622: every implicit
+ * theta-scheme time step solves
+ *     [M + theta*dt*K] U^n = [M - (1-theta)*dt*K] U^{n-1} + dt*F      (Sec. 3.1)
+ * with Jacobi-preconditioned conjugate gradient (Algorithm 1, Sec. 3.3).
+ * M and K are never assembled: they are applied element by element on a
+ * fixed grid of 8-node trilinear hexahedra with per-element heat capacity
+ * rho*C_e and conductivity k_e, and the assembly operator is evaluated as a
+ * node-centred gather -- each output degree of freedom sums the
+ * contributions of the elements around it (the DbD reading of eq. EbEvsDbD
+ * and eq. DbD, Sec. 3.2 and 4.2.2).  Every step of that path runs in HIP
+ * kernels on the GPU; the host only enqueues work and reads small flags.
+ *
+ * Conventions shared by every entry point
+ *  - Grid: nx*ny*nz elements of size hx*hy*hz, origin 0.  Nodes are numbered
+ *    i = ix + (nx+1)*(iy + (ny+1)*iz) (x fastest, as the paper's fixed grid,
+ *    Sec. 4.1); N = (nx+1)(ny+1)(nz+1).  Elements e = ex + nx*(ey + ny*ez);
+ *    E = nx*ny*nz.  Node arrays have length N, element arrays length E, dense,
+ *    in that order.  The library's internal layout never leaks out.
+ *  - Faces: 0:-x 1:+x 2:-y 3:+y 4:-z 5:+z.  Bit f of a face mask selects face f.
+ *  - Memory: array arguments are HOST pointers unless the handle was created
+ *    with FEM_DEVICE_PTRS, in which case they are device pointers on the
+ *    handle's device (e.g. torch tensors); the byte layout is the same.
+ *    The caller owns every array; create/run copy what they need before
+ *    returning, and run writes outputs before returning.  A handle owns its
+ *    device memory until fem_heat_destroy.
+ *  - Errors: every call returns FEM_OK (0) or a negative FEM_E* code and never
+ *    throws across the ABI.  fem_last_error() gives a message for the last
+ *    failing call on a handle.
+ *  - Threads: a handle belongs to one thread at a time.
+ */
+#ifndef FEM_HEAT_H
+#define FEM_HEAT_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ------------------------------------------------------ */
+#define FEM_OK 0
+#define FEM_EINVAL (-1)      /* invalid argument (nothing was changed)            */
+#define FEM_ENOMEM (-2)      /* device or host allocation failed                  */
+#define FEM_ENOCONV (-3)     /* some step reached max_iter; outputs still written  */
+#define FEM_EBREAKDOWN (-4)  /* CG breakdown (d^T A d <= 0 or non-finite scalar)   */
+#define FEM_EDEVICE (-5)     /* a HIP runtime call failed                          */
+#define FEM_EBUSY (-6)       /* resource temporarily unavailable                   */
+#define FEM_ECANCELED (-7)   /* request cancelled                                  */
+
+/* ---- options ------------------------------------------------------------ */
+#define FEM_FP64 0           /* FP64 operator, vectors, dots and scalars           */
+#define FEM_FP32_FP64DOT 1   /* FP32 operator and vectors inside FP64 refinement   */
+
+#define FEM_GUESS_EXTRAP 0   /* x0 = 2 T^{n-1} - T^{n-2} (u0_update, App. A.2)     */
+#define FEM_GUESS_PREV 1     /* x0 = T^{n-1}                                       */
+
+#define FEM_STOP_RHS 0       /* continue while r^T P^-1 r > rtol^2 b^T P^-1 b      */
+#define FEM_STOP_INITIAL 1   /* continue while r^T P^-1 r > rtol^2 r0^T P^-1 r0    */
+
+#define FEM_DEVICE_PTRS 0x1u /* array arguments are device pointers               */
+#define FEM_TIMING 0x2u      /* time every iteration kernel with HIP events        */
+
+/* Operators for fem_heat_apply */
+#define FEM_OP_A 0           /* y = (M + theta*dt*K) x                              */
+#define FEM_OP_L 1           /* y = (M - (1-theta)*dt*K) x                          */
+#define FEM_OP_JACOBI 2      /* y = P^-1 x, P = diag(M + theta*dt*K); 0 on Dirichlet */
+#define FEM_OP_LOAD 3        /* y = F (boundary load vector); x is ignored          */
+#define FEM_OP_FP32 0x100    /* OR-ed in: use the FP32 operator (x rounded to FP32) */
+
+typedef struct fem_heat fem_heat;
+
+/* Grid: elements per axis and element size per axis (all > 0). */
+typedef struct {
+  int32_t nx, ny, nz;
+  double hx, hy, hz;
+} fem_grid;
+
+/* Boundary conditions.  Flux faces carry k dT/dn = q (inward heat flux,
+ * Sec. 3.1); Dirichlet faces hold T = value (not in the paper, which uses
+ * flux conditions only: imposed by keeping those nodes fixed in every vector,
+ * equivalent to symmetric elimination).  A face may not be in both masks.
+ * Where two Dirichlet faces meet, the lower-numbered face sets the value.
+ * Faces in neither mask are insulated.  The load of step m (1-based global
+ * step index) is dt * s_m * F with s_m = flux_schedule[m-1] for
+ * 1 <= m <= n_schedule, 0 beyond it, and s_m = 1 for every m when
+ * flux_schedule is NULL.  The schedule is copied at create. */
+typedef struct {
+  uint32_t dirichlet_mask;
+  double dirichlet_value[6];
+  uint32_t flux_mask;
+  double flux[6];
+  const double *flux_schedule;  /* host pointer always */
+  int32_t n_schedule;
+} fem_bc;
+
+typedef struct {
+  int32_t precision;      /* FEM_FP64 | FEM_FP32_FP64DOT                          */
+  int32_t max_iter;       /* i_max of Algorithm 1 (per step; inner per sweep in mixed form); default 10000 */
+  int32_t replace_every;  /* residual replacement r = b - A x when i % replace_every == 0 (Algorithm 1 uses 50); 0 = never */
+  int32_t guess;          /* FEM_GUESS_*                                           */
+  int32_t stop_rule;      /* FEM_STOP_*                                            */
+  int32_t max_refine;     /* mixed form: max FP64 refinement sweeps per step (default 4) */
+  double inner_rtol;      /* mixed form: inner FP32 PCG relative tolerance (default 1e-5) */
+  uint32_t flags;         /* FEM_DEVICE_PTRS | FEM_TIMING                          */
+  void *hip_stream;       /* hipStream_t to run on; NULL = the library's own stream */
+  int32_t device;         /* HIP device ordinal                                    */
+  int32_t tile_x, tile_y, tile_z; /* gather tile overrides; 0 = automatic         */
+} fem_opts;
+
+/* Outputs of a run (inputs marked "in").  Every pointer may be NULL.
+ * Arrays follow the handle's memory kind (FEM_DEVICE_PTRS). */
+typedef struct {
+  double *T_final;           /* N: field after the last step                          */
+  double *T_saved;           /* (nsteps/save_every)*N: field after every save_every-th step */
+  int32_t save_every;        /* in                                                    */
+  const double *sensor_xyz;  /* in: 3*S point coordinates                             */
+  int32_t n_sensors;         /* in: S                                                 */
+  double *traces;            /* nsteps*S, row-major [step][sensor]: field at the points,
+                                trilinear in the containing element (lowest-index element on shared faces) */
+  int32_t *iters;            /* nsteps: PCG iterations per step (inner FP32 iterations in the mixed form) */
+  double *relres;            /* nsteps: final sqrt(r^T P^-1 r / b^T P^-1 b)           */
+  int32_t *refine_sweeps;    /* nsteps: FP64 refinement sweeps (mixed form)           */
+  int32_t first_step;        /* in: global index of the step preceding this run's first step
+                                (0 for a fresh run; the flux schedule is indexed from it) */
+  int64_t total_iters;       /* out: sum of iters                                     */
+  double device_ms;          /* out: device time of the run's stepping (HIP events)   */
+} fem_out;
+
+/* Kernel timing (filled when the handle has FEM_TIMING). */
+typedef struct {
+  int64_t gather_launches;   /* search-direction + operator-apply kernel (q = A d, d^T q) */
+  double gather_ms;
+  int64_t update_launches;   /* x/r update + preconditioned residual norm kernel         */
+  double update_ms;
+  int64_t replace_launches;  /* residual-replacement gather kernel                        */
+  double replace_ms;
+  int32_t grid_blocks;       /* blocks of the gather launch                                */
+  int32_t tile_x, tile_y, tile_z;
+} fem_stats;
+
+/* Create a solver for one grid, coefficient field and set of boundary
+ * conditions (Sec. 3.2: the element data are prepared once, only the
+ * coefficients change between solves).  Validates (FEM_EINVAL): nx,ny,nz >= 1,
+ * h* > 0 and finite, k_e >= 0 and finite, rho*c_e > 0 and finite, masks in 6
+ * bits and disjoint, finite boundary values.  Copies k_e, rho*c_e and the
+ * schedule to the device, builds the load vector F (a1 kernel).  opts may be
+ * NULL (defaults).  On success *out owns the device state. */
+int fem_heat_create(const fem_grid *grid, const double *k_e, const double *rhoc_e,
+                    const fem_bc *bc, const fem_opts *opts, fem_heat **out);
+
+/* Run nsteps theta-scheme steps from T0 (N values; Dirichlet nodes are
+ * overwritten by their boundary value).  T_prev (N values or NULL = T0) is
+ * the field one step before T0; it feeds the extrapolated initial guess, so
+ * a run split into two calls with T_prev = the field before T0 matches the
+ * uninterrupted run.  Per step: b = L T^{n-1} + dt*s_n*F, x0 by the guess
+ * rule, Algorithm 1 with the Jacobi preconditioner, stop rule, residual
+ * replacement and max_iter from the options.  Validates dt > 0,
+ * theta in [0,1], rtol > 0, nsteps >= 0 (FEM_EINVAL).  Returns FEM_OK,
+ * FEM_ENOCONV (some step hit max_iter: all outputs written, iters = max_iter
+ * marks the step) or FEM_EBREAKDOWN (outputs up to the last good step). */
+int fem_heat_run(fem_heat *h, const double *T0, const double *T_prev, double dt, double theta,
+                 int32_t nsteps, double rtol, fem_out *out);
+
+/* Apply one operator of the method (test hook; see FEM_OP_*) with the given
+ * dt and theta: y = op(x).  x and y are N-vectors. */
+int fem_heat_apply(fem_heat *h, int32_t which, double dt, double theta, const double *x, double *y);
+
+/* Kernel timing and launch shape of the last run (FEM_TIMING). */
+int fem_heat_stats(const fem_heat *h, fem_stats *out);
+
+/* Release a handle (NULL is accepted). */
+void fem_heat_destroy(fem_heat *h);
+
+/* Fill *opts with the defaults: FP64, max_iter 10000, replace_every 50,
+ * extrapolated guess, RHS stop rule, max_refine 4, inner_rtol 1e-5. */
+void fem_heat_default_opts(fem_opts *opts);
+
+const char *fem_strerror(int status);
+const char *fem_last_error(const fem_heat *h);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FEM_HEAT_H */

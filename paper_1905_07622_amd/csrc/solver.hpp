@@ -1,0 +1,81 @@
+// Host-side state of one solver handle (device-resident problem and PCG state).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/fem_heat.h"
+#include "common.hpp"
+
+struct fem_heat {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  fem_opts opts{};
+  bool devptrs = false;
+  bool timing = false;
+
+  femheat::Geom g{};
+  bool cubic = false;
+  bool nonzero_dirichlet = false;
+  std::vector<double> sched;
+
+  // element coefficients
+  double* rhoc64 = nullptr;
+  double* k64 = nullptr;
+  float* rhoc32 = nullptr;
+  float* k32 = nullptr;
+
+  // node vectors, FP64
+  double* F64 = nullptr;
+  double* pinv64 = nullptr;
+  double* b64 = nullptr;
+  double* r64 = nullptr;
+  double* q64 = nullptr;
+  double* d64[2] = {nullptr, nullptr};
+  double* pool[4] = {nullptr, nullptr, nullptr, nullptr};  // T^{n-1}, T^{n-2}, x ping-pong
+  double* lift64 = nullptr;   // A_fD g (only with non-zero Dirichlet values)
+  double ck_cached = -1.0;    // theta*dt of pinv/lift; < 0: none
+
+  // node vectors, FP32 (mixed form)
+  float* pinv32 = nullptr;
+  float* e32[2] = {nullptr, nullptr};
+  float* r32 = nullptr;
+  float* q32 = nullptr;
+  float* d32[2] = {nullptr, nullptr};
+  float* rhs32 = nullptr;
+
+  // reduction partials and device scalars
+  double* partials = nullptr;
+  uint32_t n_partials = 0;
+  femheat::Scalars* S_outer = nullptr;
+  femheat::Scalars* S_inner = nullptr;
+  femheat::Scalars* S_host = nullptr;  // pinned, 2 entries
+
+  // per-run buffers
+  double* xyz_dev = nullptr;
+  double* traces_dev = nullptr;
+  size_t traces_cap = 0;
+  size_t xyz_cap = 0;
+
+  femheat::GatherShape shape{};
+  uint32_t upd_blocks64 = 0, upd_blocks32 = 0;
+
+  fem_stats stats{};
+  std::vector<hipEvent_t> events;
+  hipEvent_t ev_run[2] = {nullptr, nullptr};
+
+  std::string err;
+};
+
+namespace femheat {
+
+int solver_init(fem_heat* h, const fem_grid* grid, const double* k_e, const double* rhoc_e, const fem_bc* bc);
+int solver_run(fem_heat* h, const double* T0, const double* T_prev, double dt, double theta, int32_t nsteps,
+               double rtol, fem_out* out);
+int solver_apply(fem_heat* h, int32_t which, double dt, double theta, const double* x, double* y);
+void solver_free(fem_heat* h);
+
+}  // namespace femheat

@@ -1,0 +1,245 @@
+// Pointwise kernels of the solver (gfx950): the fused PCG update of
+// Algorithm 1 (AXPY + DIMVM + VVM + Beta_update of App. A.2 in one pass),
+// the setup kernels (Jacobi diagonal, boundary load vector, Dirichlet
+// values), precision casts for the mixed form and sensor interpolation.
+#pragma once
+
+#include "common.hpp"
+#include "reduce.hpp"
+
+namespace femheat {
+
+template <typename V>
+struct Vec;
+template <>
+struct Vec<double> {
+  using T = double2;
+  static constexpr int W = 2;
+};
+template <>
+struct Vec<float> {
+  using T = float4;
+  static constexpr int W = 4;
+};
+
+// x += alpha d ; r -= alpha q (0 on Dirichlet rows) ; delta_new = r^T P^-1 r
+// Dirichlet rows are recognised by P^-1 = 0.
+template <typename V>
+__device__ inline void upd1(V& x, V d, V& r, V q, V p, V alpha, double& acc) {
+  x += alpha * d;
+  V rr = r - alpha * q;
+  rr = (p == V(0)) ? V(0) : rr;
+  r = rr;
+  acc += (double)rr * (double)(p * rr);
+}
+
+template <typename V>
+__global__ void __launch_bounds__(256) update_kernel(V* __restrict__ x, const V* __restrict__ d,
+                                                      V* __restrict__ r, const V* __restrict__ q,
+                                                      const V* __restrict__ pinv, uint32_t N, Scalars* S,
+                                                      double* partials, Ctl ctl) {
+  if (S->done) return;
+  using VT = typename Vec<V>::T;
+  constexpr int W = Vec<V>::W;
+  const V alpha = (V)S->alpha;
+  double acc = 0.0;
+  const uint32_t nvec = N / W;
+  const uint32_t stride = gridDim.x * blockDim.x;
+  const uint32_t tid = blockIdx.x * blockDim.x + threadIdx.x;
+  VT* xv = reinterpret_cast<VT*>(x);
+  const VT* dv = reinterpret_cast<const VT*>(d);
+  VT* rv = reinterpret_cast<VT*>(r);
+  const VT* qv = reinterpret_cast<const VT*>(q);
+  const VT* pv = reinterpret_cast<const VT*>(pinv);
+  for (uint32_t j = tid; j < nvec; j += stride) {
+    VT xx = xv[j], dd = dv[j], rr = rv[j], qq = qv[j], pp = pv[j];
+    if constexpr (W == 2) {
+      upd1(xx.x, dd.x, rr.x, qq.x, pp.x, alpha, acc);
+      upd1(xx.y, dd.y, rr.y, qq.y, pp.y, alpha, acc);
+    } else {
+      upd1(xx.x, dd.x, rr.x, qq.x, pp.x, alpha, acc);
+      upd1(xx.y, dd.y, rr.y, qq.y, pp.y, alpha, acc);
+      upd1(xx.z, dd.z, rr.z, qq.z, pp.z, alpha, acc);
+      upd1(xx.w, dd.w, rr.w, qq.w, pp.w, alpha, acc);
+    }
+    xv[j] = xx;
+    rv[j] = rr;
+  }
+  for (uint32_t i = nvec * W + tid; i < N; i += stride) {
+    V xx = x[i], rr = r[i];
+    upd1(xx, d[i], rr, q[i], pinv[i], alpha, acc);
+    x[i] = xx;
+    r[i] = rr;
+  }
+  reduce_and_finalize(acc, partials, S, gridDim.x, blockIdx.x, FIN_DELTA, ctl);
+}
+
+// Start of an inner (FP32) solve of A e = r64: rhs = r = (float) r64, e = 0,
+// delta0 = r^T P^-1 r accumulated in FP64.
+__global__ void __launch_bounds__(256) inner_start_kernel(const double* __restrict__ r64, float* __restrict__ rhs,
+                                                          float* __restrict__ r, float* __restrict__ e,
+                                                          const float* __restrict__ pinv, uint32_t N,
+                                                          Scalars* S, double* partials, Ctl ctl) {
+  double acc = 0.0;
+  const uint32_t stride = gridDim.x * blockDim.x;
+  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < N; i += stride) {
+    const float v = (float)r64[i];
+    rhs[i] = v;
+    r[i] = v;
+    e[i] = 0.0f;
+    acc += (double)v * (double)(pinv[i] * v);
+  }
+  reduce_and_finalize(acc, partials, S, gridDim.x, blockIdx.x, FIN_INIT, ctl);
+}
+
+// ---------------------------------------------------------------------------
+// setup
+// ---------------------------------------------------------------------------
+
+__device__ inline void node_xyz(const Geom& g, uint32_t i, int& ix, int& iy, int& iz) {
+  ix = (int)(i % (uint32_t)g.px);
+  const uint32_t t = i / (uint32_t)g.px;
+  iy = (int)(t % (uint32_t)g.py);
+  iz = (int)(t / (uint32_t)g.py);
+}
+
+// Dirichlet test: the lowest-numbered Dirichlet face containing the node decides.
+__device__ inline bool dirichlet_value(const Geom& g, int ix, int iy, int iz, double& val) {
+  const bool on[6] = {ix == 0, ix == g.nx, iy == 0, iy == g.ny, iz == 0, iz == g.nz};
+#pragma unroll
+  for (int f = 0; f < 6; ++f)
+    if (((g.dir_mask >> f) & 1u) && on[f]) {
+      val = g.dir_val[f];
+      return true;
+    }
+  return false;
+}
+
+// Jacobi preconditioner P = diag(A), A = M + ck*K (Sec. 3.3, Jacobi_A of App. A.2),
+// summed over the elements around each node: every diagonal entry of the
+// trilinear element blocks is M_aa = V/27 and K_aa = (V/9)(1/hx^2+1/hy^2+1/hz^2).
+// Stored as P^-1, 0 on Dirichlet nodes.
+template <typename V>
+__global__ void jacobi_kernel(Geom g, const double* __restrict__ rhoc, const double* __restrict__ kc, double ck,
+                              V* __restrict__ pinv) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= g.N) return;
+  int ix, iy, iz;
+  node_xyz(g, i, ix, iy, iz);
+  double gv;
+  if (dirichlet_value(g, ix, iy, iz, gv)) {
+    pinv[i] = V(0);
+    return;
+  }
+  const double vol = g.hx * g.hy * g.hz;
+  const double md = vol / 27.0;
+  const double kd = vol / 9.0 * (1.0 / (g.hx * g.hx) + 1.0 / (g.hy * g.hy) + 1.0 / (g.hz * g.hz));
+  double P = 0.0;
+  for (int oz = 0; oz < 2; ++oz)
+    for (int oy = 0; oy < 2; ++oy)
+      for (int ox = 0; ox < 2; ++ox) {
+        const int ex = ix - 1 + ox, ey = iy - 1 + oy, ez = iz - 1 + oz;
+        if (ex < 0 || ex >= g.nx || ey < 0 || ey >= g.ny || ez < 0 || ez >= g.nz) continue;
+        const uint32_t e = (uint32_t)ex + (uint32_t)g.nx * ((uint32_t)ey + (uint32_t)g.ny * (uint32_t)ez);
+        P += rhoc[e] * md + ck * kc[e] * kd;
+      }
+  pinv[i] = (V)(1.0 / P);
+}
+
+// Boundary load F_i = sum over flux faces f containing i of q_f * integral of
+// the bilinear face shape function = q_f * (h_u h_v / 4) * (face elements at i).
+__global__ void load_vector_kernel(Geom g, double* __restrict__ F) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= g.N) return;
+  int idx[3];
+  node_xyz(g, i, idx[0], idx[1], idx[2]);
+  const int n[3] = {g.nx, g.ny, g.nz};
+  const double h[3] = {g.hx, g.hy, g.hz};
+  double f = 0.0;
+  for (int face = 0; face < 6; ++face) {
+    if (!((g.flux_mask >> face) & 1u)) continue;
+    const int d = face >> 1;
+    if (idx[d] != ((face & 1) ? n[d] : 0)) continue;
+    const int u = (d + 1) % 3, v = (d + 2) % 3;
+    const int cu = (idx[u] > 0) + (idx[u] < n[u]);
+    const int cv = (idx[v] > 0) + (idx[v] < n[v]);
+    f += g.flux[face] * 0.25 * h[u] * h[v] * (double)(cu * cv);
+  }
+  F[i] = f;
+}
+
+// Overwrite Dirichlet nodes of T with their boundary value.
+template <typename V>
+__global__ void apply_dirichlet_kernel(Geom g, V* __restrict__ T) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= g.N) return;
+  int ix, iy, iz;
+  node_xyz(g, i, ix, iy, iz);
+  double gv;
+  if (dirichlet_value(g, ix, iy, iz, gv)) T[i] = (V)gv;
+}
+
+// g_ext: boundary value on Dirichlet nodes, 0 elsewhere.
+__global__ void dirichlet_field_kernel(Geom g, double* __restrict__ out) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= g.N) return;
+  int ix, iy, iz;
+  node_xyz(g, i, ix, iy, iz);
+  double gv = 0.0;
+  out[i] = dirichlet_value(g, ix, iy, iz, gv) ? gv : 0.0;
+}
+
+// lift_i = (A g_ext)_i on free rows, 0 on Dirichlet rows (computed in place on y).
+__global__ void mask_free_kernel(const double* __restrict__ pinv, double* __restrict__ y, uint32_t N) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < N && pinv[i] == 0.0) y[i] = 0.0;
+}
+
+template <typename A, typename B>
+__global__ void cast_kernel(const A* __restrict__ in, B* __restrict__ out, uint32_t n) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = (B)in[i];
+}
+
+template <typename V>
+__global__ void fill_kernel(V* __restrict__ out, V v, uint32_t n) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = v;
+}
+
+template <typename V>
+__global__ void scale_kernel(const V* __restrict__ a, const V* __restrict__ x, double* __restrict__ y, uint32_t n) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) y[i] = (double)(a[i] * (V)x[i]);
+}
+
+// Field value at points: trilinear interpolation in the containing element
+// (lowest-index element on shared faces).  Traces row-major [step][sensor].
+__global__ void sensor_kernel(Geom g, const double* __restrict__ T, const double* __restrict__ xyz, int32_t S,
+                              double* __restrict__ out) {
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= S) return;
+  const int n[3] = {g.nx, g.ny, g.nz};
+  const double h[3] = {g.hx, g.hy, g.hz};
+  int e[3];
+  double xi[3];
+  for (int d = 0; d < 3; ++d) {
+    const double t = xyz[3 * s + d] / h[d];
+    int k = (int)ceil(t) - 1;
+    k = k < 0 ? 0 : (k > n[d] - 1 ? n[d] - 1 : k);
+    double loc = t - (double)k;
+    loc = loc < 0.0 ? 0.0 : (loc > 1.0 ? 1.0 : loc);
+    e[d] = k;
+    xi[d] = loc;
+  }
+  double v = 0.0;
+  for (int a = 0; a < 8; ++a) {
+    const int ax = a & 1, ay = (a >> 1) & 1, az = (a >> 2) & 1;
+    const double w = (ax ? xi[0] : 1.0 - xi[0]) * (ay ? xi[1] : 1.0 - xi[1]) * (az ? xi[2] : 1.0 - xi[2]);
+    const uint32_t i = (uint32_t)(e[0] + ax) + (uint32_t)g.px * ((uint32_t)(e[1] + ay) + (uint32_t)g.py * (uint32_t)(e[2] + az));
+    v += w * T[i];
+  }
+  out[s] = v;
+}
+
+}  // namespace femheat

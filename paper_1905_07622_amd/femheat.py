@@ -1,0 +1,291 @@
+"""Python binding of the C ABI in include/fem_heat.h (libfemheat.so).
+
+Argument marshalling only: every step of the solver runs in the HIP library.
+The functions keep the C names; ``Heat`` wraps a handle for numpy arrays
+(host memory) or torch CUDA tensors (device memory, ``device_ptrs=True``).
+Loading fails loudly when the library has not been built.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional
+
+import numpy as np
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "libfemheat.so")
+
+FEM_OK, FEM_EINVAL, FEM_ENOMEM, FEM_ENOCONV, FEM_EBREAKDOWN, FEM_EDEVICE, FEM_EBUSY, FEM_ECANCELED = (
+    0, -1, -2, -3, -4, -5, -6, -7)
+FEM_FP64, FEM_FP32_FP64DOT = 0, 1
+FEM_GUESS_EXTRAP, FEM_GUESS_PREV = 0, 1
+FEM_STOP_RHS, FEM_STOP_INITIAL = 0, 1
+FEM_DEVICE_PTRS, FEM_TIMING = 0x1, 0x2
+FEM_OP_A, FEM_OP_L, FEM_OP_JACOBI, FEM_OP_LOAD, FEM_OP_FP32 = 0, 1, 2, 3, 0x100
+
+_dp = ctypes.POINTER(ctypes.c_double)
+_ip = ctypes.POINTER(ctypes.c_int32)
+
+
+class fem_grid(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
+                ("hx", ctypes.c_double), ("hy", ctypes.c_double), ("hz", ctypes.c_double)]
+
+
+class fem_bc(ctypes.Structure):
+    _fields_ = [("dirichlet_mask", ctypes.c_uint32), ("dirichlet_value", ctypes.c_double * 6),
+                ("flux_mask", ctypes.c_uint32), ("flux", ctypes.c_double * 6),
+                ("flux_schedule", _dp), ("n_schedule", ctypes.c_int32)]
+
+
+class fem_opts(ctypes.Structure):
+    _fields_ = [("precision", ctypes.c_int32), ("max_iter", ctypes.c_int32),
+                ("replace_every", ctypes.c_int32), ("guess", ctypes.c_int32),
+                ("stop_rule", ctypes.c_int32), ("max_refine", ctypes.c_int32),
+                ("inner_rtol", ctypes.c_double), ("flags", ctypes.c_uint32),
+                ("hip_stream", ctypes.c_void_p), ("device", ctypes.c_int32),
+                ("tile_x", ctypes.c_int32), ("tile_y", ctypes.c_int32), ("tile_z", ctypes.c_int32)]
+
+
+class fem_out(ctypes.Structure):
+    _fields_ = [("T_final", _dp), ("T_saved", _dp), ("save_every", ctypes.c_int32),
+                ("sensor_xyz", _dp), ("n_sensors", ctypes.c_int32), ("traces", _dp),
+                ("iters", _ip), ("relres", _dp), ("refine_sweeps", _ip),
+                ("first_step", ctypes.c_int32), ("total_iters", ctypes.c_int64),
+                ("device_ms", ctypes.c_double)]
+
+
+class fem_stats(ctypes.Structure):
+    _fields_ = [("gather_launches", ctypes.c_int64), ("gather_ms", ctypes.c_double),
+                ("update_launches", ctypes.c_int64), ("update_ms", ctypes.c_double),
+                ("replace_launches", ctypes.c_int64), ("replace_ms", ctypes.c_double),
+                ("grid_blocks", ctypes.c_int32), ("tile_x", ctypes.c_int32),
+                ("tile_y", ctypes.c_int32), ("tile_z", ctypes.c_int32)]
+
+
+class FemError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{fem_strerror(status)} ({status}): {msg}")
+        self.status = status
+
+
+EXPORTS = ("fem_heat_create", "fem_heat_run", "fem_heat_apply", "fem_heat_stats", "fem_heat_destroy",
+           "fem_heat_default_opts", "fem_strerror", "fem_last_error")
+
+_lib = None
+
+
+def lib():
+    """Load libfemheat.so; raises if it has not been built (no fallback)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with __graft_entry__.build()")
+        L = ctypes.CDLL(LIB_PATH)
+        vp = ctypes.c_void_p
+        L.fem_heat_create.argtypes = [ctypes.POINTER(fem_grid), _dp, _dp, ctypes.POINTER(fem_bc),
+                                      ctypes.POINTER(fem_opts), ctypes.POINTER(vp)]
+        L.fem_heat_run.argtypes = [vp, _dp, _dp, ctypes.c_double, ctypes.c_double, ctypes.c_int32,
+                                   ctypes.c_double, ctypes.POINTER(fem_out)]
+        L.fem_heat_apply.argtypes = [vp, ctypes.c_int32, ctypes.c_double, ctypes.c_double, _dp, _dp]
+        L.fem_heat_stats.argtypes = [vp, ctypes.POINTER(fem_stats)]
+        L.fem_heat_destroy.argtypes = [vp]
+        L.fem_heat_destroy.restype = None
+        L.fem_heat_default_opts.argtypes = [ctypes.POINTER(fem_opts)]
+        L.fem_heat_default_opts.restype = None
+        L.fem_strerror.argtypes = [ctypes.c_int]
+        L.fem_strerror.restype = ctypes.c_char_p
+        L.fem_last_error.argtypes = [vp]
+        L.fem_last_error.restype = ctypes.c_char_p
+        for n in ("fem_heat_create", "fem_heat_run", "fem_heat_apply", "fem_heat_stats"):
+            getattr(L, n).restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+# ---------------------------------------------------------------------------
+# the C entry points, same names
+# ---------------------------------------------------------------------------
+
+def fem_strerror(status: int) -> str:
+    return lib().fem_strerror(status).decode()
+
+
+def fem_last_error(h) -> str:
+    return lib().fem_last_error(h).decode()
+
+
+def fem_heat_default_opts() -> fem_opts:
+    o = fem_opts()
+    lib().fem_heat_default_opts(ctypes.byref(o))
+    return o
+
+
+def fem_heat_create(grid: fem_grid, k_e_ptr, rhoc_e_ptr, bc: Optional[fem_bc], opts: Optional[fem_opts]):
+    h = ctypes.c_void_p()
+    st = lib().fem_heat_create(ctypes.byref(grid), k_e_ptr, rhoc_e_ptr,
+                               ctypes.byref(bc) if bc is not None else None,
+                               ctypes.byref(opts) if opts is not None else None, ctypes.byref(h))
+    return st, h
+
+
+def fem_heat_run(h, T0_ptr, T_prev_ptr, dt, theta, nsteps, rtol, out: Optional[fem_out]) -> int:
+    return lib().fem_heat_run(h, T0_ptr, T_prev_ptr, dt, theta, nsteps, rtol,
+                              ctypes.byref(out) if out is not None else None)
+
+
+def fem_heat_apply(h, which, dt, theta, x_ptr, y_ptr) -> int:
+    return lib().fem_heat_apply(h, which, dt, theta, x_ptr, y_ptr)
+
+
+def fem_heat_stats(h) -> fem_stats:
+    s = fem_stats()
+    st = lib().fem_heat_stats(h, ctypes.byref(s))
+    if st != FEM_OK:
+        raise FemError(st, "fem_heat_stats")
+    return s
+
+
+def fem_heat_destroy(h) -> None:
+    lib().fem_heat_destroy(h)
+
+
+# ---------------------------------------------------------------------------
+# marshalling helpers
+# ---------------------------------------------------------------------------
+
+def _is_torch(a) -> bool:
+    return type(a).__module__.startswith("torch")
+
+
+class _Arrays:
+    """Turns numpy arrays (host) or torch CUDA tensors (device) into pointers,
+    keeping the objects alive."""
+
+    def __init__(self, device: bool):
+        self.device = device
+        self.keep = []
+
+    def inp(self, a, dtype=np.float64):
+        if a is None:
+            return None
+        if self.device:
+            import torch
+            if not (_is_torch(a) and a.is_cuda):
+                raise TypeError("device_ptrs handle: pass torch CUDA tensors")
+            t = a.contiguous().to(torch.float64 if dtype == np.float64 else torch.int32)
+            self.keep.append(t)
+            return ctypes.cast(t.data_ptr(), _dp if dtype == np.float64 else _ip)
+        arr = np.ascontiguousarray(a, dtype=dtype)
+        self.keep.append(arr)
+        return arr.ctypes.data_as(_dp if dtype == np.float64 else _ip)
+
+    def out(self, shape, dtype=np.float64):
+        if self.device:
+            import torch
+            t = torch.empty(shape, dtype=torch.float64 if dtype == np.float64 else torch.int32, device="cuda")
+            self.keep.append(t)
+            return t, ctypes.cast(t.data_ptr(), _dp if dtype == np.float64 else _ip)
+        arr = np.zeros(shape, dtype=dtype)
+        self.keep.append(arr)
+        return arr, arr.ctypes.data_as(_dp if dtype == np.float64 else _ip)
+
+
+class Heat:
+    """One solver handle for a grid, coefficient field and boundary conditions."""
+
+    def __init__(self, nx, ny, nz, hx, hy, hz, k_e, rhoc_e, *, dirichlet_mask=0, dirichlet_value=None,
+                 flux_mask=0, flux=None, flux_schedule=None, precision=FEM_FP64, max_iter=10000,
+                 replace_every=50, guess=FEM_GUESS_EXTRAP, stop_rule=FEM_STOP_RHS, max_refine=4,
+                 inner_rtol=1e-5, device_ptrs=False, timing=False, tile=(0, 0, 0), stream=None, device=0):
+        self.h = None
+        self.device_ptrs = device_ptrs
+        self.N = (nx + 1) * (ny + 1) * (nz + 1)
+        self.E = nx * ny * nz
+        self.grid = fem_grid(nx, ny, nz, hx, hy, hz)
+        bc = fem_bc()
+        bc.dirichlet_mask = dirichlet_mask
+        bc.dirichlet_value = (ctypes.c_double * 6)(*([0.0] * 6 if dirichlet_value is None else list(dirichlet_value)))
+        bc.flux_mask = flux_mask
+        bc.flux = (ctypes.c_double * 6)(*([0.0] * 6 if flux is None else list(flux)))
+        self._sched = None if flux_schedule is None else np.ascontiguousarray(flux_schedule, dtype=np.float64)
+        bc.flux_schedule = None if self._sched is None else self._sched.ctypes.data_as(_dp)
+        bc.n_schedule = 0 if self._sched is None else len(self._sched)
+        o = fem_heat_default_opts()
+        o.precision, o.max_iter, o.replace_every = precision, max_iter, replace_every
+        o.guess, o.stop_rule, o.max_refine, o.inner_rtol = guess, stop_rule, max_refine, inner_rtol
+        o.flags = (FEM_DEVICE_PTRS if device_ptrs else 0) | (FEM_TIMING if timing else 0)
+        o.hip_stream = stream
+        o.device = device
+        o.tile_x, o.tile_y, o.tile_z = tile
+        self.opts = o
+        arrs = _Arrays(device_ptrs)
+        st, h = fem_heat_create(self.grid, arrs.inp(k_e), arrs.inp(rhoc_e), bc, o)
+        if st != FEM_OK:
+            raise FemError(st, fem_last_error(None))
+        self.h = h
+
+    @classmethod
+    def from_problem(cls, p, **kw):
+        return cls(p.nx, p.ny, p.nz, p.hx, p.hy, p.hz, p.k_e, p.rhoc_e,
+                   dirichlet_mask=p.dirichlet_mask, dirichlet_value=p.dirichlet_value,
+                   flux_mask=p.flux_mask, flux=p.flux, flux_schedule=p.flux_schedule, **kw)
+
+    def run(self, T0, T_prev=None, *, dt, theta, nsteps, rtol, save_every=0, sensors=None, first_step=0,
+            check=True) -> dict:
+        a = _Arrays(self.device_ptrs)
+        out = fem_out()
+        T_final, out.T_final = a.out((self.N,))
+        n_saved = nsteps // save_every if save_every else 0
+        T_saved = None
+        if n_saved:
+            T_saved, out.T_saved = a.out((n_saved, self.N))
+        out.save_every = save_every
+        S = 0
+        traces = None
+        if sensors is not None:
+            S = len(sensors)
+            out.sensor_xyz = a.inp(sensors)
+            out.n_sensors = S
+            traces, out.traces = a.out((nsteps, S))
+        iters, out.iters = a.out((nsteps,), np.int32)
+        relres, out.relres = a.out((nsteps,))
+        sweeps, out.refine_sweeps = a.out((nsteps,), np.int32)
+        out.first_step = first_step
+        st = fem_heat_run(self.h, a.inp(T0), a.inp(T_prev), dt, theta, nsteps, rtol, out)
+        if check and st not in (FEM_OK, FEM_ENOCONV):
+            raise FemError(st, fem_last_error(self.h))
+        return dict(status=st, T_final=T_final, T_saved=T_saved, traces=traces, iters=iters, relres=relres,
+                    refine_sweeps=sweeps, total_iters=int(out.total_iters), device_ms=float(out.device_ms))
+
+    def apply(self, which, x=None, *, dt, theta, fp32=False):
+        a = _Arrays(self.device_ptrs)
+        y, yp = a.out((self.N,))
+        if x is None:
+            x = np.zeros(self.N) if not self.device_ptrs else __import__("torch").zeros(self.N, dtype=__import__("torch").float64, device="cuda")
+        st = fem_heat_apply(self.h, which | (FEM_OP_FP32 if fp32 else 0), dt, theta, a.inp(x), yp)
+        if st != FEM_OK:
+            raise FemError(st, fem_last_error(self.h))
+        return y
+
+    def stats(self) -> dict:
+        s = fem_heat_stats(self.h)
+        return {k: getattr(s, k) for k, _ in fem_stats._fields_}
+
+    def close(self):
+        if self.h:
+            fem_heat_destroy(self.h)
+            self.h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,96 @@
+"""The C-ABI library loads and exports every entry point declared in include/*.h.
+
+CPU-only: no call here touches a GPU (only string/option helpers and argument
+validation that fails before any device work).
+"""
+
+import glob
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_1905_07622_amd import femheat as fh
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    names = set()
+    for path in glob.glob(os.path.join(ROOT, "include", "*.h")):
+        text = open(path).read()
+        text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+        for m in re.finditer(r"^\s*(?:const\s+)?[A-Za-z_][\w\s\*]*?\b(fem_\w+)\s*\(", text, flags=re.M):
+            names.add(m.group(1))
+    return sorted(names)
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(fh.LIB_PATH):
+        from paper_1905_07622_amd import build
+        build.build()
+    return fh.lib()
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for n in ("fem_heat_create", "fem_heat_run", "fem_heat_apply", "fem_heat_destroy", "fem_strerror",
+              "fem_last_error"):
+        assert n in names
+
+
+def test_every_declared_symbol_is_exported(lib):
+    missing = [n for n in declared_functions() if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+def test_strerror_and_default_opts(lib):
+    for code in range(0, -8, -1):
+        assert fh.fem_strerror(code)
+    assert "unknown" in fh.fem_strerror(-99)
+    o = fh.fem_heat_default_opts()
+    assert (o.precision, o.max_iter, o.replace_every, o.guess, o.stop_rule, o.max_refine) == (0, 10000, 50, 0, 0, 4)
+    assert abs(o.inner_rtol - 1e-5) < 1e-20
+
+
+def _create(nx=2, ny=2, nz=2, h=0.5, k=None, rhoc=None, **bc_kw):
+    E = nx * ny * nz
+    k = np.ones(E) if k is None else k
+    rhoc = np.ones(E) if rhoc is None else rhoc
+    bc = fh.fem_bc()
+    for key, v in bc_kw.items():
+        setattr(bc, key, v)
+    st, h_ = fh.fem_heat_create(fh.fem_grid(nx, ny, nz, h, h, h), k.ctypes.data_as(fh._dp),
+                                rhoc.ctypes.data_as(fh._dp), bc, None)
+    return st, h_, fh.fem_last_error(None)
+
+
+@pytest.mark.parametrize("case", ["grid", "h", "k_neg", "k_nan", "rhoc_zero", "masks", "mask_bits"])
+def test_create_rejects_invalid_arguments_before_device_work(lib, case):
+    kw = {}
+    if case == "grid":
+        kw = dict(nx=0)
+    elif case == "h":
+        kw = dict(h=-1.0)
+    elif case == "k_neg":
+        kw = dict(k=np.array([1, 1, 1, -1, 1, 1, 1, 1.0]))
+    elif case == "k_nan":
+        kw = dict(k=np.array([1, 1, 1, np.nan, 1, 1, 1, 1.0]))
+    elif case == "rhoc_zero":
+        kw = dict(rhoc=np.array([1, 1, 0, 1, 1, 1, 1, 1.0]))
+    elif case == "masks":
+        kw = dict(dirichlet_mask=1 << 4, flux_mask=1 << 4)
+    elif case == "mask_bits":
+        kw = dict(flux_mask=1 << 6)
+    st, h, msg = _create(**kw)
+    assert st == fh.FEM_EINVAL and not h.value and msg
+
+
+def test_null_handle_calls_are_rejected(lib):
+    assert lib.fem_heat_run(None, None, None, 1.0, 1.0, 1, 1.0, None) == fh.FEM_EINVAL
+    assert lib.fem_heat_apply(None, 0, 1.0, 1.0, None, None) == fh.FEM_EINVAL
+    lib.fem_heat_destroy(None)
+    assert lib.fem_heat_stats(None, None) == fh.FEM_EINVAL
+
