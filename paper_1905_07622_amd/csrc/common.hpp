@@ -20,7 +20,8 @@ struct Geom {
   double flux[6];
 };
 
-// Device-resident scalars of one PCG solve (Algorithm 1), all in FP64.
+// State of one PCG solve (Algorithm 1), all scalars in FP64, relayed from
+// kernel to kernel on the device.
 struct Scalars {
   double delta;      // r^T P^-1 r of the current residual (delta_new)
   double delta_old;
@@ -30,13 +31,12 @@ struct Scalars {
   double dq;         // d^T q
   double alpha;
   double beta;
-  double aux;        // scratch for test hooks
   int32_t iter;      // completed iterations of the current solve
   int32_t done;      // 1: every further iteration kernel is a no-op
   int32_t status;    // 0 or a negative status (breakdown)
   int32_t zero_rhs;  // b^T P^-1 b == 0 with the RHS stop rule
-  uint32_t ticket;   // arrival counter of the last-block reduction
-  int32_t pad[3];
+  int32_t phase;     // which scalar update the latest partials complete
+  int32_t pad;
 };
 
 // Controls of one solve.
@@ -46,14 +46,24 @@ struct Ctl {
   int32_t stop_rule; // 0: relative to b^T P^-1 b, 1: relative to the initial residual
 };
 
-enum Finalize : int32_t {
-  FIN_NONE = 0,
-  FIN_RHS = 1,    // delta_b = sum
-  FIN_INIT = 2,   // delta = delta0 = sum; tol; done test before the first iteration
-  FIN_ALPHA = 3,  // dq = sum; alpha = delta / dq (breakdown test)
-  FIN_DELTA = 4,  // delta_old = delta; delta = sum; beta; iter++; done test
-  FIN_CHECK = 5,  // delta = sum; done test (outer refinement check)
-  FIN_STORE = 6   // aux = sum
+enum Phase : int32_t {
+  PH_NONE = 0,
+  PH_AFTER_INIT = 1,   // partials hold r0^T P^-1 r0
+  PH_AFTER_UPD = 2,    // partials hold r^T P^-1 r after an update
+  PH_AFTER_CHECK = 3,  // partials hold the FP64 residual norm of a refinement sweep
+  PH_DECIDED = 4
+};
+
+// Role of a kernel in the relay.
+enum Mode : int32_t {
+  M_NONE = 0,    // no solve state (test hooks, setup)
+  M_RHS = 1,     // right-hand side of a new step
+  M_INIT = 2,    // initial guess and residual (reads b^T P^-1 b)
+  M_START = 3,   // initial residual of an inner solve
+  M_DIR = 4,     // settles delta/beta/stop, then direction + apply
+  M_UPD = 5,     // settles alpha, then x/r update (or replacement)
+  M_CORR = 6,    // FP64 correction of a refinement sweep
+  M_DECIDE = 7   // settles the pending decision only
 };
 
 constexpr int32_t kStatusBreakdown = -4;

@@ -46,9 +46,6 @@ struct GatherArgs {
   const V* kc;     // per-element k
   V sa, sb;        // cubic: cm*h^3/216, ck*h/12 ; general: cm, ck
   V Mc[8], Kc[8];  // general elements: class entries M[c], K[c]
-  Ctl ctl;
-  int32_t fin;
-  int32_t check_done;
 };
 
 // 3x3 neighbourhood of one plane around a column: centre, x-/x+, y-/y+, and
@@ -73,11 +70,11 @@ __device__ inline void read_plane(const V* P, int pw, int lx, int ly, PlaneQ<V>&
 }
 
 template <typename V, bool CUBIC, class Pro, class Epi>
-__global__ void __launch_bounds__(256) gather_kernel(GatherArgs<V> ga, Pro pro, Epi epi, Scalars* S,
-                                                     double* partials) {
-  if (ga.check_done && S->done) return;  // uniform early exit after convergence
-  pro.init(S);
-  epi.init(S);
+__global__ void __launch_bounds__(256) gather_kernel(GatherArgs<V> ga, Pro pro, Epi epi, Relay R) {
+  Scalars st;
+  if (!stage_entry(R, st)) return;  // uniform: the solve is done (or broke down)
+  pro.init(st);
+  epi.init(st);
 
   extern __shared__ unsigned char smem_raw[];
   const int TX = ga.s.tx, TY = ga.s.ty, TZ = ga.s.tz;
@@ -194,7 +191,7 @@ __global__ void __launch_bounds__(256) gather_kernel(GatherArgs<V> ga, Pro pro, 
       buf ^= 1;
     }
   }
-  if (ga.fin != FIN_NONE) reduce_and_finalize(dot, partials, S, ga.s.nblocks, blockIdx.x, ga.fin, ga.ctl);
+  if (R.pout) publish_partial(R, dot);
 }
 
 // ---------------------------------------------------------------------------
@@ -204,7 +201,7 @@ __global__ void __launch_bounds__(256) gather_kernel(GatherArgs<V> ga, Pro pro, 
 template <typename V>
 struct ProPlain {  // v = src
   const V* src;
-  __device__ void init(const Scalars*) {}
+  __device__ void init(const Scalars&) {}
   __device__ V load(uint32_t i, bool) const { return src[i]; }
 };
 
@@ -215,7 +212,7 @@ struct ProDirection {  // d_new = P^-1 r + beta d_old   (Algorithm 1: s <- P^-1 
   const V* dold;
   V* dnew;
   V beta;
-  __device__ void init(const Scalars* S) { beta = (V)S->beta; }
+  __device__ void init(const Scalars& S) { beta = (V)S.beta; }
   __device__ V load(uint32_t i, bool owned) const {
     const V v = pinv[i] * r[i] + beta * dold[i];
     if (owned) dnew[i] = v;
@@ -230,7 +227,7 @@ struct ProAxpy {  // x_new = x + alpha d  (alpha from the solve's scalars, or 1 
   V* xnew;
   int32_t unit_alpha;
   V alpha;
-  __device__ void init(const Scalars* S) { alpha = unit_alpha ? V(1) : (V)S->alpha; }
+  __device__ void init(const Scalars& S) { alpha = unit_alpha ? V(1) : (V)S.alpha; }
   __device__ V load(uint32_t i, bool owned) const {
     const V v = x[i] + alpha * (V)d[i];
     if (owned) xnew[i] = v;
@@ -246,7 +243,7 @@ struct ProGuess {  // x0 = 2 T1 - T2 (u0_update, App. A.2) or T1; 0 on free node
   V* x;
   int32_t prev;
   int32_t zero;
-  __device__ void init(const Scalars* S) { zero = S->zero_rhs; }
+  __device__ void init(const Scalars& S) { zero = S.zero_rhs; }
   __device__ V load(uint32_t i, bool owned) const {
     V v = prev ? t1[i] : V(2) * t1[i] - t2[i];
     if (zero) v = (pinv[i] == V(0)) ? t1[i] : V(0);
@@ -262,7 +259,7 @@ struct ProGuess {  // x0 = 2 T1 - T2 (u0_update, App. A.2) or T1; 0 on free node
 template <typename V>
 struct EpiStore {  // y = A v
   V* y;
-  __device__ void init(const Scalars*) {}
+  __device__ void init(const Scalars&) {}
   __device__ double store(uint32_t i, V acc, V) const {
     y[i] = acc;
     return 0.0;
@@ -272,7 +269,7 @@ struct EpiStore {  // y = A v
 template <typename V>
 struct EpiQDot {  // q = A d ; contribution d_i q_i to d^T q
   V* q;
-  __device__ void init(const Scalars*) {}
+  __device__ void init(const Scalars&) {}
   __device__ double store(uint32_t i, V acc, V v) const {
     q[i] = acc;
     return (double)v * (double)acc;
@@ -284,7 +281,7 @@ struct EpiResidual {  // r = b - A x (0 on Dirichlet rows); contribution r_i P^-
   const V* b;
   const V* pinv;
   V* r;
-  __device__ void init(const Scalars*) {}
+  __device__ void init(const Scalars&) {}
   __device__ double store(uint32_t i, V acc, V) const {
     const V p = pinv[i];
     const V rr = (p == V(0)) ? V(0) : b[i] - acc;
@@ -300,7 +297,7 @@ struct EpiRhs {  // b = L T + dt*s*F ; contribution (b - lift)_i P^-1_i (b - lif
   const V* pinv;
   const V* lift;  // A_fD g for non-zero Dirichlet values, or nullptr
   V fs;           // dt * s_n
-  __device__ void init(const Scalars*) {}
+  __device__ void init(const Scalars&) {}
   __device__ double store(uint32_t i, V acc, V) const {
     const V bb = acc + fs * F[i];
     b[i] = bb;

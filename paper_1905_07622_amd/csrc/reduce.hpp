@@ -1,16 +1,48 @@
-// Deterministic FP64 reductions for wave64 blocks and the device-side scalar
-// updates of Algorithm 1 (VVM_A/VVM_reduce/VVM_C, Beta_update of App. A.2,
-// done here in one pass: block partials, then the last block to arrive sums
-// them in block order and updates the solve's scalars on the device).
+// Device-side control of Algorithm 1 without atomics or cross-block fences.
+//
+// The VVM_A / VVM_reduce / VVM_C / Beta_update kernels of App. A.2 become:
+//  * every kernel that produces a dot product writes one FP64 partial per
+//    block (plain stores);
+//  * the NEXT kernel in stream order reads those partials at its start: wave 0
+//    of every block sums them in one fixed order (so every block obtains the
+//    bit-identical value), evaluates the pending scalar update of Algorithm 1
+//    (alpha, or delta/beta and the stop test) and broadcasts it to the block;
+//  * the solve state is relayed through a ping-pong pair of Scalars: a kernel
+//    reads Sin and its block 0 writes the updated state to Sout, so no block
+//    ever reads a value another block of the same kernel writes.
+// Kernel boundaries order everything (stream order makes a kernel's writes
+// visible to the next one on every XCD), which is why no atomics are needed.
+// Once a solve is done, every further iteration kernel copies the state and
+// returns immediately.
 #pragma once
 
 #include "common.hpp"
 
 namespace femheat {
 
-// Sum over the block; the result is valid in thread 0.  blockDim.x must be a
-// multiple of 64 and at most 1024.  Deterministic: fixed shuffle tree, then
-// waves summed in order.
+struct Relay {
+  const Scalars* sin;
+  Scalars* sout;
+  const double* pin;   // partials of the previous kernel of this solve
+  uint32_t npin;
+  double* pout;        // this kernel's partials (one per block), or nullptr
+  int32_t mode;
+  Ctl ctl;
+};
+
+// Sum of n partials, evaluated by the 64 lanes of wave 0 in a fixed order
+// (lane-strided sequential sums, then an xor-shuffle tree); every lane gets the
+// same value, independently of the block size of the calling kernel.
+__device__ inline double wave_sum_partials(const double* p, uint32_t n) {
+  const uint32_t lane = threadIdx.x & 63u;
+  double s = 0.0;
+  for (uint32_t k = lane; k < n; k += 64) s += p[k];
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+  return s;
+}
+
+// Sum over the block (blockDim.x a multiple of 64, at most 1024); valid in thread 0.
 __device__ inline double block_sum(double v, double* wsum) {
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
@@ -26,93 +58,133 @@ __device__ inline double block_sum(double v, double* wsum) {
   return s;
 }
 
-__device__ inline void finalize_scalars(int32_t fin, Scalars* S, double s, const Ctl& c) {
-  switch (fin) {
-    case FIN_RHS:
-      S->delta_b = s;
-      S->zero_rhs = (c.stop_rule == 0 && s == 0.0) ? 1 : 0;
-      break;
-    case FIN_INIT: {
-      S->delta = s;
-      S->delta0 = s;
-      S->delta_old = s;
-      S->beta = 0.0;
-      S->iter = 0;
-      S->status = 0;
-      const double tol = c.stop_rule == 1 ? c.rtol2 * s : c.rtol2 * S->delta_b;
-      S->tol = tol;
-      if (!isfinite(s)) {
-        S->status = kStatusBreakdown;
-        S->done = 1;
+// The scalar update that the previous kernel's partial sum x completes.
+__device__ inline void evaluate_pending(Scalars& s, double x, const Ctl& c) {
+  switch (s.phase) {
+    case PH_AFTER_INIT: {  // r0^T P^-1 r0: tolerance and the test before the first iteration
+      s.delta = x;
+      s.delta0 = x;
+      s.delta_old = x;
+      s.beta = 0.0;
+      s.iter = 0;
+      s.tol = c.stop_rule == 1 ? c.rtol2 * x : c.rtol2 * s.delta_b;
+      if (!isfinite(x)) {
+        s.status = kStatusBreakdown;
+        s.done = 1;
       } else {
-        S->done = (c.max_iter <= 0 || !(s > tol)) ? 1 : 0;
+        s.done = (c.max_iter <= 0 || !(x > s.tol)) ? 1 : 0;
       }
     } break;
-    case FIN_ALPHA: {
-      S->dq = s;
-      const double a = S->delta / s;
-      if (!(s > 0.0) || !isfinite(s) || !isfinite(a)) {
-        S->status = kStatusBreakdown;
-        S->done = 1;
+    case PH_AFTER_UPD: {  // delta_new = r^T P^-1 r: beta and the stop test
+      const double old = s.delta;  // delta_old <- delta_new before the new value
+      s.delta_old = old;
+      s.delta = x;
+      s.beta = x / old;
+      if (!isfinite(x)) {
+        s.status = kStatusBreakdown;
+        s.done = 1;
       } else {
-        S->alpha = a;
+        s.done = (!(x > s.tol) || s.iter >= c.max_iter) ? 1 : 0;
       }
     } break;
-    case FIN_DELTA: {
-      const double old = S->delta;  // delta_old <- delta_new before the new value
-      S->delta_old = old;
-      S->delta = s;
-      S->beta = s / old;
-      S->iter += 1;
-      if (!isfinite(s)) {
-        S->status = kStatusBreakdown;
-        S->done = 1;
+    case PH_AFTER_CHECK:  // FP64 residual of a refinement sweep
+      s.delta = x;
+      if (!isfinite(x)) {
+        s.status = kStatusBreakdown;
+        s.done = 1;
       } else {
-        S->done = (!(s > S->tol) || S->iter >= c.max_iter) ? 1 : 0;
+        s.done = !(x > s.tol) ? 1 : 0;
       }
-    } break;
-    case FIN_CHECK:
-      S->delta = s;
-      if (!isfinite(s)) {
-        S->status = kStatusBreakdown;
-        S->done = 1;
-      } else {
-        S->done = !(s > S->tol) ? 1 : 0;
-      }
-      break;
-    case FIN_STORE:
-      S->aux = s;
       break;
     default:
       break;
   }
+  s.phase = PH_DECIDED;
 }
 
-// Publish this block's partial; the last block to arrive sums all partials in
-// block order and runs the finalisation.  Every thread of every block must
-// call it (uniform control flow).
-__device__ inline void reduce_and_finalize(double v, double* partials, Scalars* S, uint32_t nblocks,
-                                           uint32_t block, int32_t fin, const Ctl& c) {
-  __shared__ double wsum[16];
-  __shared__ int am_last;
-  const double bs = block_sum(v, wsum);
-  if (threadIdx.x == 0) {
-    __hip_atomic_store(&partials[block], bs, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-    const uint32_t t = __hip_atomic_fetch_add(&S->ticket, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-    am_last = (t == nblocks - 1) ? 1 : 0;
+// Entry of every relayed kernel: evaluates the state this kernel works with,
+// has block 0 publish it to Sout, and returns whether the kernel has work.
+__device__ inline bool stage_entry(const Relay& R, Scalars& out) {
+  __shared__ Scalars sh;
+  __shared__ int go;
+  if (threadIdx.x < 64) {
+    Scalars t{};
+    if (R.sin) t = *R.sin;
+    int g = 1;
+    switch (R.mode) {
+      case M_RHS:  // a new step: b and b^T P^-1 b
+        t.done = 0;
+        t.status = 0;
+        t.phase = PH_NONE;
+        break;
+      case M_INIT: {  // b^T P^-1 b known: the guess prologue needs the zero-RHS flag
+        const double x = wave_sum_partials(R.pin, R.npin);
+        t.delta_b = x;
+        t.zero_rhs = (R.ctl.stop_rule == 0 && x == 0.0) ? 1 : 0;
+        t.done = 0;
+        t.status = 0;
+        t.phase = PH_AFTER_INIT;
+      } break;
+      case M_START:  // a solve whose initial residual this kernel produces
+        t.done = 0;
+        t.status = 0;
+        t.delta_b = 0.0;
+        t.zero_rhs = 0;
+        t.phase = PH_AFTER_INIT;
+        break;
+      case M_DIR:
+      case M_DECIDE:
+        if (!t.done && t.phase != PH_DECIDED && t.phase != PH_NONE)
+          evaluate_pending(t, wave_sum_partials(R.pin, R.npin), R.ctl);
+        g = (R.mode == M_DIR && !t.done) ? 1 : 0;
+        break;
+      case M_UPD:
+        if (t.done) {
+          g = 0;
+        } else {
+          const double dq = wave_sum_partials(R.pin, R.npin);
+          const double a = t.delta / dq;
+          t.dq = dq;
+          if (!(dq > 0.0) || !isfinite(dq) || !isfinite(a)) {
+            t.status = kStatusBreakdown;
+            t.done = 1;
+            g = 0;
+          } else {
+            t.alpha = a;
+            t.iter += 1;
+            t.phase = PH_AFTER_UPD;
+          }
+        }
+        break;
+      case M_CORR:
+        t.phase = PH_AFTER_CHECK;
+        g = t.done ? 0 : 1;
+        break;
+      default:  // M_NONE
+        break;
+    }
+    if (threadIdx.x == 0) {
+      sh = t;
+      go = g;
+      if (blockIdx.x == 0 && R.sout) *R.sout = t;
+    }
   }
   __syncthreads();
-  if (!am_last) return;
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-  double s = 0.0;
-  for (uint32_t k = threadIdx.x; k < nblocks; k += blockDim.x)
-    s += __hip_atomic_load(&partials[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  s = block_sum(s, wsum);
-  if (threadIdx.x == 0) {
-    __hip_atomic_store(&S->ticket, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    finalize_scalars(fin, S, s, c);
-  }
+  out = sh;
+  return go != 0;
+}
+
+// One partial per block for the next kernel.
+__device__ inline void publish_partial(const Relay& R, double v) {
+  __shared__ double wsum[16];
+  const double bs = block_sum(v, wsum);
+  if (threadIdx.x == 0 && R.pout) R.pout[blockIdx.x] = bs;
+}
+
+// A kernel that only settles the pending decision (end of an iteration chunk).
+__global__ void decide_kernel(Relay R) {
+  Scalars s;
+  (void)stage_entry(R, s);
 }
 
 }  // namespace femheat

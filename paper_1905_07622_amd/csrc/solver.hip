@@ -12,10 +12,12 @@
 // printed) the update is replaced by a gather computing r = b - A x.
 //
 // The paper's host read the residual back every iteration (App. A.3).  Here
-// the convergence decision is taken on the device: once a solve is done every
-// further iteration kernel returns immediately, so the host enqueues
-// iterations in chunks and reads a small pinned scalar block once per chunk,
-// sizing the first chunk of a step from the previous step's iteration count.
+// the scalars of Algorithm 1 and the convergence decision live on the device
+// and are relayed from kernel to kernel (reduce.hpp): once a solve is done
+// every further iteration kernel returns immediately, so the host enqueues
+// iterations in chunks, ends a chunk with a one-block decide kernel and reads
+// a small pinned scalar block once per chunk, sizing the first chunk of a
+// step from the previous step's iteration count.
 #include <algorithm>
 #include <cmath>
 #include <cstring>
@@ -144,26 +146,48 @@ void fill_classes(const Geom& g, GatherArgs<V>& ga, double cm, double ck, bool c
   ga.sb = (V)ck;
 }
 
+// Relay arguments of the next kernel of a solve: it reads the state and
+// partials the previous kernel left and writes the other buffer of each pair.
+Relay next_relay(RelayCtx& c, int32_t mode, bool partials, uint32_t grid) {
+  Relay R{c.S[c.cur], c.S[c.cur ^ 1], c.P[c.cur], c.npin, partials ? c.P[c.cur ^ 1] : nullptr, mode, c.ctl};
+  c.cur ^= 1;
+  if (partials) c.npin = grid;
+  return R;
+}
+
+Relay no_relay() { return Relay{nullptr, nullptr, nullptr, 0, nullptr, M_NONE, Ctl{0.0, 0, 0}}; }
+
 template <typename V, class Pro, class Epi>
-int launch_gather(fem_heat* h, const V* rhoc, const V* kc, double cm, double ck, Pro pro, Epi epi, Scalars* S,
-                  int32_t fin, const Ctl& ctl, int32_t check_done) {
+int launch_gather(fem_heat* h, const V* rhoc, const V* kc, double cm, double ck, Pro pro, Epi epi, const Relay& R) {
   GatherArgs<V> ga{};
   ga.g = h->g;
   ga.s = h->shape;
   ga.rhoc = rhoc;
   ga.kc = kc;
   fill_classes(h->g, ga, cm, ck, h->cubic);
-  ga.ctl = ctl;
-  ga.fin = fin;
-  ga.check_done = check_done;
   const size_t smem = h->shape.smem_bytes(sizeof(V));
   if (h->cubic)
     hipLaunchKernelGGL((gather_kernel<V, true, Pro, Epi>), dim3(h->shape.nblocks), dim3(h->shape.nthreads), smem,
-                       h->stream, ga, pro, epi, S, h->partials);
+                       h->stream, ga, pro, epi, R);
   else
     hipLaunchKernelGGL((gather_kernel<V, false, Pro, Epi>), dim3(h->shape.nblocks), dim3(h->shape.nthreads), smem,
-                       h->stream, ga, pro, epi, S, h->partials);
+                       h->stream, ga, pro, epi, R);
   HIP_TRY(hipGetLastError());
+  return FEM_OK;
+}
+
+template <typename V, class Pro, class Epi>
+int gather_step(fem_heat* h, RelayCtx& c, int32_t mode, const V* rhoc, const V* kc, double cm, double ck, Pro pro,
+                Epi epi) {
+  return launch_gather<V>(h, rhoc, kc, cm, ck, pro, epi, next_relay(c, mode, true, h->shape.nblocks));
+}
+
+// Settles the pending decision of a solve and copies its state to the host.
+int decide_and_read(fem_heat* h, RelayCtx& c, Scalars* host) {
+  hipLaunchKernelGGL(decide_kernel, dim3(1), dim3(64), 0, h->stream, next_relay(c, M_DECIDE, false, 1));
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(hipMemcpyAsync(host, c.S[c.cur], sizeof(Scalars), hipMemcpyDeviceToHost, h->stream));
+  HIP_TRY(hipStreamSynchronize(h->stream));
   return FEM_OK;
 }
 
@@ -201,19 +225,12 @@ int prepare_operator(fem_heat* h, double ck, bool need32) {
   if (h->nonzero_dirichlet) {
     double* gext = h->q64;  // scratch
     hipLaunchKernelGGL(dirichlet_field_kernel, dim3(nblk(N)), dim3(kT), 0, h->stream, h->g, gext);
-    Ctl none{0.0, 0, 0};
     RC_TRY(launch_gather<double>(h, h->rhoc64, h->k64, 1.0, ck, ProPlain<double>{gext},
-                                 EpiStore<double>{h->lift64}, h->S_outer, FIN_NONE, none, 0));
+                                 EpiStore<double>{h->lift64}, no_relay()));
     hipLaunchKernelGGL(mask_free_kernel, dim3(nblk(N)), dim3(kT), 0, h->stream, h->pinv64, h->lift64, N);
     HIP_TRY(hipGetLastError());
   }
   h->ck_cached = ck;
-  return FEM_OK;
-}
-
-int read_scalars(fem_heat* h, Scalars* S_dev, Scalars* out) {
-  HIP_TRY(hipMemcpyAsync(out, S_dev, sizeof(Scalars), hipMemcpyDeviceToHost, h->stream));
-  HIP_TRY(hipStreamSynchronize(h->stream));
   return FEM_OK;
 }
 
@@ -238,9 +255,8 @@ struct PcgBufs {
   const V* b;
   const V* rhoc;
   const V* kc;
-  Scalars* S;
+  RelayCtx* ctx;
   Scalars* S_host;
-  Ctl ctl;
   double ck;
   uint32_t upd_blocks;
 };
@@ -250,6 +266,7 @@ struct PcgBufs {
 template <typename V>
 int pcg_loop(fem_heat* h, PcgBufs<V>& B, int first_chunk, int* iters) {
   const int R = h->opts.replace_every;
+  RelayCtx& c = *B.ctx;
   int done_iters = 0;
   int k = std::max(1, first_chunk);
   for (;;) {
@@ -258,22 +275,23 @@ int pcg_loop(fem_heat* h, PcgBufs<V>& B, int first_chunk, int* iters) {
     for (int j = 0; j < k; ++j) {
       const int it = done_iters + j;
       if (h->timing) HIP_TRY(hipEventRecord(h->events[3 * j], h->stream));
-      RC_TRY(launch_gather<V>(h, B.rhoc, B.kc, 1.0, B.ck, ProDirection<V>{B.r, B.pinv, B.d[dp], B.d[dp ^ 1], V(0)},
-                              EpiQDot<V>{B.q}, B.S, FIN_ALPHA, B.ctl, 1));
+      RC_TRY(gather_step<V>(h, c, M_DIR, B.rhoc, B.kc, 1.0, B.ck,
+                            ProDirection<V>{B.r, B.pinv, B.d[dp], B.d[dp ^ 1], V(0)}, EpiQDot<V>{B.q}));
       dp ^= 1;
       if (h->timing) HIP_TRY(hipEventRecord(h->events[3 * j + 1], h->stream));
       if (R > 0 && it % R == 0) {
-        RC_TRY(launch_gather<V>(h, B.rhoc, B.kc, 1.0, B.ck, ProAxpy<V, V>{B.x[xc], B.d[dp], B.x[xc ^ 1], 0, V(0)},
-                                EpiResidual<V>{B.b, B.pinv, B.r}, B.S, FIN_DELTA, B.ctl, 1));
+        RC_TRY(gather_step<V>(h, c, M_UPD, B.rhoc, B.kc, 1.0, B.ck,
+                              ProAxpy<V, V>{B.x[xc], B.d[dp], B.x[xc ^ 1], 0, V(0)},
+                              EpiResidual<V>{B.b, B.pinv, B.r}));
         xc ^= 1;
       } else {
         hipLaunchKernelGGL((update_kernel<V>), dim3(B.upd_blocks), dim3(kT), 0, h->stream, B.x[xc], B.d[dp], B.r, B.q,
-                           B.pinv, h->g.N, B.S, h->partials, B.ctl);
+                           B.pinv, h->g.N, next_relay(c, M_UPD, true, B.upd_blocks));
         HIP_TRY(hipGetLastError());
       }
       if (h->timing) HIP_TRY(hipEventRecord(h->events[3 * j + 2], h->stream));
     }
-    RC_TRY(read_scalars(h, B.S, B.S_host));
+    RC_TRY(decide_and_read(h, c, B.S_host));
     const int real = B.S_host->iter;
     const int ran = std::max(0, std::min(real - done_iters, k));
     for (int j = 0; j < ran; ++j) {
@@ -320,18 +338,17 @@ double schedule_value(const fem_heat* h, int64_t m) {
 }
 
 // One theta-scheme step in FP64.  Leaves the new field in X[*xc].
-int step_fp64(fem_heat* h, RunState& st, double dt, double theta, double s_n, const Ctl& ctl, int* iters, int* xc_out) {
+int step_fp64(fem_heat* h, RunState& st, double dt, double theta, double s_n, int* iters, int* xc_out) {
   const double ckA = theta * dt, ckL = -(1.0 - theta) * dt;
-  RC_TRY(launch_gather<double>(h, h->rhoc64, h->k64, 1.0, ckL, ProPlain<double>{st.T1},
-                               EpiRhs<double>{h->b64, h->F64, h->pinv64, h->lift64, dt * s_n}, h->S_outer, FIN_RHS,
-                               ctl, 0));
-  RC_TRY(launch_gather<double>(
-      h, h->rhoc64, h->k64, 1.0, ckA,
+  RelayCtx& c = h->outer;
+  RC_TRY(gather_step<double>(h, c, M_RHS, h->rhoc64, h->k64, 1.0, ckL, ProPlain<double>{st.T1},
+                             EpiRhs<double>{h->b64, h->F64, h->pinv64, h->lift64, dt * s_n}));
+  RC_TRY(gather_step<double>(
+      h, c, M_INIT, h->rhoc64, h->k64, 1.0, ckA,
       ProGuess<double>{st.T1, st.T2, h->pinv64, st.X[0], h->opts.guess == FEM_GUESS_PREV ? 1 : 0, 0},
-      EpiResidual<double>{h->b64, h->pinv64, h->r64}, h->S_outer, FIN_INIT, ctl, 0));
-  PcgBufs<double> B{{st.X[0], st.X[1]}, 0,        h->r64,        h->q64,  {h->d64[0], h->d64[1]}, st.dp64,
-                    h->pinv64,          h->b64,   h->rhoc64,     h->k64,  h->S_outer,            h->S_host,
-                    ctl,                ckA,      h->upd_blocks64};
+      EpiResidual<double>{h->b64, h->pinv64, h->r64}));
+  PcgBufs<double> B{{st.X[0], st.X[1]}, 0,      h->r64,   h->q64, {h->d64[0], h->d64[1]}, st.dp64, h->pinv64,
+                    h->b64,             h->rhoc64, h->k64, &c,     h->S_host,              ckA,     h->upd_blocks64};
   RC_TRY(pcg_loop<double>(h, B, st.est, iters));
   st.dp64 = B.dp;
   *xc_out = B.xc;
@@ -341,40 +358,39 @@ int step_fp64(fem_heat* h, RunState& st, double dt, double theta, double s_n, co
 // One step of the mixed form: FP64 right-hand side, guess and residual; FP32
 // inner PCG on A e = r (FP64 dot products and scalars); FP64 correction
 // x += e and residual r = b - A x, repeated until the FP64 stop rule holds.
-int step_mixed(fem_heat* h, RunState& st, double dt, double theta, double s_n, const Ctl& ctl, const Ctl& ictl,
-               int* iters, int* sweeps, int* xc_out) {
+int step_mixed(fem_heat* h, RunState& st, double dt, double theta, double s_n, int* iters, int* sweeps,
+               int* xc_out) {
   const double ckA = theta * dt, ckL = -(1.0 - theta) * dt;
   const uint32_t N = h->g.N;
-  RC_TRY(launch_gather<double>(h, h->rhoc64, h->k64, 1.0, ckL, ProPlain<double>{st.T1},
-                               EpiRhs<double>{h->b64, h->F64, h->pinv64, h->lift64, dt * s_n}, h->S_outer, FIN_RHS,
-                               ctl, 0));
-  RC_TRY(launch_gather<double>(
-      h, h->rhoc64, h->k64, 1.0, ckA,
+  RelayCtx& c = h->outer;
+  RC_TRY(gather_step<double>(h, c, M_RHS, h->rhoc64, h->k64, 1.0, ckL, ProPlain<double>{st.T1},
+                             EpiRhs<double>{h->b64, h->F64, h->pinv64, h->lift64, dt * s_n}));
+  RC_TRY(gather_step<double>(
+      h, c, M_INIT, h->rhoc64, h->k64, 1.0, ckA,
       ProGuess<double>{st.T1, st.T2, h->pinv64, st.X[0], h->opts.guess == FEM_GUESS_PREV ? 1 : 0, 0},
-      EpiResidual<double>{h->b64, h->pinv64, h->r64}, h->S_outer, FIN_INIT, ctl, 0));
+      EpiResidual<double>{h->b64, h->pinv64, h->r64}));
   int xc = 0;
   Scalars* so = h->S_host;
-  RC_TRY(read_scalars(h, h->S_outer, so));
+  RC_TRY(decide_and_read(h, c, so));
   if (so->status != 0) return fail(h, FEM_EBREAKDOWN, "non-finite initial residual");
   int total = 0, nsw = 0;
-  const uint32_t sblocks = std::min<uint32_t>(nblk(N), 4096);
+  const uint32_t sblocks = std::min<uint32_t>(nblk(N), 1024);
   while (!so->done && nsw < h->opts.max_refine) {
     hipLaunchKernelGGL(inner_start_kernel, dim3(sblocks), dim3(kT), 0, h->stream, h->r64, h->rhs32, h->r32, h->e32[0],
-                       h->pinv32, N, h->S_inner, h->partials, ictl);
+                       h->pinv32, N, next_relay(h->inner, M_START, true, sblocks));
     HIP_TRY(hipGetLastError());
-    PcgBufs<float> B{{h->e32[0], h->e32[1]}, 0,        h->r32,       h->q32, {h->d32[0], h->d32[1]}, st.dp32,
-                     h->pinv32,              h->rhs32, h->rhoc32,    h->k32, h->S_inner,            h->S_host + 1,
-                     ictl,                   ckA,      h->upd_blocks32};
+    PcgBufs<float> B{{h->e32[0], h->e32[1]}, 0,         h->r32, h->q32,    {h->d32[0], h->d32[1]}, st.dp32, h->pinv32,
+                     h->rhs32,               h->rhoc32, h->k32, &h->inner, h->S_host + 1,          ckA,     h->upd_blocks32};
     int it = 0;
     RC_TRY(pcg_loop<float>(h, B, nsw == 0 ? st.est : std::max(1, st.est / 4), &it));
     st.dp32 = B.dp;
     total += it;
-    RC_TRY(launch_gather<double>(h, h->rhoc64, h->k64, 1.0, ckA,
-                                 ProAxpy<double, float>{st.X[xc], h->e32[B.xc], st.X[xc ^ 1], 1, 0.0},
-                                 EpiResidual<double>{h->b64, h->pinv64, h->r64}, h->S_outer, FIN_CHECK, ctl, 0));
+    RC_TRY(gather_step<double>(h, c, M_CORR, h->rhoc64, h->k64, 1.0, ckA,
+                               ProAxpy<double, float>{st.X[xc], h->e32[B.xc], st.X[xc ^ 1], 1, 0.0},
+                               EpiResidual<double>{h->b64, h->pinv64, h->r64}));
     xc ^= 1;
     ++nsw;
-    RC_TRY(read_scalars(h, h->S_outer, so));
+    RC_TRY(decide_and_read(h, c, so));
     if (so->status != 0) return fail(h, FEM_EBREAKDOWN, "non-finite residual in the refinement");
   }
   *iters = total;
@@ -412,8 +428,8 @@ int solver_init(fem_heat* h, const fem_grid* grid, const double* k_e, const doub
     h->sched.assign(bc->flux_schedule, bc->flux_schedule + bc->n_schedule);
   h->cubic = (g.hx == g.hy && g.hy == g.hz);
   h->shape = choose_shape(g, h->opts);
-  h->upd_blocks64 = std::max<uint32_t>(1, std::min<uint32_t>(nblk((g.N + 1) / 2), 4096));
-  h->upd_blocks32 = std::max<uint32_t>(1, std::min<uint32_t>(nblk((g.N + 3) / 4), 4096));
+  h->upd_blocks64 = std::max<uint32_t>(1, std::min<uint32_t>(nblk((g.N + 1) / 2), 512));
+  h->upd_blocks32 = std::max<uint32_t>(1, std::min<uint32_t>(nblk((g.N + 3) / 4), 512));
   h->stats.tile_x = h->shape.tx;
   h->stats.tile_y = h->shape.ty;
   h->stats.tile_z = h->shape.tz;
@@ -438,13 +454,15 @@ int solver_init(fem_heat* h, const fem_grid* grid, const double* k_e, const doub
   RC_TRY(dalloc(h, &h->d64[1], N));
   for (auto& p : h->pool) RC_TRY(dalloc(h, &p, N));
   if (h->nonzero_dirichlet) RC_TRY(dalloc(h, &h->lift64, N));
-  h->n_partials = std::max({h->shape.nblocks, h->upd_blocks64, h->upd_blocks32, 4096u});
-  RC_TRY(dalloc(h, &h->partials, h->n_partials));
-  RC_TRY(dalloc(h, &h->S_outer, 1));
-  RC_TRY(dalloc(h, &h->S_inner, 1));
+  h->n_partials = std::max({h->shape.nblocks, h->upd_blocks64, h->upd_blocks32, 1024u});
+  for (RelayCtx* c : {&h->outer, &h->inner})
+    for (int k = 0; k < 2; ++k) {
+      RC_TRY(dalloc(h, &c->S[k], 1));
+      RC_TRY(dalloc(h, &c->P[k], h->n_partials));
+      HIP_TRY(hipMemsetAsync(c->S[k], 0, sizeof(Scalars), h->stream));
+      HIP_TRY(hipMemsetAsync(c->P[k], 0, h->n_partials * sizeof(double), h->stream));
+    }
   HIP_TRY(hipHostMalloc(reinterpret_cast<void**>(&h->S_host), 2 * sizeof(Scalars), hipHostMallocDefault));
-  HIP_TRY(hipMemsetAsync(h->S_outer, 0, sizeof(Scalars), h->stream));
-  HIP_TRY(hipMemsetAsync(h->S_inner, 0, sizeof(Scalars), h->stream));
   RC_TRY(copy_in(h, h->rhoc64, rhoc_e, E));
   RC_TRY(copy_in(h, h->k64, k_e, E));
   hipLaunchKernelGGL(load_vector_kernel, dim3(nblk(N)), dim3(kT), 0, h->stream, g, h->F64);
@@ -498,8 +516,8 @@ int solver_run(fem_heat* h, const double* T0, const double* T_prev, double dt, d
   h->stats.gather_launches = h->stats.update_launches = h->stats.replace_launches = 0;
   h->stats.gather_ms = h->stats.update_ms = h->stats.replace_ms = 0.0;
 
-  const Ctl ctl{rtol * rtol, h->opts.max_iter, h->opts.stop_rule};
-  const Ctl ictl{h->opts.inner_rtol * h->opts.inner_rtol, h->opts.max_iter, 1};
+  h->outer.ctl = Ctl{rtol * rtol, h->opts.max_iter, h->opts.stop_rule};
+  h->inner.ctl = Ctl{h->opts.inner_rtol * h->opts.inner_rtol, h->opts.max_iter, 1};
   const int first = o ? o->first_step : 0;
   int status = FEM_OK;
   int64_t total = 0;
@@ -507,8 +525,7 @@ int solver_run(fem_heat* h, const double* T0, const double* T_prev, double dt, d
   for (int32_t n = 1; n <= nsteps; ++n) {
     const double s_n = schedule_value(h, (int64_t)first + n);
     int it = 0, nsw = 0, xc = 0;
-    int rc = mixed ? step_mixed(h, st, dt, theta, s_n, ctl, ictl, &it, &nsw, &xc)
-                   : step_fp64(h, st, dt, theta, s_n, ctl, &it, &xc);
+    int rc = mixed ? step_mixed(h, st, dt, theta, s_n, &it, &nsw, &xc) : step_fp64(h, st, dt, theta, s_n, &it, &xc);
     if (rc == FEM_EBREAKDOWN) {
       status = rc;
       break;
@@ -579,18 +596,17 @@ int solver_apply(fem_heat* h, int32_t which, double dt, double theta, const doub
   double* xd = h->pool[0];
   double* yd = h->pool[1];
   if (op != FEM_OP_LOAD) RC_TRY(copy_in(h, xd, x, N));
-  const Ctl none{0.0, 0, 0};
   if (op == FEM_OP_A || op == FEM_OP_L) {
     const double ck = op == FEM_OP_A ? theta * dt : -(1.0 - theta) * dt;
     if (fp32) {
       RC_TRY(ensure_fp32(h));
       hipLaunchKernelGGL((cast_kernel<double, float>), dim3(nblk(N)), dim3(kT), 0, h->stream, xd, h->e32[0], N);
       RC_TRY(launch_gather<float>(h, h->rhoc32, h->k32, 1.0, ck, ProPlain<float>{h->e32[0]}, EpiStore<float>{h->q32},
-                                  h->S_inner, FIN_NONE, none, 0));
+                                  no_relay()));
       hipLaunchKernelGGL((cast_kernel<float, double>), dim3(nblk(N)), dim3(kT), 0, h->stream, h->q32, yd, N);
     } else {
       RC_TRY(launch_gather<double>(h, h->rhoc64, h->k64, 1.0, ck, ProPlain<double>{xd}, EpiStore<double>{yd},
-                                   h->S_outer, FIN_NONE, none, 0));
+                                   no_relay()));
     }
   } else if (op == FEM_OP_JACOBI) {
     RC_TRY(prepare_operator(h, theta * dt, fp32));
@@ -631,9 +647,11 @@ void solver_free(fem_heat* h) {
   dfree(h->q32);
   for (auto& p : h->d32) dfree(p);
   dfree(h->rhs32);
-  dfree(h->partials);
-  dfree(h->S_outer);
-  dfree(h->S_inner);
+  for (RelayCtx* c : {&h->outer, &h->inner})
+    for (int k = 0; k < 2; ++k) {
+      dfree(c->S[k]);
+      dfree(c->P[k]);
+    }
   dfree(h->xyz_dev);
   dfree(h->traces_dev);
   if (h->S_host) (void)hipHostFree(h->S_host);

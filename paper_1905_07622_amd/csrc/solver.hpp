@@ -9,6 +9,18 @@
 #include "../../include/fem_heat.h"
 #include "common.hpp"
 
+namespace femheat {
+// Host view of one relayed solve: the ping-pong state blocks and partial
+// buffers, which one the next kernel reads, and how many partials it holds.
+struct RelayCtx {
+  Scalars* S[2] = {nullptr, nullptr};
+  double* P[2] = {nullptr, nullptr};
+  int cur = 0;
+  uint32_t npin = 0;
+  Ctl ctl{};
+};
+}  // namespace femheat
+
 struct fem_heat {
   int device = 0;
   hipStream_t stream = nullptr;
@@ -47,11 +59,9 @@ struct fem_heat {
   float* d32[2] = {nullptr, nullptr};
   float* rhs32 = nullptr;
 
-  // reduction partials and device scalars
-  double* partials = nullptr;
+  // relayed solve state: outer (FP64) and inner (FP32) solves
+  femheat::RelayCtx outer, inner;
   uint32_t n_partials = 0;
-  femheat::Scalars* S_outer = nullptr;
-  femheat::Scalars* S_inner = nullptr;
   femheat::Scalars* S_host = nullptr;  // pinned, 2 entries
 
   // per-run buffers

@@ -36,12 +36,12 @@ __device__ inline void upd1(V& x, V d, V& r, V q, V p, V alpha, double& acc) {
 template <typename V>
 __global__ void __launch_bounds__(256) update_kernel(V* __restrict__ x, const V* __restrict__ d,
                                                       V* __restrict__ r, const V* __restrict__ q,
-                                                      const V* __restrict__ pinv, uint32_t N, Scalars* S,
-                                                      double* partials, Ctl ctl) {
-  if (S->done) return;
+                                                      const V* __restrict__ pinv, uint32_t N, Relay R) {
+  Scalars st;
+  if (!stage_entry(R, st)) return;  // settles alpha = delta / d^T q; no-op once done
   using VT = typename Vec<V>::T;
   constexpr int W = Vec<V>::W;
-  const V alpha = (V)S->alpha;
+  const V alpha = (V)st.alpha;
   double acc = 0.0;
   const uint32_t nvec = N / W;
   const uint32_t stride = gridDim.x * blockDim.x;
@@ -71,15 +71,16 @@ __global__ void __launch_bounds__(256) update_kernel(V* __restrict__ x, const V*
     x[i] = xx;
     r[i] = rr;
   }
-  reduce_and_finalize(acc, partials, S, gridDim.x, blockIdx.x, FIN_DELTA, ctl);
+  publish_partial(R, acc);
 }
 
 // Start of an inner (FP32) solve of A e = r64: rhs = r = (float) r64, e = 0,
 // delta0 = r^T P^-1 r accumulated in FP64.
 __global__ void __launch_bounds__(256) inner_start_kernel(const double* __restrict__ r64, float* __restrict__ rhs,
                                                           float* __restrict__ r, float* __restrict__ e,
-                                                          const float* __restrict__ pinv, uint32_t N,
-                                                          Scalars* S, double* partials, Ctl ctl) {
+                                                          const float* __restrict__ pinv, uint32_t N, Relay R) {
+  Scalars st;
+  (void)stage_entry(R, st);  // a fresh solve: the next kernel settles r0^T P^-1 r0
   double acc = 0.0;
   const uint32_t stride = gridDim.x * blockDim.x;
   for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < N; i += stride) {
@@ -89,7 +90,7 @@ __global__ void __launch_bounds__(256) inner_start_kernel(const double* __restri
     e[i] = 0.0f;
     acc += (double)v * (double)(pinv[i] * v);
   }
-  reduce_and_finalize(acc, partials, S, gridDim.x, blockIdx.x, FIN_INIT, ctl);
+  publish_partial(R, acc);
 }
 
 // ---------------------------------------------------------------------------
