@@ -59,6 +59,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-timing", action="store_true", help="time without per-kernel HIP events")
     ap.add_argument("--tile", type=int, nargs=3, default=(0, 0, 0))
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain 256 MiB device copy 3 times (scale for rocprof FETCH/WRITE_SIZE)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}): the solver has no multi-GPU path; "
@@ -67,6 +69,16 @@ def main():
 
     import numpy as np
     import torch
+
+    if args.copy_calibration:
+        n = 32 * 1024 * 1024  # 32 Mi doubles = 256 MiB per tensor
+        src = torch.ones(n, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calibration_bytes": n * 8, "launches": 3}))
+        return
 
     from paper_1905_07622_amd import femheat as fh
     from paper_1905_07622_amd import workloads as wl

@@ -74,10 +74,11 @@ struct GatherShape {
   int32_t tx, ty, tz;
   int32_t ntx, nty, ntz;
   int32_t nthreads;   // TX*TY rounded up to a multiple of 64
+  int32_t pw, cw;     // LDS row pitches of the plane tile (>= TX+2) and coefficient tile (>= TX+1)
   uint32_t ntiles;    // ntx*nty*ntz
   uint32_t nblocks;   // ntiles rounded up to a multiple of 8 (one share per XCD)
   size_t smem_bytes(size_t vbytes) const {
-    return vbytes * (2 * (size_t)(tx + 2) * (ty + 2) + 4 * (size_t)(tx + 1) * (ty + 1));
+    return vbytes * (2 * (size_t)pw * (ty + 2) + 4 * (size_t)cw * (ty + 1));
   }
 };
 

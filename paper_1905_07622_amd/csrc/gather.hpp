@@ -33,6 +33,8 @@
 // the device.
 #pragma once
 
+#include <type_traits>
+
 #include "common.hpp"
 #include "reduce.hpp"
 
@@ -46,6 +48,7 @@ struct GatherArgs {
   const V* kc;     // per-element k
   V sa, sb;        // cubic: cm*h^3/216, ck*h/12 ; general: cm, ck
   V Mc[8], Kc[8];  // general elements: class entries M[c], K[c]
+  V* sink;         // >= 256 scratch values: stores of lanes without a node land here
 };
 
 // 3x3 neighbourhood of one plane around a column: centre, x-/x+, y-/y+, and
@@ -69,6 +72,10 @@ __device__ inline void read_plane(const V* P, int pw, int lx, int ly, PlaneQ<V>&
   q.b[3] = row0[2 * pw + 2];
 }
 
+// Staging slots: thread t stages LDS entries t and t + nthreads of a plane
+// tile (and of a coefficient tile); the launch guarantees both tiles fit.
+constexpr int kSlots = 2;
+
 template <typename V, bool CUBIC, class Pro, class Epi>
 __global__ void __launch_bounds__(256) gather_kernel(GatherArgs<V> ga, Pro pro, Epi epi, Relay R) {
   Scalars st;
@@ -78,13 +85,15 @@ __global__ void __launch_bounds__(256) gather_kernel(GatherArgs<V> ga, Pro pro, 
 
   extern __shared__ unsigned char smem_raw[];
   const int TX = ga.s.tx, TY = ga.s.ty, TZ = ga.s.tz;
-  const int PW = TX + 2, PH = TY + 2, CW = TX + 1, CH = TY + 1;
+  const int NW = TX + 2, PH = TY + 2, NC = TX + 1, CH = TY + 1;  // tile widths (nodes, elements)
+  const int PW = ga.s.pw, CW = ga.s.cw;                          // LDS row pitches (bank-conflict padding)
   V* plane = reinterpret_cast<V*>(smem_raw);  // [2][PH*PW]
   V* ca = plane + 2 * PW * PH;               // [2][CH*CW]
   V* cb = ca + 2 * CW * CH;                  // [2][CH*CW]
 
   const int px = ga.g.px, py = ga.g.py, pz = ga.g.pz;
   const int nx = ga.g.nx, ny = ga.g.ny, nz = ga.g.nz;
+  const uint32_t pstride = (uint32_t)px * (uint32_t)py, lstride = (uint32_t)nx * (uint32_t)ny;
 
   // XCD-aware tile order: blocks are dispatched round-robin over the 8 XCDs,
   // so block b runs on XCD b%8.  Logical tile = (b%8)*share + b/8 gives every
@@ -111,54 +120,80 @@ __global__ void __launch_bounds__(256) gather_kernel(GatherArgs<V> ga, Pro pro, 
     const int gx = x0 + ltx, gy = y0 + lty;
     const bool col_ok = has_col && gx < px && gy < py;
 
-    auto stage_plane = [&](int z, int buf) {
-      V* P = plane + buf * PW * PH;
-      const bool zin = z >= 0 && z < pz;
-      const bool zown = z >= z0 && z < z1;
-      for (int s = t; s < PW * PH; s += nthr) {
-        const int ly = s / PW, lx = s - ly * PW;
-        const int x = x0 - 1 + lx, y = y0 - 1 + ly;
-        V v = V(0);
-        if (zin && x >= 0 && x < px && y >= 0 && y < py) {
-          const uint32_t i = (uint32_t)x + (uint32_t)px * ((uint32_t)y + (uint32_t)py * (uint32_t)z);
-          const bool owned = zown && lx >= 1 && lx <= TX && ly >= 1 && ly <= TY;
-          v = pro.load(i, owned);
-        }
-        P[s] = v;
+    // Per-slot staging coordinates, fixed for the whole z march.  Node
+    // addresses are clamped into the grid: a value staged outside the grid
+    // only ever meets elements outside the grid, whose coefficients are 0, so
+    // any finite value is exact there.  Element coefficients outside the grid
+    // are stored as 0 explicitly.  Unused slots load a valid dummy address.
+    // Every global load and store of the z march is unconditional, so the
+    // compiler can count outstanding memory operations exactly and the loads
+    // issued two layers ahead stay in flight while the current layer computes.
+    int pl[kSlots], cl[kSlots];
+    uint32_t pxy[kSlots], cxy[kSlots];
+    bool cin[kSlots];
+#pragma unroll
+    for (int k = 0; k < kSlots; ++k) {
+      const int idx = t + k * nthr;
+      const int ly = idx / NW, lx = idx - ly * NW;
+      const bool pv = idx < NW * PH;
+      pl[k] = pv ? ly * PW + lx : -1;
+      const int x = x0 - 1 + lx, y = y0 - 1 + ly;
+      pxy[k] = pv ? (uint32_t)min(max(x, 0), px - 1) + (uint32_t)px * (uint32_t)min(max(y, 0), py - 1) : 0u;
+      const int ey_ = idx / NC, ex_ = idx - ey_ * NC;
+      const bool cv = idx < NC * CH;
+      cl[k] = cv ? ey_ * CW + ex_ : -1;
+      const int ex = x0 - 1 + ex_, ey = y0 - 1 + ey_;
+      cin[k] = cv && ex >= 0 && ex < nx && ey >= 0 && ey < ny;
+      cxy[k] = cv ? (uint32_t)min(max(ex, 0), nx - 1) + (uint32_t)nx * (uint32_t)min(max(ey, 0), ny - 1) : 0u;
+    }
+    const uint32_t col_xy = col_ok ? (uint32_t)gx + (uint32_t)px * (uint32_t)gy : 0u;
+
+    // Two register sets hold the planes l+1 and l+2 (and coefficient layers
+    // l and l+1) while layer l computes.
+    struct Stage {
+      typename Pro::Raw p[kSlots];
+      V a[kSlots], b[kSlots];
+    };
+    auto fetch = [&](Stage& S, int z, int l) {  // plane z, coefficient layer l (both clamped)
+      const uint32_t zo = pstride * (uint32_t)min(max(z, 0), pz - 1);
+      const uint32_t lo_ = lstride * (uint32_t)min(max(l, 0), nz - 1);
+#pragma unroll
+      for (int k = 0; k < kSlots; ++k) {
+        S.p[k] = pro.fetch(pxy[k] + zo);
+        S.a[k] = ga.rhoc[cxy[k] + lo_];
+        S.b[k] = ga.kc[cxy[k] + lo_];
       }
     };
-    auto stage_coef = [&](int l, int buf) {
+    auto store = [&](const Stage& S, int l, int buf) {  // LDS only
+      V* P = plane + buf * PW * PH;
       V* A = ca + buf * CW * CH;
       V* B = cb + buf * CW * CH;
       const bool lin = l >= 0 && l < nz;
-      for (int s = t; s < CW * CH; s += nthr) {
-        const int ly = s / CW, lx = s - ly * CW;
-        const int ex = x0 - 1 + lx, ey = y0 - 1 + ly;
-        V a = V(0), bb = V(0);
-        if (lin && ex >= 0 && ex < nx && ey >= 0 && ey < ny) {
-          const uint32_t e = (uint32_t)ex + (uint32_t)nx * ((uint32_t)ey + (uint32_t)ny * (uint32_t)l);
-          a = ga.sa * ga.rhoc[e];
-          bb = ga.sb * ga.kc[e];
+#pragma unroll
+      for (int k = 0; k < kSlots; ++k) {
+        if (pl[k] >= 0) P[pl[k]] = pro.finish(S.p[k]);
+        if (cl[k] >= 0) {
+          const bool ok = lin && cin[k];
+          A[cl[k]] = ok ? ga.sa * S.a[k] : V(0);
+          B[cl[k]] = ok ? ga.sb * S.b[k] : V(0);
         }
-        A[s] = a;
-        B[s] = bb;
       }
     };
 
     PlaneQ<V> lo, hi;
-    stage_plane(z0 - 1, 0);
-    __syncthreads();
-    read_plane(plane, PW, ltx, lty, lo);
-    V acc_lo = V(0);
-    int buf = 1;
-    for (int l = z0 - 1; l < z1; ++l) {
-      stage_plane(l + 1, buf);
-      stage_coef(l, buf);
+    V acc_lo = V(0), acc_hi = V(0);
+    // One layer l (elements between planes l and l+1): completes node l of
+    // this column (lower layer accumulated in acc_lo) and starts node l+1.
+    // Loads for plane l+3 / layer l+2 are issued here (clamped to the chunk:
+    // past its end they re-read the last plane, an L2 hit).
+    auto layer = [&](int l, int buf, Stage& S, auto emit) {
+      store(S, l, buf);
       __syncthreads();
+      fetch(S, min(l + 3, z1), min(l + 2, z1 - 1));
       read_plane(plane + buf * PW * PH, PW, ltx, lty, hi);
       const V* A = ca + buf * CW * CH;
       const V* B = cb + buf * CW * CH;
-      V acc_hi = V(0);
+      acc_hi = V(0);
 #pragma unroll
       for (int sy = 0; sy < 2; ++sy) {
 #pragma unroll
@@ -167,29 +202,60 @@ __global__ void __launch_bounds__(256) gather_kernel(GatherArgs<V> ga, Pro pro, 
           const V a = A[ci], bk = B[ci];
           const V xl = sx ? lo.xp : lo.xm, yl = sy ? lo.yp : lo.ym, bl = lo.b[sy * 2 + sx];
           const V xh = sx ? hi.xp : hi.xm, yh = sy ? hi.yp : hi.ym, bh = hi.b[sy * 2 + sx];
+          // Explicit fused multiply-adds in a fixed order (the library is built
+          // without automatic contraction): every copy of this code rounds
+          // identically, so results do not depend on the tiling.
           if (CUBIC) {
             // classes by popcount: c0 = 8a+4b, c1 = 4a, c2 = 2a-b, c3 = a-b
-            const V c0 = V(8) * a + V(4) * bk, c1 = V(4) * a, c2 = V(2) * a - bk, c3 = a - bk;
+            const V c0 = fma(V(8), a, V(4) * bk), c1 = V(4) * a, c2 = fma(V(2), a, -bk), c3 = a - bk;
             const V al = xl + yl, ah = xh + yh;
-            acc_lo += c0 * lo.c + c1 * (al + hi.c) + c2 * (bl + ah) + c3 * bh;
-            acc_hi += c0 * hi.c + c1 * (ah + lo.c) + c2 * (bh + al) + c3 * bl;
+            acc_lo = fma(c0, lo.c, acc_lo);
+            acc_lo = fma(c1, al + hi.c, acc_lo);
+            acc_lo = fma(c2, bl + ah, acc_lo);
+            acc_lo = fma(c3, bh, acc_lo);
+            acc_hi = fma(c0, hi.c, acc_hi);
+            acc_hi = fma(c1, ah + lo.c, acc_hi);
+            acc_hi = fma(c2, bh + al, acc_hi);
+            acc_hi = fma(c3, bl, acc_hi);
           } else {
             V k[8];
 #pragma unroll
-            for (int c = 0; c < 8; ++c) k[c] = a * ga.Mc[c] + bk * ga.Kc[c];
-            acc_lo += k[0] * lo.c + k[1] * xl + k[2] * yl + k[3] * bl + k[4] * hi.c + k[5] * xh + k[6] * yh + k[7] * bh;
-            acc_hi += k[0] * hi.c + k[1] * xh + k[2] * yh + k[3] * bh + k[4] * lo.c + k[5] * xl + k[6] * yl + k[7] * bl;
+            for (int c = 0; c < 8; ++c) k[c] = fma(a, ga.Mc[c], bk * ga.Kc[c]);
+            const V vl[8] = {lo.c, xl, yl, bl, hi.c, xh, yh, bh};
+            const V vh[8] = {hi.c, xh, yh, bh, lo.c, xl, yl, bl};
+#pragma unroll
+            for (int c = 0; c < 8; ++c) {
+              acc_lo = fma(k[c], vl[c], acc_lo);
+              acc_hi = fma(k[c], vh[c], acc_hi);
+            }
           }
         }
       }
-      if (l >= z0 && col_ok) {
-        const uint32_t i = (uint32_t)gx + (uint32_t)px * ((uint32_t)gy + (uint32_t)py * (uint32_t)l);
-        dot += epi.store(i, acc_lo, lo.c);
+      if (decltype(emit)::value) {  // node l is owned by this block
+        const uint32_t i = col_xy + pstride * (uint32_t)l;
+        pro.write(i, lo.c, col_ok, ga.sink);
+        dot += epi.store(i, acc_lo, lo.c, col_ok, ga.sink);
       }
       acc_lo = acc_hi;
       lo = hi;
-      buf ^= 1;
+    };
+
+    Stage SA, SB;
+    fetch(SA, z0 - 1, z0 - 1);
+    store(SA, -1, 0);  // plane z0-1 into buffer 0 (its coefficient slots are rewritten before use)
+    fetch(SA, z0, z0 - 1);
+    fetch(SB, min(z0 + 1, z1), z0);
+    __syncthreads();
+    read_plane(plane, PW, ltx, lty, lo);
+    using no = std::integral_constant<bool, false>;
+    using yes = std::integral_constant<bool, true>;
+    layer(z0 - 1, 1, SA, no{});  // node z0-1 belongs to the chunk below
+    int l = z0;
+    for (; l + 1 < z1; l += 2) {  // two register sets alternate: indices stay compile-time
+      layer(l, 0, SB, yes{});
+      layer(l + 1, 1, SA, yes{});
     }
+    if (l < z1) layer(l, 0, SB, yes{});
   }
   if (R.pout) publish_partial(R, dot);
 }
@@ -198,11 +264,21 @@ __global__ void __launch_bounds__(256) gather_kernel(GatherArgs<V> ga, Pro pro, 
 // prologues: value of the gathered vector at node i (and write-back when owned)
 // ---------------------------------------------------------------------------
 
+// A prologue has fetch(i) -> Raw (the global loads of one node, issued two
+// layers early), finish(raw) -> value (pure arithmetic, also for halo nodes)
+// and write(i, v, live, sink): the write-back of the value at an owned node
+// (lanes without a node store to the sink instead of branching).
+
 template <typename V>
 struct ProPlain {  // v = src
   const V* src;
+  struct Raw {
+    V a;
+  };
   __device__ void init(const Scalars&) {}
-  __device__ V load(uint32_t i, bool) const { return src[i]; }
+  __device__ Raw fetch(uint32_t i) const { return Raw{src[i]}; }
+  __device__ V finish(const Raw& w) const { return w.a; }
+  __device__ void write(uint32_t, V, bool, V*) const {}
 };
 
 template <typename V>
@@ -212,12 +288,13 @@ struct ProDirection {  // d_new = P^-1 r + beta d_old   (Algorithm 1: s <- P^-1 
   const V* dold;
   V* dnew;
   V beta;
+  struct Raw {
+    V r, p, d;
+  };
   __device__ void init(const Scalars& S) { beta = (V)S.beta; }
-  __device__ V load(uint32_t i, bool owned) const {
-    const V v = pinv[i] * r[i] + beta * dold[i];
-    if (owned) dnew[i] = v;
-    return v;
-  }
+  __device__ Raw fetch(uint32_t i) const { return Raw{r[i], pinv[i], dold[i]}; }
+  __device__ V finish(const Raw& w) const { return fma(beta, w.d, w.p * w.r); }
+  __device__ void write(uint32_t i, V v, bool live, V* sink) const { *(live ? dnew + i : sink + threadIdx.x) = v; }
 };
 
 template <typename V, typename W>
@@ -227,12 +304,14 @@ struct ProAxpy {  // x_new = x + alpha d  (alpha from the solve's scalars, or 1 
   V* xnew;
   int32_t unit_alpha;
   V alpha;
+  struct Raw {
+    V x;
+    W d;
+  };
   __device__ void init(const Scalars& S) { alpha = unit_alpha ? V(1) : (V)S.alpha; }
-  __device__ V load(uint32_t i, bool owned) const {
-    const V v = x[i] + alpha * (V)d[i];
-    if (owned) xnew[i] = v;
-    return v;
-  }
+  __device__ Raw fetch(uint32_t i) const { return Raw{x[i], d[i]}; }
+  __device__ V finish(const Raw& w) const { return fma(alpha, (V)w.d, w.x); }
+  __device__ void write(uint32_t i, V v, bool live, V* sink) const { *(live ? xnew + i : sink + threadIdx.x) = v; }
 };
 
 template <typename V>
@@ -243,25 +322,32 @@ struct ProGuess {  // x0 = 2 T1 - T2 (u0_update, App. A.2) or T1; 0 on free node
   V* x;
   int32_t prev;
   int32_t zero;
+  struct Raw {
+    V a, b, p;
+  };
   __device__ void init(const Scalars& S) { zero = S.zero_rhs; }
-  __device__ V load(uint32_t i, bool owned) const {
-    V v = prev ? t1[i] : V(2) * t1[i] - t2[i];
-    if (zero) v = (pinv[i] == V(0)) ? t1[i] : V(0);
-    if (owned) x[i] = v;
+  __device__ Raw fetch(uint32_t i) const { return Raw{t1[i], t2[i], pinv[i]}; }
+  __device__ V finish(const Raw& w) const {
+    V v = prev ? w.a : fma(V(2), w.a, -w.b);
+    if (zero) v = (w.p == V(0)) ? w.a : V(0);
     return v;
   }
+  __device__ void write(uint32_t i, V v, bool live, V* sink) const { *(live ? x + i : sink + threadIdx.x) = v; }
 };
 
 // ---------------------------------------------------------------------------
 // epilogues: consume y_i at an owned node, return the dot-product contribution
 // ---------------------------------------------------------------------------
 
+// An epilogue consumes y_i at an owned node and returns the node's dot
+// contribution; lanes without a node (live = false) store to the sink.
+
 template <typename V>
 struct EpiStore {  // y = A v
   V* y;
   __device__ void init(const Scalars&) {}
-  __device__ double store(uint32_t i, V acc, V) const {
-    y[i] = acc;
+  __device__ double store(uint32_t i, V acc, V, bool live, V* sink) const {
+    *(live ? y + i : sink + threadIdx.x) = acc;
     return 0.0;
   }
 };
@@ -270,9 +356,9 @@ template <typename V>
 struct EpiQDot {  // q = A d ; contribution d_i q_i to d^T q
   V* q;
   __device__ void init(const Scalars&) {}
-  __device__ double store(uint32_t i, V acc, V v) const {
-    q[i] = acc;
-    return (double)v * (double)acc;
+  __device__ double store(uint32_t i, V acc, V v, bool live, V* sink) const {
+    *(live ? q + i : sink + threadIdx.x) = acc;
+    return live ? (double)v * (double)acc : 0.0;
   }
 };
 
@@ -282,11 +368,11 @@ struct EpiResidual {  // r = b - A x (0 on Dirichlet rows); contribution r_i P^-
   const V* pinv;
   V* r;
   __device__ void init(const Scalars&) {}
-  __device__ double store(uint32_t i, V acc, V) const {
+  __device__ double store(uint32_t i, V acc, V, bool live, V* sink) const {
     const V p = pinv[i];
     const V rr = (p == V(0)) ? V(0) : b[i] - acc;
-    r[i] = rr;
-    return (double)rr * (double)(p * rr);
+    *(live ? r + i : sink + threadIdx.x) = rr;
+    return live ? (double)rr * (double)(p * rr) : 0.0;
   }
 };
 
@@ -298,11 +384,11 @@ struct EpiRhs {  // b = L T + dt*s*F ; contribution (b - lift)_i P^-1_i (b - lif
   const V* lift;  // A_fD g for non-zero Dirichlet values, or nullptr
   V fs;           // dt * s_n
   __device__ void init(const Scalars&) {}
-  __device__ double store(uint32_t i, V acc, V) const {
-    const V bb = acc + fs * F[i];
-    b[i] = bb;
+  __device__ double store(uint32_t i, V acc, V, bool live, V* sink) const {
+    const V bb = fma(fs, F[i], acc);
+    *(live ? b + i : sink + threadIdx.x) = bb;
     const V bh = lift ? bb - lift[i] : bb;
-    return (double)bh * (double)(pinv[i] * bh);
+    return live ? (double)bh * (double)(pinv[i] * bh) : 0.0;
   }
 };
 

@@ -30,16 +30,31 @@ struct Relay {
   Ctl ctl;
 };
 
-// Sum of n partials, evaluated by the 64 lanes of wave 0 in a fixed order
-// (lane-strided sequential sums, then an xor-shuffle tree); every lane gets the
-// same value, independently of the block size of the calling kernel.
-__device__ inline double wave_sum_partials(const double* p, uint32_t n) {
-  const uint32_t lane = threadIdx.x & 63u;
-  double s = 0.0;
-  for (uint32_t k = lane; k < n; k += 64) s += p[k];
+// Sum of n partials in one canonical order that does not depend on the block
+// size: 256 slots (slot j adds partials j, j+256, j+512, ... in sequence),
+// grouped in 4 virtual waves of 64 reduced by an xor-shuffle tree, then the 4
+// wave sums added in order.  Real wave w handles virtual waves w, w+nw, ...
+// All threads of the block must call it; every thread gets the same value.
+__device__ inline double canonical_sum(const double* p, uint32_t n, double* red4) {
+  const uint32_t lane = threadIdx.x & 63u, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  for (uint32_t vw = wid; vw < 4; vw += nw) {
+    const uint32_t slot = vw * 64 + lane;
+    double v[8];
 #pragma unroll
-  for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
-  return s;
+    for (int u = 0; u < 8; ++u) {
+      const uint32_t k = slot + 256u * u;
+      v[u] = k < n ? p[k] : 0.0;
+    }
+    double s = v[0];
+#pragma unroll
+    for (int u = 1; u < 8; ++u) s += v[u];
+    for (uint32_t k = slot + 2048u; k < n; k += 256u) s += p[k];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+    if (lane == 0) red4[vw] = s;
+  }
+  __syncthreads();
+  return ((red4[0] + red4[1]) + red4[2]) + red4[3];
 }
 
 // Sum over the block (blockDim.x a multiple of 64, at most 1024); valid in thread 0.
@@ -104,12 +119,18 @@ __device__ inline void evaluate_pending(Scalars& s, double x, const Ctl& c) {
 
 // Entry of every relayed kernel: evaluates the state this kernel works with,
 // has block 0 publish it to Sout, and returns whether the kernel has work.
+// Called by all threads of the block.
 __device__ inline bool stage_entry(const Relay& R, Scalars& out) {
   __shared__ Scalars sh;
   __shared__ int go;
-  if (threadIdx.x < 64) {
-    Scalars t{};
-    if (R.sin) t = *R.sin;
+  __shared__ double red4[4];
+  Scalars t{};
+  if (R.sin) t = *R.sin;
+  const bool pending = !t.done && t.phase != PH_DECIDED && t.phase != PH_NONE;
+  const bool need = R.mode == M_INIT || (R.mode == M_UPD && !t.done) ||
+                    ((R.mode == M_DIR || R.mode == M_DECIDE) && pending);
+  const double x = need ? canonical_sum(R.pin, R.npin, red4) : 0.0;
+  if (threadIdx.x == 0) {
     int g = 1;
     switch (R.mode) {
       case M_RHS:  // a new step: b and b^T P^-1 b
@@ -117,14 +138,13 @@ __device__ inline bool stage_entry(const Relay& R, Scalars& out) {
         t.status = 0;
         t.phase = PH_NONE;
         break;
-      case M_INIT: {  // b^T P^-1 b known: the guess prologue needs the zero-RHS flag
-        const double x = wave_sum_partials(R.pin, R.npin);
+      case M_INIT:  // b^T P^-1 b known: the guess prologue needs the zero-RHS flag
         t.delta_b = x;
         t.zero_rhs = (R.ctl.stop_rule == 0 && x == 0.0) ? 1 : 0;
         t.done = 0;
         t.status = 0;
         t.phase = PH_AFTER_INIT;
-      } break;
+        break;
       case M_START:  // a solve whose initial residual this kernel produces
         t.done = 0;
         t.status = 0;
@@ -134,18 +154,16 @@ __device__ inline bool stage_entry(const Relay& R, Scalars& out) {
         break;
       case M_DIR:
       case M_DECIDE:
-        if (!t.done && t.phase != PH_DECIDED && t.phase != PH_NONE)
-          evaluate_pending(t, wave_sum_partials(R.pin, R.npin), R.ctl);
+        if (pending) evaluate_pending(t, x, R.ctl);
         g = (R.mode == M_DIR && !t.done) ? 1 : 0;
         break;
       case M_UPD:
         if (t.done) {
           g = 0;
         } else {
-          const double dq = wave_sum_partials(R.pin, R.npin);
-          const double a = t.delta / dq;
-          t.dq = dq;
-          if (!(dq > 0.0) || !isfinite(dq) || !isfinite(a)) {
+          const double a = t.delta / x;
+          t.dq = x;
+          if (!(x > 0.0) || !isfinite(x) || !isfinite(a)) {
             t.status = kStatusBreakdown;
             t.done = 1;
             g = 0;
@@ -163,11 +181,9 @@ __device__ inline bool stage_entry(const Relay& R, Scalars& out) {
       default:  // M_NONE
         break;
     }
-    if (threadIdx.x == 0) {
-      sh = t;
-      go = g;
-      if (blockIdx.x == 0 && R.sout) *R.sout = t;
-    }
+    sh = t;
+    go = g;
+    if (blockIdx.x == 0 && R.sout) *R.sout = t;
   }
   __syncthreads();
   out = sh;

@@ -81,9 +81,40 @@ int copy_out(fem_heat* h, void* dst, const void* src, size_t bytes) {
   return FEM_OK;
 }
 
+// LDS row pitch (in values) of a tile of width `width`: the smallest pitch
+// for which the 64 lanes of every wave, split into half-waves of 32 lanes,
+// read 8-byte words in distinct banks (64 banks of 4 bytes) for each of the
+// neighbourhood offsets the gather uses (3x3 for the plane, 2x2 for the
+// coefficients).  Falls back to the width when no pitch within 64 is free.
+int lds_pitch(int tx, int ty, int nthreads, int width, bool plane) {
+  const int span = plane ? 3 : 2;
+  for (int p = width; p < width + 64; ++p) {
+    bool ok = true;
+    for (int w = 0; w < nthreads / 64 && ok; ++w)
+      for (int half = 0; half < 2 && ok; ++half)
+        for (int dy = 0; dy < span && ok; ++dy)
+          for (int dx = 0; dx < span && ok; ++dx) {
+            bool used[32] = {false};
+            for (int l = 0; l < 32; ++l) {
+              const int t = w * 64 + half * 32 + l;
+              const int lx = t < tx * ty ? t % tx : 0, ly = t < tx * ty ? t / tx : 0;
+              if (t >= tx * ty) continue;
+              const int slot = (((ly + dy) * p + lx + dx) % 32 + 32) % 32;
+              if (used[slot]) {
+                ok = false;
+                break;
+              }
+              used[slot] = true;
+            }
+          }
+    if (ok) return p;
+  }
+  return width;
+}
+
 // Launch shape of the gather: TX spans the x-row of nodes in as few equal
 // pieces of at most 64 as possible, TY fills the block to <= 256 threads,
-// TZ is chosen so that the launch has ~2048 tiles (8 per CU) unless given.
+// TZ is chosen so that the launch has ~512 tiles (2 per CU) unless given.
 GatherShape choose_shape(const Geom& g, const fem_opts& o) {
   GatherShape s{};
   const int px = g.px, py = g.py, pz = g.pz;
@@ -98,6 +129,13 @@ GatherShape choose_shape(const Geom& g, const fem_opts& o) {
     ty = (py + nty - 1) / nty;
   }
   ty = std::max(1, std::min(ty, 256 / tx));
+  // every thread stages at most kSlots entries of the plane and coefficient tiles
+  auto fits = [](int a, int b) {
+    const int nt = ((a * b + 63) / 64) * 64;
+    return (a + 2) * (b + 2) <= kSlots * nt && (a + 1) * (b + 1) <= kSlots * nt;
+  };
+  if (o.tile_y <= 0)
+    while (ty > 1 && !fits(tx, ty)) --ty;
   s.tx = tx;
   s.ty = ty;
   s.ntx = (px + tx - 1) / tx;
@@ -106,14 +144,19 @@ GatherShape choose_shape(const Geom& g, const fem_opts& o) {
   if (o.tile_z > 0) {
     tz = o.tile_z;
   } else {
+    // about two blocks per CU (512 tiles) with at least 4 planes per march:
+    // the march hides memory latency by prefetching two planes ahead, so
+    // longer marches with fewer z-halo planes beat more, shorter blocks
     const int cols = s.ntx * s.nty;
-    const int ntz_target = std::max(1, (2048 + cols - 1) / cols);
+    const int ntz_target = std::max(1, (512 + cols - 1) / cols);
     tz = std::max(4, (pz + ntz_target - 1) / ntz_target);
   }
   tz = std::max(1, std::min(tz, pz));
   s.tz = tz;
   s.ntz = (pz + tz - 1) / tz;
   s.nthreads = ((tx * ty + 63) / 64) * 64;
+  s.pw = lds_pitch(tx, ty, s.nthreads, tx + 2, true);
+  s.cw = lds_pitch(tx, ty, s.nthreads, tx + 1, false);
   s.ntiles = (uint32_t)s.ntx * s.nty * s.ntz;
   s.nblocks = ((s.ntiles + 7) / 8) * 8;
   return s;
@@ -164,6 +207,7 @@ int launch_gather(fem_heat* h, const V* rhoc, const V* kc, double cm, double ck,
   ga.s = h->shape;
   ga.rhoc = rhoc;
   ga.kc = kc;
+  ga.sink = reinterpret_cast<V*>(h->sink);
   fill_classes(h->g, ga, cm, ck, h->cubic);
   const size_t smem = h->shape.smem_bytes(sizeof(V));
   if (h->cubic)
@@ -428,6 +472,11 @@ int solver_init(fem_heat* h, const fem_grid* grid, const double* k_e, const doub
     h->sched.assign(bc->flux_schedule, bc->flux_schedule + bc->n_schedule);
   h->cubic = (g.hx == g.hy && g.hy == g.hz);
   h->shape = choose_shape(g, h->opts);
+  {
+    const GatherShape& s = h->shape;
+    if ((s.tx + 2) * (s.ty + 2) > kSlots * s.nthreads || (s.tx + 1) * (s.ty + 1) > kSlots * s.nthreads)
+      return fail(h, FEM_EINVAL, "tile shape too thin for the staging scheme");
+  }
   h->upd_blocks64 = std::max<uint32_t>(1, std::min<uint32_t>(nblk((g.N + 1) / 2), 512));
   h->upd_blocks32 = std::max<uint32_t>(1, std::min<uint32_t>(nblk((g.N + 3) / 4), 512));
   h->stats.tile_x = h->shape.tx;
@@ -454,6 +503,7 @@ int solver_init(fem_heat* h, const fem_grid* grid, const double* k_e, const doub
   RC_TRY(dalloc(h, &h->d64[1], N));
   for (auto& p : h->pool) RC_TRY(dalloc(h, &p, N));
   if (h->nonzero_dirichlet) RC_TRY(dalloc(h, &h->lift64, N));
+  RC_TRY(dalloc(h, &h->sink, 256));
   h->n_partials = std::max({h->shape.nblocks, h->upd_blocks64, h->upd_blocks32, 1024u});
   for (RelayCtx* c : {&h->outer, &h->inner})
     for (int k = 0; k < 2; ++k) {
@@ -641,6 +691,7 @@ void solver_free(fem_heat* h) {
   for (auto& p : h->d64) dfree(p);
   for (auto& p : h->pool) dfree(p);
   dfree(h->lift64);
+  dfree(h->sink);
   dfree(h->pinv32);
   for (auto& p : h->e32) dfree(p);
   dfree(h->r32);

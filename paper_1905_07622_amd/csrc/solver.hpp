@@ -49,6 +49,7 @@ struct fem_heat {
   double* d64[2] = {nullptr, nullptr};
   double* pool[4] = {nullptr, nullptr, nullptr, nullptr};  // T^{n-1}, T^{n-2}, x ping-pong
   double* lift64 = nullptr;   // A_fD g (only with non-zero Dirichlet values)
+  double* sink = nullptr;     // 256 scratch values for stores of lanes without a node
   double ck_cached = -1.0;    // theta*dt of pinv/lift; < 0: none
 
   // node vectors, FP32 (mixed form)

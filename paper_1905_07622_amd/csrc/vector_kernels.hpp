@@ -26,8 +26,8 @@ struct Vec<float> {
 // Dirichlet rows are recognised by P^-1 = 0.
 template <typename V>
 __device__ inline void upd1(V& x, V d, V& r, V q, V p, V alpha, double& acc) {
-  x += alpha * d;
-  V rr = r - alpha * q;
+  x = fma(alpha, d, x);
+  V rr = fma(-alpha, q, r);
   rr = (p == V(0)) ? V(0) : rr;
   r = rr;
   acc += (double)rr * (double)(p * rr);
