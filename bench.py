@@ -31,6 +31,21 @@ def algorithmic_bytes(N: int, E: int, w: int) -> dict:
     return {"gather": (5 * N + 2 * E) * w, "update": 7 * N * w}
 
 
+def committed_traffic(kernel: str, precision: str):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 FETCH_SIZE /
+    WRITE_SIZE summary of this workload, or None when there is none or the
+    kernel sources changed since it was taken."""
+    from paper_1905_07622_amd.profile_summary import kernel_source_hash
+    path = os.path.join(ROOT, "profiles", f"traffic_{kernel}_lognormal100_{precision}.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        rec = json.load(f)
+    if rec.get("source_sha256") != kernel_source_hash():
+        return None
+    return int(round(rec["traffic_bytes"]))
+
+
 def cpu_baseline(problem, steps_a=1, steps_b=3):
     """The oracle (serial, 1 thread) on the same workload: the per-iteration
     rate of steps 2..steps_b, taken as the difference of two runs so that the
@@ -129,7 +144,8 @@ def main():
         dom = max(("gather", "update"), key=lambda kname: stats[kname + "_ms"])
         achieved = ab[dom] / (per[dom] * 1e-3) / 1e9
         roof = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": committed_traffic(dom, args.precision),
                 "bytes_per_launch": ab[dom], "avg_launch_us": round(per[dom] * 1e3, 3),
                 "other_kernels_us": {kname: round(v * 1e3, 3) for kname, v in per.items() if kname != dom}}
 

@@ -103,7 +103,8 @@ typedef struct {
   int32_t guess;          /* FEM_GUESS_*                                           */
   int32_t stop_rule;      /* FEM_STOP_*                                            */
   int32_t max_refine;     /* mixed form: max FP64 refinement sweeps per step (default 4) */
-  double inner_rtol;      /* mixed form: inner FP32 PCG relative tolerance (default 1e-5) */
+  double inner_rtol;      /* mixed form: floor of the inner FP32 PCG relative tolerance (default 1e-5);
+                             each sweep targets half the residual reduction the FP64 stop rule still needs */
   uint32_t flags;         /* FEM_DEVICE_PTRS | FEM_TIMING                          */
   void *hip_stream;       /* hipStream_t to run on; NULL = the library's own stream */
   int32_t device;         /* HIP device ordinal                                    */

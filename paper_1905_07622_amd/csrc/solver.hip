@@ -420,6 +420,13 @@ int step_mixed(fem_heat* h, RunState& st, double dt, double theta, double s_n, i
   int total = 0, nsw = 0;
   const uint32_t sblocks = std::min<uint32_t>(nblk(N), 1024);
   while (!so->done && nsw < h->opts.max_refine) {
+    // Inner tolerance: half the reduction the FP64 stop rule still needs,
+    // never tighter than inner_rtol (FP32 arithmetic bounds what the inner
+    // solve can reach); one sweep then usually suffices.
+    const double ref = h->opts.stop_rule == FEM_STOP_INITIAL ? so->delta0 : so->delta_b;
+    const double need = so->delta > 0 ? 0.5 * std::sqrt(c.ctl.rtol2 * ref / so->delta) : 1.0;
+    const double irt = std::min(0.5, std::max(h->opts.inner_rtol, need));
+    h->inner.ctl.rtol2 = irt * irt;
     hipLaunchKernelGGL(inner_start_kernel, dim3(sblocks), dim3(kT), 0, h->stream, h->r64, h->rhs32, h->r32, h->e32[0],
                        h->pinv32, N, next_relay(h->inner, M_START, true, sblocks));
     HIP_TRY(hipGetLastError());

@@ -1,0 +1,135 @@
+"""Summarise rocprofv3 CSV output of a benchmark run into a short text file.
+
+Two kinds of input:
+  * a --kernel-trace --stats directory  -> per-kernel calls / average / share
+  * --pmc FETCH_SIZE and --pmc WRITE_SIZE directories of the same workload,
+    plus the same counters for a plain copy of known size (bench.py
+    --copy-calibration) -> per-dispatch HBM traffic of each kernel, scaled by
+    (copy bytes / copy counter bytes) for each counter.
+
+The traffic of the dominant kernel is also written as JSON together with a
+hash of the kernel sources, so that the benchmark reports it only while the
+kernels are unchanged.
+
+Usage:
+  python -m paper_1905_07622_amd.profile_summary stats DIR OUT.txt --command "..."
+  python -m paper_1905_07622_amd.profile_summary traffic FETCH_DIR WRITE_DIR COPY_FETCH_DIR COPY_WRITE_DIR \
+        OUT.txt OUT.json --kernel-regex REGEX --command "..." [--command ...]
+"""
+from __future__ import annotations
+
+import argparse
+import csv
+import glob
+import hashlib
+import json
+import os
+import re
+from collections import defaultdict
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+COPY_BYTES = 32 * 1024 * 1024 * 8  # bench.py --copy-calibration copies 256 MiB
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for path in sorted(glob.glob(os.path.join(PKG, "csrc", "*"))):
+        with open(path, "rb") as f:
+            h.update(os.path.basename(path).encode())
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def short_name(name: str) -> str:
+    n = name.split("(")[0].replace("void ", "").replace("femheat::", "")
+    return n
+
+
+def find_csv(d: str, suffix: str) -> str:
+    hits = glob.glob(os.path.join(d, "**", "*" + suffix), recursive=True)
+    if not hits:
+        raise FileNotFoundError(f"no *{suffix} under {d}")
+    return hits[0]
+
+
+def stats(d: str, out: str, commands):
+    rows = list(csv.DictReader(open(find_csv(d, "kernel_stats.csv"))))
+    lines = ["# rocprofv3 kernel statistics", ""]
+    lines += [f"command: {c}" for c in commands]
+    lines += ["", f"{'kernel':90s} {'calls':>7s} {'avg_us':>9s} {'min_us':>8s} {'max_us':>8s} {'share%':>7s}"]
+    for r in rows:
+        lines.append(f"{short_name(r['Name'])[:90]:90s} {int(r['Calls']):7d} {float(r['AverageNs']) / 1e3:9.3f} "
+                     f"{float(r['MinNs']) / 1e3:8.3f} {float(r['MaxNs']) / 1e3:8.3f} {float(r['Percentage']):7.2f}")
+    with open(out, "w") as f:
+        f.write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+
+
+def counter_means(d: str):
+    rows = list(csv.DictReader(open(find_csv(d, "counter_collection.csv"))))
+    acc = defaultdict(list)
+    for r in rows:
+        acc[(short_name(r["Kernel_Name"]), r["Counter_Name"])].append(float(r["Counter_Value"]))
+    return {k: (sum(v) / len(v), len(v)) for k, v in acc.items()}
+
+
+def traffic(fetch_dir, write_dir, copy_fetch_dir, copy_write_dir, out_txt, out_json, kernel_regex, commands,
+            algorithmic_bytes=None):
+    fetch = counter_means(fetch_dir)
+    write = counter_means(write_dir)
+    cf = [v for (k, c), v in counter_means(copy_fetch_dir).items() if "copy" in k.lower() and c == "FETCH_SIZE"]
+    cw = [v for (k, c), v in counter_means(copy_write_dir).items() if "copy" in k.lower() and c == "WRITE_SIZE"]
+    # the copy kernel with the largest count is the 256 MiB calibration copy
+    fscale = COPY_BYTES / (max(x[0] for x in cf) * 1024.0)
+    wscale = COPY_BYTES / (max(x[0] for x in cw) * 1024.0)
+    lines = ["# HBM traffic per dispatch from rocprofv3 FETCH_SIZE / WRITE_SIZE (KiB), scaled by a plain copy", ""]
+    lines += [f"command: {c}" for c in commands]
+    lines += ["", f"copy calibration: {COPY_BYTES} bytes copied; FETCH_SIZE scale {fscale:.4f}, "
+                  f"WRITE_SIZE scale {wscale:.4f}", "",
+              f"{'kernel':80s} {'fetch_KiB':>11s} {'write_KiB':>11s} {'traffic_MB':>11s} {'dispatches':>10s}"]
+    chosen = None
+    for (k, c), (v, n) in sorted(fetch.items()):
+        if c != "FETCH_SIZE":
+            continue
+        wv = write.get((k, "WRITE_SIZE"), (0.0, 0))[0]
+        t = v * 1024 * fscale + wv * 1024 * wscale
+        lines.append(f"{k[:80]:80s} {v:11.1f} {wv:11.1f} {t / 1e6:11.2f} {n:10d}")
+        if re.search(kernel_regex, k) and (chosen is None or n > chosen[3]):
+            chosen = (k, v, wv, n, t)
+    with open(out_txt, "w") as f:
+        f.write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+    if chosen and out_json:
+        k, v, wv, n, t = chosen
+        rec = {"kernel": k, "fetch_kib": v, "write_kib": wv, "fetch_scale": fscale, "write_scale": wscale,
+               "traffic_bytes": t, "dispatches": n, "source_sha256": kernel_source_hash()}
+        if algorithmic_bytes:
+            rec["algorithmic_bytes"] = algorithmic_bytes
+        with open(out_json, "w") as f:
+            json.dump(rec, f, indent=1)
+        print("wrote", out_json)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    sub = ap.add_subparsers(dest="cmd", required=True)
+    a = sub.add_parser("stats")
+    a.add_argument("dir")
+    a.add_argument("out")
+    a.add_argument("--command", action="append", default=[])
+    b = sub.add_parser("traffic")
+    for n in ("fetch_dir", "write_dir", "copy_fetch_dir", "copy_write_dir", "out_txt", "out_json"):
+        b.add_argument(n)
+    b.add_argument("--kernel-regex", required=True)
+    b.add_argument("--command", action="append", default=[])
+    b.add_argument("--algorithmic-bytes", type=float, default=None)
+    args = ap.parse_args()
+    if args.cmd == "stats":
+        stats(args.dir, args.out, args.command)
+    else:
+        traffic(args.fetch_dir, args.write_dir, args.copy_fetch_dir, args.copy_write_dir, args.out_txt,
+                args.out_json, args.kernel_regex, args.command, args.algorithmic_bytes)
+
+
+if __name__ == "__main__":
+    main()
