@@ -6,7 +6,7 @@
 #include <string>
 #include <vector>
 
-#include "../../include/fem_heat.h"
+#include "fem_heat.h"
 #include "common.hpp"
 
 namespace femheat {
