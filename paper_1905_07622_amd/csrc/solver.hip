@@ -112,10 +112,41 @@ int lds_pitch(int tx, int ty, int nthreads, int width, bool plane) {
   return width;
 }
 
+// Blocks of the hot gather (search direction fused with the apply) that one
+// CU holds at once for a block of `nthreads` threads: occupancy is bounded by
+// the kernel's registers and LDS, so it is asked of the runtime.
+int resident_blocks(bool cubic, bool fp32, int nthreads, size_t smem) {
+  int n = 0;
+  hipError_t e;
+  if (fp32)
+    e = cubic ? hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                    &n, reinterpret_cast<const void*>(&gather_kernel<float, true, ProDirection<float>, EpiQDot<float>>),
+                    nthreads, smem)
+              : hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                    &n, reinterpret_cast<const void*>(&gather_kernel<float, false, ProDirection<float>, EpiQDot<float>>),
+                    nthreads, smem);
+  else
+    e = cubic ? hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                    &n, reinterpret_cast<const void*>(&gather_kernel<double, true, ProDirection<double>, EpiQDot<double>>),
+                    nthreads, smem)
+              : hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                    &n, reinterpret_cast<const void*>(&gather_kernel<double, false, ProDirection<double>, EpiQDot<double>>),
+                    nthreads, smem);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return 2;
+  }
+  return std::max(n, 1);
+}
+
 // Launch shape of the gather: TX spans the x-row of nodes in as few equal
-// pieces of at most 64 as possible, TY fills the block to <= 256 threads,
-// TZ is chosen so that the launch has ~512 tiles (2 per CU) unless given.
-GatherShape choose_shape(const Geom& g, const fem_opts& o) {
+// pieces of at most 64 as possible, TY fills the block to <= 256 threads.
+// Unless given, TZ splits the columns into as many z-chunks as the chip holds
+// blocks at once (`capacity`): the gather is latency-bound, so the launch
+// should fill every CU to its occupancy limit in a single round -- a second,
+// partial round of blocks costs a whole extra block time -- and longer
+// z-marches pay the start-up of the plane pipeline less often.
+GatherShape choose_shape(const Geom& g, const fem_opts& o, int capacity) {
   GatherShape s{};
   const int px = g.px, py = g.py, pz = g.pz;
   int tx = o.tile_x > 0 ? o.tile_x : (px + (px + 63) / 64 - 1) / ((px + 63) / 64);
@@ -144,11 +175,8 @@ GatherShape choose_shape(const Geom& g, const fem_opts& o) {
   if (o.tile_z > 0) {
     tz = o.tile_z;
   } else {
-    // about two blocks per CU (512 tiles) with at least 4 planes per march:
-    // the march hides memory latency by prefetching two planes ahead, so
-    // longer marches with fewer z-halo planes beat more, shorter blocks
     const int cols = s.ntx * s.nty;
-    const int ntz_target = std::max(1, (512 + cols - 1) / cols);
+    const int ntz_target = std::max(1, capacity / cols);
     tz = std::max(4, (pz + ntz_target - 1) / ntz_target);
   }
   tz = std::max(1, std::min(tz, pz));
@@ -478,7 +506,16 @@ int solver_init(fem_heat* h, const fem_grid* grid, const double* k_e, const doub
   if (bc && bc->flux_schedule && bc->n_schedule > 0)
     h->sched.assign(bc->flux_schedule, bc->flux_schedule + bc->n_schedule);
   h->cubic = (g.hx == g.hy && g.hy == g.hz);
-  h->shape = choose_shape(g, h->opts);
+  HIP_TRY(hipSetDevice(h->opts.device));
+  {
+    // the x-y tiling does not depend on the capacity: size the block first
+    const GatherShape probe = choose_shape(g, h->opts, 1);
+    const bool fp32 = h->opts.precision == FEM_FP32_FP64DOT;
+    int cus = 0;
+    HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, h->opts.device));
+    const int per_cu = resident_blocks(h->cubic, fp32, probe.nthreads, probe.smem_bytes(fp32 ? 4 : 8));
+    h->shape = choose_shape(g, h->opts, std::max(1, cus) * per_cu);
+  }
   {
     const GatherShape& s = h->shape;
     if ((s.tx + 2) * (s.ty + 2) > kSlots * s.nthreads || (s.tx + 1) * (s.ty + 1) > kSlots * s.nthreads)
@@ -491,7 +528,6 @@ int solver_init(fem_heat* h, const fem_grid* grid, const double* k_e, const doub
   h->stats.tile_z = h->shape.tz;
   h->stats.grid_blocks = (int32_t)h->shape.nblocks;
 
-  HIP_TRY(hipSetDevice(h->opts.device));
   if (h->opts.hip_stream) {
     h->stream = reinterpret_cast<hipStream_t>(h->opts.hip_stream);
   } else {
