@@ -169,6 +169,38 @@ int fem_heat_run(fem_heat *h, const double *T0, const double *T_prev, double dt,
  * dt and theta: y = op(x).  x and y are N-vectors. */
 int fem_heat_apply(fem_heat *h, int32_t which, double dt, double theta, const double *x, double *y);
 
+/* One simulation of a batch: a problem as for fem_heat_create and a run as
+ * for fem_heat_run (same meanings, validation and outputs). */
+typedef struct {
+  fem_grid grid;
+  const double *k_e;
+  const double *rhoc_e;
+  fem_bc bc;
+  const double *T0;
+  const double *T_prev;      /* NULL = T0 */
+  double dt, theta, rtol;
+  int32_t nsteps;
+  fem_out *out;              /* may be NULL */
+} fem_request;
+
+/* Run n independent simulations together on one GPU: the repeated forward
+ * solves of a coefficient study (Sec. 5.4), each with its own grid,
+ * coefficients, boundary conditions, dt, theta, rtol and step count.  Every
+ * kernel launch serves all of them (a simulation's blocks work only on its
+ * own data, with its own reductions), they advance one time step per epoch
+ * in lockstep, and each leaves the batch after its last step.  A
+ * simulation's results do not depend on the others in the batch: they are
+ * bit-identical to those of a batch holding it alone.  opts (may be NULL)
+ * apply to all: precision, iteration controls, flags (FEM_DEVICE_PTRS covers
+ * every array of every request), stream, device and tile overrides; without
+ * a tile_z override every simulation marches z-chunks of at most 32 planes.
+ * Validates every request first and runs none if one is invalid
+ * (FEM_EINVAL, status[i] names it).  Otherwise status[i] (n entries, may be
+ * NULL) receives each simulation's outcome as fem_heat_run would return it,
+ * and the call returns FEM_OK when all are FEM_OK, else the first other
+ * status in request order; FEM_ENOMEM / FEM_EDEVICE abort the whole batch. */
+int fem_heat_run_batch(const fem_request *reqs, int32_t n, const fem_opts *opts, int32_t *status);
+
 /* Kernel timing and launch shape of the last run (FEM_TIMING). */
 int fem_heat_stats(const fem_heat *h, fem_stats *out);
 
@@ -180,6 +212,8 @@ void fem_heat_destroy(fem_heat *h);
 void fem_heat_default_opts(fem_opts *opts);
 
 const char *fem_strerror(int status);
+/* Message of the last failing call on a handle; with NULL, of the last failing
+ * fem_heat_create or fem_heat_run_batch on the calling thread. */
 const char *fem_last_error(const fem_heat *h);
 
 #ifdef __cplusplus

@@ -1,0 +1,247 @@
+// Batched launches of the time-stepping path (gfx950).
+//
+// One launch of each kernel below serves every simulation of a batch: the
+// repeated forward solves of a coefficient study (Sec. 5.4) share the GPU
+// instead of taking it in turn.  Every block belongs to one simulation: a
+// work table maps the block's work item to (simulation, block index within
+// it), and the block then runs exactly the code, on exactly the data, that a
+// launch for that simulation alone would run -- same tiles, same block
+// counts, partials stored at the same index, same relay state -- so a
+// simulation's results do not depend on its co-runners, bit for bit.
+//
+// What differs between the launches of one time step is uniform across the
+// batch: all simulations advance one step per epoch in lockstep, and inside
+// a solve the buffer parities follow from the iteration index alone (the
+// search direction ping-pongs every iteration, x every residual
+// replacement).  Per-simulation data -- buffers, operator constants, relay
+// state, tolerances -- sit in a SimDev array in device memory that the host
+// rewrites only at step and refinement-sweep boundaries.  A simulation whose
+// solve has converged stays in the launches: its blocks read the relayed
+// state, see that it is done and return.
+#pragma once
+
+#include "gather.hpp"
+#include "vector_kernels.hpp"
+
+namespace femheat {
+
+// Kernel kinds whose block partials a relay reads (their block counts differ).
+enum PartKind : int32_t { PK_GATHER = 0, PK_UPD64 = 1, PK_UPD32 = 2, PK_START = 3 };
+
+// Everything the batched kernels need of one simulation.
+struct SimDev {
+  GatherArgs<double> A64;  // A = M + theta*dt*K
+  GatherArgs<double> L64;  // L = M - (1-theta)*dt*K
+  GatherArgs<float> A32;   // A in FP32 (mixed form)
+  const double* F64;
+  const double* pinv64;
+  const double* lift64;
+  double* b64;
+  double* r64;
+  double* q64;
+  double* d64[2];
+  const double* T1;  // T^{n-1}
+  const double* T2;  // T^{n-2}
+  double* X[2];      // iterate ping-pong; the guess is written to X[0]
+  const float* pinv32;
+  float* r32;
+  float* q32;
+  float* d32[2];
+  float* e32[2];
+  float* rhs32;
+  Scalars* oS[2];  // outer (FP64) relay state and partials
+  double* oP[2];
+  Scalars* iS[2];  // inner (FP32) relay state and partials
+  double* iP[2];
+  Ctl octl, ictl;
+  uint32_t N;
+  uint32_t nblk[4];    // blocks of each PartKind
+  double fs;           // dt * s_n of the current step
+  int32_t guess_prev;  // 1: x0 = T^{n-1}
+  int32_t xc;          // mixed form: X buffer of the current FP64 iterate
+  int32_t exc;         // mixed form: e buffer of the last inner solution
+  int32_t sweep;       // mixed form: this sweep runs an inner solve and a correction
+};
+
+// Uniform arguments of one batched launch.
+struct BatchArgs {
+  const SimDev* sims;
+  const uint2* table;  // work item -> (simulation, block within it); nullptr: one simulation
+  Scalars* snap;       // decide: per-simulation copy of the settled state
+  int32_t cur;         // relay parity: state/partials buffer this launch reads
+  int32_t prev;        // PartKind of the partials it reads
+  int32_t j;           // iteration index within the current solve
+  int32_t xpar;        // replacements so far in this solve, mod 2 (x or e buffer)
+  int32_t inner;       // decide: 1 = inner relay
+};
+
+__device__ inline Relay outer_relay(const SimDev& s, const BatchArgs& a, int32_t mode, bool partials) {
+  return Relay{s.oS[a.cur], s.oS[a.cur ^ 1], s.oP[a.cur], s.nblk[a.prev], partials ? s.oP[a.cur ^ 1] : nullptr,
+               mode, s.octl};
+}
+__device__ inline Relay inner_relay(const SimDev& s, const BatchArgs& a, int32_t mode, bool partials) {
+  return Relay{s.iS[a.cur], s.iS[a.cur ^ 1], s.iP[a.cur], s.nblk[a.prev], partials ? s.iP[a.cur ^ 1] : nullptr,
+               mode, s.ictl};
+}
+
+// The direction ping-pongs every iteration: iteration j reads d[j&1] and
+// writes d[(j+1)&1], which the update of iteration j then uses.
+__device__ inline int dir_in(const BatchArgs& a) { return a.j & 1; }
+__device__ inline int dir_out(const BatchArgs& a) { return (a.j + 1) & 1; }
+
+// ---- gather roles: operator, prologue, epilogue and relay of each gather ----
+
+struct RoleRhs {  // b = L T^{n-1} + dt*s_n*F, with b^T P^-1 b (a2)
+  using V = double;
+  using Pro = ProPlain<double>;
+  using Epi = EpiRhs<double>;
+  static __device__ const GatherArgs<V>& ga(const SimDev& s) { return s.L64; }
+  static __device__ Pro pro(const SimDev& s, const BatchArgs&) { return Pro{s.T1}; }
+  static __device__ Epi epi(const SimDev& s, const BatchArgs&) { return Epi{s.b64, s.F64, s.pinv64, s.lift64, s.fs}; }
+  static __device__ Relay relay(const SimDev& s, const BatchArgs& a) { return outer_relay(s, a, M_RHS, true); }
+};
+
+struct RoleInit {  // x0 by the guess rule, r = b - A x0, r^T P^-1 r (a3)
+  using V = double;
+  using Pro = ProGuess<double>;
+  using Epi = EpiResidual<double>;
+  static __device__ const GatherArgs<V>& ga(const SimDev& s) { return s.A64; }
+  static __device__ Pro pro(const SimDev& s, const BatchArgs&) {
+    return Pro{s.T1, s.T2, s.pinv64, s.X[0], s.guess_prev, 0};
+  }
+  static __device__ Epi epi(const SimDev& s, const BatchArgs&) { return Epi{s.b64, s.pinv64, s.r64}; }
+  static __device__ Relay relay(const SimDev& s, const BatchArgs& a) { return outer_relay(s, a, M_INIT, true); }
+};
+
+template <typename V>
+struct RoleDir;  // d = P^-1 r + beta d, q = A d, d^T q (a6 + a4)
+
+template <>
+struct RoleDir<double> {
+  using V = double;
+  using Pro = ProDirection<double>;
+  using Epi = EpiQDot<double>;
+  static __device__ const GatherArgs<V>& ga(const SimDev& s) { return s.A64; }
+  static __device__ Pro pro(const SimDev& s, const BatchArgs& a) {
+    return Pro{s.r64, s.pinv64, s.d64[dir_in(a)], s.d64[dir_out(a)], 0.0};
+  }
+  static __device__ Epi epi(const SimDev& s, const BatchArgs&) { return Epi{s.q64}; }
+  static __device__ Relay relay(const SimDev& s, const BatchArgs& a) { return outer_relay(s, a, M_DIR, true); }
+};
+
+template <>
+struct RoleDir<float> {
+  using V = float;
+  using Pro = ProDirection<float>;
+  using Epi = EpiQDot<float>;
+  static __device__ const GatherArgs<V>& ga(const SimDev& s) { return s.A32; }
+  static __device__ Pro pro(const SimDev& s, const BatchArgs& a) {
+    return Pro{s.r32, s.pinv32, s.d32[dir_in(a)], s.d32[dir_out(a)], 0.0f};
+  }
+  static __device__ Epi epi(const SimDev& s, const BatchArgs&) { return Epi{s.q32}; }
+  static __device__ Relay relay(const SimDev& s, const BatchArgs& a) { return inner_relay(s, a, M_DIR, true); }
+};
+
+template <typename V>
+struct RoleRepl;  // residual replacement: x += alpha d, r = b - A x (a5, i mod 50 == 0)
+
+template <>
+struct RoleRepl<double> {
+  using V = double;
+  using Pro = ProAxpy<double, double>;
+  using Epi = EpiResidual<double>;
+  static __device__ const GatherArgs<V>& ga(const SimDev& s) { return s.A64; }
+  static __device__ Pro pro(const SimDev& s, const BatchArgs& a) {
+    return Pro{s.X[a.xpar], s.d64[dir_out(a)], s.X[a.xpar ^ 1], 0, 0.0};
+  }
+  static __device__ Epi epi(const SimDev& s, const BatchArgs&) { return Epi{s.b64, s.pinv64, s.r64}; }
+  static __device__ Relay relay(const SimDev& s, const BatchArgs& a) { return outer_relay(s, a, M_UPD, true); }
+};
+
+template <>
+struct RoleRepl<float> {
+  using V = float;
+  using Pro = ProAxpy<float, float>;
+  using Epi = EpiResidual<float>;
+  static __device__ const GatherArgs<V>& ga(const SimDev& s) { return s.A32; }
+  static __device__ Pro pro(const SimDev& s, const BatchArgs& a) {
+    return Pro{s.e32[a.xpar], s.d32[dir_out(a)], s.e32[a.xpar ^ 1], 0, 0.0f};
+  }
+  static __device__ Epi epi(const SimDev& s, const BatchArgs&) { return Epi{s.rhs32, s.pinv32, s.r32}; }
+  static __device__ Relay relay(const SimDev& s, const BatchArgs& a) { return inner_relay(s, a, M_UPD, true); }
+};
+
+struct RoleCorr {  // mixed form: x64 += e, r64 = b - A x64, FP64 residual norm (a9)
+  using V = double;
+  using Pro = ProAxpy<double, float>;
+  using Epi = EpiResidual<double>;
+  static __device__ const GatherArgs<V>& ga(const SimDev& s) { return s.A64; }
+  static __device__ Pro pro(const SimDev& s, const BatchArgs&) {
+    return Pro{s.X[s.xc], s.e32[s.exc], s.X[s.xc ^ 1], 1, 0.0};
+  }
+  static __device__ Epi epi(const SimDev& s, const BatchArgs&) { return Epi{s.b64, s.pinv64, s.r64}; }
+  static __device__ Relay relay(const SimDev& s, const BatchArgs& a) {
+    return outer_relay(s, a, s.sweep ? M_CORR : M_SKIP, true);
+  }
+};
+
+// ---- kernels -----------------------------------------------------------------
+
+__device__ inline void work_item(const BatchArgs& a, uint32_t w, uint32_t& sim, uint32_t& local) {
+  sim = 0;
+  local = w;
+  if (a.table) {
+    const uint2 e = a.table[w];
+    sim = e.x;
+    local = e.y;
+  }
+}
+
+// One gather role over every simulation of a launch group (grid = the sum
+// of the group's per-simulation block counts, each a multiple of 8).
+template <bool CUBIC, class Role>
+__global__ void __launch_bounds__(256) gather_batch_kernel(BatchArgs a) {
+  uint32_t sim, local;
+  work_item(a, xcd_work_item(blockIdx.x, gridDim.x), sim, local);
+  const SimDev& s = a.sims[sim];
+  const GatherArgs<typename Role::V> ga = Role::ga(s);
+  gather_tile<typename Role::V, CUBIC>(ga, Role::pro(s, a), Role::epi(s, a), Role::relay(s, a), local);
+}
+
+// Fused x/r update and preconditioned residual norm (a5), FP64 outer solve
+// or FP32 inner solve.
+template <typename V>
+__global__ void __launch_bounds__(256) update_batch_kernel(BatchArgs a) {
+  uint32_t sim, local;
+  work_item(a, blockIdx.x, sim, local);
+  const SimDev& s = a.sims[sim];
+  if constexpr (sizeof(V) == 8) {
+    update_body<double>(s.X[a.xpar], s.d64[dir_out(a)], s.r64, s.q64, s.pinv64, s.N,
+                        outer_relay(s, a, M_UPD, true), local, s.nblk[PK_UPD64]);
+  } else {
+    update_body<float>(s.e32[a.xpar], s.d32[dir_out(a)], s.r32, s.q32, s.pinv32, s.N,
+                       inner_relay(s, a, M_UPD, true), local, s.nblk[PK_UPD32]);
+  }
+}
+
+// Start of the inner solves of a refinement sweep (a9); simulations that do
+// not sweep this time get an idle, already finished inner solve.
+static __global__ void __launch_bounds__(256) inner_start_batch_kernel(BatchArgs a) {
+  uint32_t sim, local;
+  work_item(a, blockIdx.x, sim, local);
+  const SimDev& s = a.sims[sim];
+  inner_start_body(s.r64, s.rhs32, s.r32, s.e32[0], s.pinv32, s.N,
+                   inner_relay(s, a, s.sweep ? M_START : M_IDLE, true), local, s.nblk[PK_START]);
+}
+
+// Settles the pending decision of every simulation (one block each) and
+// copies the settled state to snap[sim] for the host.
+static __global__ void __launch_bounds__(64) decide_batch_kernel(BatchArgs a) {
+  const SimDev& s = a.sims[blockIdx.x];
+  const Relay R = a.inner ? inner_relay(s, a, M_DECIDE, false) : outer_relay(s, a, M_DECIDE, false);
+  Scalars st;
+  (void)stage_entry(R, st, true);
+  if (threadIdx.x == 0) a.snap[blockIdx.x] = st;
+}
+
+}  // namespace femheat

@@ -1,10 +1,13 @@
 // extern "C" entry points of include/fem_heat.h: argument validation, handle
-// lifetime and error reporting.  The work itself is in solver.hip.
+// lifetime and error reporting.  The work itself is in solver.hip (set-up,
+// operator hook) and engine.hip (time stepping, single and batched).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <new>
+#include <string>
 #include <vector>
 
 #include "solver.hpp"
@@ -24,6 +27,119 @@ bool fetch(const double* src, size_t n, bool device, std::vector<double>& out) {
 }
 
 thread_local std::string g_create_error;
+
+int check_opts(const fem_opts* opts, fem_opts& o, std::string& why) {
+  fem_heat_default_opts(&o);
+  if (opts) o = *opts;
+  auto bad = [&](const char* m) {
+    why = m;
+    return FEM_EINVAL;
+  };
+  if (o.precision != FEM_FP64 && o.precision != FEM_FP32_FP64DOT) return bad("unknown precision");
+  if (o.max_iter < 0 || o.replace_every < 0 || o.max_refine < 0) return bad("negative iteration controls");
+  if (o.guess != FEM_GUESS_EXTRAP && o.guess != FEM_GUESS_PREV) return bad("unknown guess rule");
+  if (o.stop_rule != FEM_STOP_RHS && o.stop_rule != FEM_STOP_INITIAL) return bad("unknown stop rule");
+  if (o.precision == FEM_FP32_FP64DOT && !finite_pos(o.inner_rtol)) return bad("inner_rtol must be > 0");
+  if (o.tile_x < 0 || o.tile_y < 0 || o.tile_z < 0 || o.tile_x > 256 || o.tile_x * std::max(o.tile_y, 1) > 256)
+    return bad("tile overrides out of range");
+  return FEM_OK;
+}
+
+// Grid, coefficients and boundary conditions of a problem.
+int check_problem(const fem_grid* grid, const double* k_e, const double* rhoc_e, const fem_bc* bc, const fem_opts& o,
+                  std::string& why) {
+  auto bad = [&](const char* m) {
+    why = m;
+    return FEM_EINVAL;
+  };
+  if (!grid || !k_e || !rhoc_e) return bad("grid, k_e and rhoc_e are required");
+  if (grid->nx < 1 || grid->ny < 1 || grid->nz < 1) return bad("nx, ny, nz must be >= 1");
+  const double N = (double)(grid->nx + 1) * (grid->ny + 1) * (grid->nz + 1);
+  if (N >= 2147483647.0) return bad("grid too large (N must fit in 31 bits)");
+  if (!finite_pos(grid->hx) || !finite_pos(grid->hy) || !finite_pos(grid->hz)) return bad("h must be finite and > 0");
+  if (bc) {
+    if ((bc->dirichlet_mask | bc->flux_mask) >= 64u) return bad("face masks have 6 bits");
+    if (bc->dirichlet_mask & bc->flux_mask) return bad("a face is both Dirichlet and flux");
+    for (int f = 0; f < 6; ++f)
+      if (!std::isfinite(bc->dirichlet_value[f]) || !std::isfinite(bc->flux[f])) return bad("non-finite boundary value");
+    if (bc->n_schedule < 0 || (bc->n_schedule > 0 && !bc->flux_schedule)) return bad("bad flux schedule");
+    for (int32_t m = 0; m < bc->n_schedule; ++m)
+      if (!std::isfinite(bc->flux_schedule[m])) return bad("non-finite flux schedule value");
+  }
+  const bool dev = (o.flags & FEM_DEVICE_PTRS) != 0;
+  const size_t E = (size_t)grid->nx * grid->ny * grid->nz;
+  if (dev && hipSetDevice(o.device) != hipSuccess) {
+    why = "hipSetDevice failed";
+    return FEM_EDEVICE;
+  }
+  std::vector<double> chk;
+  if (!fetch(k_e, E, dev, chk)) {
+    why = "reading k_e failed";
+    return FEM_EDEVICE;
+  }
+  for (double v : chk)
+    if (!(v >= 0.0) || !std::isfinite(v)) return bad("k_e must be finite and >= 0");
+  if (!fetch(rhoc_e, E, dev, chk)) {
+    why = "reading rhoc_e failed";
+    return FEM_EDEVICE;
+  }
+  for (double v : chk)
+    if (!finite_pos(v)) return bad("rhoc_e must be finite and > 0");
+  return FEM_OK;
+}
+
+// Arguments of a run on grid g (only the sizes and spacings of g are used).
+int check_run(const femheat::Geom& g, bool dev, const double* T0, double dt, double theta, double rtol,
+              int32_t nsteps, const fem_out* out, std::string& why) {
+  auto bad = [&](const char* m) {
+    why = m;
+    return FEM_EINVAL;
+  };
+  if (!T0) return bad("T0 is required");
+  if (!finite_pos(dt)) return bad("dt must be finite and > 0");
+  if (!(theta >= 0.0 && theta <= 1.0)) return bad("theta must be in [0, 1]");
+  if (!finite_pos(rtol)) return bad("rtol must be finite and > 0");
+  if (nsteps < 0) return bad("nsteps must be >= 0");
+  if (out) {
+    if (out->save_every < 0) return bad("save_every must be >= 0");
+    if (out->n_sensors < 0 || (out->n_sensors > 0 && !out->sensor_xyz)) return bad("bad sensor points");
+    if (out->n_sensors > 0) {
+      std::vector<double> p;
+      if (!fetch(out->sensor_xyz, 3 * (size_t)out->n_sensors, dev, p)) {
+        why = "reading sensor points failed";
+        return FEM_EDEVICE;
+      }
+      const double L[3] = {g.nx * g.hx, g.ny * g.hy, g.nz * g.hz};
+      for (int32_t s = 0; s < out->n_sensors; ++s)
+        for (int d = 0; d < 3; ++d) {
+          const double v = p[3 * (size_t)s + d], tol = 1e-12 * L[d];
+          if (!std::isfinite(v) || v < -tol || v > L[d] + tol) return bad("sensor point outside the domain");
+        }
+    }
+  }
+  return FEM_OK;
+}
+
+// A validated problem's handle; `batched` selects the tile rule of batch members.
+int make_handle(const fem_grid* grid, const double* k_e, const double* rhoc_e, const fem_bc* bc, const fem_opts& o,
+                bool batched, fem_heat** out, std::string& why) {
+  fem_heat* h = new (std::nothrow) fem_heat();
+  if (!h) return FEM_ENOMEM;
+  h->opts = o;
+  h->devptrs = (o.flags & FEM_DEVICE_PTRS) != 0;
+  h->timing = (o.flags & FEM_TIMING) != 0;
+  h->device = o.device;
+  h->batched = batched;
+  const int rc = femheat::solver_init(h, grid, k_e, rhoc_e, bc);
+  if (rc != FEM_OK) {
+    why = h->err;
+    femheat::solver_free(h);
+    delete h;
+    return rc;
+  }
+  *out = h;
+  return FEM_OK;
+}
 
 }  // namespace
 
@@ -62,98 +178,19 @@ int fem_heat_create(const fem_grid* grid, const double* k_e, const double* rhoc_
   g_create_error.clear();
   if (!out) return FEM_EINVAL;
   *out = nullptr;
-  auto bad = [](const char* m) {
-    g_create_error = m;
-    return FEM_EINVAL;
-  };
-  if (!grid || !k_e || !rhoc_e) return bad("grid, k_e and rhoc_e are required");
-  if (grid->nx < 1 || grid->ny < 1 || grid->nz < 1) return bad("nx, ny, nz must be >= 1");
-  const double N = (double)(grid->nx + 1) * (grid->ny + 1) * (grid->nz + 1);
-  if (N >= 2147483647.0) return bad("grid too large (N must fit in 31 bits)");
-  if (!finite_pos(grid->hx) || !finite_pos(grid->hy) || !finite_pos(grid->hz)) return bad("h must be finite and > 0");
   fem_opts o;
-  fem_heat_default_opts(&o);
-  if (opts) o = *opts;
-  if (o.precision != FEM_FP64 && o.precision != FEM_FP32_FP64DOT) return bad("unknown precision");
-  if (o.max_iter < 0 || o.replace_every < 0 || o.max_refine < 0) return bad("negative iteration controls");
-  if (o.guess != FEM_GUESS_EXTRAP && o.guess != FEM_GUESS_PREV) return bad("unknown guess rule");
-  if (o.stop_rule != FEM_STOP_RHS && o.stop_rule != FEM_STOP_INITIAL) return bad("unknown stop rule");
-  if (o.precision == FEM_FP32_FP64DOT && !finite_pos(o.inner_rtol)) return bad("inner_rtol must be > 0");
-  if (o.tile_x < 0 || o.tile_y < 0 || o.tile_z < 0 || o.tile_x > 256 || o.tile_x * std::max(o.tile_y, 1) > 256)
-    return bad("tile overrides out of range");
-  if (bc) {
-    if ((bc->dirichlet_mask | bc->flux_mask) >= 64u) return bad("face masks have 6 bits");
-    if (bc->dirichlet_mask & bc->flux_mask) return bad("a face is both Dirichlet and flux");
-    for (int f = 0; f < 6; ++f)
-      if (!std::isfinite(bc->dirichlet_value[f]) || !std::isfinite(bc->flux[f])) return bad("non-finite boundary value");
-    if (bc->n_schedule < 0 || (bc->n_schedule > 0 && !bc->flux_schedule)) return bad("bad flux schedule");
-    for (int32_t m = 0; m < bc->n_schedule; ++m)
-      if (!std::isfinite(bc->flux_schedule[m])) return bad("non-finite flux schedule value");
-  }
-  const bool dev = (o.flags & FEM_DEVICE_PTRS) != 0;
-  const size_t E = (size_t)grid->nx * grid->ny * grid->nz;
-  if (dev && hipSetDevice(o.device) != hipSuccess) {
-    g_create_error = "hipSetDevice failed";
-    return FEM_EDEVICE;
-  }
-  std::vector<double> chk;
-  if (!fetch(k_e, E, dev, chk)) {
-    g_create_error = "reading k_e failed";
-    return FEM_EDEVICE;
-  }
-  for (double v : chk)
-    if (!(v >= 0.0) || !std::isfinite(v)) return bad("k_e must be finite and >= 0");
-  if (!fetch(rhoc_e, E, dev, chk)) {
-    g_create_error = "reading rhoc_e failed";
-    return FEM_EDEVICE;
-  }
-  for (double v : chk)
-    if (!finite_pos(v)) return bad("rhoc_e must be finite and > 0");
-
-  fem_heat* h = new (std::nothrow) fem_heat();
-  if (!h) return FEM_ENOMEM;
-  h->opts = o;
-  h->devptrs = dev;
-  h->timing = (o.flags & FEM_TIMING) != 0;
-  h->device = o.device;
-  int rc = femheat::solver_init(h, grid, k_e, rhoc_e, bc);
-  if (rc != FEM_OK) {
-    g_create_error = h->err;
-    femheat::solver_free(h);
-    delete h;
-    return rc;
-  }
-  *out = h;
-  return FEM_OK;
+  int rc = check_opts(opts, o, g_create_error);
+  if (rc == FEM_OK) rc = check_problem(grid, k_e, rhoc_e, bc, o, g_create_error);
+  if (rc != FEM_OK) return rc;
+  return make_handle(grid, k_e, rhoc_e, bc, o, false, out, g_create_error);
 }
 
 int fem_heat_run(fem_heat* h, const double* T0, const double* T_prev, double dt, double theta, int32_t nsteps,
                  double rtol, fem_out* out) {
   if (!h) return FEM_EINVAL;
   h->err.clear();
-  auto bad = [h](const char* m) {
-    h->err = m;
-    return FEM_EINVAL;
-  };
-  if (!T0) return bad("T0 is required");
-  if (!finite_pos(dt)) return bad("dt must be finite and > 0");
-  if (!(theta >= 0.0 && theta <= 1.0)) return bad("theta must be in [0, 1]");
-  if (!finite_pos(rtol)) return bad("rtol must be finite and > 0");
-  if (nsteps < 0) return bad("nsteps must be >= 0");
-  if (out) {
-    if (out->save_every < 0) return bad("save_every must be >= 0");
-    if (out->n_sensors < 0 || (out->n_sensors > 0 && !out->sensor_xyz)) return bad("bad sensor points");
-    if (out->n_sensors > 0) {
-      std::vector<double> p;
-      if (!fetch(out->sensor_xyz, 3 * (size_t)out->n_sensors, h->devptrs, p)) return FEM_EDEVICE;
-      const double L[3] = {h->g.nx * h->g.hx, h->g.ny * h->g.hy, h->g.nz * h->g.hz};
-      for (int32_t s = 0; s < out->n_sensors; ++s)
-        for (int d = 0; d < 3; ++d) {
-          const double v = p[3 * (size_t)s + d], tol = 1e-12 * L[d];
-          if (!std::isfinite(v) || v < -tol || v > L[d] + tol) return bad("sensor point outside the domain");
-        }
-    }
-  }
+  const int rc = check_run(h->g, h->devptrs, T0, dt, theta, rtol, nsteps, out, h->err);
+  if (rc != FEM_OK) return rc;
   try {
     return femheat::solver_run(h, T0, T_prev, dt, theta, nsteps, rtol, out);
   } catch (const std::bad_alloc&) {
@@ -163,6 +200,86 @@ int fem_heat_run(fem_heat* h, const double* T0, const double* T_prev, double dt,
     h->err = "unexpected exception";
     return FEM_EDEVICE;
   }
+}
+
+int fem_heat_run_batch(const fem_request* reqs, int32_t n, const fem_opts* opts, int32_t* status) {
+  g_create_error.clear();
+  if (n < 0 || (n > 0 && !reqs)) {
+    g_create_error = "reqs and n >= 0 are required";
+    return FEM_EINVAL;
+  }
+  if (n == 0) return FEM_OK;
+  std::vector<int32_t> st((size_t)n, FEM_OK);
+  fem_opts o;
+  int rc = check_opts(opts, o, g_create_error);
+  if (rc != FEM_OK) return rc;
+  // validate every request before anything runs
+  int first_bad = FEM_OK;
+  for (int32_t i = 0; i < n && first_bad == FEM_OK; ++i) {
+    const fem_request& r = reqs[i];
+    std::string why;
+    int v = check_problem(&r.grid, r.k_e, r.rhoc_e, &r.bc, o, why);
+    if (v == FEM_OK) {
+      femheat::Geom g{};
+      g.nx = r.grid.nx;
+      g.ny = r.grid.ny;
+      g.nz = r.grid.nz;
+      g.hx = r.grid.hx;
+      g.hy = r.grid.hy;
+      g.hz = r.grid.hz;
+      v = check_run(g, (o.flags & FEM_DEVICE_PTRS) != 0, r.T0, r.dt, r.theta, r.rtol, r.nsteps, r.out, why);
+    }
+    if (v != FEM_OK) {
+      st[(size_t)i] = v;
+      first_bad = v;
+      g_create_error = "request " + std::to_string(i) + ": " + why;
+    }
+  }
+  if (first_bad != FEM_OK) {
+    if (status) std::copy(st.begin(), st.end(), status);
+    return first_bad;
+  }
+  hipStream_t stream = reinterpret_cast<hipStream_t>(o.hip_stream);
+  bool own = false;
+  if (hipSetDevice(o.device) != hipSuccess) {
+    g_create_error = "hipSetDevice failed";
+    return FEM_EDEVICE;
+  }
+  if (!stream) {
+    if (hipStreamCreateWithFlags(&stream, hipStreamNonBlocking) != hipSuccess) {
+      g_create_error = "hipStreamCreate failed";
+      return FEM_EDEVICE;
+    }
+    own = true;
+    o.hip_stream = stream;
+  }
+  std::vector<fem_heat*> hs((size_t)n, nullptr);
+  std::vector<femheat::RunRequest> rq((size_t)n);
+  try {
+    for (int32_t i = 0; i < n && rc == FEM_OK; ++i) {
+      const fem_request& r = reqs[i];
+      rc = make_handle(&r.grid, r.k_e, r.rhoc_e, &r.bc, o, true, &hs[(size_t)i], g_create_error);
+      rq[(size_t)i] = femheat::RunRequest{hs[(size_t)i], r.T0, r.T_prev, r.dt, r.theta, r.rtol, r.nsteps, r.out};
+    }
+    if (rc == FEM_OK) rc = femheat::engine_run(rq.data(), n, stream, o, st.data(), &g_create_error);
+  } catch (const std::bad_alloc&) {
+    g_create_error = "host allocation failed";
+    rc = FEM_ENOMEM;
+  } catch (...) {
+    g_create_error = "unexpected exception";
+    rc = FEM_EDEVICE;
+  }
+  for (fem_heat* h : hs) {
+    if (!h) continue;
+    femheat::solver_free(h);
+    delete h;
+  }
+  if (own) (void)hipStreamDestroy(stream);
+  if (rc != FEM_OK) return rc;
+  if (status) std::copy(st.begin(), st.end(), status);
+  for (int32_t v : st)
+    if (v != FEM_OK) return v;
+  return FEM_OK;
 }
 
 int fem_heat_apply(fem_heat* h, int32_t which, double dt, double theta, const double* x, double* y) {

@@ -63,7 +63,9 @@ enum Mode : int32_t {
   M_DIR = 4,     // settles delta/beta/stop, then direction + apply
   M_UPD = 5,     // settles alpha, then x/r update (or replacement)
   M_CORR = 6,    // FP64 correction of a refinement sweep
-  M_DECIDE = 7   // settles the pending decision only
+  M_DECIDE = 7,  // settles the pending decision only
+  M_SKIP = 8,    // relays the state unchanged and does no work
+  M_IDLE = 9     // an inner solve that is not needed: starts done, zero iterations
 };
 
 constexpr int32_t kStatusBreakdown = -4;

@@ -1,0 +1,679 @@
+// Time stepping of one simulation or of a batch of simulations (gfx950).
+//
+// Every implicit theta-scheme step (Sec. 3.1) is, per simulation: the
+// right-hand side b = L T^{n-1} + dt*s_n*F (one gather, RHS epilogue), the
+// initial guess and residual (one gather), then the iterations of
+// Algorithm 1, two kernels each: the search-direction update fused into the
+// operator apply (q = A d, d^T q -> alpha on the device) and the fused x/r
+// update with the preconditioned residual norm (delta, beta and the stop
+// test on the device).  When i mod replace_every == 0 (50 in Algorithm 1)
+// the update is a gather computing r = b - A x instead.  The mixed form runs
+// that loop in FP32 on A e = r64 inside FP64 refinement sweeps.
+//
+// The paper's host read the residual back every iteration (App. A.3).  Here
+// the scalars of Algorithm 1 and the convergence decision live on the device
+// and are relayed from kernel to kernel (reduce.hpp): once a solve is done,
+// every further iteration kernel returns immediately.  The host enqueues
+// iterations in chunks, ends a chunk with a decide kernel and reads one small
+// pinned state block per simulation, sizing the first chunk of a step from
+// the previous step's iteration count.
+//
+// The engine advances every simulation it holds in lockstep, one step per
+// epoch, with batched launches (batch.hpp): one launch of each kernel serves
+// all simulations, each block working for one of them.  A single run is the
+// batch of one.  Between epochs, finished simulations leave the batch.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "batch.hpp"
+#include "runtime.hpp"
+
+namespace femheat {
+namespace {
+
+double schedule_value(const fem_heat* h, int64_t m) {
+  if (h->sched.empty()) return 1.0;
+  if (m < 1 || m > (int64_t)h->sched.size()) return 0.0;
+  return h->sched[(size_t)(m - 1)];
+}
+
+// Residual replacements among iterations 0..j-1 of a solve (i mod R == 0).
+int replacements_before(int j, int R) { return (R <= 0 || j <= 0) ? 0 : (j - 1) / R + 1; }
+
+// Host state of one simulation of the engine.
+struct Sim {
+  RunRequest rq{};
+  int status = FEM_OK;
+  bool finished = false;
+  int32_t step = 0;   // steps completed
+  int32_t first = 0;  // global index of the step before the run's first step
+  double* T1 = nullptr;
+  double* T2 = nullptr;
+  double* X[2] = {nullptr, nullptr};
+  int32_t nsens = 0;
+  std::vector<int32_t> iters, sweeps;
+  std::vector<double> relres;
+  int64_t total = 0;
+  int est = 8;
+  // within the current step
+  int32_t it = 0, nsw = 0, xc = 0, exc = 0;
+  bool sweeping = false, broke = false;
+  Scalars so{}, si{};  // latest settled outer and inner state
+};
+
+// A set of simulations launched together: one kernel per gather for the
+// cubic and one for the general-element members.
+struct Group {
+  bool cubic = true;
+  uint32_t off = 0, nwork = 0, nthreads = 64;
+  size_t smem64 = 0, smem32 = 0;
+};
+
+class Engine {
+ public:
+  Engine(hipStream_t stream, const fem_opts& o, fem_heat* err) : stream_(stream), opts_(o), h_(err) {
+    mixed_ = o.precision == FEM_FP32_FP64DOT;
+    timing_ = (o.flags & FEM_TIMING) != 0;
+    R_ = o.replace_every;
+  }
+  ~Engine() {
+    (void)hipStreamSynchronize(stream_);
+    dfree(sd_dev_);
+    dfree(snap_dev_);
+    dfree(tab_dev_);
+    for (auto& p : sd_host_)
+      if (p) (void)hipHostFree(p);
+    if (snap_host_) (void)hipHostFree(snap_host_);
+    if (tab_host_) (void)hipHostFree(tab_host_);
+    for (auto e : ev_) (void)hipEventDestroy(e);
+    for (auto e : ev_run_)
+      if (e) (void)hipEventDestroy(e);
+  }
+
+  int add(const RunRequest& r);
+  int run();
+  std::vector<Sim>& sims() { return sims_; }
+  fem_stats stats{};
+
+ private:
+  int compose();
+  int upload_simdev();
+  void fill_simdev(const Sim& s, SimDev& d) const;
+  BatchArgs args(int cur, int prev, int j, int xpar) const {
+    return BatchArgs{sd_dev_, nullptr, snap_dev_, cur, prev, j, xpar, 0};
+  }
+  template <class Role>
+  int gather(BatchArgs a);
+  template <typename V>
+  int update(BatchArgs a);
+  int decide(bool inner);
+  template <typename V>
+  int pcg(int first_chunk);
+  int epoch();
+  int mixed_sweeps();
+  int finish_step(Sim& s);
+  int write_outputs(Sim& s, float ms);
+  int ensure_events(size_t n);
+
+  hipStream_t stream_;
+  fem_opts opts_;
+  fem_heat* h_;  // receives error messages
+  bool mixed_ = false, timing_ = false;
+  int R_ = 50;
+
+  std::vector<Sim> sims_;
+  std::vector<int> act_;  // simulations of the current epoch, in SimDev order
+  bool multi_ = false;    // more than one simulation: launches go through work tables
+
+  SimDev* sd_dev_ = nullptr;
+  SimDev* sd_host_[2] = {nullptr, nullptr};  // pinned staging, used alternately
+  int sd_flip_ = 0;
+  size_t sd_cap_ = 0;
+  Scalars* snap_dev_ = nullptr;
+  Scalars* snap_host_ = nullptr;
+  size_t snap_cap_ = 0;
+  uint2* tab_dev_ = nullptr;
+  uint2* tab_host_ = nullptr;
+  size_t tab_cap_ = 0;
+
+  Group groups_[2];
+  int ngroups_ = 0;
+  uint32_t off_upd64_ = 0, n_upd64_ = 0, off_upd32_ = 0, n_upd32_ = 0, off_start_ = 0, n_start_ = 0;
+
+  // relay parity and the kind of partials the next kernel reads, per relay
+  int ocur_ = 0, oprev_ = PK_GATHER, icur_ = 0, iprev_ = PK_GATHER;
+
+  std::vector<hipEvent_t> ev_;
+  hipEvent_t ev_run_[2] = {nullptr, nullptr};
+};
+
+int Engine::ensure_events(size_t n) {
+  fem_heat* h = h_;
+  while (ev_.size() < n) {
+    hipEvent_t e;
+    HIP_TRY(hipEventCreate(&e));
+    ev_.push_back(e);
+  }
+  return FEM_OK;
+}
+
+// Set-up of one simulation: operator for its theta*dt, fields, sensors.
+int Engine::add(const RunRequest& r) {
+  fem_heat* h = r.h;
+  Sim s;
+  s.rq = r;
+  const uint32_t N = h->g.N;
+  RC_TRY(prepare_operator(h, r.theta * r.dt, mixed_));
+  s.T1 = h->pool[0];
+  s.T2 = h->pool[1];
+  s.X[0] = h->pool[2];
+  s.X[1] = h->pool[3];
+  RC_TRY(copy_in(h, s.T1, r.T0, N));
+  RC_TRY(copy_in(h, s.T2, r.T_prev ? r.T_prev : r.T0, N));
+  hipLaunchKernelGGL((apply_dirichlet_kernel<double>), dim3(nblk(N)), dim3(kT), 0, stream_, h->g, s.T1);
+  hipLaunchKernelGGL((apply_dirichlet_kernel<double>), dim3(nblk(N)), dim3(kT), 0, stream_, h->g, s.T2);
+  // the first direction of every solve has beta = 0, but 0 * d must be 0
+  for (int k = 0; k < 2; ++k)
+    hipLaunchKernelGGL((fill_kernel<double>), dim3(nblk(N)), dim3(kT), 0, stream_, h->d64[k], 0.0, N);
+  if (mixed_)
+    for (int k = 0; k < 2; ++k)
+      hipLaunchKernelGGL((fill_kernel<float>), dim3(nblk(N)), dim3(kT), 0, stream_, h->d32[k], 0.0f, N);
+  HIP_TRY(hipGetLastError());
+  const fem_out* o = r.out;
+  s.first = o ? o->first_step : 0;
+  s.nsens = (o && o->sensor_xyz && o->n_sensors > 0) ? o->n_sensors : 0;
+  if (s.nsens > 0) {
+    if (h->xyz_cap < (size_t)s.nsens) {
+      dfree(h->xyz_dev);
+      RC_TRY(dalloc(h, &h->xyz_dev, 3 * (size_t)s.nsens));
+      h->xyz_cap = s.nsens;
+    }
+    RC_TRY(copy_in(h, h->xyz_dev, o->sensor_xyz, 3 * (size_t)s.nsens));
+    const size_t need = (size_t)std::max(r.nsteps, 1) * s.nsens;
+    if (h->traces_cap < need) {
+      dfree(h->traces_dev);
+      RC_TRY(dalloc(h, &h->traces_dev, need));
+      h->traces_cap = need;
+    }
+  }
+  const size_t ns = (size_t)std::max(r.nsteps, 0);
+  s.iters.assign(ns, 0);
+  s.sweeps.assign(ns, 0);
+  s.relres.assign(ns, 0.0);
+  s.finished = r.nsteps <= 0;
+  sims_.push_back(std::move(s));
+  return FEM_OK;
+}
+
+void Engine::fill_simdev(const Sim& s, SimDev& d) const {
+  const fem_heat* h = s.rq.h;
+  const double dt = s.rq.dt, theta = s.rq.theta;
+  std::memset(&d, 0, sizeof(d));
+  d.A64 = gather_args<double>(h, 1.0, theta * dt);
+  d.L64 = gather_args<double>(h, 1.0, -(1.0 - theta) * dt);
+  if (mixed_) d.A32 = gather_args<float>(h, 1.0, theta * dt);
+  d.F64 = h->F64;
+  d.pinv64 = h->pinv64;
+  d.lift64 = h->lift64;
+  d.b64 = h->b64;
+  d.r64 = h->r64;
+  d.q64 = h->q64;
+  d.d64[0] = h->d64[0];
+  d.d64[1] = h->d64[1];
+  d.T1 = s.T1;
+  d.T2 = s.T2;
+  d.X[0] = s.X[0];
+  d.X[1] = s.X[1];
+  d.pinv32 = h->pinv32;
+  d.r32 = h->r32;
+  d.q32 = h->q32;
+  d.d32[0] = h->d32[0];
+  d.d32[1] = h->d32[1];
+  d.e32[0] = h->e32[0];
+  d.e32[1] = h->e32[1];
+  d.rhs32 = h->rhs32;
+  for (int k = 0; k < 2; ++k) {
+    d.oS[k] = h->outer.S[k];
+    d.oP[k] = h->outer.P[k];
+    d.iS[k] = h->inner.S[k];
+    d.iP[k] = h->inner.P[k];
+  }
+  d.octl = Ctl{s.rq.rtol * s.rq.rtol, opts_.max_iter, opts_.stop_rule};
+  double irt = opts_.inner_rtol;
+  if (s.sweeping) {
+    // Inner tolerance: half the reduction the FP64 stop rule still needs,
+    // never tighter than inner_rtol (FP32 arithmetic bounds what the inner
+    // solve can reach); one sweep then usually suffices.
+    const double ref = opts_.stop_rule == FEM_STOP_INITIAL ? s.so.delta0 : s.so.delta_b;
+    const double need = s.so.delta > 0 ? 0.5 * std::sqrt(d.octl.rtol2 * ref / s.so.delta) : 1.0;
+    irt = std::min(0.5, std::max(opts_.inner_rtol, need));
+  }
+  d.ictl = Ctl{irt * irt, opts_.max_iter, FEM_STOP_INITIAL};
+  d.N = h->g.N;
+  d.nblk[PK_GATHER] = h->shape.nblocks;
+  d.nblk[PK_UPD64] = h->upd_blocks64;
+  d.nblk[PK_UPD32] = h->upd_blocks32;
+  d.nblk[PK_START] = h->start_blocks;
+  d.fs = dt * schedule_value(h, (int64_t)s.first + s.step + 1);
+  d.guess_prev = opts_.guess == FEM_GUESS_PREV ? 1 : 0;
+  d.xc = s.xc;
+  d.exc = s.exc;
+  d.sweep = s.sweeping ? 1 : 0;
+}
+
+// Copies the SimDev array of the current epoch to the device.  Callers only
+// do so after the stream has been synchronised since the previous copy, so
+// the staging buffer being written is never still in use.
+int Engine::upload_simdev() {
+  fem_heat* h = h_;
+  SimDev* stage = sd_host_[sd_flip_];
+  sd_flip_ ^= 1;
+  for (size_t k = 0; k < act_.size(); ++k) fill_simdev(sims_[act_[k]], stage[k]);
+  HIP_TRY(hipMemcpyAsync(sd_dev_, stage, act_.size() * sizeof(SimDev), hipMemcpyHostToDevice, stream_));
+  return FEM_OK;
+}
+
+// The simulations that still have steps to run form the next epoch's batch;
+// rebuilds the launch groups and work tables when that set changed.
+int Engine::compose() {
+  fem_heat* h = h_;
+  std::vector<int> next;
+  for (size_t i = 0; i < sims_.size(); ++i)
+    if (!sims_[i].finished) next.push_back((int)i);
+  if (next == act_ && ngroups_ > 0) return FEM_OK;
+  HIP_TRY(hipStreamSynchronize(stream_));  // buffers below may be freed or rewritten
+  act_ = next;
+  const size_t n = act_.size();
+  if (n == 0) return FEM_OK;
+  multi_ = n > 1;
+  if (sd_cap_ < n) {
+    dfree(sd_dev_);
+    for (auto& p : sd_host_)
+      if (p) (void)hipHostFree(p);
+    sd_host_[0] = sd_host_[1] = nullptr;
+    RC_TRY(dalloc(h, &sd_dev_, n));
+    for (auto& p : sd_host_) HIP_TRY(hipHostMalloc(reinterpret_cast<void**>(&p), n * sizeof(SimDev), hipHostMallocDefault));
+    sd_cap_ = n;
+  }
+  if (snap_cap_ < n) {
+    dfree(snap_dev_);
+    if (snap_host_) (void)hipHostFree(snap_host_);
+    snap_host_ = nullptr;
+    RC_TRY(dalloc(h, &snap_dev_, n));
+    HIP_TRY(hipHostMalloc(reinterpret_cast<void**>(&snap_host_), n * sizeof(Scalars), hipHostMallocDefault));
+    snap_cap_ = n;
+  }
+  // launch groups by element class, each with its work table
+  ngroups_ = 0;
+  std::vector<uint2> tab;
+  for (int cls = 0; cls < 2; ++cls) {
+    Group g;
+    g.cubic = cls == 0;
+    g.off = (uint32_t)tab.size();
+    for (size_t k = 0; k < n; ++k) {
+      const fem_heat* sh = sims_[act_[k]].rq.h;
+      if (sh->cubic != g.cubic) continue;
+      for (uint32_t b = 0; b < sh->shape.nblocks; ++b) tab.push_back(make_uint2((uint32_t)k, b));
+      g.nthreads = std::max<uint32_t>(g.nthreads, (uint32_t)sh->shape.nthreads);
+      g.smem64 = std::max(g.smem64, sh->shape.smem_bytes(8));
+      g.smem32 = std::max(g.smem32, sh->shape.smem_bytes(4));
+    }
+    g.nwork = (uint32_t)tab.size() - g.off;
+    if (g.nwork > 0) groups_[ngroups_++] = g;
+  }
+  auto add_kind = [&](uint32_t fem_heat::*count, uint32_t& off, uint32_t& total) {
+    off = (uint32_t)tab.size();
+    for (size_t k = 0; k < n; ++k) {
+      const fem_heat* sh = sims_[act_[k]].rq.h;
+      for (uint32_t b = 0; b < sh->*count; ++b) tab.push_back(make_uint2((uint32_t)k, b));
+    }
+    total = (uint32_t)tab.size() - off;
+  };
+  add_kind(&fem_heat::upd_blocks64, off_upd64_, n_upd64_);
+  add_kind(&fem_heat::upd_blocks32, off_upd32_, n_upd32_);
+  add_kind(&fem_heat::start_blocks, off_start_, n_start_);
+  if (multi_) {
+    if (tab_cap_ < tab.size()) {
+      dfree(tab_dev_);
+      if (tab_host_) (void)hipHostFree(tab_host_);
+      tab_host_ = nullptr;
+      RC_TRY(dalloc(h, &tab_dev_, tab.size()));
+      HIP_TRY(hipHostMalloc(reinterpret_cast<void**>(&tab_host_), tab.size() * sizeof(uint2), hipHostMallocDefault));
+      tab_cap_ = tab.size();
+    }
+    std::memcpy(tab_host_, tab.data(), tab.size() * sizeof(uint2));
+    HIP_TRY(hipMemcpyAsync(tab_dev_, tab_host_, tab.size() * sizeof(uint2), hipMemcpyHostToDevice, stream_));
+  }
+  return FEM_OK;
+}
+
+template <class Role>
+int Engine::gather(BatchArgs a) {
+  fem_heat* h = h_;
+  for (int gi = 0; gi < ngroups_; ++gi) {
+    const Group& g = groups_[gi];
+    a.table = multi_ ? tab_dev_ + g.off : nullptr;
+    const size_t smem = sizeof(typename Role::V) == 8 ? g.smem64 : g.smem32;
+    if (g.cubic)
+      hipLaunchKernelGGL((gather_batch_kernel<true, Role>), dim3(g.nwork), dim3(g.nthreads), smem, stream_, a);
+    else
+      hipLaunchKernelGGL((gather_batch_kernel<false, Role>), dim3(g.nwork), dim3(g.nthreads), smem, stream_, a);
+  }
+  HIP_TRY(hipGetLastError());
+  return FEM_OK;
+}
+
+template <typename V>
+int Engine::update(BatchArgs a) {
+  fem_heat* h = h_;
+  const bool f64 = sizeof(V) == 8;
+  a.table = multi_ ? tab_dev_ + (f64 ? off_upd64_ : off_upd32_) : nullptr;
+  hipLaunchKernelGGL((update_batch_kernel<V>), dim3(f64 ? n_upd64_ : n_upd32_), dim3(kT), 0, stream_, a);
+  HIP_TRY(hipGetLastError());
+  return FEM_OK;
+}
+
+// Settles the pending decision of every simulation of a relay and reads the
+// settled states into snap_host_ (synchronises the stream).
+int Engine::decide(bool inner) {
+  fem_heat* h = h_;
+  int& cur = inner ? icur_ : ocur_;
+  int& prev = inner ? iprev_ : oprev_;
+  BatchArgs a = args(cur, prev, 0, 0);
+  a.inner = inner ? 1 : 0;
+  hipLaunchKernelGGL(decide_batch_kernel, dim3((uint32_t)act_.size()), dim3(64), 0, stream_, a);
+  HIP_TRY(hipGetLastError());
+  cur ^= 1;
+  HIP_TRY(hipMemcpyAsync(snap_host_, snap_dev_, act_.size() * sizeof(Scalars), hipMemcpyDeviceToHost, stream_));
+  HIP_TRY(hipStreamSynchronize(stream_));
+  return FEM_OK;
+}
+
+// Iterations of Algorithm 1 for every simulation of the batch until all are
+// done (FP64 outer solve, or FP32 inner solves of the mixed form).
+template <typename V>
+int Engine::pcg(int first_chunk) {
+  fem_heat* h = h_;
+  constexpr bool inner = sizeof(V) == 4;
+  int& cur = inner ? icur_ : ocur_;
+  int& prev = inner ? iprev_ : oprev_;
+  const int upd_kind = inner ? PK_UPD32 : PK_UPD64;
+  int j = 0;
+  int k = std::max(1, first_chunk);
+  for (;;) {
+    if (timing_) RC_TRY(ensure_events(3 * (size_t)k));
+    for (int c = 0; c < k; ++c) {
+      const int jj = j + c;
+      if (timing_) HIP_TRY(hipEventRecord(ev_[3 * c], stream_));
+      RC_TRY(gather<RoleDir<V>>(args(cur, prev, jj, 0)));
+      cur ^= 1;
+      prev = PK_GATHER;
+      if (timing_) HIP_TRY(hipEventRecord(ev_[3 * c + 1], stream_));
+      const int xpar = replacements_before(jj, R_) & 1;
+      if (R_ > 0 && jj % R_ == 0) {
+        RC_TRY(gather<RoleRepl<V>>(args(cur, prev, jj, xpar)));
+        prev = PK_GATHER;
+      } else {
+        RC_TRY(update<V>(args(cur, prev, jj, xpar)));
+        prev = upd_kind;
+      }
+      cur ^= 1;
+      if (timing_) HIP_TRY(hipEventRecord(ev_[3 * c + 2], stream_));
+    }
+    RC_TRY(decide(inner));
+    bool all_done = true;
+    int most = j;
+    for (size_t q = 0; q < act_.size(); ++q) {
+      Sim& s = sims_[act_[q]];
+      const Scalars& t = snap_host_[q];
+      (inner ? s.si : s.so) = t;
+      if (!t.done) all_done = false;
+      most = std::max(most, (int)t.iter);
+    }
+    if (timing_) {
+      const int ran = std::max(0, std::min(most - j, k));
+      for (int c = 0; c < ran; ++c) {
+        float g_ms = 0.f, u_ms = 0.f;
+        HIP_TRY(hipEventElapsedTime(&g_ms, ev_[3 * c], ev_[3 * c + 1]));
+        HIP_TRY(hipEventElapsedTime(&u_ms, ev_[3 * c + 1], ev_[3 * c + 2]));
+        stats.gather_launches += 1;
+        stats.gather_ms += g_ms;
+        if (R_ > 0 && (j + c) % R_ == 0) {
+          stats.replace_launches += 1;
+          stats.replace_ms += u_ms;
+        } else {
+          stats.update_launches += 1;
+          stats.update_ms += u_ms;
+        }
+      }
+    }
+    j += k;
+    if (all_done) break;
+    k = 4;
+  }
+  return FEM_OK;
+}
+
+// Refinement sweeps of the mixed form: FP32 inner PCG on A e = r64 (FP64 dot
+// products and scalars), then x64 += e and the FP64 residual, repeated until
+// the FP64 stop rule holds or max_refine sweeps are spent.
+int Engine::mixed_sweeps() {
+  fem_heat* h = h_;
+  RC_TRY(decide(false));
+  for (size_t q = 0; q < act_.size(); ++q) {
+    Sim& s = sims_[act_[q]];
+    s.so = snap_host_[q];
+    if (s.so.status != 0) s.broke = true;
+  }
+  for (;;) {
+    bool any = false;
+    int est = 1;
+    for (int i : act_) {
+      Sim& s = sims_[i];
+      s.sweeping = !s.broke && !s.so.done && s.nsw < opts_.max_refine;
+      if (s.sweeping) {
+        any = true;
+        est = std::max(est, s.nsw == 0 ? s.est : std::max(1, s.est / 4));
+      }
+    }
+    if (!any) break;
+    RC_TRY(upload_simdev());
+    BatchArgs a = args(icur_, iprev_, 0, 0);
+    a.table = multi_ ? tab_dev_ + off_start_ : nullptr;
+    hipLaunchKernelGGL(inner_start_batch_kernel, dim3(n_start_), dim3(kT), 0, stream_, a);
+    HIP_TRY(hipGetLastError());
+    icur_ ^= 1;
+    iprev_ = PK_START;
+    RC_TRY(pcg<float>(est));
+    for (int i : act_) {
+      Sim& s = sims_[i];
+      if (!s.sweeping) continue;
+      if (s.si.status != 0) {
+        s.broke = true;
+        s.sweeping = false;  // no correction from a broken inner solve
+        continue;
+      }
+      s.it += s.si.iter;
+      s.exc = replacements_before(s.si.iter, R_) & 1;
+    }
+    RC_TRY(upload_simdev());
+    RC_TRY(gather<RoleCorr>(args(ocur_, oprev_, 0, 0)));
+    ocur_ ^= 1;
+    oprev_ = PK_GATHER;
+    for (int i : act_) {
+      Sim& s = sims_[i];
+      if (!s.sweeping) continue;
+      s.xc ^= 1;
+      s.nsw += 1;
+    }
+    RC_TRY(decide(false));
+    for (size_t q = 0; q < act_.size(); ++q) {
+      Sim& s = sims_[act_[q]];
+      s.so = snap_host_[q];
+      if (s.so.status != 0) s.broke = true;
+    }
+  }
+  for (int i : act_) sims_[i].sweeping = false;
+  return FEM_OK;
+}
+
+// One theta-scheme step of every simulation of the batch.
+int Engine::epoch() {
+  for (int i : act_) {
+    Sim& s = sims_[i];
+    s.it = s.nsw = s.xc = s.exc = 0;
+    s.sweeping = s.broke = false;
+  }
+  RC_TRY(upload_simdev());
+  RC_TRY(gather<RoleRhs>(args(ocur_, oprev_, 0, 0)));
+  ocur_ ^= 1;
+  oprev_ = PK_GATHER;
+  RC_TRY(gather<RoleInit>(args(ocur_, oprev_, 0, 0)));
+  ocur_ ^= 1;
+  oprev_ = PK_GATHER;
+  if (mixed_) {
+    RC_TRY(mixed_sweeps());
+  } else {
+    int est = 1;
+    for (int i : act_) est = std::max(est, sims_[i].est);
+    RC_TRY(pcg<double>(est));
+    for (int i : act_) {
+      Sim& s = sims_[i];
+      s.it = s.so.iter;
+      if (s.so.status != 0) s.broke = true;
+      s.xc = replacements_before(s.it, R_) & 1;
+    }
+  }
+  for (int i : act_) RC_TRY(finish_step(sims_[i]));
+  return FEM_OK;
+}
+
+// Records a finished step of one simulation and rotates its fields.
+int Engine::finish_step(Sim& s) {
+  fem_heat* h = s.rq.h;
+  if (s.broke) {  // outputs stop at the last good step
+    if (s.status == FEM_OK || s.status == FEM_ENOCONV) s.status = FEM_EBREAKDOWN;
+    h->err = "PCG breakdown (d^T A d <= 0 or non-finite scalar)";
+    s.finished = true;
+    return FEM_OK;
+  }
+  const uint32_t N = h->g.N;
+  const int n = s.step + 1;
+  const Scalars& so = s.so;
+  s.iters[n - 1] = s.it;
+  s.sweeps[n - 1] = s.nsw;
+  s.relres[n - 1] = so.delta_b > 0 ? std::sqrt(std::max(so.delta, 0.0) / so.delta_b) : 0.0;
+  const bool unconverged = mixed_ ? (so.delta > so.tol) : (s.it >= opts_.max_iter && so.delta > so.tol);
+  if (unconverged && s.status == FEM_OK) s.status = FEM_ENOCONV;
+  s.total += s.it;
+  s.est = std::max(1, s.it);
+  double* xnew = s.X[s.xc];
+  if (s.nsens > 0) {
+    hipLaunchKernelGGL(sensor_kernel, dim3((s.nsens + 63) / 64), dim3(64), 0, stream_, h->g, xnew, h->xyz_dev,
+                       s.nsens, h->traces_dev + (size_t)(n - 1) * s.nsens);
+    HIP_TRY(hipGetLastError());
+  }
+  const fem_out* o = s.rq.out;
+  if (o && o->T_saved && o->save_every > 0 && n % o->save_every == 0)
+    RC_TRY(copy_out(h, o->T_saved + (size_t)(n / o->save_every - 1) * N, xnew, (size_t)N * sizeof(double)));
+  double* freed = s.T2;
+  double* spare = s.X[s.xc ^ 1];
+  s.T2 = s.T1;
+  s.T1 = xnew;
+  s.X[0] = freed;
+  s.X[1] = spare;
+  s.step = n;
+  if (s.step >= s.rq.nsteps) s.finished = true;
+  return FEM_OK;
+}
+
+int Engine::write_outputs(Sim& s, float ms) {
+  fem_heat* h = s.rq.h;
+  fem_out* o = s.rq.out;
+  if (!o) return FEM_OK;
+  const uint32_t N = h->g.N;
+  o->device_ms = ms;
+  o->total_iters = s.total;
+  if (o->T_final) RC_TRY(copy_out(h, o->T_final, s.T1, (size_t)N * sizeof(double)));
+  if (s.nsens > 0 && o->traces)
+    RC_TRY(copy_out(h, o->traces, h->traces_dev, (size_t)std::max(s.rq.nsteps, 0) * s.nsens * sizeof(double)));
+  auto put = [&](void* dst, const void* src, size_t bytes) -> int {
+    if (!dst || bytes == 0) return FEM_OK;
+    if (h->devptrs) {
+      HIP_TRY(hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, stream_));
+      HIP_TRY(hipStreamSynchronize(stream_));  // src is host memory that goes away
+    } else {
+      std::memcpy(dst, src, bytes);
+    }
+    return FEM_OK;
+  };
+  RC_TRY(put(o->iters, s.iters.data(), s.iters.size() * sizeof(int32_t)));
+  RC_TRY(put(o->relres, s.relres.data(), s.relres.size() * sizeof(double)));
+  RC_TRY(put(o->refine_sweeps, s.sweeps.data(), s.sweeps.size() * sizeof(int32_t)));
+  return FEM_OK;
+}
+
+int Engine::run() {
+  fem_heat* h = h_;
+  for (auto& e : ev_run_) HIP_TRY(hipEventCreate(&e));
+  HIP_TRY(hipEventRecord(ev_run_[0], stream_));
+  for (;;) {
+    RC_TRY(compose());
+    if (act_.empty()) break;
+    RC_TRY(epoch());
+  }
+  HIP_TRY(hipEventRecord(ev_run_[1], stream_));
+  HIP_TRY(hipEventSynchronize(ev_run_[1]));
+  float ms = 0.f;
+  HIP_TRY(hipEventElapsedTime(&ms, ev_run_[0], ev_run_[1]));
+  for (auto& s : sims_) RC_TRY(write_outputs(s, ms));
+  HIP_TRY(hipStreamSynchronize(stream_));
+  return FEM_OK;
+}
+
+}  // namespace
+
+int solver_run(fem_heat* h, const double* T0, const double* T_prev, double dt, double theta, int32_t nsteps,
+               double rtol, fem_out* out) {
+  HIP_TRY(hipSetDevice(h->opts.device));
+  RunRequest r{h, T0, T_prev, dt, theta, rtol, nsteps, out};
+  int32_t st = FEM_OK;
+  std::string err;
+  RC_TRY(engine_run(&r, 1, h->stream, h->opts, &st, &err));
+  return st;
+}
+
+int engine_run(const RunRequest* reqs, int32_t n, hipStream_t stream, const fem_opts& opts, int32_t* status,
+               std::string* err) {
+  fem_heat* h = n == 1 ? reqs[0].h : nullptr;
+  fem_heat scratch;
+  if (!h) h = &scratch;
+  Engine e(stream, opts, h);
+  for (int32_t i = 0; i < n; ++i) {
+    const int rc = e.add(reqs[i]);
+    if (rc != FEM_OK) {
+      if (err) *err = reqs[i].h->err;
+      return rc;
+    }
+  }
+  const int rc = e.run();
+  if (rc != FEM_OK) {
+    if (err) *err = h->err;
+    return rc;
+  }
+  for (int32_t i = 0; i < n; ++i) status[i] = e.sims()[i].status;
+  if (n == 1 && (opts.flags & FEM_TIMING)) {
+    fem_heat* one = reqs[0].h;
+    const fem_stats keep = one->stats;
+    one->stats = e.stats;
+    one->stats.grid_blocks = keep.grid_blocks;
+    one->stats.tile_x = keep.tile_x;
+    one->stats.tile_y = keep.tile_y;
+    one->stats.tile_z = keep.tile_z;
+  }
+  return FEM_OK;
+}
+
+}  // namespace femheat

@@ -76,10 +76,22 @@ __device__ inline void read_plane(const V* P, int pw, int lx, int ly, PlaneQ<V>&
 // tile (and of a coefficient tile); the launch guarantees both tiles fit.
 constexpr int kSlots = 2;
 
+// XCD-aware tile order: blocks are dispatched round-robin over the 8 XCDs,
+// so block b runs on XCD b%8.  Work item (b%8)*share + b/8 gives every XCD a
+// contiguous range of tiles with z fastest, so the z-halo planes that
+// neighbouring chunks share are reused from the same L2.  `nblocks` is a
+// multiple of 8.
+__device__ inline uint32_t xcd_work_item(uint32_t b, uint32_t nblocks) {
+  return (b & 7u) * (nblocks >> 3) + (b >> 3);
+}
+
+// One block's share of a gather: tile `logical` of the solve that `ga`, the
+// functors and the relay describe.  The block's dot-product partial is
+// stored at index `logical`, and tile 0 publishes the relayed state.
 template <typename V, bool CUBIC, class Pro, class Epi>
-__global__ void __launch_bounds__(256) gather_kernel(GatherArgs<V> ga, Pro pro, Epi epi, Relay R) {
+__device__ inline void gather_tile(const GatherArgs<V>& ga, Pro pro, Epi epi, const Relay& R, uint32_t logical) {
   Scalars st;
-  if (!stage_entry(R, st)) return;  // uniform: the solve is done (or broke down)
+  if (!stage_entry(R, st, logical == 0)) return;  // uniform: the solve is done (or broke down)
   pro.init(st);
   epi.init(st);
 
@@ -95,12 +107,6 @@ __global__ void __launch_bounds__(256) gather_kernel(GatherArgs<V> ga, Pro pro, 
   const int nx = ga.g.nx, ny = ga.g.ny, nz = ga.g.nz;
   const uint32_t pstride = (uint32_t)px * (uint32_t)py, lstride = (uint32_t)nx * (uint32_t)ny;
 
-  // XCD-aware tile order: blocks are dispatched round-robin over the 8 XCDs,
-  // so block b runs on XCD b%8.  Logical tile = (b%8)*share + b/8 gives every
-  // XCD a contiguous range of tiles with z fastest, so the z-halo planes that
-  // neighbouring chunks share are reused from the same L2.
-  const uint32_t share = ga.s.nblocks >> 3;
-  const uint32_t logical = (blockIdx.x & 7u) * share + (blockIdx.x >> 3);
   const bool idle = logical >= ga.s.ntiles;
   double dot = 0.0;
 
@@ -257,7 +263,13 @@ __global__ void __launch_bounds__(256) gather_kernel(GatherArgs<V> ga, Pro pro, 
     }
     if (l < z1) layer(l, 0, SB, yes{});
   }
-  if (R.pout) publish_partial(R, dot);
+  if (R.pout) publish_partial(R, dot, logical);
+}
+
+// A gather of one solve: one block per tile (grid = ga.s.nblocks).
+template <typename V, bool CUBIC, class Pro, class Epi>
+__global__ void __launch_bounds__(256) gather_kernel(GatherArgs<V> ga, Pro pro, Epi epi, Relay R) {
+  gather_tile<V, CUBIC>(ga, pro, epi, R, xcd_work_item(blockIdx.x, ga.s.nblocks));
 }
 
 // ---------------------------------------------------------------------------

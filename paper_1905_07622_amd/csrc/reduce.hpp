@@ -8,8 +8,13 @@
 //    bit-identical value), evaluates the pending scalar update of Algorithm 1
 //    (alpha, or delta/beta and the stop test) and broadcasts it to the block;
 //  * the solve state is relayed through a ping-pong pair of Scalars: a kernel
-//    reads Sin and its block 0 writes the updated state to Sout, so no block
-//    ever reads a value another block of the same kernel writes.
+//    reads Sin and one block of the solve (its tile 0) writes the updated
+//    state to Sout, so no block ever reads a value another block of the same
+//    kernel writes.
+// A kernel may serve many independent solves at once (batched launches):
+// each block belongs to one solve and sees only that solve's Relay, and the
+// partial of a block is stored at its index within its solve, so a solve's
+// reductions do not depend on what else shares the launch.
 // Kernel boundaries order everything (stream order makes a kernel's writes
 // visible to the next one on every XCD), which is why no atomics are needed.
 // Once a solve is done, every further iteration kernel copies the state and
@@ -118,9 +123,9 @@ __device__ inline void evaluate_pending(Scalars& s, double x, const Ctl& c) {
 }
 
 // Entry of every relayed kernel: evaluates the state this kernel works with,
-// has block 0 publish it to Sout, and returns whether the kernel has work.
-// Called by all threads of the block.
-__device__ inline bool stage_entry(const Relay& R, Scalars& out) {
+// has the writer block of the solve publish it to Sout, and returns whether
+// the kernel has work.  Called by all threads of the block.
+__device__ inline bool stage_entry(const Relay& R, Scalars& out, bool writer) {
   __shared__ Scalars sh;
   __shared__ int go;
   __shared__ double red4[4];
@@ -178,29 +183,34 @@ __device__ inline bool stage_entry(const Relay& R, Scalars& out) {
         t.phase = PH_AFTER_CHECK;
         g = t.done ? 0 : 1;
         break;
+      case M_SKIP:
+        g = 0;
+        break;
+      case M_IDLE:  // settled: done with zero iterations, nothing pending
+        t.done = 1;
+        t.status = 0;
+        t.iter = 0;
+        t.phase = PH_DECIDED;
+        g = 0;
+        break;
       default:  // M_NONE
         break;
     }
     sh = t;
     go = g;
-    if (blockIdx.x == 0 && R.sout) *R.sout = t;
+    if (writer && R.sout) *R.sout = t;
   }
   __syncthreads();
   out = sh;
   return go != 0;
 }
 
-// One partial per block for the next kernel.
-__device__ inline void publish_partial(const Relay& R, double v) {
+// One partial per block for the next kernel, at the block's index `slot`
+// within its solve.
+__device__ inline void publish_partial(const Relay& R, double v, uint32_t slot) {
   __shared__ double wsum[16];
   const double bs = block_sum(v, wsum);
-  if (threadIdx.x == 0 && R.pout) R.pout[blockIdx.x] = bs;
-}
-
-// A kernel that only settles the pending decision (end of an iteration chunk).
-__global__ void decide_kernel(Relay R) {
-  Scalars s;
-  (void)stage_entry(R, s);
+  if (threadIdx.x == 0 && R.pout) R.pout[slot] = bs;
 }
 
 }  // namespace femheat

@@ -1,85 +1,19 @@
-// Host runtime of the assembly-free theta-scheme heat solver on gfx950.
+// Set-up, operator test hook and teardown of a solver handle (gfx950).
 //
-// One handle keeps the whole problem resident in HBM: coefficients, load
-// vector, Jacobi preconditioner, the two previous fields and the PCG vectors.
-// A run enqueues, per time step (Sec. 3.1): the right-hand side b = L T + dt*s*F
-// (gather with the RHS epilogue), the initial guess and residual (gather with
-// the guess prologue and residual epilogue), then the iterations of
-// Algorithm 1, two kernels each: the search-direction update fused into the
-// operator apply (q = A d, d^T q -> alpha on the device) and the fused x/r
-// update with the preconditioned residual norm (delta, beta and the
-// convergence test on the device).  Every 50th iteration (i mod 50 == 0, as
-// printed) the update is replaced by a gather computing r = b - A x.
-//
-// The paper's host read the residual back every iteration (App. A.3).  Here
-// the scalars of Algorithm 1 and the convergence decision live on the device
-// and are relayed from kernel to kernel (reduce.hpp): once a solve is done
-// every further iteration kernel returns immediately, so the host enqueues
-// iterations in chunks, ends a chunk with a one-block decide kernel and reads
-// a small pinned scalar block once per chunk, sizing the first chunk of a
-// step from the previous step's iteration count.
+// One handle keeps a whole problem resident in HBM: coefficients, load
+// vector, Jacobi preconditioner, the previous fields and the PCG vectors.
+// Creating it uploads the coefficients and builds the boundary load vector
+// (Sec. 3.1); the time stepping itself lives in engine.hip, which drives one
+// handle or a batch of them.
 #include <algorithm>
 #include <cmath>
 #include <cstring>
 
-#include "gather.hpp"
-#include "solver.hpp"
+#include "runtime.hpp"
 #include "vector_kernels.hpp"
 
 namespace femheat {
 namespace {
-
-constexpr int kT = 256;  // threads of the 1-D kernels
-
-int fail(fem_heat* h, int code, const std::string& msg) {
-  h->err = msg;
-  return code;
-}
-
-#define HIP_TRY(expr)                                                                     \
-  do {                                                                                    \
-    hipError_t e_ = (expr);                                                               \
-    if (e_ != hipSuccess) {                                                               \
-      (void)hipGetLastError();                                                            \
-      return fail(h, FEM_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(e_));     \
-    }                                                                                     \
-  } while (0)
-
-#define RC_TRY(expr)           \
-  do {                         \
-    int rc_ = (expr);          \
-    if (rc_ != FEM_OK) return rc_; \
-  } while (0)
-
-template <typename T>
-int dalloc(fem_heat* h, T** p, size_t n) {
-  if (hipMalloc(reinterpret_cast<void**>(p), std::max<size_t>(n, 1) * sizeof(T)) != hipSuccess) {
-    (void)hipGetLastError();
-    *p = nullptr;
-    return fail(h, FEM_ENOMEM, "hipMalloc of " + std::to_string(n * sizeof(T)) + " bytes failed");
-  }
-  return FEM_OK;
-}
-
-template <typename T>
-void dfree(T*& p) {
-  if (p) (void)hipFree(p);
-  p = nullptr;
-}
-
-uint32_t nblk(uint32_t n) { return (n + kT - 1) / kT; }
-
-hipMemcpyKind in_kind(const fem_heat* h) { return h->devptrs ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice; }
-hipMemcpyKind out_kind(const fem_heat* h) { return h->devptrs ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost; }
-
-int copy_in(fem_heat* h, double* dst, const double* src, size_t n) {
-  HIP_TRY(hipMemcpyAsync(dst, src, n * sizeof(double), in_kind(h), h->stream));
-  return FEM_OK;
-}
-int copy_out(fem_heat* h, void* dst, const void* src, size_t bytes) {
-  HIP_TRY(hipMemcpyAsync(dst, src, bytes, out_kind(h), h->stream));
-  return FEM_OK;
-}
 
 // LDS row pitch (in values) of a tile of width `width`: the smallest pitch
 // for which the 64 lanes of every wave, split into half-waves of 32 lanes,
@@ -141,11 +75,13 @@ int resident_blocks(bool cubic, bool fp32, int nthreads, size_t smem) {
 
 // Launch shape of the gather: TX spans the x-row of nodes in as few equal
 // pieces of at most 64 as possible, TY fills the block to <= 256 threads.
-// Unless given, TZ splits the columns into as many z-chunks as the chip holds
-// blocks at once (`capacity`): the gather is latency-bound, so the launch
-// should fill every CU to its occupancy limit in a single round -- a second,
-// partial round of blocks costs a whole extra block time -- and longer
-// z-marches pay the start-up of the plane pipeline less often.
+// Unless given, TZ splits the columns of a simulation that has the GPU to
+// itself into as many z-chunks as the chip holds blocks at once
+// (`capacity`): the gather is latency-bound, so the launch should fill every
+// CU to its occupancy limit in a single round -- a second, partial round of
+// blocks costs a whole extra block time -- and longer z-marches pay the
+// start-up of the plane pipeline less often.  capacity <= 0 selects the rule
+// for members of a batch.
 GatherShape choose_shape(const Geom& g, const fem_opts& o, int capacity) {
   GatherShape s{};
   const int px = g.px, py = g.py, pz = g.pz;
@@ -174,6 +110,13 @@ GatherShape choose_shape(const Geom& g, const fem_opts& o, int capacity) {
   int tz;
   if (o.tile_z > 0) {
     tz = o.tile_z;
+  } else if (capacity <= 0) {
+    // a member of a batch: the launch is filled by many simulations, so each
+    // marches chunks of at most 32 planes (balanced); the rule depends on the
+    // simulation's own grid only, which keeps its results independent of
+    // what it shares the launch with
+    const int nchunks = (pz + 31) / 32;
+    tz = (pz + nchunks - 1) / nchunks;
   } else {
     const int cols = s.ntx * s.nty;
     const int ntz_target = std::max(1, capacity / cols);
@@ -217,26 +160,35 @@ void fill_classes(const Geom& g, GatherArgs<V>& ga, double cm, double ck, bool c
   ga.sb = (V)ck;
 }
 
-// Relay arguments of the next kernel of a solve: it reads the state and
-// partials the previous kernel left and writes the other buffer of each pair.
-Relay next_relay(RelayCtx& c, int32_t mode, bool partials, uint32_t grid) {
-  Relay R{c.S[c.cur], c.S[c.cur ^ 1], c.P[c.cur], c.npin, partials ? c.P[c.cur ^ 1] : nullptr, mode, c.ctl};
-  c.cur ^= 1;
-  if (partials) c.npin = grid;
-  return R;
-}
-
 Relay no_relay() { return Relay{nullptr, nullptr, nullptr, 0, nullptr, M_NONE, Ctl{0.0, 0, 0}}; }
 
-template <typename V, class Pro, class Epi>
-int launch_gather(fem_heat* h, const V* rhoc, const V* kc, double cm, double ck, Pro pro, Epi epi, const Relay& R) {
+}  // namespace
+
+template <typename V>
+GatherArgs<V> gather_args(const fem_heat* h, double cm, double ck) {
   GatherArgs<V> ga{};
   ga.g = h->g;
   ga.s = h->shape;
-  ga.rhoc = rhoc;
-  ga.kc = kc;
+  if constexpr (sizeof(V) == 8) {
+    ga.rhoc = h->rhoc64;
+    ga.kc = h->k64;
+  } else {
+    ga.rhoc = h->rhoc32;
+    ga.kc = h->k32;
+  }
   ga.sink = reinterpret_cast<V*>(h->sink);
   fill_classes(h->g, ga, cm, ck, h->cubic);
+  return ga;
+}
+template GatherArgs<double> gather_args<double>(const fem_heat*, double, double);
+template GatherArgs<float> gather_args<float>(const fem_heat*, double, double);
+
+namespace {
+
+// One gather of one handle outside the time stepping (set-up, test hook).
+template <typename V, class Pro, class Epi>
+int launch_gather(fem_heat* h, double cm, double ck, Pro pro, Epi epi, const Relay& R) {
+  const GatherArgs<V> ga = gather_args<V>(h, cm, ck);
   const size_t smem = h->shape.smem_bytes(sizeof(V));
   if (h->cubic)
     hipLaunchKernelGGL((gather_kernel<V, true, Pro, Epi>), dim3(h->shape.nblocks), dim3(h->shape.nthreads), smem,
@@ -248,20 +200,7 @@ int launch_gather(fem_heat* h, const V* rhoc, const V* kc, double cm, double ck,
   return FEM_OK;
 }
 
-template <typename V, class Pro, class Epi>
-int gather_step(fem_heat* h, RelayCtx& c, int32_t mode, const V* rhoc, const V* kc, double cm, double ck, Pro pro,
-                Epi epi) {
-  return launch_gather<V>(h, rhoc, kc, cm, ck, pro, epi, next_relay(c, mode, true, h->shape.nblocks));
-}
-
-// Settles the pending decision of a solve and copies its state to the host.
-int decide_and_read(fem_heat* h, RelayCtx& c, Scalars* host) {
-  hipLaunchKernelGGL(decide_kernel, dim3(1), dim3(64), 0, h->stream, next_relay(c, M_DECIDE, false, 1));
-  HIP_TRY(hipGetLastError());
-  HIP_TRY(hipMemcpyAsync(host, c.S[c.cur], sizeof(Scalars), hipMemcpyDeviceToHost, h->stream));
-  HIP_TRY(hipStreamSynchronize(h->stream));
-  return FEM_OK;
-}
+}  // namespace
 
 int ensure_fp32(fem_heat* h) {
   if (h->pinv32) return FEM_OK;
@@ -297,7 +236,7 @@ int prepare_operator(fem_heat* h, double ck, bool need32) {
   if (h->nonzero_dirichlet) {
     double* gext = h->q64;  // scratch
     hipLaunchKernelGGL(dirichlet_field_kernel, dim3(nblk(N)), dim3(kT), 0, h->stream, h->g, gext);
-    RC_TRY(launch_gather<double>(h, h->rhoc64, h->k64, 1.0, ck, ProPlain<double>{gext},
+    RC_TRY(launch_gather<double>(h, 1.0, ck, ProPlain<double>{gext},
                                  EpiStore<double>{h->lift64}, no_relay()));
     hipLaunchKernelGGL(mask_free_kernel, dim3(nblk(N)), dim3(kT), 0, h->stream, h->pinv64, h->lift64, N);
     HIP_TRY(hipGetLastError());
@@ -305,180 +244,6 @@ int prepare_operator(fem_heat* h, double ck, bool need32) {
   h->ck_cached = ck;
   return FEM_OK;
 }
-
-int ensure_events(fem_heat* h, size_t n) {
-  while (h->events.size() < n) {
-    hipEvent_t e;
-    HIP_TRY(hipEventCreate(&e));
-    h->events.push_back(e);
-  }
-  return FEM_OK;
-}
-
-template <typename V>
-struct PcgBufs {
-  V* x[2];
-  int xc;
-  V* r;
-  V* q;
-  V* d[2];
-  int dp;
-  const V* pinv;
-  const V* b;
-  const V* rhoc;
-  const V* kc;
-  RelayCtx* ctx;
-  Scalars* S_host;
-  double ck;
-  uint32_t upd_blocks;
-};
-
-// Iterations of Algorithm 1 until the device marks the solve done.  Returns
-// FEM_OK with *iters set, FEM_EBREAKDOWN or a device error.
-template <typename V>
-int pcg_loop(fem_heat* h, PcgBufs<V>& B, int first_chunk, int* iters) {
-  const int R = h->opts.replace_every;
-  RelayCtx& c = *B.ctx;
-  int done_iters = 0;
-  int k = std::max(1, first_chunk);
-  for (;;) {
-    if (h->timing) RC_TRY(ensure_events(h, 3 * (size_t)k));
-    int dp = B.dp, xc = B.xc;
-    for (int j = 0; j < k; ++j) {
-      const int it = done_iters + j;
-      if (h->timing) HIP_TRY(hipEventRecord(h->events[3 * j], h->stream));
-      RC_TRY(gather_step<V>(h, c, M_DIR, B.rhoc, B.kc, 1.0, B.ck,
-                            ProDirection<V>{B.r, B.pinv, B.d[dp], B.d[dp ^ 1], V(0)}, EpiQDot<V>{B.q}));
-      dp ^= 1;
-      if (h->timing) HIP_TRY(hipEventRecord(h->events[3 * j + 1], h->stream));
-      if (R > 0 && it % R == 0) {
-        RC_TRY(gather_step<V>(h, c, M_UPD, B.rhoc, B.kc, 1.0, B.ck,
-                              ProAxpy<V, V>{B.x[xc], B.d[dp], B.x[xc ^ 1], 0, V(0)},
-                              EpiResidual<V>{B.b, B.pinv, B.r}));
-        xc ^= 1;
-      } else {
-        hipLaunchKernelGGL((update_kernel<V>), dim3(B.upd_blocks), dim3(kT), 0, h->stream, B.x[xc], B.d[dp], B.r, B.q,
-                           B.pinv, h->g.N, next_relay(c, M_UPD, true, B.upd_blocks));
-        HIP_TRY(hipGetLastError());
-      }
-      if (h->timing) HIP_TRY(hipEventRecord(h->events[3 * j + 2], h->stream));
-    }
-    RC_TRY(decide_and_read(h, c, B.S_host));
-    const int real = B.S_host->iter;
-    const int ran = std::max(0, std::min(real - done_iters, k));
-    for (int j = 0; j < ran; ++j) {
-      const int it = done_iters + j;
-      B.dp ^= 1;
-      const bool rep = R > 0 && it % R == 0;
-      if (rep) B.xc ^= 1;
-      if (h->timing) {
-        float g_ms = 0.f, u_ms = 0.f;
-        HIP_TRY(hipEventElapsedTime(&g_ms, h->events[3 * j], h->events[3 * j + 1]));
-        HIP_TRY(hipEventElapsedTime(&u_ms, h->events[3 * j + 1], h->events[3 * j + 2]));
-        h->stats.gather_launches += 1;
-        h->stats.gather_ms += g_ms;
-        if (rep) {
-          h->stats.replace_launches += 1;
-          h->stats.replace_ms += u_ms;
-        } else {
-          h->stats.update_launches += 1;
-          h->stats.update_ms += u_ms;
-        }
-      }
-    }
-    done_iters = real;
-    if (B.S_host->status != 0) return fail(h, FEM_EBREAKDOWN, "PCG breakdown (d^T A d <= 0 or non-finite scalar)");
-    if (B.S_host->done) break;
-    k = 4;
-  }
-  *iters = done_iters;
-  return FEM_OK;
-}
-
-struct RunState {
-  double* T1;
-  double* T2;
-  double* X[2];
-  int dp64 = 0, dp32 = 0;
-  int est = 8;
-};
-
-double schedule_value(const fem_heat* h, int64_t m) {
-  if (h->sched.empty()) return 1.0;
-  if (m < 1 || m > (int64_t)h->sched.size()) return 0.0;
-  return h->sched[(size_t)(m - 1)];
-}
-
-// One theta-scheme step in FP64.  Leaves the new field in X[*xc].
-int step_fp64(fem_heat* h, RunState& st, double dt, double theta, double s_n, int* iters, int* xc_out) {
-  const double ckA = theta * dt, ckL = -(1.0 - theta) * dt;
-  RelayCtx& c = h->outer;
-  RC_TRY(gather_step<double>(h, c, M_RHS, h->rhoc64, h->k64, 1.0, ckL, ProPlain<double>{st.T1},
-                             EpiRhs<double>{h->b64, h->F64, h->pinv64, h->lift64, dt * s_n}));
-  RC_TRY(gather_step<double>(
-      h, c, M_INIT, h->rhoc64, h->k64, 1.0, ckA,
-      ProGuess<double>{st.T1, st.T2, h->pinv64, st.X[0], h->opts.guess == FEM_GUESS_PREV ? 1 : 0, 0},
-      EpiResidual<double>{h->b64, h->pinv64, h->r64}));
-  PcgBufs<double> B{{st.X[0], st.X[1]}, 0,      h->r64,   h->q64, {h->d64[0], h->d64[1]}, st.dp64, h->pinv64,
-                    h->b64,             h->rhoc64, h->k64, &c,     h->S_host,              ckA,     h->upd_blocks64};
-  RC_TRY(pcg_loop<double>(h, B, st.est, iters));
-  st.dp64 = B.dp;
-  *xc_out = B.xc;
-  return FEM_OK;
-}
-
-// One step of the mixed form: FP64 right-hand side, guess and residual; FP32
-// inner PCG on A e = r (FP64 dot products and scalars); FP64 correction
-// x += e and residual r = b - A x, repeated until the FP64 stop rule holds.
-int step_mixed(fem_heat* h, RunState& st, double dt, double theta, double s_n, int* iters, int* sweeps,
-               int* xc_out) {
-  const double ckA = theta * dt, ckL = -(1.0 - theta) * dt;
-  const uint32_t N = h->g.N;
-  RelayCtx& c = h->outer;
-  RC_TRY(gather_step<double>(h, c, M_RHS, h->rhoc64, h->k64, 1.0, ckL, ProPlain<double>{st.T1},
-                             EpiRhs<double>{h->b64, h->F64, h->pinv64, h->lift64, dt * s_n}));
-  RC_TRY(gather_step<double>(
-      h, c, M_INIT, h->rhoc64, h->k64, 1.0, ckA,
-      ProGuess<double>{st.T1, st.T2, h->pinv64, st.X[0], h->opts.guess == FEM_GUESS_PREV ? 1 : 0, 0},
-      EpiResidual<double>{h->b64, h->pinv64, h->r64}));
-  int xc = 0;
-  Scalars* so = h->S_host;
-  RC_TRY(decide_and_read(h, c, so));
-  if (so->status != 0) return fail(h, FEM_EBREAKDOWN, "non-finite initial residual");
-  int total = 0, nsw = 0;
-  const uint32_t sblocks = std::min<uint32_t>(nblk(N), 1024);
-  while (!so->done && nsw < h->opts.max_refine) {
-    // Inner tolerance: half the reduction the FP64 stop rule still needs,
-    // never tighter than inner_rtol (FP32 arithmetic bounds what the inner
-    // solve can reach); one sweep then usually suffices.
-    const double ref = h->opts.stop_rule == FEM_STOP_INITIAL ? so->delta0 : so->delta_b;
-    const double need = so->delta > 0 ? 0.5 * std::sqrt(c.ctl.rtol2 * ref / so->delta) : 1.0;
-    const double irt = std::min(0.5, std::max(h->opts.inner_rtol, need));
-    h->inner.ctl.rtol2 = irt * irt;
-    hipLaunchKernelGGL(inner_start_kernel, dim3(sblocks), dim3(kT), 0, h->stream, h->r64, h->rhs32, h->r32, h->e32[0],
-                       h->pinv32, N, next_relay(h->inner, M_START, true, sblocks));
-    HIP_TRY(hipGetLastError());
-    PcgBufs<float> B{{h->e32[0], h->e32[1]}, 0,         h->r32, h->q32,    {h->d32[0], h->d32[1]}, st.dp32, h->pinv32,
-                     h->rhs32,               h->rhoc32, h->k32, &h->inner, h->S_host + 1,          ckA,     h->upd_blocks32};
-    int it = 0;
-    RC_TRY(pcg_loop<float>(h, B, nsw == 0 ? st.est : std::max(1, st.est / 4), &it));
-    st.dp32 = B.dp;
-    total += it;
-    RC_TRY(gather_step<double>(h, c, M_CORR, h->rhoc64, h->k64, 1.0, ckA,
-                               ProAxpy<double, float>{st.X[xc], h->e32[B.xc], st.X[xc ^ 1], 1, 0.0},
-                               EpiResidual<double>{h->b64, h->pinv64, h->r64}));
-    xc ^= 1;
-    ++nsw;
-    RC_TRY(decide_and_read(h, c, so));
-    if (so->status != 0) return fail(h, FEM_EBREAKDOWN, "non-finite residual in the refinement");
-  }
-  *iters = total;
-  *sweeps = nsw;
-  *xc_out = xc;
-  return FEM_OK;
-}
-
-}  // namespace
 
 // ---------------------------------------------------------------------------
 
@@ -514,7 +279,7 @@ int solver_init(fem_heat* h, const fem_grid* grid, const double* k_e, const doub
     int cus = 0;
     HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, h->opts.device));
     const int per_cu = resident_blocks(h->cubic, fp32, probe.nthreads, probe.smem_bytes(fp32 ? 4 : 8));
-    h->shape = choose_shape(g, h->opts, std::max(1, cus) * per_cu);
+    h->shape = choose_shape(g, h->opts, h->batched ? 0 : std::max(1, cus) * per_cu);
   }
   {
     const GatherShape& s = h->shape;
@@ -523,6 +288,7 @@ int solver_init(fem_heat* h, const fem_grid* grid, const double* k_e, const doub
   }
   h->upd_blocks64 = std::max<uint32_t>(1, std::min<uint32_t>(nblk((g.N + 1) / 2), 512));
   h->upd_blocks32 = std::max<uint32_t>(1, std::min<uint32_t>(nblk((g.N + 3) / 4), 512));
+  h->start_blocks = std::max<uint32_t>(1, std::min<uint32_t>(nblk(g.N), 1024));
   h->stats.tile_x = h->shape.tx;
   h->stats.tile_y = h->shape.ty;
   h->stats.tile_z = h->shape.tz;
@@ -547,7 +313,7 @@ int solver_init(fem_heat* h, const fem_grid* grid, const double* k_e, const doub
   for (auto& p : h->pool) RC_TRY(dalloc(h, &p, N));
   if (h->nonzero_dirichlet) RC_TRY(dalloc(h, &h->lift64, N));
   RC_TRY(dalloc(h, &h->sink, 256));
-  h->n_partials = std::max({h->shape.nblocks, h->upd_blocks64, h->upd_blocks32, 1024u});
+  h->n_partials = std::max({h->shape.nblocks, h->upd_blocks64, h->upd_blocks32, h->start_blocks});
   for (RelayCtx* c : {&h->outer, &h->inner})
     for (int k = 0; k < 2; ++k) {
       RC_TRY(dalloc(h, &c->S[k], 1));
@@ -555,130 +321,13 @@ int solver_init(fem_heat* h, const fem_grid* grid, const double* k_e, const doub
       HIP_TRY(hipMemsetAsync(c->S[k], 0, sizeof(Scalars), h->stream));
       HIP_TRY(hipMemsetAsync(c->P[k], 0, h->n_partials * sizeof(double), h->stream));
     }
-  HIP_TRY(hipHostMalloc(reinterpret_cast<void**>(&h->S_host), 2 * sizeof(Scalars), hipHostMallocDefault));
   RC_TRY(copy_in(h, h->rhoc64, rhoc_e, E));
   RC_TRY(copy_in(h, h->k64, k_e, E));
   hipLaunchKernelGGL(load_vector_kernel, dim3(nblk(N)), dim3(kT), 0, h->stream, g, h->F64);
   HIP_TRY(hipGetLastError());
   if (h->opts.precision == FEM_FP32_FP64DOT) RC_TRY(ensure_fp32(h));
-  HIP_TRY(hipEventCreate(&h->ev_run[0]));
-  HIP_TRY(hipEventCreate(&h->ev_run[1]));
   HIP_TRY(hipStreamSynchronize(h->stream));
   return FEM_OK;
-}
-
-int solver_run(fem_heat* h, const double* T0, const double* T_prev, double dt, double theta, int32_t nsteps,
-               double rtol, fem_out* o) {
-  HIP_TRY(hipSetDevice(h->opts.device));
-  const bool mixed = h->opts.precision == FEM_FP32_FP64DOT;
-  const uint32_t N = h->g.N;
-  RC_TRY(prepare_operator(h, theta * dt, mixed));
-  RunState st;
-  st.T1 = h->pool[0];
-  st.T2 = h->pool[1];
-  st.X[0] = h->pool[2];
-  st.X[1] = h->pool[3];
-  RC_TRY(copy_in(h, st.T1, T0, N));
-  RC_TRY(copy_in(h, st.T2, T_prev ? T_prev : T0, N));
-  hipLaunchKernelGGL((apply_dirichlet_kernel<double>), dim3(nblk(N)), dim3(kT), 0, h->stream, h->g, st.T1);
-  hipLaunchKernelGGL((apply_dirichlet_kernel<double>), dim3(nblk(N)), dim3(kT), 0, h->stream, h->g, st.T2);
-  for (int k = 0; k < 2; ++k)
-    hipLaunchKernelGGL((fill_kernel<double>), dim3(nblk(N)), dim3(kT), 0, h->stream, h->d64[k], 0.0, N);
-  if (mixed)
-    for (int k = 0; k < 2; ++k)
-      hipLaunchKernelGGL((fill_kernel<float>), dim3(nblk(N)), dim3(kT), 0, h->stream, h->d32[k], 0.0f, N);
-  HIP_TRY(hipGetLastError());
-
-  const int S = (o && o->sensor_xyz && o->n_sensors > 0) ? o->n_sensors : 0;
-  if (S > 0) {
-    if (h->xyz_cap < (size_t)S) {
-      dfree(h->xyz_dev);
-      RC_TRY(dalloc(h, &h->xyz_dev, 3 * (size_t)S));
-      h->xyz_cap = S;
-    }
-    RC_TRY(copy_in(h, h->xyz_dev, o->sensor_xyz, 3 * (size_t)S));
-    const size_t need = (size_t)std::max(nsteps, 1) * S;
-    if (h->traces_cap < need) {
-      dfree(h->traces_dev);
-      RC_TRY(dalloc(h, &h->traces_dev, need));
-      h->traces_cap = need;
-    }
-  }
-  std::vector<int32_t> iters((size_t)std::max(nsteps, 0), 0), sweeps(iters.size(), 0);
-  std::vector<double> relres(iters.size(), 0.0);
-  h->stats.gather_launches = h->stats.update_launches = h->stats.replace_launches = 0;
-  h->stats.gather_ms = h->stats.update_ms = h->stats.replace_ms = 0.0;
-
-  h->outer.ctl = Ctl{rtol * rtol, h->opts.max_iter, h->opts.stop_rule};
-  h->inner.ctl = Ctl{h->opts.inner_rtol * h->opts.inner_rtol, h->opts.max_iter, 1};
-  const int first = o ? o->first_step : 0;
-  int status = FEM_OK;
-  int64_t total = 0;
-  HIP_TRY(hipEventRecord(h->ev_run[0], h->stream));
-  for (int32_t n = 1; n <= nsteps; ++n) {
-    const double s_n = schedule_value(h, (int64_t)first + n);
-    int it = 0, nsw = 0, xc = 0;
-    int rc = mixed ? step_mixed(h, st, dt, theta, s_n, &it, &nsw, &xc) : step_fp64(h, st, dt, theta, s_n, &it, &xc);
-    if (rc == FEM_EBREAKDOWN) {
-      status = rc;
-      break;
-    }
-    if (rc != FEM_OK) return rc;
-    const Scalars& so = h->S_host[0];
-    iters[n - 1] = it;
-    sweeps[n - 1] = nsw;
-    relres[n - 1] = so.delta_b > 0 ? std::sqrt(std::max(so.delta, 0.0) / so.delta_b) : 0.0;
-    const bool unconverged = mixed ? (so.delta > so.tol) : (it >= h->opts.max_iter && so.delta > so.tol);
-    if (unconverged && status == FEM_OK) status = FEM_ENOCONV;
-    total += it;
-    st.est = std::max(1, it);
-    double* xnew = st.X[xc];
-    if (S > 0) {
-      hipLaunchKernelGGL(sensor_kernel, dim3((S + 63) / 64), dim3(64), 0, h->stream, h->g, xnew, h->xyz_dev, S,
-                         h->traces_dev + (size_t)(n - 1) * S);
-      HIP_TRY(hipGetLastError());
-    }
-    if (o && o->T_saved && o->save_every > 0 && n % o->save_every == 0)
-      RC_TRY(copy_out(h, o->T_saved + (size_t)(n / o->save_every - 1) * N, xnew, (size_t)N * sizeof(double)));
-    double* freed = st.T2;
-    double* spare = st.X[xc ^ 1];
-    st.T2 = st.T1;
-    st.T1 = xnew;
-    st.X[0] = freed;
-    st.X[1] = spare;
-  }
-  HIP_TRY(hipEventRecord(h->ev_run[1], h->stream));
-  HIP_TRY(hipEventSynchronize(h->ev_run[1]));
-  float ms = 0.f;
-  HIP_TRY(hipEventElapsedTime(&ms, h->ev_run[0], h->ev_run[1]));
-  if (o) {
-    o->device_ms = ms;
-    o->total_iters = total;
-    if (o->T_final) RC_TRY(copy_out(h, o->T_final, st.T1, (size_t)N * sizeof(double)));
-    if (S > 0 && o->traces)
-      RC_TRY(copy_out(h, o->traces, h->traces_dev, (size_t)std::max(nsteps, 0) * S * sizeof(double)));
-    if (o->iters) {
-      if (h->devptrs)
-        HIP_TRY(hipMemcpyAsync(o->iters, iters.data(), iters.size() * sizeof(int32_t), hipMemcpyHostToDevice, h->stream));
-      else
-        std::memcpy(o->iters, iters.data(), iters.size() * sizeof(int32_t));
-    }
-    if (o->relres) {
-      if (h->devptrs)
-        HIP_TRY(hipMemcpyAsync(o->relres, relres.data(), relres.size() * sizeof(double), hipMemcpyHostToDevice, h->stream));
-      else
-        std::memcpy(o->relres, relres.data(), relres.size() * sizeof(double));
-    }
-    if (o->refine_sweeps) {
-      if (h->devptrs)
-        HIP_TRY(hipMemcpyAsync(o->refine_sweeps, sweeps.data(), sweeps.size() * sizeof(int32_t), hipMemcpyHostToDevice,
-                               h->stream));
-      else
-        std::memcpy(o->refine_sweeps, sweeps.data(), sweeps.size() * sizeof(int32_t));
-    }
-  }
-  HIP_TRY(hipStreamSynchronize(h->stream));
-  return status;
 }
 
 int solver_apply(fem_heat* h, int32_t which, double dt, double theta, const double* x, double* y) {
@@ -694,11 +343,11 @@ int solver_apply(fem_heat* h, int32_t which, double dt, double theta, const doub
     if (fp32) {
       RC_TRY(ensure_fp32(h));
       hipLaunchKernelGGL((cast_kernel<double, float>), dim3(nblk(N)), dim3(kT), 0, h->stream, xd, h->e32[0], N);
-      RC_TRY(launch_gather<float>(h, h->rhoc32, h->k32, 1.0, ck, ProPlain<float>{h->e32[0]}, EpiStore<float>{h->q32},
+      RC_TRY(launch_gather<float>(h, 1.0, ck, ProPlain<float>{h->e32[0]}, EpiStore<float>{h->q32},
                                   no_relay()));
       hipLaunchKernelGGL((cast_kernel<float, double>), dim3(nblk(N)), dim3(kT), 0, h->stream, h->q32, yd, N);
     } else {
-      RC_TRY(launch_gather<double>(h, h->rhoc64, h->k64, 1.0, ck, ProPlain<double>{xd}, EpiStore<double>{yd},
+      RC_TRY(launch_gather<double>(h, 1.0, ck, ProPlain<double>{xd}, EpiStore<double>{yd},
                                    no_relay()));
     }
   } else if (op == FEM_OP_JACOBI) {
@@ -748,12 +397,6 @@ void solver_free(fem_heat* h) {
     }
   dfree(h->xyz_dev);
   dfree(h->traces_dev);
-  if (h->S_host) (void)hipHostFree(h->S_host);
-  h->S_host = nullptr;
-  for (auto e : h->events) (void)hipEventDestroy(e);
-  h->events.clear();
-  for (auto& e : h->ev_run)
-    if (e) (void)hipEventDestroy(e);
   if (h->own_stream && h->stream) (void)hipStreamDestroy(h->stream);
   h->stream = nullptr;
 }

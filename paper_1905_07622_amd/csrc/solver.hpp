@@ -10,14 +10,11 @@
 #include "common.hpp"
 
 namespace femheat {
-// Host view of one relayed solve: the ping-pong state blocks and partial
-// buffers, which one the next kernel reads, and how many partials it holds.
+// Device buffers of one relayed solve: the ping-pong state blocks and the
+// block-partial buffers.
 struct RelayCtx {
   Scalars* S[2] = {nullptr, nullptr};
   double* P[2] = {nullptr, nullptr};
-  int cur = 0;
-  uint32_t npin = 0;
-  Ctl ctl{};
 };
 }  // namespace femheat
 
@@ -28,6 +25,7 @@ struct fem_heat {
   fem_opts opts{};
   bool devptrs = false;
   bool timing = false;
+  bool batched = false;  // created as a member of a batch (tile rule of batch members)
 
   femheat::Geom g{};
   bool cubic = false;
@@ -63,7 +61,6 @@ struct fem_heat {
   // relayed solve state: outer (FP64) and inner (FP32) solves
   femheat::RelayCtx outer, inner;
   uint32_t n_partials = 0;
-  femheat::Scalars* S_host = nullptr;  // pinned, 2 entries
 
   // per-run buffers
   double* xyz_dev = nullptr;
@@ -72,11 +69,9 @@ struct fem_heat {
   size_t xyz_cap = 0;
 
   femheat::GatherShape shape{};
-  uint32_t upd_blocks64 = 0, upd_blocks32 = 0;
+  uint32_t upd_blocks64 = 0, upd_blocks32 = 0, start_blocks = 0;
 
   fem_stats stats{};
-  std::vector<hipEvent_t> events;
-  hipEvent_t ev_run[2] = {nullptr, nullptr};
 
   std::string err;
 };
@@ -84,9 +79,22 @@ struct fem_heat {
 namespace femheat {
 
 int solver_init(fem_heat* h, const fem_grid* grid, const double* k_e, const double* rhoc_e, const fem_bc* bc);
-int solver_run(fem_heat* h, const double* T0, const double* T_prev, double dt, double theta, int32_t nsteps,
-               double rtol, fem_out* out);
 int solver_apply(fem_heat* h, int32_t which, double dt, double theta, const double* x, double* y);
 void solver_free(fem_heat* h);
+
+// Time stepping (engine.hip): one handle, or a batch of handles advanced
+// together (status[i] receives the outcome of sims[i]).
+struct RunRequest {
+  fem_heat* h;
+  const double* T0;
+  const double* T_prev;
+  double dt, theta, rtol;
+  int32_t nsteps;
+  fem_out* out;
+};
+int solver_run(fem_heat* h, const double* T0, const double* T_prev, double dt, double theta, int32_t nsteps,
+               double rtol, fem_out* out);
+int engine_run(const RunRequest* reqs, int32_t n, hipStream_t stream, const fem_opts& opts, int32_t* status,
+               std::string* err);
 
 }  // namespace femheat

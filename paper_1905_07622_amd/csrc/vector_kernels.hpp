@@ -33,19 +33,23 @@ __device__ inline void upd1(V& x, V d, V& r, V q, V p, V alpha, double& acc) {
   acc += (double)rr * (double)(p * rr);
 }
 
+// Fused update of one solve by block `blk` of its `nblk` blocks (a
+// grid-stride loop over the solve's own block count, so the partial sums do
+// not depend on the launch the block belongs to).  Settles alpha = delta /
+// d^T q first; a no-op once the solve is done.
 template <typename V>
-__global__ void __launch_bounds__(256) update_kernel(V* __restrict__ x, const V* __restrict__ d,
-                                                      V* __restrict__ r, const V* __restrict__ q,
-                                                      const V* __restrict__ pinv, uint32_t N, Relay R) {
+__device__ inline void update_body(V* __restrict__ x, const V* __restrict__ d, V* __restrict__ r,
+                                   const V* __restrict__ q, const V* __restrict__ pinv, uint32_t N, const Relay& R,
+                                   uint32_t blk, uint32_t nblk) {
   Scalars st;
-  if (!stage_entry(R, st)) return;  // settles alpha = delta / d^T q; no-op once done
+  if (!stage_entry(R, st, blk == 0)) return;
   using VT = typename Vec<V>::T;
   constexpr int W = Vec<V>::W;
   const V alpha = (V)st.alpha;
   double acc = 0.0;
   const uint32_t nvec = N / W;
-  const uint32_t stride = gridDim.x * blockDim.x;
-  const uint32_t tid = blockIdx.x * blockDim.x + threadIdx.x;
+  const uint32_t stride = nblk * blockDim.x;
+  const uint32_t tid = blk * blockDim.x + threadIdx.x;
   VT* xv = reinterpret_cast<VT*>(x);
   const VT* dv = reinterpret_cast<const VT*>(d);
   VT* rv = reinterpret_cast<VT*>(r);
@@ -71,26 +75,28 @@ __global__ void __launch_bounds__(256) update_kernel(V* __restrict__ x, const V*
     x[i] = xx;
     r[i] = rr;
   }
-  publish_partial(R, acc);
+  publish_partial(R, acc, blk);
 }
 
-// Start of an inner (FP32) solve of A e = r64: rhs = r = (float) r64, e = 0,
-// delta0 = r^T P^-1 r accumulated in FP64.
-__global__ void __launch_bounds__(256) inner_start_kernel(const double* __restrict__ r64, float* __restrict__ rhs,
-                                                          float* __restrict__ r, float* __restrict__ e,
-                                                          const float* __restrict__ pinv, uint32_t N, Relay R) {
+// Start of an inner (FP32) solve of A e = r64 by block `blk` of `nblk`:
+// rhs = r = (float) r64, e = 0, r0^T P^-1 r0 accumulated in FP64.  A solve
+// relayed as M_IDLE is not needed and does nothing.
+__device__ inline void inner_start_body(const double* __restrict__ r64, float* __restrict__ rhs,
+                                        float* __restrict__ r, float* __restrict__ e,
+                                        const float* __restrict__ pinv, uint32_t N, const Relay& R, uint32_t blk,
+                                        uint32_t nblk) {
   Scalars st;
-  (void)stage_entry(R, st);  // a fresh solve: the next kernel settles r0^T P^-1 r0
+  if (!stage_entry(R, st, blk == 0)) return;
   double acc = 0.0;
-  const uint32_t stride = gridDim.x * blockDim.x;
-  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < N; i += stride) {
+  const uint32_t stride = nblk * blockDim.x;
+  for (uint32_t i = blk * blockDim.x + threadIdx.x; i < N; i += stride) {
     const float v = (float)r64[i];
     rhs[i] = v;
     r[i] = v;
     e[i] = 0.0f;
     acc += (double)v * (double)(pinv[i] * v);
   }
-  publish_partial(R, acc);
+  publish_partial(R, acc, blk);
 }
 
 // ---------------------------------------------------------------------------
@@ -149,7 +155,7 @@ __global__ void jacobi_kernel(Geom g, const double* __restrict__ rhoc, const dou
 
 // Boundary load F_i = sum over flux faces f containing i of q_f * integral of
 // the bilinear face shape function = q_f * (h_u h_v / 4) * (face elements at i).
-__global__ void load_vector_kernel(Geom g, double* __restrict__ F) {
+[[maybe_unused]] static __global__ void load_vector_kernel(Geom g, double* __restrict__ F) {
   const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= g.N) return;
   int idx[3];
@@ -181,7 +187,7 @@ __global__ void apply_dirichlet_kernel(Geom g, V* __restrict__ T) {
 }
 
 // g_ext: boundary value on Dirichlet nodes, 0 elsewhere.
-__global__ void dirichlet_field_kernel(Geom g, double* __restrict__ out) {
+[[maybe_unused]] static __global__ void dirichlet_field_kernel(Geom g, double* __restrict__ out) {
   const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= g.N) return;
   int ix, iy, iz;
@@ -191,7 +197,7 @@ __global__ void dirichlet_field_kernel(Geom g, double* __restrict__ out) {
 }
 
 // lift_i = (A g_ext)_i on free rows, 0 on Dirichlet rows (computed in place on y).
-__global__ void mask_free_kernel(const double* __restrict__ pinv, double* __restrict__ y, uint32_t N) {
+[[maybe_unused]] static __global__ void mask_free_kernel(const double* __restrict__ pinv, double* __restrict__ y, uint32_t N) {
   const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < N && pinv[i] == 0.0) y[i] = 0.0;
 }
@@ -216,7 +222,7 @@ __global__ void scale_kernel(const V* __restrict__ a, const V* __restrict__ x, d
 
 // Field value at points: trilinear interpolation in the containing element
 // (lowest-index element on shared faces).  Traces row-major [step][sensor].
-__global__ void sensor_kernel(Geom g, const double* __restrict__ T, const double* __restrict__ xyz, int32_t S,
+[[maybe_unused]] static __global__ void sensor_kernel(Geom g, const double* __restrict__ T, const double* __restrict__ xyz, int32_t S,
                               double* __restrict__ out) {
   const int s = blockIdx.x * blockDim.x + threadIdx.x;
   if (s >= S) return;

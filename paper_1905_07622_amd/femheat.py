@@ -64,6 +64,12 @@ class fem_stats(ctypes.Structure):
                 ("tile_y", ctypes.c_int32), ("tile_z", ctypes.c_int32)]
 
 
+class fem_request(ctypes.Structure):
+    _fields_ = [("grid", fem_grid), ("k_e", _dp), ("rhoc_e", _dp), ("bc", fem_bc),
+                ("T0", _dp), ("T_prev", _dp), ("dt", ctypes.c_double), ("theta", ctypes.c_double),
+                ("rtol", ctypes.c_double), ("nsteps", ctypes.c_int32), ("out", ctypes.POINTER(fem_out))]
+
+
 class FemError(RuntimeError):
     def __init__(self, status: int, msg: str):
         super().__init__(f"{fem_strerror(status)} ({status}): {msg}")
@@ -71,7 +77,7 @@ class FemError(RuntimeError):
 
 
 EXPORTS = ("fem_heat_create", "fem_heat_run", "fem_heat_apply", "fem_heat_stats", "fem_heat_destroy",
-           "fem_heat_default_opts", "fem_strerror", "fem_last_error")
+           "fem_heat_default_opts", "fem_strerror", "fem_last_error", "fem_heat_run_batch")
 
 _lib = None
 
@@ -90,6 +96,8 @@ def lib():
                                    ctypes.c_double, ctypes.POINTER(fem_out)]
         L.fem_heat_apply.argtypes = [vp, ctypes.c_int32, ctypes.c_double, ctypes.c_double, _dp, _dp]
         L.fem_heat_stats.argtypes = [vp, ctypes.POINTER(fem_stats)]
+        L.fem_heat_run_batch.argtypes = [ctypes.POINTER(fem_request), ctypes.c_int32, ctypes.POINTER(fem_opts), _ip]
+        L.fem_heat_run_batch.restype = ctypes.c_int
         L.fem_heat_destroy.argtypes = [vp]
         L.fem_heat_destroy.restype = None
         L.fem_heat_default_opts.argtypes = [ctypes.POINTER(fem_opts)]
@@ -151,6 +159,10 @@ def fem_heat_destroy(h) -> None:
     lib().fem_heat_destroy(h)
 
 
+def fem_heat_run_batch(reqs, n: int, opts: Optional[fem_opts], status_ptr) -> int:
+    return lib().fem_heat_run_batch(reqs, n, ctypes.byref(opts) if opts is not None else None, status_ptr)
+
+
 # ---------------------------------------------------------------------------
 # marshalling helpers
 # ---------------------------------------------------------------------------
@@ -190,6 +202,90 @@ class _Arrays:
         arr = np.zeros(shape, dtype=dtype)
         self.keep.append(arr)
         return arr, arr.ctypes.data_as(_dp if dtype == np.float64 else _ip)
+
+
+def make_opts(*, precision=FEM_FP64, max_iter=10000, replace_every=50, guess=FEM_GUESS_EXTRAP,
+              stop_rule=FEM_STOP_RHS, max_refine=4, inner_rtol=1e-5, device_ptrs=False, timing=False,
+              tile=(0, 0, 0), stream=None, device=0) -> fem_opts:
+    o = fem_heat_default_opts()
+    o.precision, o.max_iter, o.replace_every = precision, max_iter, replace_every
+    o.guess, o.stop_rule, o.max_refine, o.inner_rtol = guess, stop_rule, max_refine, inner_rtol
+    o.flags = (FEM_DEVICE_PTRS if device_ptrs else 0) | (FEM_TIMING if timing else 0)
+    o.hip_stream = stream
+    o.device = device
+    o.tile_x, o.tile_y, o.tile_z = tile
+    return o
+
+
+def _bc(p, keep):
+    bc = fem_bc()
+    bc.dirichlet_mask = p.dirichlet_mask
+    bc.dirichlet_value = (ctypes.c_double * 6)(*[float(v) for v in p.dirichlet_value])
+    bc.flux_mask = p.flux_mask
+    bc.flux = (ctypes.c_double * 6)(*[float(v) for v in p.flux])
+    if p.flux_schedule is not None:
+        sched = np.ascontiguousarray(p.flux_schedule, dtype=np.float64)
+        keep.append(sched)
+        bc.flux_schedule = sched.ctypes.data_as(_dp)
+        bc.n_schedule = len(sched)
+    return bc
+
+
+def _outputs(a: "_Arrays", N: int, nsteps: int, save_every: int, sensors):
+    out = fem_out()
+    res = {}
+    res["T_final"], out.T_final = a.out((N,))
+    n_saved = nsteps // save_every if save_every else 0
+    res["T_saved"] = None
+    if n_saved:
+        res["T_saved"], out.T_saved = a.out((n_saved, N))
+    out.save_every = save_every
+    res["traces"] = None
+    if sensors is not None:
+        out.sensor_xyz = a.inp(sensors)
+        out.n_sensors = len(sensors)
+        res["traces"], out.traces = a.out((nsteps, len(sensors)))
+    res["iters"], out.iters = a.out((nsteps,), np.int32)
+    res["relres"], out.relres = a.out((nsteps,))
+    res["refine_sweeps"], out.refine_sweeps = a.out((nsteps,), np.int32)
+    return out, res
+
+
+def run_batch(problems, *, save_every=0, sensors=False, T_prev=None, check=True, **opt_kw):
+    """Runs workloads.Problem instances together through fem_heat_run_batch.
+
+    Each problem brings its grid, coefficients, boundary data, T0, dt, theta,
+    nsteps and rtol (and its sensor points when ``sensors`` is true); the
+    keyword options (precision, tile, device_ptrs, ...) apply to all.
+    Returns (status, list of per-simulation result dicts)."""
+    device = bool(opt_kw.get("device_ptrs", False))
+    a = _Arrays(device)
+    n = len(problems)
+    reqs = (fem_request * max(n, 1))()
+    outs, results = [], []
+    for i, p in enumerate(problems):
+        r = reqs[i]
+        r.grid = fem_grid(p.nx, p.ny, p.nz, p.hx, p.hy, p.hz)
+        r.k_e = a.inp(p.k_e)
+        r.rhoc_e = a.inp(p.rhoc_e)
+        r.bc = _bc(p, a.keep)
+        r.T0 = a.inp(p.T0)
+        r.T_prev = a.inp(T_prev[i]) if T_prev is not None else None
+        r.dt, r.theta, r.rtol, r.nsteps = p.dt, p.theta, p.rtol, p.nsteps
+        out, res = _outputs(a, p.n_nodes, p.nsteps, save_every, p.sensors if sensors else None)
+        outs.append(out)
+        r.out = ctypes.pointer(out)
+        results.append(res)
+    status = np.zeros(max(n, 1), dtype=np.int32)
+    opts = make_opts(**opt_kw)
+    st = fem_heat_run_batch(reqs, n, opts, status.ctypes.data_as(_ip))
+    if check and st not in (FEM_OK, FEM_ENOCONV):
+        raise FemError(st, fem_last_error(None))
+    for i, res in enumerate(results):
+        res["status"] = int(status[i])
+        res["total_iters"] = int(outs[i].total_iters)
+        res["device_ms"] = float(outs[i].device_ms)
+    return st, results
 
 
 class Heat:

@@ -94,3 +94,49 @@ def test_null_handle_calls_are_rejected(lib):
     lib.fem_heat_destroy(None)
     assert lib.fem_heat_stats(None, None) == fh.FEM_EINVAL
 
+
+
+def _request(nx=2, ny=2, nz=2, dt=1e-3, theta=1.0, rtol=1e-8, nsteps=1, k=None, keep=None):
+    from paper_1905_07622_amd import workloads as wl
+    p = wl.random_problem(nx, ny, nz, seed=1, nsteps=nsteps, dt=dt, theta=theta, rtol=rtol)
+    if k is not None:
+        p = p.replace(k_e=k)
+    return p
+
+
+@pytest.mark.parametrize("case", ["dt", "theta", "rtol", "nsteps", "k_neg", "grid"])
+def test_run_batch_rejects_invalid_requests_before_device_work(lib, case):
+    """One invalid request makes the whole batch fail with FEM_EINVAL before
+    anything runs; status[] names the request."""
+    good = _request()
+    bad = {"dt": dict(dt=0.0), "theta": dict(theta=1.5), "rtol": dict(rtol=-1.0), "nsteps": dict(nsteps=-1),
+           "k_neg": dict(k=-np.ones(8)), "grid": {}}[case]
+    if case == "grid":
+        p = good.replace(nx=0)
+    elif case == "nsteps":
+        p = good.replace(nsteps=-1)
+    else:
+        p = _request(**bad)
+    a = fh._Arrays(False)
+    reqs = (fh.fem_request * 3)()
+    for i, q in enumerate([good, p, good]):
+        r = reqs[i]
+        r.grid = fh.fem_grid(q.nx, q.ny, q.nz, q.hx, q.hy, q.hz)
+        r.k_e = a.inp(q.k_e)
+        r.rhoc_e = a.inp(q.rhoc_e)
+        r.bc = fh._bc(q, a.keep)
+        r.T0 = a.inp(q.T0)
+        r.dt, r.theta, r.rtol, r.nsteps = q.dt, q.theta, q.rtol, q.nsteps
+    status = np.full(3, 99, dtype=np.int32)
+    st = fh.fem_heat_run_batch(reqs, 3, fh.make_opts(), status.ctypes.data_as(fh._ip))
+    assert st == fh.FEM_EINVAL
+    assert list(status) == [fh.FEM_OK, fh.FEM_EINVAL, fh.FEM_OK]
+    assert fh.fem_last_error(None).startswith("request 1:")
+
+
+def test_run_batch_argument_checks(lib):
+    assert fh.fem_heat_run_batch(None, 1, None, None) == fh.FEM_EINVAL
+    assert fh.fem_heat_run_batch(None, 0, None, None) == fh.FEM_OK
+    reqs = (fh.fem_request * 1)()
+    bad_opts = fh.make_opts(precision=7)
+    assert fh.fem_heat_run_batch(reqs, 1, bad_opts, None) == fh.FEM_EINVAL
