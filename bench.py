@@ -18,6 +18,8 @@ import os
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
@@ -63,6 +65,136 @@ def cpu_baseline(problem, steps_a=1, steps_b=3):
                       f"({iters} iterations, {secs:.2f} s), serial CSR oracle, assembly excluded"}
 
 
+def _to_device(p, torch):
+    dev = "cuda"
+    return p.replace(k_e=torch.tensor(p.k_e, device=dev), rhoc_e=torch.tensor(p.rhoc_e, device=dev),
+                     T0=torch.tensor(p.T0, device=dev))
+
+
+def _plain_solve(p, rtol, stream):
+    """One forward solve on the plain path: a fresh FP64 handle, fem_heat_run."""
+    from paper_1905_07622_amd import femheat as fh
+    with fh.Heat(p.nx, p.ny, p.nz, p.hx, p.hy, p.hz, p.k_e, p.rhoc_e, dirichlet_mask=p.dirichlet_mask,
+                 flux_mask=p.flux_mask, flux=p.flux, device_ptrs=True, stream=stream) as h:
+        return h.run(p.T0, dt=p.dt, theta=p.theta, nsteps=p.nsteps, rtol=rtol)
+
+
+def _rel(a, b, torch):
+    return float(torch.linalg.norm(a - b) / torch.linalg.norm(b))
+
+
+def bench_batched(args, torch):
+    """Batched proposals: S simulations on 48^3 random-sphere fields, 100
+    backward-Euler steps each, in one fem_heat_run_batch call (mixed form),
+    against the plain one-at-a-time FP64 path on a sample of the same
+    simulations, at the workload's rtol and at a looser rtol that still keeps
+    the error within the mixed form's stated accuracy.  Inputs resident in
+    HBM; handle set-up inside the timed region on both sides."""
+    from paper_1905_07622_amd import femheat as fh
+    from paper_1905_07622_amd import workloads as wl
+    stream = torch.cuda.current_stream().cuda_stream
+    probs = [_to_device(wl.sphere_proposal(s, n=args.batch_n, nsteps=args.batch_nsteps), torch)
+             for s in range(args.batch_sims)]
+    prec = fh.FEM_FP32_FP64DOT if args.batch_precision == "mixed" else fh.FEM_FP64
+    fh.run_batch(probs[:2], precision=prec, device_ptrs=True, stream=stream)  # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    st, res = fh.run_batch(probs, precision=prec, device_ptrs=True, stream=stream)
+    torch.cuda.synchronize()
+    t_batch = time.perf_counter() - t0
+    print(f"batched: {len(probs)} simulations in {t_batch:.2f} s (status {st})", file=sys.stderr, flush=True)
+    sample = probs[:args.plain_sample]
+    out = {"workload": f"{len(probs)} x {args.batch_n}^3 random-sphere proposals, backward Euler dt=1e-3, "
+                       f"{args.batch_nsteps} steps, rtol 1e-8", "precision": args.batch_precision,
+           "solves_per_s": round(len(probs) / t_batch, 3), "seconds": round(t_batch, 3),
+           "nodes_per_sim": probs[0].n_nodes, "iterations_per_sim_mean": float(np.mean([r["total_iters"] for r in res]))}
+    plain = {}
+    refs = {}
+    for rtol in (1e-8,) + tuple(args.loose_rtols):
+        t0 = time.perf_counter()
+        outs = [_plain_solve(p, rtol, stream) for p in sample]
+        torch.cuda.synchronize()
+        dt_ = time.perf_counter() - t0
+        if rtol == 1e-8:
+            refs = outs
+        errs = [_rel(o["T_final"], r["T_final"], torch) for o, r in zip(outs, refs)]
+        plain[rtol] = {"solves_per_s": round(len(sample) / dt_, 3), "max_rel_err_vs_fp64_rtol_1e-8": max(errs)}
+        print(f"plain fp64 rtol {rtol:g}: {len(sample)} solves in {dt_:.2f} s", file=sys.stderr, flush=True)
+    errs = [_rel(res[i]["T_final"], refs[i]["T_final"], torch) for i in range(len(sample))]
+    out["max_rel_err_vs_plain_fp64"] = max(errs)
+    out["plain_fp64"] = {"sample": len(sample), "at_rtol_1e-8": plain[1e-8]}
+    ok_loose = [r for r in args.loose_rtols if plain[r]["max_rel_err_vs_fp64_rtol_1e-8"] <= 1e-5]
+    if ok_loose:
+        loose = max(ok_loose)
+        out["plain_fp64"]["loosest_within_1e-5"] = dict(plain[loose], rtol=loose)
+        base = plain[loose]["solves_per_s"]
+    else:
+        base = plain[1e-8]["solves_per_s"]
+    out["speedup_vs_plain"] = round(out["solves_per_s"] / base, 3)
+    return out
+
+
+def bench_served(args, torch):
+    """Serving: a Poisson stream of forward-solve requests (edge from
+    {32,48,64,96,128}, log-normal or two-phase field, 50-300 steps, theta in
+    {0.5,1}, rtol 1e-8) replayed in real time into a server (continuous
+    batching, mixed form, HBM budget), against the plain FP64 path serving the
+    same stream one request at a time (FCFS latencies from its measured
+    per-request service times)."""
+    from paper_1905_07622_amd import femheat as fh
+    from paper_1905_07622_amd import workloads as wl
+    stream = torch.cuda.current_stream().cuda_stream
+    reqs = [wl.serve_request(i) for i in range(args.serve_requests)]
+    arrivals = wl.poisson_arrivals(len(reqs), args.serve_rate, seed=5)
+    prec = fh.FEM_FP32_FP64DOT if args.batch_precision == "mixed" else fh.FEM_FP64
+    with fh.Server(precision=prec) as srv:  # warm-up of the server path
+        srv.wait(srv.submit(wl.serve_request(10_000).replace(nsteps=3)))
+    srv = fh.Server(precision=prec)
+    t_start = time.perf_counter()
+    tickets = []
+    for p, ta in zip(reqs, arrivals):
+        delay = ta - (time.perf_counter() - t_start)
+        if delay > 0:
+            time.sleep(delay)
+        tickets.append(srv.submit(p))
+    got = [srv.wait(t) for t in tickets]
+    t_all = time.perf_counter() - t_start
+    info = srv.info()
+    srv.close()
+    lat = np.array([d["t_done"] - d["t_arrive"] for _, d, _ in got])
+    served_T = [r["T_final"] for _, _, r in got]
+    print(f"served: {len(reqs)} requests in {t_all:.2f} s, p50 {np.percentile(lat, 50):.3f} s, "
+          f"p99 {np.percentile(lat, 99):.3f} s", file=sys.stderr, flush=True)
+    # plain FP64, one request at a time, same stream of arrivals
+    service, errs = [], []
+    for p, T in zip(reqs, served_T):
+        pd = _to_device(p, torch)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        o = _plain_solve(pd, p.rtol, stream)
+        torch.cuda.synchronize()
+        service.append(time.perf_counter() - t0)
+        errs.append(_rel(torch.tensor(T, device="cuda"), o["T_final"], torch))
+    done, plain_lat = 0.0, []
+    for ta, sv in zip(arrivals, service):
+        start = max(ta, done)
+        done = start + sv
+        plain_lat.append(done - ta)
+    plain_lat = np.array(plain_lat)
+    plain_span = done - 0.0
+    print(f"plain fp64: busy {sum(service):.2f} s, p99 {np.percentile(plain_lat, 99):.3f} s",
+          file=sys.stderr, flush=True)
+    return {"workload": f"{len(reqs)} Poisson-arrival requests at {args.serve_rate}/s, edge in {{32..128}}, "
+                        f"50-300 steps, rtol 1e-8", "precision": args.batch_precision,
+            "solves_per_s": round(len(reqs) / t_all, 3), "p50_s": round(float(np.percentile(lat, 50)), 4),
+            "p99_s": round(float(np.percentile(lat, 99)), 4), "max_rel_err_vs_plain_fp64": max(errs),
+            "peak_hbm_bytes": int(info["peak_bytes_in_use"]), "epochs": int(info["epochs"]),
+            "plain_fp64": {"solves_per_s": round(len(reqs) / plain_span, 3),
+                           "busy_solves_per_s": round(len(reqs) / sum(service), 3),
+                           "p50_s": round(float(np.percentile(plain_lat, 50)), 4),
+                           "p99_s": round(float(np.percentile(plain_lat, 99)), 4)}}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -74,6 +206,17 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-timing", action="store_true", help="time without per-kernel HIP events")
     ap.add_argument("--tile", type=int, nargs=3, default=(0, 0, 0))
+    ap.add_argument("--batched", action="store_true", help="add the batched-proposals measurement")
+    ap.add_argument("--served", action="store_true", help="add the serving measurement")
+    ap.add_argument("--only-extra", action="store_true", help="skip the 1M-DOF headline run")
+    ap.add_argument("--batch-sims", type=int, default=64)
+    ap.add_argument("--batch-n", type=int, default=48)
+    ap.add_argument("--batch-nsteps", type=int, default=100)
+    ap.add_argument("--batch-precision", choices=["fp64", "mixed"], default="mixed")
+    ap.add_argument("--plain-sample", type=int, default=8)
+    ap.add_argument("--loose-rtols", type=float, nargs="*", default=[1e-6, 1e-7])
+    ap.add_argument("--serve-requests", type=int, default=32)
+    ap.add_argument("--serve-rate", type=float, default=8.0)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 256 MiB device copy 3 times (scale for rocprof FETCH/WRITE_SIZE)")
     args = ap.parse_args()
@@ -82,7 +225,6 @@ def main():
               "independent simulations would shard across GPUs with no communication.", file=sys.stderr)
         sys.exit(2)
 
-    import numpy as np
     import torch
 
     if args.copy_calibration:
@@ -99,6 +241,14 @@ def main():
     from paper_1905_07622_amd import workloads as wl
 
     torch.cuda.set_device(0)
+    extra = {}
+    if args.batched:
+        extra["batched"] = bench_batched(args, torch)
+    if args.served:
+        extra["served"] = bench_served(args, torch)
+    if args.only_extra:
+        print(json.dumps(extra), flush=True)
+        return
     p = wl.lognormal_cube(args.n, seed=2, nsteps=args.nsteps)
     dev = "cuda"
     k = torch.tensor(p.k_e, device=dev)
@@ -169,10 +319,10 @@ def main():
                    "grid_blocks": shape["grid_blocks"]},
         "roofline": roof,
     }
+    line.update(extra)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(p)
     print(json.dumps(line), flush=True)
-    del np
 
 
 if __name__ == "__main__":

@@ -201,6 +201,78 @@ typedef struct {
  * status in request order; FEM_ENOMEM / FEM_EDEVICE abort the whole batch. */
 int fem_heat_run_batch(const fem_request *reqs, int32_t n, const fem_opts *opts, int32_t *status);
 
+/* ---- serving: continuous batching of forward simulations ------------------
+ *
+ * A server owns one HIP stream and a worker thread that advances every
+ * admitted simulation one time step per epoch with the batched launches of
+ * fem_heat_run_batch.  Submitted requests wait in a FIFO queue; at each epoch
+ * boundary finished simulations retire (outputs written, device memory
+ * released, completion stamped) and queued ones are admitted in order while
+ * their device footprint fits the free part of the HBM budget and a slot is
+ * free (the head of the queue is never overtaken).  An admitted simulation
+ * keeps its whole PCG state resident until it finishes, and joins the
+ * launches at the next epoch while the others continue: its results are
+ * bit-identical to those of a batch holding it alone.  The use case is the
+ * paper's coefficient study of thousands of forward solves (Sec. 5.4). */
+
+#define FEM_REQ_QUEUED 0
+#define FEM_REQ_RUNNING 1
+#define FEM_REQ_DONE 2       /* finished: status holds the run's outcome        */
+#define FEM_REQ_CANCELED 3
+
+typedef struct fem_server fem_server;
+
+typedef struct {
+  uint64_t hbm_budget_bytes; /* device bytes admitted simulations may hold; 0 = 3/4 of free memory at create */
+  int32_t max_slots;         /* simulations in flight at most; 0 = 256 */
+  fem_opts opts;             /* as for fem_heat_run_batch; FEM_DEVICE_PTRS and FEM_TIMING are not accepted */
+} fem_server_opts;
+
+typedef struct {
+  int32_t state;             /* FEM_REQ_*                                          */
+  int32_t status;            /* DONE: FEM_OK / FEM_ENOCONV / FEM_EBREAKDOWN / FEM_ENOMEM / FEM_EDEVICE;
+                                CANCELED: FEM_ECANCELED; otherwise FEM_OK          */
+  int32_t steps_done;
+  double t_arrive, t_admit, t_done; /* seconds on the server's monotonic clock; < 0 until reached */
+  uint64_t bytes;            /* device footprint charged against the budget          */
+} fem_status;
+
+typedef struct {
+  int64_t submitted, completed, canceled, failed, epochs;
+  int32_t queued, running;
+  uint64_t budget_bytes, bytes_in_use, peak_bytes_in_use;
+  double now;                /* the server's clock                                   */
+} fem_server_info;
+
+/* Start a server on opts->opts.device (opts may be NULL: defaults). */
+int fem_server_create(const fem_server_opts *opts, fem_server **out);
+
+/* Queue a request (validated as by fem_heat_run_batch; host pointers).  All
+ * inputs -- coefficients, fields, schedule, sensor points -- are copied before
+ * returning; the output arrays named by req->out (may be NULL) must stay
+ * valid until the request is DONE or CANCELED, and are written by then
+ * (total_iters and device_ms = time from admission to completion, too).
+ * FEM_ENOMEM: the request alone exceeds the budget (nothing queued). */
+int fem_server_submit(fem_server *s, const fem_request *req, uint64_t *ticket);
+
+/* Current state of a request (non-blocking).  FEM_EINVAL: unknown ticket. */
+int fem_server_poll(fem_server *s, uint64_t ticket, fem_status *st);
+
+/* Wait until the request is DONE or CANCELED or timeout_s passes (< 0: no
+ * limit).  Returns its final status, or FEM_EBUSY on timeout; *st (may be
+ * NULL) receives the state either way. */
+int fem_server_wait(fem_server *s, uint64_t ticket, double timeout_s, fem_status *st);
+
+/* Cancel a queued or running request (a running one leaves at the next epoch
+ * boundary; its outputs are not written).  No effect once DONE. */
+int fem_server_cancel(fem_server *s, uint64_t ticket);
+
+/* Counters and memory use. */
+int fem_server_info_get(fem_server *s, fem_server_info *info);
+
+/* Cancel everything outstanding, stop the worker and release the server. */
+void fem_server_destroy(fem_server *s);
+
 /* Kernel timing and launch shape of the last run (FEM_TIMING). */
 int fem_heat_stats(const fem_heat *h, fem_stats *out);
 
@@ -213,7 +285,7 @@ void fem_heat_default_opts(fem_opts *opts);
 
 const char *fem_strerror(int status);
 /* Message of the last failing call on a handle; with NULL, of the last failing
- * fem_heat_create or fem_heat_run_batch on the calling thread. */
+ * fem_heat_create, fem_heat_run_batch or fem_server_* call on the calling thread. */
 const char *fem_last_error(const fem_heat *h);
 
 #ifdef __cplusplus

@@ -10,6 +10,7 @@
 #include <string>
 #include <vector>
 
+#include "server.hpp"
 #include "solver.hpp"
 
 namespace {
@@ -120,27 +121,6 @@ int check_run(const femheat::Geom& g, bool dev, const double* T0, double dt, dou
   return FEM_OK;
 }
 
-// A validated problem's handle; `batched` selects the tile rule of batch members.
-int make_handle(const fem_grid* grid, const double* k_e, const double* rhoc_e, const fem_bc* bc, const fem_opts& o,
-                bool batched, fem_heat** out, std::string& why) {
-  fem_heat* h = new (std::nothrow) fem_heat();
-  if (!h) return FEM_ENOMEM;
-  h->opts = o;
-  h->devptrs = (o.flags & FEM_DEVICE_PTRS) != 0;
-  h->timing = (o.flags & FEM_TIMING) != 0;
-  h->device = o.device;
-  h->batched = batched;
-  const int rc = femheat::solver_init(h, grid, k_e, rhoc_e, bc);
-  if (rc != FEM_OK) {
-    why = h->err;
-    femheat::solver_free(h);
-    delete h;
-    return rc;
-  }
-  *out = h;
-  return FEM_OK;
-}
-
 }  // namespace
 
 extern "C" {
@@ -182,7 +162,7 @@ int fem_heat_create(const fem_grid* grid, const double* k_e, const double* rhoc_
   int rc = check_opts(opts, o, g_create_error);
   if (rc == FEM_OK) rc = check_problem(grid, k_e, rhoc_e, bc, o, g_create_error);
   if (rc != FEM_OK) return rc;
-  return make_handle(grid, k_e, rhoc_e, bc, o, false, out, g_create_error);
+  return femheat::make_handle(grid, k_e, rhoc_e, bc, o, false, out, &g_create_error);
 }
 
 int fem_heat_run(fem_heat* h, const double* T0, const double* T_prev, double dt, double theta, int32_t nsteps,
@@ -258,7 +238,7 @@ int fem_heat_run_batch(const fem_request* reqs, int32_t n, const fem_opts* opts,
   try {
     for (int32_t i = 0; i < n && rc == FEM_OK; ++i) {
       const fem_request& r = reqs[i];
-      rc = make_handle(&r.grid, r.k_e, r.rhoc_e, &r.bc, o, true, &hs[(size_t)i], g_create_error);
+      rc = femheat::make_handle(&r.grid, r.k_e, r.rhoc_e, &r.bc, o, true, &hs[(size_t)i], &g_create_error);
       rq[(size_t)i] = femheat::RunRequest{hs[(size_t)i], r.T0, r.T_prev, r.dt, r.theta, r.rtol, r.nsteps, r.out};
     }
     if (rc == FEM_OK) rc = femheat::engine_run(rq.data(), n, stream, o, st.data(), &g_create_error);
@@ -304,6 +284,88 @@ int fem_heat_apply(fem_heat* h, int32_t which, double dt, double theta, const do
     h->err = "unexpected exception";
     return FEM_EDEVICE;
   }
+}
+
+int fem_server_create(const fem_server_opts* opts, fem_server** out) {
+  g_create_error.clear();
+  if (!out) return FEM_EINVAL;
+  *out = nullptr;
+  fem_server_opts so{};
+  fem_heat_default_opts(&so.opts);
+  if (opts) so = *opts;
+  fem_opts o;
+  int rc = check_opts(&so.opts, o, g_create_error);
+  if (rc != FEM_OK) return rc;
+  if (o.flags & (FEM_DEVICE_PTRS | FEM_TIMING)) {
+    g_create_error = "the server takes host pointers and does not time kernels";
+    return FEM_EINVAL;
+  }
+  if (so.max_slots < 0) {
+    g_create_error = "max_slots must be >= 0";
+    return FEM_EINVAL;
+  }
+  so.opts = o;
+  try {
+    return femheat::server_create(so, out, &g_create_error);
+  } catch (const std::bad_alloc&) {
+    g_create_error = "host allocation failed";
+    return FEM_ENOMEM;
+  } catch (...) {
+    g_create_error = "unexpected exception";
+    return FEM_EDEVICE;
+  }
+}
+
+int fem_server_submit(fem_server* s, const fem_request* req, uint64_t* ticket) {
+  g_create_error.clear();
+  if (!s || !req || !ticket) {
+    g_create_error = "server, request and ticket are required";
+    return FEM_EINVAL;
+  }
+  fem_opts o;
+  fem_heat_default_opts(&o);  // host pointers: validation reads them directly
+  int rc = check_problem(&req->grid, req->k_e, req->rhoc_e, &req->bc, o, g_create_error);
+  if (rc == FEM_OK) {
+    femheat::Geom g{};
+    g.nx = req->grid.nx;
+    g.ny = req->grid.ny;
+    g.nz = req->grid.nz;
+    g.hx = req->grid.hx;
+    g.hy = req->grid.hy;
+    g.hz = req->grid.hz;
+    rc = check_run(g, false, req->T0, req->dt, req->theta, req->rtol, req->nsteps, req->out, g_create_error);
+  }
+  if (rc != FEM_OK) return rc;
+  try {
+    return femheat::server_submit(s, *req, ticket, &g_create_error);
+  } catch (const std::bad_alloc&) {
+    g_create_error = "host allocation failed";
+    return FEM_ENOMEM;
+  }
+}
+
+int fem_server_poll(fem_server* s, uint64_t ticket, fem_status* st) {
+  if (!s || !st) return FEM_EINVAL;
+  return femheat::server_poll(s, ticket, st);
+}
+
+int fem_server_wait(fem_server* s, uint64_t ticket, double timeout_s, fem_status* st) {
+  if (!s) return FEM_EINVAL;
+  return femheat::server_wait(s, ticket, timeout_s, st);
+}
+
+int fem_server_cancel(fem_server* s, uint64_t ticket) {
+  if (!s) return FEM_EINVAL;
+  return femheat::server_cancel(s, ticket);
+}
+
+int fem_server_info_get(fem_server* s, fem_server_info* info) {
+  if (!s || !info) return FEM_EINVAL;
+  return femheat::server_info(s, info);
+}
+
+void fem_server_destroy(fem_server* s) {
+  if (s) femheat::server_destroy(s);
 }
 
 int fem_heat_stats(const fem_heat* h, fem_stats* out) {

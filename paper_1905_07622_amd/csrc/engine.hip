@@ -25,9 +25,11 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <memory>
 #include <vector>
 
 #include "batch.hpp"
+#include "engine.hpp"
 #include "runtime.hpp"
 
 namespace femheat {
@@ -41,6 +43,8 @@ double schedule_value(const fem_heat* h, int64_t m) {
 
 // Residual replacements among iterations 0..j-1 of a solve (i mod R == 0).
 int replacements_before(int j, int R) { return (R <= 0 || j <= 0) ? 0 : (j - 1) / R + 1; }
+
+}  // namespace
 
 // Host state of one simulation of the engine.
 struct Sim {
@@ -63,6 +67,8 @@ struct Sim {
   Scalars so{}, si{};  // latest settled outer and inner state
 };
 
+namespace {
+
 // A set of simulations launched together: one kernel per gather for the
 // cubic and one for the general-element members.
 struct Group {
@@ -70,6 +76,8 @@ struct Group {
   uint32_t off = 0, nwork = 0, nthreads = 64;
   size_t smem64 = 0, smem32 = 0;
 };
+
+}  // namespace
 
 class Engine {
  public:
@@ -92,9 +100,12 @@ class Engine {
       if (e) (void)hipEventDestroy(e);
   }
 
-  int add(const RunRequest& r);
+  int add(const RunRequest& r, Sim** out = nullptr);
   int run();
-  std::vector<Sim>& sims() { return sims_; }
+  int step(int* active);
+  int write_outputs(Sim& s, float ms);
+  void remove(Sim* s);
+  std::vector<std::unique_ptr<Sim>>& sims() { return sims_; }
   fem_stats stats{};
 
  private:
@@ -114,7 +125,6 @@ class Engine {
   int epoch();
   int mixed_sweeps();
   int finish_step(Sim& s);
-  int write_outputs(Sim& s, float ms);
   int ensure_events(size_t n);
 
   hipStream_t stream_;
@@ -123,9 +133,10 @@ class Engine {
   bool mixed_ = false, timing_ = false;
   int R_ = 50;
 
-  std::vector<Sim> sims_;
-  std::vector<int> act_;  // simulations of the current epoch, in SimDev order
-  bool multi_ = false;    // more than one simulation: launches go through work tables
+  std::vector<std::unique_ptr<Sim>> sims_;
+  std::vector<Sim*> act_;  // simulations of the current epoch, in SimDev order
+  bool dirty_ = true;      // membership changed since the last composition
+  bool multi_ = false;     // more than one simulation: launches go through work tables
 
   SimDev* sd_dev_ = nullptr;
   SimDev* sd_host_[2] = {nullptr, nullptr};  // pinned staging, used alternately
@@ -160,9 +171,10 @@ int Engine::ensure_events(size_t n) {
 }
 
 // Set-up of one simulation: operator for its theta*dt, fields, sensors.
-int Engine::add(const RunRequest& r) {
+int Engine::add(const RunRequest& r, Sim** out) {
   fem_heat* h = r.h;
-  Sim s;
+  auto sp = std::make_unique<Sim>();
+  Sim& s = *sp;
   s.rq = r;
   const uint32_t N = h->g.N;
   RC_TRY(prepare_operator(h, r.theta * r.dt, mixed_));
@@ -203,8 +215,19 @@ int Engine::add(const RunRequest& r) {
   s.sweeps.assign(ns, 0);
   s.relres.assign(ns, 0.0);
   s.finished = r.nsteps <= 0;
-  sims_.push_back(std::move(s));
+  if (out) *out = sp.get();
+  sims_.push_back(std::move(sp));
+  dirty_ = true;
   return FEM_OK;
+}
+
+void Engine::remove(Sim* s) {
+  for (size_t i = 0; i < sims_.size(); ++i)
+    if (sims_[i].get() == s) {
+      sims_.erase(sims_.begin() + (long)i);
+      dirty_ = true;
+      return;
+    }
 }
 
 void Engine::fill_simdev(const Sim& s, SimDev& d) const {
@@ -270,7 +293,7 @@ int Engine::upload_simdev() {
   fem_heat* h = h_;
   SimDev* stage = sd_host_[sd_flip_];
   sd_flip_ ^= 1;
-  for (size_t k = 0; k < act_.size(); ++k) fill_simdev(sims_[act_[k]], stage[k]);
+  for (size_t k = 0; k < act_.size(); ++k) fill_simdev(*act_[k], stage[k]);
   HIP_TRY(hipMemcpyAsync(sd_dev_, stage, act_.size() * sizeof(SimDev), hipMemcpyHostToDevice, stream_));
   return FEM_OK;
 }
@@ -279,10 +302,11 @@ int Engine::upload_simdev() {
 // rebuilds the launch groups and work tables when that set changed.
 int Engine::compose() {
   fem_heat* h = h_;
-  std::vector<int> next;
-  for (size_t i = 0; i < sims_.size(); ++i)
-    if (!sims_[i].finished) next.push_back((int)i);
-  if (next == act_ && ngroups_ > 0) return FEM_OK;
+  std::vector<Sim*> next;
+  for (auto& sp : sims_)
+    if (!sp->finished) next.push_back(sp.get());
+  if (!dirty_ && next == act_ && ngroups_ > 0) return FEM_OK;
+  dirty_ = false;
   HIP_TRY(hipStreamSynchronize(stream_));  // buffers below may be freed or rewritten
   act_ = next;
   const size_t n = act_.size();
@@ -313,7 +337,7 @@ int Engine::compose() {
     g.cubic = cls == 0;
     g.off = (uint32_t)tab.size();
     for (size_t k = 0; k < n; ++k) {
-      const fem_heat* sh = sims_[act_[k]].rq.h;
+      const fem_heat* sh = act_[k]->rq.h;
       if (sh->cubic != g.cubic) continue;
       for (uint32_t b = 0; b < sh->shape.nblocks; ++b) tab.push_back(make_uint2((uint32_t)k, b));
       g.nthreads = std::max<uint32_t>(g.nthreads, (uint32_t)sh->shape.nthreads);
@@ -326,7 +350,7 @@ int Engine::compose() {
   auto add_kind = [&](uint32_t fem_heat::*count, uint32_t& off, uint32_t& total) {
     off = (uint32_t)tab.size();
     for (size_t k = 0; k < n; ++k) {
-      const fem_heat* sh = sims_[act_[k]].rq.h;
+      const fem_heat* sh = act_[k]->rq.h;
       for (uint32_t b = 0; b < sh->*count; ++b) tab.push_back(make_uint2((uint32_t)k, b));
     }
     total = (uint32_t)tab.size() - off;
@@ -426,7 +450,7 @@ int Engine::pcg(int first_chunk) {
     bool all_done = true;
     int most = j;
     for (size_t q = 0; q < act_.size(); ++q) {
-      Sim& s = sims_[act_[q]];
+      Sim& s = *act_[q];
       const Scalars& t = snap_host_[q];
       (inner ? s.si : s.so) = t;
       if (!t.done) all_done = false;
@@ -463,15 +487,15 @@ int Engine::mixed_sweeps() {
   fem_heat* h = h_;
   RC_TRY(decide(false));
   for (size_t q = 0; q < act_.size(); ++q) {
-    Sim& s = sims_[act_[q]];
+    Sim& s = *act_[q];
     s.so = snap_host_[q];
     if (s.so.status != 0) s.broke = true;
   }
   for (;;) {
     bool any = false;
     int est = 1;
-    for (int i : act_) {
-      Sim& s = sims_[i];
+    for (Sim* sp : act_) {
+      Sim& s = *sp;
       s.sweeping = !s.broke && !s.so.done && s.nsw < opts_.max_refine;
       if (s.sweeping) {
         any = true;
@@ -487,8 +511,8 @@ int Engine::mixed_sweeps() {
     icur_ ^= 1;
     iprev_ = PK_START;
     RC_TRY(pcg<float>(est));
-    for (int i : act_) {
-      Sim& s = sims_[i];
+    for (Sim* sp : act_) {
+      Sim& s = *sp;
       if (!s.sweeping) continue;
       if (s.si.status != 0) {
         s.broke = true;
@@ -502,27 +526,27 @@ int Engine::mixed_sweeps() {
     RC_TRY(gather<RoleCorr>(args(ocur_, oprev_, 0, 0)));
     ocur_ ^= 1;
     oprev_ = PK_GATHER;
-    for (int i : act_) {
-      Sim& s = sims_[i];
+    for (Sim* sp : act_) {
+      Sim& s = *sp;
       if (!s.sweeping) continue;
       s.xc ^= 1;
       s.nsw += 1;
     }
     RC_TRY(decide(false));
     for (size_t q = 0; q < act_.size(); ++q) {
-      Sim& s = sims_[act_[q]];
+      Sim& s = *act_[q];
       s.so = snap_host_[q];
       if (s.so.status != 0) s.broke = true;
     }
   }
-  for (int i : act_) sims_[i].sweeping = false;
+  for (Sim* sp : act_) sp->sweeping = false;
   return FEM_OK;
 }
 
 // One theta-scheme step of every simulation of the batch.
 int Engine::epoch() {
-  for (int i : act_) {
-    Sim& s = sims_[i];
+  for (Sim* sp : act_) {
+    Sim& s = *sp;
     s.it = s.nsw = s.xc = s.exc = 0;
     s.sweeping = s.broke = false;
   }
@@ -537,16 +561,16 @@ int Engine::epoch() {
     RC_TRY(mixed_sweeps());
   } else {
     int est = 1;
-    for (int i : act_) est = std::max(est, sims_[i].est);
+    for (Sim* sp : act_) est = std::max(est, sp->est);
     RC_TRY(pcg<double>(est));
-    for (int i : act_) {
-      Sim& s = sims_[i];
+    for (Sim* sp : act_) {
+      Sim& s = *sp;
       s.it = s.so.iter;
       if (s.so.status != 0) s.broke = true;
       s.xc = replacements_before(s.it, R_) & 1;
     }
   }
-  for (int i : act_) RC_TRY(finish_step(sims_[i]));
+  for (Sim* sp : act_) RC_TRY(finish_step(*sp));
   return FEM_OK;
 }
 
@@ -615,25 +639,48 @@ int Engine::write_outputs(Sim& s, float ms) {
   return FEM_OK;
 }
 
+// One epoch: every simulation that still has steps advances by one step.
+// *active receives how many took part (0: nothing left to do).
+int Engine::step(int* active) {
+  RC_TRY(compose());
+  *active = (int)act_.size();
+  if (act_.empty()) return FEM_OK;
+  return epoch();
+}
+
 int Engine::run() {
   fem_heat* h = h_;
   for (auto& e : ev_run_) HIP_TRY(hipEventCreate(&e));
   HIP_TRY(hipEventRecord(ev_run_[0], stream_));
   for (;;) {
-    RC_TRY(compose());
-    if (act_.empty()) break;
-    RC_TRY(epoch());
+    int active = 0;
+    RC_TRY(step(&active));
+    if (active == 0) break;
   }
   HIP_TRY(hipEventRecord(ev_run_[1], stream_));
   HIP_TRY(hipEventSynchronize(ev_run_[1]));
   float ms = 0.f;
   HIP_TRY(hipEventElapsedTime(&ms, ev_run_[0], ev_run_[1]));
-  for (auto& s : sims_) RC_TRY(write_outputs(s, ms));
+  for (auto& s : sims_) RC_TRY(write_outputs(*s, ms));
   HIP_TRY(hipStreamSynchronize(stream_));
   return FEM_OK;
 }
 
-}  // namespace
+// ---- opaque interface for the server ------------------------------------------
+
+Engine* engine_new(hipStream_t stream, const fem_opts& opts, fem_heat* err) { return new Engine(stream, opts, err); }
+void engine_delete(Engine* e) { delete e; }
+int engine_add(Engine* e, const RunRequest& r, Sim** out) { return e->add(r, out); }
+int engine_step(Engine* e, int* active) { return e->step(active); }
+bool engine_sim_finished(const Sim* s) { return s->finished; }
+int engine_sim_status(const Sim* s) { return s->status; }
+int32_t engine_sim_steps(const Sim* s) { return s->step; }
+int engine_finish(Engine* e, Sim* s, double ms) {
+  const int rc = e->write_outputs(*s, (float)ms);
+  e->remove(s);
+  return rc;
+}
+void engine_drop(Engine* e, Sim* s) { e->remove(s); }
 
 int solver_run(fem_heat* h, const double* T0, const double* T_prev, double dt, double theta, int32_t nsteps,
                double rtol, fem_out* out) {
@@ -663,7 +710,7 @@ int engine_run(const RunRequest* reqs, int32_t n, hipStream_t stream, const fem_
     if (err) *err = h->err;
     return rc;
   }
-  for (int32_t i = 0; i < n; ++i) status[i] = e.sims()[i].status;
+  for (int32_t i = 0; i < n; ++i) status[i] = e.sims()[(size_t)i]->status;
   if (n == 1 && (opts.flags & FEM_TIMING)) {
     fem_heat* one = reqs[0].h;
     const fem_stats keep = one->stats;

@@ -1,0 +1,395 @@
+// Serving loop: continuous batching of forward simulations on one GPU.
+//
+// A worker thread owns the stream and an engine.  Each turn of its loop is
+// one epoch boundary: finished simulations retire (outputs, memory,
+// completion stamp), cancelled ones leave, queued requests are admitted in
+// FIFO order while their device footprint fits the free budget and a slot
+// is free, and then every admitted simulation advances one time step with
+// the batched launches.  Requests that arrive while others run therefore
+// join them at the next step boundary.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <thread>
+#include <vector>
+
+#include "engine.hpp"
+#include "server.hpp"
+
+namespace {
+
+using Clock = std::chrono::steady_clock;
+
+// A request with its own copies of every input.
+struct Request {
+  uint64_t ticket = 0;
+  fem_grid grid{};
+  fem_bc bc{};
+  std::vector<double> k_e, rhoc_e, T0, T_prev, sched, sensors;
+  double dt = 0, theta = 0, rtol = 0;
+  int32_t nsteps = 0;
+  fem_out out{};                  // outputs point into the caller's arrays; inputs into ours
+  fem_out* caller_out = nullptr;  // receives total_iters and device_ms
+  fem_status st{};
+  bool cancel = false;
+  fem_heat* h = nullptr;
+  femheat::Sim* sim = nullptr;
+};
+
+}  // namespace
+
+struct fem_server {
+  fem_server_opts o{};
+  hipStream_t stream = nullptr;
+  femheat::Engine* eng = nullptr;
+  fem_heat errh;  // receives the engine's messages
+
+  std::mutex mu;
+  std::condition_variable cv_work, cv_done;
+  std::deque<Request*> queue;
+  std::map<uint64_t, std::unique_ptr<Request>> reqs;
+  std::vector<Request*> running;  // admitted (touched by the worker only, counted under mu)
+  uint64_t next_ticket = 1;
+  uint64_t budget = 0, in_use = 0, peak = 0;
+  int64_t submitted = 0, completed = 0, canceled = 0, failed = 0, epochs = 0;
+  int32_t nrunning = 0;
+  bool stop = false;
+  Clock::time_point t0;
+  std::thread worker;
+
+  double now() const { return std::chrono::duration<double>(Clock::now() - t0).count(); }
+  void loop();
+  void finish(Request* r, int state, int status, bool charged);
+  void fail_all(int status);
+};
+
+namespace {
+
+void free_handle(Request* r) {
+  if (r->h) {
+    femheat::solver_free(r->h);
+    delete r->h;
+    r->h = nullptr;
+  }
+  r->sim = nullptr;
+}
+
+}  // namespace
+
+// Marks a request terminal and releases its budget if it was admitted
+// (called with mu held).
+void fem_server::finish(Request* r, int state, int status, bool charged) {
+  r->st.state = state;
+  r->st.status = status;
+  r->st.t_done = now();
+  if (charged) in_use -= r->st.bytes;
+  if (state == FEM_REQ_CANCELED)
+    ++canceled;
+  else if (status == FEM_OK || status == FEM_ENOCONV)
+    ++completed;
+  else
+    ++failed;
+}
+
+void fem_server::loop() {
+  (void)hipSetDevice(o.opts.device);
+  for (;;) {
+    std::vector<Request*> admit, cancelled;
+    {
+      std::unique_lock<std::mutex> lk(mu);
+      cv_work.wait(lk, [&] { return stop || !queue.empty() || !running.empty(); });
+      if (stop) {
+        for (Request* r : queue) finish(r, FEM_REQ_CANCELED, FEM_ECANCELED, false);
+        queue.clear();
+        for (Request* r : running) r->cancel = true;
+      }
+      for (Request* r : running)
+        if (r->cancel) cancelled.push_back(r);
+      // admission: FIFO, the head is never overtaken
+      const size_t slots = (size_t)o.max_slots;
+      while (!queue.empty() && running.size() - cancelled.size() + admit.size() < slots) {
+        Request* r = queue.front();
+        if (r->st.bytes > budget - in_use) break;
+        queue.pop_front();
+        in_use += r->st.bytes;
+        peak = std::max(peak, in_use);
+        admit.push_back(r);
+      }
+    }
+    // cancelled simulations leave without outputs
+    for (Request* r : cancelled) {
+      femheat::engine_drop(eng, r->sim);
+      free_handle(r);
+      std::lock_guard<std::mutex> lk(mu);
+      running.erase(std::find(running.begin(), running.end(), r));
+      finish(r, FEM_REQ_CANCELED, FEM_ECANCELED, true);
+    }
+    {
+      std::lock_guard<std::mutex> lk(mu);
+      if (stop && running.empty()) {
+        for (Request* r : admit) finish(r, FEM_REQ_CANCELED, FEM_ECANCELED, true);
+        nrunning = 0;
+        cv_done.notify_all();
+        return;
+      }
+    }
+    // admitted requests: device state and engine membership
+    for (Request* r : admit) {
+      fem_opts ho = o.opts;
+      ho.hip_stream = stream;
+      std::string why;
+      fem_heat* h = nullptr;
+      int rc = femheat::make_handle(&r->grid, r->k_e.data(), r->rhoc_e.data(), &r->bc, ho, true, &h, &why);
+      if (rc == FEM_OK) {
+        r->h = h;
+        femheat::RunRequest rq{h, r->T0.data(), r->T_prev.empty() ? nullptr : r->T_prev.data(), r->dt, r->theta,
+                               r->rtol, r->nsteps, &r->out};
+        rc = femheat::engine_add(eng, rq, &r->sim);
+      }
+      std::lock_guard<std::mutex> lk(mu);
+      if (rc != FEM_OK) {
+        free_handle(r);
+        finish(r, FEM_REQ_DONE, rc, true);
+        continue;
+      }
+      r->st.state = FEM_REQ_RUNNING;
+      r->st.t_admit = now();
+      running.push_back(r);
+    }
+    {
+      std::lock_guard<std::mutex> lk(mu);
+      nrunning = (int32_t)running.size();
+    }
+    if (running.empty()) {
+      cv_done.notify_all();
+      continue;
+    }
+    // one epoch for every admitted simulation
+    int active = 0;
+    const int rc = femheat::engine_step(eng, &active);
+    std::vector<Request*> done;
+    {
+      std::lock_guard<std::mutex> lk(mu);
+      ++epochs;
+      for (Request* r : running) {
+        r->st.steps_done = femheat::engine_sim_steps(r->sim);
+        if (rc != FEM_OK || femheat::engine_sim_finished(r->sim)) done.push_back(r);
+      }
+    }
+    for (Request* r : done) {
+      int status = rc != FEM_OK ? rc : femheat::engine_sim_status(r->sim);
+      const double ms = (now() - r->st.t_admit) * 1e3;
+      if (rc == FEM_OK) {
+        const int wrc = femheat::engine_finish(eng, r->sim, ms);
+        if (wrc != FEM_OK) status = wrc;
+      } else {
+        femheat::engine_drop(eng, r->sim);
+      }
+      if (r->caller_out && status != FEM_EDEVICE) {
+        r->caller_out->total_iters = r->out.total_iters;
+        r->caller_out->device_ms = r->out.device_ms;
+      }
+      free_handle(r);
+      std::lock_guard<std::mutex> lk(mu);
+      running.erase(std::find(running.begin(), running.end(), r));
+      finish(r, FEM_REQ_DONE, status, true);
+    }
+    {
+      std::lock_guard<std::mutex> lk(mu);
+      nrunning = (int32_t)running.size();
+    }
+    cv_done.notify_all();
+  }
+}
+
+// Ends every outstanding request with `status` and stops admitting (after an
+// exception in the worker, whose engine state is then unknown).
+void fem_server::fail_all(int status) {
+  std::lock_guard<std::mutex> lk(mu);
+  for (Request* r : running) {
+    free_handle(r);
+    finish(r, FEM_REQ_DONE, status, true);
+  }
+  running.clear();
+  for (Request* r : queue) finish(r, FEM_REQ_DONE, status, false);
+  queue.clear();
+  nrunning = 0;
+  stop = true;
+  cv_done.notify_all();
+}
+
+namespace femheat {
+
+int server_create(const fem_server_opts& o, fem_server** out, std::string* err) {
+  auto s = std::make_unique<fem_server>();
+  s->o = o;
+  if (s->o.max_slots <= 0) s->o.max_slots = 256;
+  if (hipSetDevice(o.opts.device) != hipSuccess) {
+    *err = "hipSetDevice failed";
+    return FEM_EDEVICE;
+  }
+  s->budget = o.hbm_budget_bytes;
+  if (s->budget == 0) {
+    size_t free_b = 0, total_b = 0;
+    if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) {
+      *err = "hipMemGetInfo failed";
+      return FEM_EDEVICE;
+    }
+    s->budget = free_b / 4 * 3;
+  }
+  if (hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking) != hipSuccess) {
+    *err = "hipStreamCreate failed";
+    return FEM_EDEVICE;
+  }
+  fem_opts eo = s->o.opts;
+  eo.hip_stream = s->stream;
+  s->o.opts = eo;
+  s->eng = engine_new(s->stream, eo, &s->errh);
+  s->t0 = Clock::now();
+  fem_server* raw = s.release();
+  raw->worker = std::thread([raw] {
+    try {
+      raw->loop();
+    } catch (const std::bad_alloc&) {
+      raw->fail_all(FEM_ENOMEM);
+    } catch (...) {
+      raw->fail_all(FEM_EDEVICE);
+    }
+  });
+  *out = raw;
+  return FEM_OK;
+}
+
+int server_submit(fem_server* s, const fem_request& q, uint64_t* ticket, std::string* err) {
+  auto r = std::make_unique<Request>();
+  const size_t E = (size_t)q.grid.nx * q.grid.ny * q.grid.nz;
+  const size_t N = (size_t)(q.grid.nx + 1) * (q.grid.ny + 1) * (q.grid.nz + 1);
+  r->grid = q.grid;
+  r->k_e.assign(q.k_e, q.k_e + E);
+  r->rhoc_e.assign(q.rhoc_e, q.rhoc_e + E);
+  r->T0.assign(q.T0, q.T0 + N);
+  if (q.T_prev) r->T_prev.assign(q.T_prev, q.T_prev + N);
+  r->bc = q.bc;
+  if (q.bc.flux_schedule && q.bc.n_schedule > 0) {
+    r->sched.assign(q.bc.flux_schedule, q.bc.flux_schedule + q.bc.n_schedule);
+    r->bc.flux_schedule = r->sched.data();
+  } else {
+    r->bc.flux_schedule = nullptr;
+    r->bc.n_schedule = 0;
+  }
+  r->dt = q.dt;
+  r->theta = q.theta;
+  r->rtol = q.rtol;
+  r->nsteps = q.nsteps;
+  int32_t nsens = 0;
+  if (q.out) {
+    r->out = *q.out;
+    r->caller_out = q.out;
+    if (q.out->sensor_xyz && q.out->n_sensors > 0) {
+      nsens = q.out->n_sensors;
+      r->sensors.assign(q.out->sensor_xyz, q.out->sensor_xyz + 3 * (size_t)nsens);
+      r->out.sensor_xyz = r->sensors.data();
+    }
+    r->out.first_step = q.out->first_step;
+  }
+  r->st.state = FEM_REQ_QUEUED;
+  r->st.status = FEM_OK;
+  r->st.t_admit = r->st.t_done = -1.0;
+  r->st.bytes = handle_device_bytes(q.grid, s->o.opts, &q.bc, q.nsteps, nsens);
+  std::lock_guard<std::mutex> lk(s->mu);
+  if (r->st.bytes > s->budget) {
+    *err = "request needs " + std::to_string(r->st.bytes) + " device bytes, budget " + std::to_string(s->budget);
+    return FEM_ENOMEM;
+  }
+  if (s->stop) {
+    *err = "server is stopping";
+    return FEM_EBUSY;
+  }
+  r->ticket = s->next_ticket++;
+  r->st.t_arrive = s->now();
+  *ticket = r->ticket;
+  s->queue.push_back(r.get());
+  s->reqs[r->ticket] = std::move(r);
+  ++s->submitted;
+  s->cv_work.notify_one();
+  return FEM_OK;
+}
+
+int server_poll(fem_server* s, uint64_t ticket, fem_status* st) {
+  std::lock_guard<std::mutex> lk(s->mu);
+  auto it = s->reqs.find(ticket);
+  if (it == s->reqs.end()) return FEM_EINVAL;
+  if (st) *st = it->second->st;
+  return FEM_OK;
+}
+
+int server_wait(fem_server* s, uint64_t ticket, double timeout_s, fem_status* st) {
+  std::unique_lock<std::mutex> lk(s->mu);
+  auto it = s->reqs.find(ticket);
+  if (it == s->reqs.end()) return FEM_EINVAL;
+  Request* r = it->second.get();
+  auto terminal = [r] { return r->st.state == FEM_REQ_DONE || r->st.state == FEM_REQ_CANCELED; };
+  bool ok;
+  if (timeout_s < 0) {
+    s->cv_done.wait(lk, terminal);
+    ok = true;
+  } else {
+    ok = s->cv_done.wait_for(lk, std::chrono::duration<double>(timeout_s), terminal);
+  }
+  if (st) *st = r->st;
+  return ok ? r->st.status : FEM_EBUSY;
+}
+
+int server_cancel(fem_server* s, uint64_t ticket) {
+  std::lock_guard<std::mutex> lk(s->mu);
+  auto it = s->reqs.find(ticket);
+  if (it == s->reqs.end()) return FEM_EINVAL;
+  Request* r = it->second.get();
+  if (r->st.state == FEM_REQ_QUEUED) {
+    s->queue.erase(std::find(s->queue.begin(), s->queue.end(), r));
+    s->finish(r, FEM_REQ_CANCELED, FEM_ECANCELED, false);
+    s->cv_done.notify_all();
+  } else if (r->st.state == FEM_REQ_RUNNING) {
+    r->cancel = true;
+    s->cv_work.notify_one();
+  }
+  return FEM_OK;
+}
+
+int server_info(fem_server* s, fem_server_info* info) {
+  std::lock_guard<std::mutex> lk(s->mu);
+  info->submitted = s->submitted;
+  info->completed = s->completed;
+  info->canceled = s->canceled;
+  info->failed = s->failed;
+  info->epochs = s->epochs;
+  info->queued = (int32_t)s->queue.size();
+  info->running = s->nrunning;
+  info->budget_bytes = s->budget;
+  info->bytes_in_use = s->in_use;
+  info->peak_bytes_in_use = s->peak;
+  info->now = s->now();
+  return FEM_OK;
+}
+
+void server_destroy(fem_server* s) {
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    s->stop = true;
+  }
+  s->cv_work.notify_all();
+  if (s->worker.joinable()) s->worker.join();
+  engine_delete(s->eng);
+  (void)hipStreamSynchronize(s->stream);
+  (void)hipStreamDestroy(s->stream);
+  delete s;
+}
+
+}  // namespace femheat

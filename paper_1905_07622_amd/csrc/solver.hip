@@ -6,9 +6,11 @@
 // (Sec. 3.1); the time stepping itself lives in engine.hip, which drives one
 // handle or a batch of them.
 #include <algorithm>
+#include <new>
 #include <cmath>
 #include <cstring>
 
+#include "engine.hpp"
 #include "runtime.hpp"
 #include "vector_kernels.hpp"
 
@@ -367,6 +369,44 @@ int solver_apply(fem_heat* h, int32_t which, double dt, double theta, const doub
   RC_TRY(copy_out(h, y, yd, (size_t)N * sizeof(double)));
   HIP_TRY(hipStreamSynchronize(h->stream));
   return FEM_OK;
+}
+
+int make_handle(const fem_grid* grid, const double* k_e, const double* rhoc_e, const fem_bc* bc, const fem_opts& o,
+                bool batched, fem_heat** out, std::string* why) {
+  fem_heat* h = new (std::nothrow) fem_heat();
+  if (!h) return FEM_ENOMEM;
+  h->opts = o;
+  h->devptrs = (o.flags & FEM_DEVICE_PTRS) != 0;
+  h->timing = (o.flags & FEM_TIMING) != 0;
+  h->device = o.device;
+  h->batched = batched;
+  const int rc = solver_init(h, grid, k_e, rhoc_e, bc);
+  if (rc != FEM_OK) {
+    if (why) *why = h->err;
+    solver_free(h);
+    delete h;
+    return rc;
+  }
+  *out = h;
+  return FEM_OK;
+}
+
+size_t handle_device_bytes(const fem_grid& grid, const fem_opts& opts, const fem_bc* bc, int32_t nsteps,
+                           int32_t n_sensors) {
+  const size_t N = (size_t)(grid.nx + 1) * (grid.ny + 1) * (grid.nz + 1);
+  const size_t E = (size_t)grid.nx * grid.ny * grid.nz;
+  bool lift = false;
+  if (bc)
+    for (int f = 0; f < 6; ++f)
+      if (((bc->dirichlet_mask >> f) & 1u) && bc->dirichlet_value[f] != 0.0) lift = true;
+  // FP64: coefficients; F, pinv, b, r, q, two directions, four fields (+ lift)
+  size_t bytes = 8 * (2 * E + (11 + (lift ? 1 : 0)) * N);
+  if (opts.precision == FEM_FP32_FP64DOT) bytes += 4 * (2 * E + 8 * N);  // FP32 set
+  // relay state and partials (at most max(tiles, update blocks) per buffer) and the sink
+  const size_t tiles_bound = N / 32 + 1024;
+  bytes += 4 * (sizeof(Scalars) + 8 * tiles_bound) + 8 * 256;
+  if (n_sensors > 0) bytes += 8 * (3 * (size_t)n_sensors + (size_t)std::max(nsteps, 1) * n_sensors);
+  return bytes;
 }
 
 void solver_free(fem_heat* h) {

@@ -79,6 +79,10 @@ struct fem_heat {
 namespace femheat {
 
 int solver_init(fem_heat* h, const fem_grid* grid, const double* k_e, const double* rhoc_e, const fem_bc* bc);
+// A handle for a validated problem; `batched` selects the tile rule of batch
+// members.  On failure *why (may be NULL) receives the message.
+int make_handle(const fem_grid* grid, const double* k_e, const double* rhoc_e, const fem_bc* bc, const fem_opts& o,
+                bool batched, fem_heat** out, std::string* why);
 int solver_apply(fem_heat* h, int32_t which, double dt, double theta, const double* x, double* y);
 void solver_free(fem_heat* h);
 

@@ -70,6 +70,26 @@ class fem_request(ctypes.Structure):
                 ("rtol", ctypes.c_double), ("nsteps", ctypes.c_int32), ("out", ctypes.POINTER(fem_out))]
 
 
+FEM_REQ_QUEUED, FEM_REQ_RUNNING, FEM_REQ_DONE, FEM_REQ_CANCELED = 0, 1, 2, 3
+
+
+class fem_server_opts(ctypes.Structure):
+    _fields_ = [("hbm_budget_bytes", ctypes.c_uint64), ("max_slots", ctypes.c_int32), ("opts", fem_opts)]
+
+
+class fem_status(ctypes.Structure):
+    _fields_ = [("state", ctypes.c_int32), ("status", ctypes.c_int32), ("steps_done", ctypes.c_int32),
+                ("t_arrive", ctypes.c_double), ("t_admit", ctypes.c_double), ("t_done", ctypes.c_double),
+                ("bytes", ctypes.c_uint64)]
+
+
+class fem_server_info(ctypes.Structure):
+    _fields_ = [("submitted", ctypes.c_int64), ("completed", ctypes.c_int64), ("canceled", ctypes.c_int64),
+                ("failed", ctypes.c_int64), ("epochs", ctypes.c_int64), ("queued", ctypes.c_int32),
+                ("running", ctypes.c_int32), ("budget_bytes", ctypes.c_uint64), ("bytes_in_use", ctypes.c_uint64),
+                ("peak_bytes_in_use", ctypes.c_uint64), ("now", ctypes.c_double)]
+
+
 class FemError(RuntimeError):
     def __init__(self, status: int, msg: str):
         super().__init__(f"{fem_strerror(status)} ({status}): {msg}")
@@ -77,7 +97,9 @@ class FemError(RuntimeError):
 
 
 EXPORTS = ("fem_heat_create", "fem_heat_run", "fem_heat_apply", "fem_heat_stats", "fem_heat_destroy",
-           "fem_heat_default_opts", "fem_strerror", "fem_last_error", "fem_heat_run_batch")
+           "fem_heat_default_opts", "fem_strerror", "fem_last_error", "fem_heat_run_batch",
+           "fem_server_create", "fem_server_submit", "fem_server_poll", "fem_server_wait", "fem_server_cancel",
+           "fem_server_info_get", "fem_server_destroy")
 
 _lib = None
 
@@ -98,6 +120,17 @@ def lib():
         L.fem_heat_stats.argtypes = [vp, ctypes.POINTER(fem_stats)]
         L.fem_heat_run_batch.argtypes = [ctypes.POINTER(fem_request), ctypes.c_int32, ctypes.POINTER(fem_opts), _ip]
         L.fem_heat_run_batch.restype = ctypes.c_int
+        L.fem_server_create.argtypes = [ctypes.POINTER(fem_server_opts), ctypes.POINTER(vp)]
+        L.fem_server_submit.argtypes = [vp, ctypes.POINTER(fem_request), ctypes.POINTER(ctypes.c_uint64)]
+        L.fem_server_poll.argtypes = [vp, ctypes.c_uint64, ctypes.POINTER(fem_status)]
+        L.fem_server_wait.argtypes = [vp, ctypes.c_uint64, ctypes.c_double, ctypes.POINTER(fem_status)]
+        L.fem_server_cancel.argtypes = [vp, ctypes.c_uint64]
+        L.fem_server_info_get.argtypes = [vp, ctypes.POINTER(fem_server_info)]
+        L.fem_server_destroy.argtypes = [vp]
+        L.fem_server_destroy.restype = None
+        for n in ("fem_server_create", "fem_server_submit", "fem_server_poll", "fem_server_wait",
+                  "fem_server_cancel", "fem_server_info_get"):
+            getattr(L, n).restype = ctypes.c_int
         L.fem_heat_destroy.argtypes = [vp]
         L.fem_heat_destroy.restype = None
         L.fem_heat_default_opts.argtypes = [ctypes.POINTER(fem_opts)]
@@ -161,6 +194,44 @@ def fem_heat_destroy(h) -> None:
 
 def fem_heat_run_batch(reqs, n: int, opts: Optional[fem_opts], status_ptr) -> int:
     return lib().fem_heat_run_batch(reqs, n, ctypes.byref(opts) if opts is not None else None, status_ptr)
+
+
+def fem_server_create(opts: Optional[fem_server_opts]):
+    s = ctypes.c_void_p()
+    st = lib().fem_server_create(ctypes.byref(opts) if opts is not None else None, ctypes.byref(s))
+    return st, s
+
+
+def fem_server_submit(s, req: fem_request):
+    t = ctypes.c_uint64()
+    st = lib().fem_server_submit(s, ctypes.byref(req), ctypes.byref(t))
+    return st, t.value
+
+
+def fem_server_poll(s, ticket: int):
+    out = fem_status()
+    st = lib().fem_server_poll(s, ticket, ctypes.byref(out))
+    return st, out
+
+
+def fem_server_wait(s, ticket: int, timeout_s: float):
+    out = fem_status()
+    st = lib().fem_server_wait(s, ticket, timeout_s, ctypes.byref(out))
+    return st, out
+
+
+def fem_server_cancel(s, ticket: int) -> int:
+    return lib().fem_server_cancel(s, ticket)
+
+
+def fem_server_info_get(s):
+    out = fem_server_info()
+    st = lib().fem_server_info_get(s, ctypes.byref(out))
+    return st, out
+
+
+def fem_server_destroy(s) -> None:
+    lib().fem_server_destroy(s)
 
 
 # ---------------------------------------------------------------------------
@@ -286,6 +357,88 @@ def run_batch(problems, *, save_every=0, sensors=False, T_prev=None, check=True,
         res["total_iters"] = int(outs[i].total_iters)
         res["device_ms"] = float(outs[i].device_ms)
     return st, results
+
+
+def _status_dict(st: fem_status) -> dict:
+    return {k: getattr(st, k) for k, _ in fem_status._fields_}
+
+
+class Server:
+    """A fem_server: submit workloads.Problem requests, poll or wait for them.
+
+    Output arrays of each request are allocated here and kept alive until the
+    request is finished; ``wait`` returns them."""
+
+    def __init__(self, budget_bytes=0, max_slots=0, **opt_kw):
+        so = fem_server_opts()
+        so.hbm_budget_bytes = int(budget_bytes)
+        so.max_slots = int(max_slots)
+        so.opts = make_opts(**opt_kw)
+        st, self.s = fem_server_create(so)
+        if st != FEM_OK:
+            raise FemError(st, fem_last_error(None))
+        self._pending = {}
+
+    def submit(self, p, *, save_every=0, sensors=False) -> int:
+        a = _Arrays(False)
+        r = fem_request()
+        r.grid = fem_grid(p.nx, p.ny, p.nz, p.hx, p.hy, p.hz)
+        r.k_e = a.inp(p.k_e)
+        r.rhoc_e = a.inp(p.rhoc_e)
+        r.bc = _bc(p, a.keep)
+        r.T0 = a.inp(p.T0)
+        r.dt, r.theta, r.rtol, r.nsteps = p.dt, p.theta, p.rtol, p.nsteps
+        out, res = _outputs(a, p.n_nodes, p.nsteps, save_every, p.sensors if sensors else None)
+        r.out = ctypes.pointer(out)
+        st, ticket = fem_server_submit(self.s, r)
+        if st != FEM_OK:
+            raise FemError(st, fem_last_error(None))
+        self._pending[ticket] = (a, out, res)
+        return ticket
+
+    def poll(self, ticket: int) -> dict:
+        st, s = fem_server_poll(self.s, ticket)
+        if st != FEM_OK:
+            raise FemError(st, "unknown ticket")
+        return _status_dict(s)
+
+    def wait(self, ticket: int, timeout: float = -1.0):
+        """Returns (status, state dict, result dict or None if not finished)."""
+        st, s = fem_server_wait(self.s, ticket, timeout)
+        d = _status_dict(s)
+        if d["state"] not in (FEM_REQ_DONE, FEM_REQ_CANCELED):
+            return st, d, None
+        a, out, res = self._pending.pop(ticket)
+        res = dict(res)
+        res["status"] = d["status"]
+        res["total_iters"] = int(out.total_iters)
+        res["device_ms"] = float(out.device_ms)
+        return st, d, res
+
+    def cancel(self, ticket: int) -> int:
+        return fem_server_cancel(self.s, ticket)
+
+    def info(self) -> dict:
+        st, i = fem_server_info_get(self.s)
+        return {k: getattr(i, k) for k, _ in fem_server_info._fields_}
+
+    def close(self):
+        if getattr(self, "s", None):
+            fem_server_destroy(self.s)
+            self.s = None
+            self._pending.clear()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 class Heat:

@@ -140,3 +140,50 @@ def test_run_batch_argument_checks(lib):
     reqs = (fh.fem_request * 1)()
     bad_opts = fh.make_opts(precision=7)
     assert fh.fem_heat_run_batch(reqs, 1, bad_opts, None) == fh.FEM_EINVAL
+
+
+STRUCTS = ("fem_grid", "fem_bc", "fem_opts", "fem_out", "fem_stats", "fem_request", "fem_server_opts",
+           "fem_status", "fem_server_info")
+
+
+def test_struct_layouts_match_the_c_compiler(tmp_path):
+    """Every ctypes mirror of a header struct has the C compiler's size and
+    field offsets (compiled with gcc against include/fem_heat.h)."""
+    import ctypes
+    import shutil
+    import subprocess
+    if not shutil.which("gcc"):
+        pytest.skip("gcc not available")
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "fem_heat.h"', "int main(void) {"]
+    for name in STRUCTS:
+        cls = getattr(fh, name)
+        lines.append(f'printf("{name} %zu\\n", sizeof({name}));')
+        for field, _ in cls._fields_:
+            lines.append(f'printf("{name}.{field} %zu\\n", offsetof({name}, {field}));')
+    lines.append("return 0; }")
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c99", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    got = dict(l.split() for l in subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split("\n") if l)
+    for name in STRUCTS:
+        cls = getattr(fh, name)
+        assert int(got[name]) == ctypes.sizeof(cls), name
+        for field, _ in cls._fields_:
+            assert int(got[f"{name}.{field}"]) == getattr(cls, field).offset, f"{name}.{field}"
+
+
+def test_server_rejects_invalid_options_before_device_work(lib):
+    so = fh.fem_server_opts()
+    so.opts = fh.make_opts(device_ptrs=True)
+    st, s = fh.fem_server_create(so)
+    assert st == fh.FEM_EINVAL and not s.value
+    so.opts = fh.make_opts(precision=5)
+    assert fh.fem_server_create(so)[0] == fh.FEM_EINVAL
+    so.opts = fh.make_opts()
+    so.max_slots = -1
+    assert fh.fem_server_create(so)[0] == fh.FEM_EINVAL
+    assert fh.fem_server_poll(None, 1)[0] == fh.FEM_EINVAL
+    assert fh.fem_server_cancel(None, 1) == fh.FEM_EINVAL
+    r = fh.fem_request()
+    assert fh.fem_server_submit(None, r)[0] == fh.FEM_EINVAL
