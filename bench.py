@@ -9,6 +9,10 @@ N * (PCG iterations) / wall time / 1e6 over the timed steps, FP64.
 Printed as one JSON line with a roofline object for the dominant kernel
 (algorithmic bytes per launch / average launch time measured with HIP events
 over the timed region) and a CPU baseline (the oracle on a bounded sample).
+The same line carries the batched-proposals result ("batched": 64 x 48^3
+simulations in one fem_heat_run_batch call) and the serving result
+("served": a Poisson request stream through fem_server), each next to the
+plain one-at-a-time FP64 path on the same inputs.
 """
 from __future__ import annotations
 
@@ -206,8 +210,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-timing", action="store_true", help="time without per-kernel HIP events")
     ap.add_argument("--tile", type=int, nargs=3, default=(0, 0, 0))
-    ap.add_argument("--batched", action="store_true", help="add the batched-proposals measurement")
-    ap.add_argument("--served", action="store_true", help="add the serving measurement")
+    ap.add_argument("--no-batched", action="store_true", help="skip the batched-proposals measurement")
+    ap.add_argument("--no-served", action="store_true", help="skip the serving measurement")
     ap.add_argument("--only-extra", action="store_true", help="skip the 1M-DOF headline run")
     ap.add_argument("--batch-sims", type=int, default=64)
     ap.add_argument("--batch-n", type=int, default=48)
@@ -242,9 +246,9 @@ def main():
 
     torch.cuda.set_device(0)
     extra = {}
-    if args.batched:
+    if not args.no_batched:
         extra["batched"] = bench_batched(args, torch)
-    if args.served:
+    if not args.no_served:
         extra["served"] = bench_served(args, torch)
     if args.only_extra:
         print(json.dumps(extra), flush=True)
