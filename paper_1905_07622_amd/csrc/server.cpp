@@ -1,12 +1,16 @@
 // Serving loop: continuous batching of forward simulations on one GPU.
 //
-// A worker thread owns the stream and an engine.  Each turn of its loop is
-// one epoch boundary: finished simulations retire (outputs, memory,
-// completion stamp), cancelled ones leave, queued requests are admitted in
-// FIFO order while their device footprint fits the free budget and a slot
-// is free, and then every admitted simulation advances one time step with
-// the batched launches.  Requests that arrive while others run therefore
-// join them at the next step boundary.
+// Requests are grouped into size classes (the binary order of magnitude of
+// their node count).  Each class has a lane: a worker thread with its own
+// HIP stream and engine, so the classes' kernels run concurrently and a
+// small request never waits for the epochs of a large one.  Each turn of a
+// lane's loop is one epoch boundary: finished simulations retire (outputs,
+// memory, completion stamp), cancelled ones leave, queued requests of the
+// lane's class are admitted while their device footprint fits the free
+// budget and a slot is free, and then every simulation of the lane advances
+// one time step with the batched launches.  Admission follows arrival order
+// across all classes: a request that does not fit blocks every later one,
+// so large requests cannot starve.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -38,37 +42,61 @@ struct Request {
   fem_out out{};                  // outputs point into the caller's arrays; inputs into ours
   fem_out* caller_out = nullptr;  // receives total_iters and device_ms
   fem_status st{};
+  int key = 0;  // size class
   bool cancel = false;
   fem_heat* h = nullptr;
   femheat::Sim* sim = nullptr;
 };
 
+// Size class of a problem: floor(log2(node count)).
+int size_class(const fem_grid& g) {
+  const double n = (double)(g.nx + 1) * (g.ny + 1) * (g.nz + 1);
+  int k = 0;
+  while ((double)(1ull << (k + 1)) <= n && k < 62) ++k;
+  return k;
+}
+
+struct Lane;
+
 }  // namespace
 
 struct fem_server {
   fem_server_opts o{};
-  hipStream_t stream = nullptr;
-  femheat::Engine* eng = nullptr;
-  fem_heat errh;  // receives the engine's messages
 
   std::mutex mu;
   std::condition_variable cv_work, cv_done;
-  std::deque<Request*> queue;
+  std::deque<Request*> queue;  // all classes, arrival order
   std::map<uint64_t, std::unique_ptr<Request>> reqs;
-  std::vector<Request*> running;  // admitted (touched by the worker only, counted under mu)
+  std::map<int, std::unique_ptr<Lane>> lanes;
   uint64_t next_ticket = 1;
   uint64_t budget = 0, in_use = 0, peak = 0;
   int64_t submitted = 0, completed = 0, canceled = 0, failed = 0, epochs = 0;
-  int32_t nrunning = 0;
+  int32_t nrunning = 0;  // admitted and not yet finished, all lanes
   bool stop = false;
   Clock::time_point t0;
-  std::thread worker;
 
   double now() const { return std::chrono::duration<double>(Clock::now() - t0).count(); }
-  void loop();
   void finish(Request* r, int state, int status, bool charged);
+  int open_lane(int key, std::string* err);
+};
+
+namespace {
+
+// One size class: a stream, an engine and the worker that drives them.
+struct Lane {
+  fem_server* srv = nullptr;
+  int key = 0;
+  hipStream_t stream = nullptr;
+  femheat::Engine* eng = nullptr;
+  fem_heat errh;                  // receives the engine's messages
+  std::vector<Request*> running;  // touched by the worker; counted under srv->mu
+  bool dead = false;              // the worker stopped after an exception
+  std::thread worker;
+  void loop();
   void fail_all(int status);
 };
+
+}  // namespace
 
 namespace {
 
@@ -98,51 +126,63 @@ void fem_server::finish(Request* r, int state, int status, bool charged) {
     ++failed;
 }
 
-void fem_server::loop() {
-  (void)hipSetDevice(o.opts.device);
+void Lane::loop() {
+  fem_server& S = *srv;
+  (void)hipSetDevice(S.o.opts.device);
   for (;;) {
     std::vector<Request*> admit, cancelled;
     {
-      std::unique_lock<std::mutex> lk(mu);
-      cv_work.wait(lk, [&] { return stop || !queue.empty() || !running.empty(); });
-      if (stop) {
-        for (Request* r : queue) finish(r, FEM_REQ_CANCELED, FEM_ECANCELED, false);
-        queue.clear();
+      std::unique_lock<std::mutex> lk(S.mu);
+      // a queued request of this class that admission would take now
+      auto admissible = [&] {
+        if (S.nrunning >= S.o.max_slots) return false;
+        for (Request* r : S.queue) {
+          if (r->st.bytes > S.budget - S.in_use) return false;
+          if (r->key == key) return true;
+        }
+        return false;
+      };
+      S.cv_work.wait(lk, [&] { return S.stop || !running.empty() || admissible(); });
+      if (S.stop)
         for (Request* r : running) r->cancel = true;
-      }
       for (Request* r : running)
         if (r->cancel) cancelled.push_back(r);
-      // admission: FIFO, the head is never overtaken
-      const size_t slots = (size_t)o.max_slots;
-      while (!queue.empty() && running.size() - cancelled.size() + admit.size() < slots) {
-        Request* r = queue.front();
-        if (r->st.bytes > budget - in_use) break;
-        queue.pop_front();
-        in_use += r->st.bytes;
-        peak = std::max(peak, in_use);
-        admit.push_back(r);
+      // admission in arrival order; the first request that does not fit
+      // blocks all later ones, of any class
+      if (!S.stop) {
+        for (auto it = S.queue.begin(); it != S.queue.end();) {
+          Request* r = *it;
+          if (r->st.bytes > S.budget - S.in_use) break;
+          if (r->key != key) {
+            ++it;
+            continue;
+          }
+          if (S.nrunning + (int32_t)admit.size() >= S.o.max_slots) break;
+          it = S.queue.erase(it);
+          S.in_use += r->st.bytes;
+          S.peak = std::max(S.peak, S.in_use);
+          admit.push_back(r);
+        }
+        S.nrunning += (int32_t)admit.size();
       }
     }
     // cancelled simulations leave without outputs
     for (Request* r : cancelled) {
       femheat::engine_drop(eng, r->sim);
       free_handle(r);
-      std::lock_guard<std::mutex> lk(mu);
+      std::lock_guard<std::mutex> lk(S.mu);
       running.erase(std::find(running.begin(), running.end(), r));
-      finish(r, FEM_REQ_CANCELED, FEM_ECANCELED, true);
+      --S.nrunning;
+      S.finish(r, FEM_REQ_CANCELED, FEM_ECANCELED, true);
+      S.cv_done.notify_all();
     }
-    {
-      std::lock_guard<std::mutex> lk(mu);
-      if (stop && running.empty()) {
-        for (Request* r : admit) finish(r, FEM_REQ_CANCELED, FEM_ECANCELED, true);
-        nrunning = 0;
-        cv_done.notify_all();
-        return;
-      }
+    if (S.stop) {
+      std::lock_guard<std::mutex> lk(S.mu);
+      if (running.empty()) return;
     }
     // admitted requests: device state and engine membership
     for (Request* r : admit) {
-      fem_opts ho = o.opts;
+      fem_opts ho = S.o.opts;
       ho.hip_stream = stream;
       std::string why;
       fem_heat* h = nullptr;
@@ -153,31 +193,26 @@ void fem_server::loop() {
                                r->rtol, r->nsteps, &r->out};
         rc = femheat::engine_add(eng, rq, &r->sim);
       }
-      std::lock_guard<std::mutex> lk(mu);
+      std::lock_guard<std::mutex> lk(S.mu);
       if (rc != FEM_OK) {
         free_handle(r);
-        finish(r, FEM_REQ_DONE, rc, true);
+        --S.nrunning;
+        S.finish(r, FEM_REQ_DONE, rc, true);
+        S.cv_done.notify_all();
         continue;
       }
       r->st.state = FEM_REQ_RUNNING;
-      r->st.t_admit = now();
+      r->st.t_admit = S.now();
       running.push_back(r);
     }
-    {
-      std::lock_guard<std::mutex> lk(mu);
-      nrunning = (int32_t)running.size();
-    }
-    if (running.empty()) {
-      cv_done.notify_all();
-      continue;
-    }
-    // one epoch for every admitted simulation
+    if (running.empty()) continue;
+    // one epoch for every simulation of this lane
     int active = 0;
     const int rc = femheat::engine_step(eng, &active);
     std::vector<Request*> done;
     {
-      std::lock_guard<std::mutex> lk(mu);
-      ++epochs;
+      std::lock_guard<std::mutex> lk(S.mu);
+      ++S.epochs;
       for (Request* r : running) {
         r->st.steps_done = femheat::engine_sim_steps(r->sim);
         if (rc != FEM_OK || femheat::engine_sim_finished(r->sim)) done.push_back(r);
@@ -185,7 +220,7 @@ void fem_server::loop() {
     }
     for (Request* r : done) {
       int status = rc != FEM_OK ? rc : femheat::engine_sim_status(r->sim);
-      const double ms = (now() - r->st.t_admit) * 1e3;
+      const double ms = (S.now() - r->st.t_admit) * 1e3;
       if (rc == FEM_OK) {
         const int wrc = femheat::engine_finish(eng, r->sim, ms);
         if (wrc != FEM_OK) status = wrc;
@@ -197,32 +232,65 @@ void fem_server::loop() {
         r->caller_out->device_ms = r->out.device_ms;
       }
       free_handle(r);
-      std::lock_guard<std::mutex> lk(mu);
+      std::lock_guard<std::mutex> lk(S.mu);
       running.erase(std::find(running.begin(), running.end(), r));
-      finish(r, FEM_REQ_DONE, status, true);
+      --S.nrunning;
+      S.finish(r, FEM_REQ_DONE, status, true);
     }
-    {
-      std::lock_guard<std::mutex> lk(mu);
-      nrunning = (int32_t)running.size();
+    if (!done.empty()) {
+      S.cv_done.notify_all();
+      S.cv_work.notify_all();  // released budget or slots may admit other lanes' requests
     }
-    cv_done.notify_all();
   }
 }
 
-// Ends every outstanding request with `status` and stops admitting (after an
-// exception in the worker, whose engine state is then unknown).
-void fem_server::fail_all(int status) {
-  std::lock_guard<std::mutex> lk(mu);
+// Ends this lane's requests with `status` (after an exception in its worker,
+// whose engine state is then unknown); the lane admits nothing more.
+void Lane::fail_all(int status) {
+  std::lock_guard<std::mutex> lk(srv->mu);
+  dead = true;
   for (Request* r : running) {
     free_handle(r);
-    finish(r, FEM_REQ_DONE, status, true);
+    --srv->nrunning;
+    srv->finish(r, FEM_REQ_DONE, status, true);
   }
   running.clear();
-  for (Request* r : queue) finish(r, FEM_REQ_DONE, status, false);
-  queue.clear();
-  nrunning = 0;
-  stop = true;
-  cv_done.notify_all();
+  for (auto it = srv->queue.begin(); it != srv->queue.end();) {
+    if ((*it)->key == key) {
+      srv->finish(*it, FEM_REQ_DONE, status, false);
+      it = srv->queue.erase(it);
+    } else {
+      ++it;
+    }
+  }
+  srv->cv_done.notify_all();
+}
+
+// Starts the lane of size class `key` (called with mu held).
+int fem_server::open_lane(int key, std::string* err) {
+  auto ln = std::make_unique<Lane>();
+  ln->srv = this;
+  ln->key = key;
+  if (hipSetDevice(o.opts.device) != hipSuccess ||
+      hipStreamCreateWithFlags(&ln->stream, hipStreamNonBlocking) != hipSuccess) {
+    *err = "hipStreamCreate failed";
+    return FEM_EDEVICE;
+  }
+  fem_opts eo = o.opts;
+  eo.hip_stream = ln->stream;
+  ln->eng = femheat::engine_new(ln->stream, eo, &ln->errh);
+  Lane* raw = ln.get();
+  ln->worker = std::thread([raw] {
+    try {
+      raw->loop();
+    } catch (const std::bad_alloc&) {
+      raw->fail_all(FEM_ENOMEM);
+    } catch (...) {
+      raw->fail_all(FEM_EDEVICE);
+    }
+  });
+  lanes[key] = std::move(ln);
+  return FEM_OK;
 }
 
 namespace femheat {
@@ -244,26 +312,8 @@ int server_create(const fem_server_opts& o, fem_server** out, std::string* err) 
     }
     s->budget = free_b / 4 * 3;
   }
-  if (hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking) != hipSuccess) {
-    *err = "hipStreamCreate failed";
-    return FEM_EDEVICE;
-  }
-  fem_opts eo = s->o.opts;
-  eo.hip_stream = s->stream;
-  s->o.opts = eo;
-  s->eng = engine_new(s->stream, eo, &s->errh);
   s->t0 = Clock::now();
-  fem_server* raw = s.release();
-  raw->worker = std::thread([raw] {
-    try {
-      raw->loop();
-    } catch (const std::bad_alloc&) {
-      raw->fail_all(FEM_ENOMEM);
-    } catch (...) {
-      raw->fail_all(FEM_EDEVICE);
-    }
-  });
-  *out = raw;
+  *out = s.release();
   return FEM_OK;
 }
 
@@ -303,6 +353,7 @@ int server_submit(fem_server* s, const fem_request& q, uint64_t* ticket, std::st
   r->st.status = FEM_OK;
   r->st.t_admit = r->st.t_done = -1.0;
   r->st.bytes = handle_device_bytes(q.grid, s->o.opts, &q.bc, q.nsteps, nsens);
+  r->key = size_class(q.grid);
   std::lock_guard<std::mutex> lk(s->mu);
   if (r->st.bytes > s->budget) {
     *err = "request needs " + std::to_string(r->st.bytes) + " device bytes, budget " + std::to_string(s->budget);
@@ -312,13 +363,20 @@ int server_submit(fem_server* s, const fem_request& q, uint64_t* ticket, std::st
     *err = "server is stopping";
     return FEM_EBUSY;
   }
+  if (!s->lanes.count(r->key)) {
+    const int rc = s->open_lane(r->key, err);
+    if (rc != FEM_OK) return rc;
+  } else if (s->lanes[r->key]->dead) {
+    *err = "the worker of this size class stopped after a device error";
+    return FEM_EDEVICE;
+  }
   r->ticket = s->next_ticket++;
   r->st.t_arrive = s->now();
   *ticket = r->ticket;
   s->queue.push_back(r.get());
   s->reqs[r->ticket] = std::move(r);
   ++s->submitted;
-  s->cv_work.notify_one();
+  s->cv_work.notify_all();
   return FEM_OK;
 }
 
@@ -358,7 +416,7 @@ int server_cancel(fem_server* s, uint64_t ticket) {
     s->cv_done.notify_all();
   } else if (r->st.state == FEM_REQ_RUNNING) {
     r->cancel = true;
-    s->cv_work.notify_one();
+    s->cv_work.notify_all();
   }
   return FEM_OK;
 }
@@ -383,12 +441,18 @@ void server_destroy(fem_server* s) {
   {
     std::lock_guard<std::mutex> lk(s->mu);
     s->stop = true;
+    for (Request* r : s->queue) s->finish(r, FEM_REQ_CANCELED, FEM_ECANCELED, false);
+    s->queue.clear();
   }
   s->cv_work.notify_all();
-  if (s->worker.joinable()) s->worker.join();
-  engine_delete(s->eng);
-  (void)hipStreamSynchronize(s->stream);
-  (void)hipStreamDestroy(s->stream);
+  for (auto& kv : s->lanes) {
+    Lane& ln = *kv.second;
+    if (ln.worker.joinable()) ln.worker.join();
+    femheat::engine_delete(ln.eng);
+    (void)hipStreamSynchronize(ln.stream);
+    (void)hipStreamDestroy(ln.stream);
+  }
+  s->cv_done.notify_all();
   delete s;
 }
 
