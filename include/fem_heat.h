@@ -61,7 +61,8 @@ extern "C" {
 #define FEM_STOP_INITIAL 1   /* continue while r^T P^-1 r > rtol^2 r0^T P^-1 r0    */
 
 #define FEM_DEVICE_PTRS 0x1u /* array arguments are device pointers               */
-#define FEM_TIMING 0x2u      /* time every iteration kernel with HIP events        */
+#define FEM_TIMING 0x2u      /* time iteration kernels with HIP events (every 8th iteration and every
+                                residual replacement, so the events barely perturb the run) */
 
 /* Operators for fem_heat_apply */
 #define FEM_OP_A 0           /* y = (M + theta*dt*K) x                              */
@@ -130,7 +131,8 @@ typedef struct {
   double device_ms;          /* out: device time of the run's stepping (HIP events)   */
 } fem_out;
 
-/* Kernel timing (filled when the handle has FEM_TIMING). */
+/* Kernel timing (filled when the handle has FEM_TIMING): launches timed and
+ * their summed durations, per kernel kind. */
 typedef struct {
   int64_t gather_launches;   /* search-direction + operator-apply kernel (q = A d, d^T q) */
   double gather_ms;

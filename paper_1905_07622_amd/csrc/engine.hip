@@ -424,17 +424,22 @@ int Engine::pcg(int first_chunk) {
   int& cur = inner ? icur_ : ocur_;
   int& prev = inner ? iprev_ : oprev_;
   const int upd_kind = inner ? PK_UPD32 : PK_UPD64;
+  // Timing samples one iteration in kSampleEvery and every replacement:
+  // events between every launch would lengthen the very run they time.
+  constexpr int kSampleEvery = 8;
+  auto sampled = [&](int jj) { return timing_ && (jj % kSampleEvery == 1 || (R_ > 0 && jj % R_ == 0)); };
   int j = 0;
   int k = std::max(1, first_chunk);
   for (;;) {
     if (timing_) RC_TRY(ensure_events(3 * (size_t)k));
     for (int c = 0; c < k; ++c) {
       const int jj = j + c;
-      if (timing_) HIP_TRY(hipEventRecord(ev_[3 * c], stream_));
+      const bool ev = sampled(jj);
+      if (ev) HIP_TRY(hipEventRecord(ev_[3 * c], stream_));
       RC_TRY(gather<RoleDir<V>>(args(cur, prev, jj, 0)));
       cur ^= 1;
       prev = PK_GATHER;
-      if (timing_) HIP_TRY(hipEventRecord(ev_[3 * c + 1], stream_));
+      if (ev) HIP_TRY(hipEventRecord(ev_[3 * c + 1], stream_));
       const int xpar = replacements_before(jj, R_) & 1;
       if (R_ > 0 && jj % R_ == 0) {
         RC_TRY(gather<RoleRepl<V>>(args(cur, prev, jj, xpar)));
@@ -444,7 +449,7 @@ int Engine::pcg(int first_chunk) {
         prev = upd_kind;
       }
       cur ^= 1;
-      if (timing_) HIP_TRY(hipEventRecord(ev_[3 * c + 2], stream_));
+      if (ev) HIP_TRY(hipEventRecord(ev_[3 * c + 2], stream_));
     }
     RC_TRY(decide(inner));
     bool all_done = true;
@@ -459,6 +464,7 @@ int Engine::pcg(int first_chunk) {
     if (timing_) {
       const int ran = std::max(0, std::min(most - j, k));
       for (int c = 0; c < ran; ++c) {
+        if (!sampled(j + c)) continue;
         float g_ms = 0.f, u_ms = 0.f;
         HIP_TRY(hipEventElapsedTime(&g_ms, ev_[3 * c], ev_[3 * c + 1]));
         HIP_TRY(hipEventElapsedTime(&u_ms, ev_[3 * c + 1], ev_[3 * c + 2]));

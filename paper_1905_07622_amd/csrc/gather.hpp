@@ -90,10 +90,9 @@ __device__ inline uint32_t xcd_work_item(uint32_t b, uint32_t nblocks) {
 // stored at index `logical`, and tile 0 publishes the relayed state.
 template <typename V, bool CUBIC, class Pro, class Epi>
 __device__ inline void gather_tile(const GatherArgs<V>& ga, Pro pro, Epi epi, const Relay& R, uint32_t logical) {
+  const StageIn in = stage_load(R);
+  if (stage_idle(R, in, logical == 0)) return;  // uniform: a finished solve
   Scalars st;
-  if (!stage_entry(R, st, logical == 0)) return;  // uniform: the solve is done (or broke down)
-  pro.init(st);
-  epi.init(st);
 
   extern __shared__ unsigned char smem_raw[];
   const int TX = ga.s.tx, TY = ga.s.ty, TZ = ga.s.tz;
@@ -107,10 +106,12 @@ __device__ inline void gather_tile(const GatherArgs<V>& ga, Pro pro, Epi epi, co
   const int nx = ga.g.nx, ny = ga.g.ny, nz = ga.g.nz;
   const uint32_t pstride = (uint32_t)px * (uint32_t)py, lstride = (uint32_t)nx * (uint32_t)ny;
 
-  const bool idle = logical >= ga.s.ntiles;
+  if (logical >= ga.s.ntiles) {  // a padding block: partial 0 (never the writer)
+    if (stage_finish(R, in, st, false) && R.pout) publish_partial(R, 0.0, logical);
+    return;
+  }
   double dot = 0.0;
-
-  if (!idle) {
+  {
     uint32_t b = logical;
     const int tz = (int)(b % (uint32_t)ga.s.ntz);
     b /= (uint32_t)ga.s.ntz;
@@ -246,22 +247,31 @@ __device__ inline void gather_tile(const GatherArgs<V>& ga, Pro pro, Epi epi, co
       lo = hi;
     };
 
+    // Prologue: the first three planes (z0-1, z0, z0+1) and the coefficient
+    // layers z0-1, z0 are requested at once, before the relayed partial sum,
+    // so that sum and the plane pipeline's fill overlap one memory latency.
     Stage SA, SB;
-    fetch(SA, z0 - 1, z0 - 1);
-    store(SA, -1, 0);  // plane z0-1 into buffer 0 (its coefficient slots are rewritten before use)
-    fetch(SA, z0, z0 - 1);
-    fetch(SB, min(z0 + 1, z1), z0);
+    {
+      Stage S0;
+      fetch(S0, z0 - 1, z0 - 1);
+      fetch(SB, z0, z0 - 1);
+      fetch(SA, min(z0 + 1, z1), z0);
+      if (!stage_finish(R, in, st, logical == 0)) return;  // uniform
+      pro.init(st);
+      epi.init(st);
+      store(S0, -1, 0);  // plane z0-1 into buffer 0 (its coefficient slots are rewritten before use)
+    }
     __syncthreads();
     read_plane(plane, PW, ltx, lty, lo);
     using no = std::integral_constant<bool, false>;
     using yes = std::integral_constant<bool, true>;
-    layer(z0 - 1, 1, SA, no{});  // node z0-1 belongs to the chunk below
+    layer(z0 - 1, 1, SB, no{});  // node z0-1 belongs to the chunk below
     int l = z0;
     for (; l + 1 < z1; l += 2) {  // two register sets alternate: indices stay compile-time
-      layer(l, 0, SB, yes{});
-      layer(l + 1, 1, SA, yes{});
+      layer(l, 0, SA, yes{});
+      layer(l + 1, 1, SB, yes{});
     }
-    if (l < z1) layer(l, 0, SB, yes{});
+    if (l < z1) layer(l, 0, SA, yes{});
   }
   if (R.pout) publish_partial(R, dot, logical);
 }

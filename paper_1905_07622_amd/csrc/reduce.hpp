@@ -122,19 +122,46 @@ __device__ inline void evaluate_pending(Scalars& s, double x, const Ctl& c) {
   s.phase = PH_DECIDED;
 }
 
-// Entry of every relayed kernel: evaluates the state this kernel works with,
-// has the writer block of the solve publish it to Sout, and returns whether
+// The relayed state as a kernel finds it, before the pending update.
+struct StageIn {
+  Scalars t;
+  bool pending;  // the previous kernel's partials complete a scalar update
+  bool need;     // this kernel sums those partials
+};
+
+// First half of a relayed kernel's entry: reads the state (one uniform load).
+// Kernels can issue their first global loads after it and before
+// stage_finish, whose partial sum then overlaps them.
+__device__ inline StageIn stage_load(const Relay& R) {
+  StageIn in;
+  in.t = Scalars{};
+  if (R.sin) in.t = *R.sin;
+  in.pending = !in.t.done && in.t.phase != PH_DECIDED && in.t.phase != PH_NONE;
+  in.need = R.mode == M_INIT || (R.mode == M_UPD && !in.t.done) ||
+            ((R.mode == M_DIR || R.mode == M_DECIDE) && in.pending);
+  return in;
+}
+
+// A search-direction or update kernel of a finished solve has no work and
+// leaves the state unchanged: only the writer relays it.  Uniform.
+__device__ inline bool stage_idle(const Relay& R, const StageIn& in, bool writer) {
+  if ((R.mode == M_DIR || R.mode == M_UPD) && in.t.done) {
+    if (writer && threadIdx.x == 0 && R.sout) *R.sout = in.t;
+    return true;
+  }
+  return false;
+}
+
+// Second half: sums the partials if needed, evaluates the state this kernel
+// works with, has the writer block publish it to Sout, and returns whether
 // the kernel has work.  Called by all threads of the block.
-__device__ inline bool stage_entry(const Relay& R, Scalars& out, bool writer) {
+__device__ inline bool stage_finish(const Relay& R, const StageIn& in, Scalars& out, bool writer) {
   __shared__ Scalars sh;
   __shared__ int go;
   __shared__ double red4[4];
-  Scalars t{};
-  if (R.sin) t = *R.sin;
-  const bool pending = !t.done && t.phase != PH_DECIDED && t.phase != PH_NONE;
-  const bool need = R.mode == M_INIT || (R.mode == M_UPD && !t.done) ||
-                    ((R.mode == M_DIR || R.mode == M_DECIDE) && pending);
-  const double x = need ? canonical_sum(R.pin, R.npin, red4) : 0.0;
+  Scalars t = in.t;
+  const bool pending = in.pending;
+  const double x = in.need ? canonical_sum(R.pin, R.npin, red4) : 0.0;
   if (threadIdx.x == 0) {
     int g = 1;
     switch (R.mode) {
@@ -203,6 +230,12 @@ __device__ inline bool stage_entry(const Relay& R, Scalars& out, bool writer) {
   __syncthreads();
   out = sh;
   return go != 0;
+}
+
+// Entry of a relayed kernel in one piece.
+__device__ inline bool stage_entry(const Relay& R, Scalars& out, bool writer) {
+  const StageIn in = stage_load(R);
+  return stage_finish(R, in, out, writer);
 }
 
 // One partial per block for the next kernel, at the block's index `slot`

@@ -36,17 +36,16 @@ __device__ inline void upd1(V& x, V d, V& r, V q, V p, V alpha, double& acc) {
 // Fused update of one solve by block `blk` of its `nblk` blocks (a
 // grid-stride loop over the solve's own block count, so the partial sums do
 // not depend on the launch the block belongs to).  Settles alpha = delta /
-// d^T q first; a no-op once the solve is done.
+// d^T q first -- the block's first loads are already in flight while it sums
+// the partials -- and is a no-op once the solve is done.
 template <typename V>
 __device__ inline void update_body(V* __restrict__ x, const V* __restrict__ d, V* __restrict__ r,
                                    const V* __restrict__ q, const V* __restrict__ pinv, uint32_t N, const Relay& R,
                                    uint32_t blk, uint32_t nblk) {
-  Scalars st;
-  if (!stage_entry(R, st, blk == 0)) return;
+  const StageIn in = stage_load(R);
+  if (stage_idle(R, in, blk == 0)) return;
   using VT = typename Vec<V>::T;
   constexpr int W = Vec<V>::W;
-  const V alpha = (V)st.alpha;
-  double acc = 0.0;
   const uint32_t nvec = N / W;
   const uint32_t stride = nblk * blockDim.x;
   const uint32_t tid = blk * blockDim.x + threadIdx.x;
@@ -55,8 +54,28 @@ __device__ inline void update_body(V* __restrict__ x, const V* __restrict__ d, V
   VT* rv = reinterpret_cast<VT*>(r);
   const VT* qv = reinterpret_cast<const VT*>(q);
   const VT* pv = reinterpret_cast<const VT*>(pinv);
+  // first vector of this thread (clamped: always a valid address)
+  const uint32_t j0 = nvec > 0 ? min(tid, nvec - 1) : 0;
+  VT xx{}, dd{}, rr{}, qq{}, pp{};
+  if (nvec > 0) {
+    xx = xv[j0];
+    dd = dv[j0];
+    rr = rv[j0];
+    qq = qv[j0];
+    pp = pv[j0];
+  }
+  Scalars st;
+  if (!stage_finish(R, in, st, blk == 0)) return;
+  const V alpha = (V)st.alpha;
+  double acc = 0.0;
   for (uint32_t j = tid; j < nvec; j += stride) {
-    VT xx = xv[j], dd = dv[j], rr = rv[j], qq = qv[j], pp = pv[j];
+    if (j != tid) {
+      xx = xv[j];
+      dd = dv[j];
+      rr = rv[j];
+      qq = qv[j];
+      pp = pv[j];
+    }
     if constexpr (W == 2) {
       upd1(xx.x, dd.x, rr.x, qq.x, pp.x, alpha, acc);
       upd1(xx.y, dd.y, rr.y, qq.y, pp.y, alpha, acc);
@@ -70,10 +89,10 @@ __device__ inline void update_body(V* __restrict__ x, const V* __restrict__ d, V
     rv[j] = rr;
   }
   for (uint32_t i = nvec * W + tid; i < N; i += stride) {
-    V xx = x[i], rr = r[i];
-    upd1(xx, d[i], rr, q[i], pinv[i], alpha, acc);
-    x[i] = xx;
-    r[i] = rr;
+    V xs = x[i], rs = r[i];
+    upd1(xs, d[i], rs, q[i], pinv[i], alpha, acc);
+    x[i] = xs;
+    r[i] = rs;
   }
   publish_partial(R, acc, blk);
 }

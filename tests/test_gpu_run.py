@@ -166,3 +166,18 @@ def test_full_size_lognormal_first_steps(gpu):
     err = rel_l2(out["T_final"], ref["T_final"])
     say(f"  iters {list(out['iters'])}, rel L2 {err:.3e}")
     assert err <= 1e-10
+
+
+def test_timing_changes_nothing_and_samples(gpu):
+    """FEM_TIMING records events around a sample of the iterations; the
+    results are bit-identical to an untimed run."""
+    p = wl.random_problem(14, 12, 10, seed=12, nsteps=4, rtol=1e-11)
+    with fh.Heat.from_problem(p) as h:
+        a = h.run(p.T0, dt=p.dt, theta=p.theta, nsteps=p.nsteps, rtol=p.rtol)
+    with fh.Heat.from_problem(p, timing=True) as h:
+        b = h.run(p.T0, dt=p.dt, theta=p.theta, nsteps=p.nsteps, rtol=p.rtol)
+        st = h.stats()
+    assert np.array_equal(a["T_final"], b["T_final"]) and np.array_equal(a["iters"], b["iters"])
+    total = int(np.sum(b["iters"]))
+    assert 0 < st["gather_launches"] < total and st["gather_ms"] > 0
+    assert st["replace_launches"] >= p.nsteps  # iteration 0 of every step is a replacement
