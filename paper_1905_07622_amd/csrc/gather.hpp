@@ -78,9 +78,9 @@ constexpr int kSlots = 2;
 
 // XCD-aware tile order: blocks are dispatched round-robin over the 8 XCDs,
 // so block b runs on XCD b%8.  Work item (b%8)*share + b/8 gives every XCD a
-// contiguous range of tiles with z fastest, so the z-halo planes that
-// neighbouring chunks share are reused from the same L2.  `nblocks` is a
-// multiple of 8.
+// contiguous range of tiles (z fastest, then x, then y), so the halo planes,
+// columns and rows that neighbouring tiles share are mostly reused from the
+// same L2.  `nblocks` is a multiple of 8.
 __device__ inline uint32_t xcd_work_item(uint32_t b, uint32_t nblocks) {
   return (b & 7u) * (nblocks >> 3) + (b >> 3);
 }
@@ -112,11 +112,14 @@ __device__ inline void gather_tile(const GatherArgs<V>& ga, Pro pro, Epi epi, co
   }
   double dot = 0.0;
   {
+    // tile order: z-chunk fastest, then x, then y -- the tiles that split a
+    // row in x are neighbours in the order and so share an XCD (and its L2),
+    // which serves the cache lines and halo columns they both read
     uint32_t b = logical;
     const int tz = (int)(b % (uint32_t)ga.s.ntz);
     b /= (uint32_t)ga.s.ntz;
-    const int tyi = (int)(b % (uint32_t)ga.s.nty);
-    const int txi = (int)(b / (uint32_t)ga.s.nty);
+    const int txi = (int)(b % (uint32_t)ga.s.ntx);
+    const int tyi = (int)(b / (uint32_t)ga.s.ntx);
     const int x0 = txi * TX, y0 = tyi * TY, z0 = tz * TZ;
     const int z1 = min(z0 + TZ, pz);
 

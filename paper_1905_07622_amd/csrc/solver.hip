@@ -280,7 +280,10 @@ int solver_init(fem_heat* h, const fem_grid* grid, const double* k_e, const doub
     const bool fp32 = h->opts.precision == FEM_FP32_FP64DOT;
     int cus = 0;
     HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, h->opts.device));
-    const int per_cu = resident_blocks(h->cubic, fp32, probe.nthreads, probe.smem_bytes(fp32 ? 4 : 8));
+    // at most two blocks per CU: beyond that, the shorter z-marches pay the
+    // plane pipeline's fill more often than the extra blocks hide latency
+    // (measured for the FP32 gather, which could hold four)
+    const int per_cu = std::min(2, resident_blocks(h->cubic, fp32, probe.nthreads, probe.smem_bytes(fp32 ? 4 : 8)));
     h->shape = choose_shape(g, h->opts, h->batched ? 0 : std::max(1, cus) * per_cu);
   }
   {
