@@ -28,6 +28,8 @@
 #include <memory>
 #include <vector>
 
+#include <hip/hip_ext.h>
+
 #include "batch.hpp"
 #include "engine.hpp"
 #include "runtime.hpp"
@@ -115,10 +117,12 @@ class Engine {
   BatchArgs args(int cur, int prev, int j, int xpar) const {
     return BatchArgs{sd_dev_, nullptr, snap_dev_, cur, prev, j, xpar, 0};
   }
+  // Launches; e0/e1 (optional) are recorded at the start of the first and the
+  // end of the last kernel of the launch by the dispatch itself.
   template <class Role>
-  int gather(BatchArgs a);
+  int gather(BatchArgs a, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
   template <typename V>
-  int update(BatchArgs a);
+  int update(BatchArgs a, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
   int decide(bool inner);
   template <typename V>
   int pcg(int first_chunk);
@@ -374,27 +378,31 @@ int Engine::compose() {
 }
 
 template <class Role>
-int Engine::gather(BatchArgs a) {
+int Engine::gather(BatchArgs a, hipEvent_t e0, hipEvent_t e1) {
   fem_heat* h = h_;
   for (int gi = 0; gi < ngroups_; ++gi) {
     const Group& g = groups_[gi];
     a.table = multi_ ? tab_dev_ + g.off : nullptr;
     const size_t smem = sizeof(typename Role::V) == 8 ? g.smem64 : g.smem32;
+    hipEvent_t s0 = gi == 0 ? e0 : nullptr, s1 = gi == ngroups_ - 1 ? e1 : nullptr;
     if (g.cubic)
-      hipLaunchKernelGGL((gather_batch_kernel<true, Role>), dim3(g.nwork), dim3(g.nthreads), smem, stream_, a);
+      hipExtLaunchKernelGGL((gather_batch_kernel<true, Role>), dim3(g.nwork), dim3(g.nthreads), smem, stream_, s0, s1,
+                            0, a);
     else
-      hipLaunchKernelGGL((gather_batch_kernel<false, Role>), dim3(g.nwork), dim3(g.nthreads), smem, stream_, a);
+      hipExtLaunchKernelGGL((gather_batch_kernel<false, Role>), dim3(g.nwork), dim3(g.nthreads), smem, stream_, s0, s1,
+                            0, a);
   }
   HIP_TRY(hipGetLastError());
   return FEM_OK;
 }
 
 template <typename V>
-int Engine::update(BatchArgs a) {
+int Engine::update(BatchArgs a, hipEvent_t e0, hipEvent_t e1) {
   fem_heat* h = h_;
   const bool f64 = sizeof(V) == 8;
   a.table = multi_ ? tab_dev_ + (f64 ? off_upd64_ : off_upd32_) : nullptr;
-  hipLaunchKernelGGL((update_batch_kernel<V>), dim3(f64 ? n_upd64_ : n_upd32_), dim3(kT), 0, stream_, a);
+  hipExtLaunchKernelGGL((update_batch_kernel<V>), dim3(f64 ? n_upd64_ : n_upd32_), dim3(kT), 0, stream_, e0, e1, 0,
+                        a);
   HIP_TRY(hipGetLastError());
   return FEM_OK;
 }
@@ -424,32 +432,31 @@ int Engine::pcg(int first_chunk) {
   int& cur = inner ? icur_ : ocur_;
   int& prev = inner ? iprev_ : oprev_;
   const int upd_kind = inner ? PK_UPD32 : PK_UPD64;
-  // Timing samples one iteration in kSampleEvery and every replacement:
-  // events between every launch would lengthen the very run they time.
+  // Timing samples one iteration in kSampleEvery and every replacement, with
+  // events the dispatch itself records at the start and end of each kernel
+  // (marker events between every launch would lengthen the run they time).
   constexpr int kSampleEvery = 8;
   auto sampled = [&](int jj) { return timing_ && (jj % kSampleEvery == 1 || (R_ > 0 && jj % R_ == 0)); };
   int j = 0;
   int k = std::max(1, first_chunk);
   for (;;) {
-    if (timing_) RC_TRY(ensure_events(3 * (size_t)k));
+    if (timing_) RC_TRY(ensure_events(4 * (size_t)k));
     for (int c = 0; c < k; ++c) {
       const int jj = j + c;
       const bool ev = sampled(jj);
-      if (ev) HIP_TRY(hipEventRecord(ev_[3 * c], stream_));
-      RC_TRY(gather<RoleDir<V>>(args(cur, prev, jj, 0)));
+      hipEvent_t* e = ev_.data() + 4 * c;
+      RC_TRY(gather<RoleDir<V>>(args(cur, prev, jj, 0), ev ? e[0] : nullptr, ev ? e[1] : nullptr));
       cur ^= 1;
       prev = PK_GATHER;
-      if (ev) HIP_TRY(hipEventRecord(ev_[3 * c + 1], stream_));
       const int xpar = replacements_before(jj, R_) & 1;
       if (R_ > 0 && jj % R_ == 0) {
-        RC_TRY(gather<RoleRepl<V>>(args(cur, prev, jj, xpar)));
+        RC_TRY(gather<RoleRepl<V>>(args(cur, prev, jj, xpar), ev ? e[2] : nullptr, ev ? e[3] : nullptr));
         prev = PK_GATHER;
       } else {
-        RC_TRY(update<V>(args(cur, prev, jj, xpar)));
+        RC_TRY(update<V>(args(cur, prev, jj, xpar), ev ? e[2] : nullptr, ev ? e[3] : nullptr));
         prev = upd_kind;
       }
       cur ^= 1;
-      if (ev) HIP_TRY(hipEventRecord(ev_[3 * c + 2], stream_));
     }
     RC_TRY(decide(inner));
     bool all_done = true;
@@ -466,8 +473,8 @@ int Engine::pcg(int first_chunk) {
       for (int c = 0; c < ran; ++c) {
         if (!sampled(j + c)) continue;
         float g_ms = 0.f, u_ms = 0.f;
-        HIP_TRY(hipEventElapsedTime(&g_ms, ev_[3 * c], ev_[3 * c + 1]));
-        HIP_TRY(hipEventElapsedTime(&u_ms, ev_[3 * c + 1], ev_[3 * c + 2]));
+        HIP_TRY(hipEventElapsedTime(&g_ms, ev_[4 * c], ev_[4 * c + 1]));
+        HIP_TRY(hipEventElapsedTime(&u_ms, ev_[4 * c + 2], ev_[4 * c + 3]));
         stats.gather_launches += 1;
         stats.gather_ms += g_ms;
         if (R_ > 0 && (j + c) % R_ == 0) {

@@ -26,6 +26,9 @@
 // nodes are staged as 0 and out-of-grid elements carry zero coefficients, so
 // boundaries need no branches in the arithmetic.
 //
+// Neighbouring z-chunks march in opposite directions, so they read the halo
+// planes they share at the same time, from the same L2.
+//
 // A prologue functor produces the input value at every staged node (and
 // writes it back for owned nodes: fused search-direction or x updates), an
 // epilogue functor consumes the result at owned nodes (q, residual, RHS) and
@@ -190,91 +193,100 @@ __device__ inline void gather_tile(const GatherArgs<V>& ga, Pro pro, Epi epi, co
       }
     };
 
+    // The march visits planes vis(0..n) and the n layers between consecutive
+    // ones; node vis(k) is owned for 1 <= k <= n-1.  Odd z-chunks march
+    // down, even ones up, so two neighbouring chunks read the planes and the
+    // coefficient layer they share at the same end of their marches, while
+    // both are in the same L2 (with one direction, one chunk reads them first
+    // and its neighbour a whole march later, from memory again).
+    const bool down = (tz & 1) != 0;
+    const int n = z1 - z0 + 1;
+    auto vis = [&](int k) { return down ? z1 - k : z0 - 1 + k; };
+    auto lay = [&](int k) { return down ? z1 - 1 - k : z0 - 1 + k; };  // layer between vis(k) and vis(k+1)
+
     PlaneQ<V> lo, hi;
-    V acc_lo = V(0), acc_hi = V(0);
-    // One layer l (elements between planes l and l+1): completes node l of
-    // this column (lower layer accumulated in acc_lo) and starts node l+1.
-    // Loads for plane l+3 / layer l+2 are issued here (clamped to the chunk:
-    // past its end they re-read the last plane, an L2 hit).
-    auto layer = [&](int l, int buf, Stage& S, auto emit) {
-      store(S, l, buf);
-      __syncthreads();
-      fetch(S, min(l + 3, z1), min(l + 2, z1 - 1));
-      read_plane(plane + buf * PW * PH, PW, ltx, lty, hi);
-      const V* A = ca + buf * CW * CH;
-      const V* B = cb + buf * CW * CH;
-      acc_hi = V(0);
+    V carry = V(0);
+    // Contribution of one layer's 4 elements to the node of this column on
+    // plane `own`, whose other plane is `oth`.  A node's value is the sum of
+    // the contributions of its two layers, each computed by this function
+    // from zero (explicit FMAs in a fixed order; the library is built without
+    // automatic contraction) -- so it does not depend on the tiling or on the
+    // direction of the march.
+    auto contribution = [&](const PlaneQ<V>& own, const PlaneQ<V>& oth, const V* A, const V* B) {
+      V part[4];
 #pragma unroll
       for (int sy = 0; sy < 2; ++sy) {
 #pragma unroll
         for (int sx = 0; sx < 2; ++sx) {
+          const int e = sy * 2 + sx;
           const int ci = (lty + sy) * CW + ltx + sx;
           const V a = A[ci], bk = B[ci];
-          const V xl = sx ? lo.xp : lo.xm, yl = sy ? lo.yp : lo.ym, bl = lo.b[sy * 2 + sx];
-          const V xh = sx ? hi.xp : hi.xm, yh = sy ? hi.yp : hi.ym, bh = hi.b[sy * 2 + sx];
-          // Explicit fused multiply-adds in a fixed order (the library is built
-          // without automatic contraction): every copy of this code rounds
-          // identically, so results do not depend on the tiling.
+          const V xo = sx ? own.xp : own.xm, yo = sy ? own.yp : own.ym, bo = own.b[e];
+          const V xt = sx ? oth.xp : oth.xm, yt = sy ? oth.yp : oth.ym, bt = oth.b[e];
           if (CUBIC) {
             // classes by popcount: c0 = 8a+4b, c1 = 4a, c2 = 2a-b, c3 = a-b
             const V c0 = fma(V(8), a, V(4) * bk), c1 = V(4) * a, c2 = fma(V(2), a, -bk), c3 = a - bk;
-            const V al = xl + yl, ah = xh + yh;
-            acc_lo = fma(c0, lo.c, acc_lo);
-            acc_lo = fma(c1, al + hi.c, acc_lo);
-            acc_lo = fma(c2, bl + ah, acc_lo);
-            acc_lo = fma(c3, bh, acc_lo);
-            acc_hi = fma(c0, hi.c, acc_hi);
-            acc_hi = fma(c1, ah + lo.c, acc_hi);
-            acc_hi = fma(c2, bh + al, acc_hi);
-            acc_hi = fma(c3, bl, acc_hi);
+            V u = c0 * own.c;
+            u = fma(c1, (xo + yo) + oth.c, u);
+            u = fma(c2, bo + (xt + yt), u);
+            part[e] = fma(c3, bt, u);
           } else {
-            V k[8];
+            const V v[8] = {own.c, xo, yo, bo, oth.c, xt, yt, bt};  // corner differing by class c
+            V u = fma(a, ga.Mc[0], bk * ga.Kc[0]) * v[0];
 #pragma unroll
-            for (int c = 0; c < 8; ++c) k[c] = fma(a, ga.Mc[c], bk * ga.Kc[c]);
-            const V vl[8] = {lo.c, xl, yl, bl, hi.c, xh, yh, bh};
-            const V vh[8] = {hi.c, xh, yh, bh, lo.c, xl, yl, bl};
-#pragma unroll
-            for (int c = 0; c < 8; ++c) {
-              acc_lo = fma(k[c], vl[c], acc_lo);
-              acc_hi = fma(k[c], vh[c], acc_hi);
-            }
+            for (int c = 1; c < 8; ++c) u = fma(fma(a, ga.Mc[c], bk * ga.Kc[c]), v[c], u);
+            part[e] = u;
           }
         }
       }
-      if (decltype(emit)::value) {  // node l is owned by this block
-        const uint32_t i = col_xy + pstride * (uint32_t)l;
+      return (part[0] + part[1]) + (part[2] + part[3]);
+    };
+    // Layer k: completes node vis(k) (its other layer was layer k-1) and
+    // starts node vis(k+1).  Loads for plane vis(k+3) and layer k+2 are issued
+    // here (clamped to the march: past its end they re-read the last ones).
+    auto layer = [&](int k, int buf, Stage& S, auto emit) {
+      store(S, lay(k), buf);
+      __syncthreads();
+      fetch(S, vis(min(k + 3, n)), lay(min(k + 2, n - 1)));
+      read_plane(plane + buf * PW * PH, PW, ltx, lty, hi);
+      const V* A = ca + buf * CW * CH;
+      const V* B = cb + buf * CW * CH;
+      const V p_lo = contribution(lo, hi, A, B);
+      const V p_hi = contribution(hi, lo, A, B);
+      if (decltype(emit)::value) {  // node vis(k) is owned by this block
+        const uint32_t i = col_xy + pstride * (uint32_t)vis(k);
         pro.write(i, lo.c, col_ok, ga.sink);
-        dot += epi.store(i, acc_lo, lo.c, col_ok, ga.sink);
+        dot += epi.store(i, carry + p_lo, lo.c, col_ok, ga.sink);
       }
-      acc_lo = acc_hi;
+      carry = p_hi;
       lo = hi;
     };
 
-    // Prologue: the first three planes (z0-1, z0, z0+1) and the coefficient
-    // layers z0-1, z0 are requested at once, before the relayed partial sum,
-    // so that sum and the plane pipeline's fill overlap one memory latency.
+    // Prologue: the first three planes and the first two coefficient layers
+    // are requested at once, before the relayed partial sum, so that sum and
+    // the fill of the plane pipeline overlap.
     Stage SA, SB;
     {
       Stage S0;
-      fetch(S0, z0 - 1, z0 - 1);
-      fetch(SB, z0, z0 - 1);
-      fetch(SA, min(z0 + 1, z1), z0);
+      fetch(S0, vis(0), lay(0));
+      fetch(SB, vis(1), lay(0));
+      fetch(SA, vis(min(2, n)), lay(min(1, n - 1)));
       if (!stage_finish(R, in, st, logical == 0)) return;  // uniform
       pro.init(st);
       epi.init(st);
-      store(S0, -1, 0);  // plane z0-1 into buffer 0 (its coefficient slots are rewritten before use)
+      store(S0, -1, 0);  // plane vis(0) into buffer 0 (its coefficient slots are rewritten before use)
     }
     __syncthreads();
     read_plane(plane, PW, ltx, lty, lo);
     using no = std::integral_constant<bool, false>;
     using yes = std::integral_constant<bool, true>;
-    layer(z0 - 1, 1, SB, no{});  // node z0-1 belongs to the chunk below
-    int l = z0;
-    for (; l + 1 < z1; l += 2) {  // two register sets alternate: indices stay compile-time
-      layer(l, 0, SA, yes{});
-      layer(l + 1, 1, SB, yes{});
+    layer(0, 1, SB, no{});  // node vis(0) belongs to the neighbouring chunk
+    int k = 1;
+    for (; k + 1 < n; k += 2) {  // two register sets alternate: indices stay compile-time
+      layer(k, 0, SA, yes{});
+      layer(k + 1, 1, SB, yes{});
     }
-    if (l < z1) layer(l, 0, SA, yes{});
+    if (k < n) layer(k, 0, SA, yes{});
   }
   if (R.pout) publish_partial(R, dot, logical);
 }
