@@ -30,11 +30,25 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 
 
-def algorithmic_bytes(N: int, E: int, w: int) -> dict:
-    """Bytes each kernel must move per launch (no re-reads counted).
-    gather (direction + apply): read r, P^-1, d_old, rho*c_e, k_e; write d_new, q.
-    update: read x, d, r, q, P^-1; write x, r."""
-    return {"gather": (5 * N + 2 * E) * w, "update": 7 * N * w}
+def deferred_fraction(iters, R: int = 50) -> float:
+    """Share of the direction launches that also apply the previous
+    iteration's x += alpha d: those of iterations 1..it-1 not preceded by a
+    residual replacement (iterations 0, R, 2R, ... of each solve replace)."""
+    total = corr = 0
+    for it in np.asarray(iters, dtype=np.int64).tolist():
+        total += it
+        if it >= 1:
+            corr += (it - 1) - (0 if it < 2 else (it - 2) // R + 1)
+    return corr / total if total else 0.0
+
+
+def algorithmic_bytes(N: int, E: int, w: int, f_corr: float) -> dict:
+    """Bytes each kernel must move per launch (no re-reads counted), averaged
+    over the launches the timing samples.
+    gather (direction + apply): read r, P^-1, d_old, rho*c_e, k_e; write d_new,
+    q; in the share f_corr of launches also read and write x.
+    update: read r, q, P^-1; write r."""
+    return {"gather": (5 * N + 2 * E) * w + 2 * N * w * f_corr, "update": 4 * N * w}
 
 
 def committed_traffic(kernel: str, precision: str):
@@ -290,7 +304,9 @@ def main():
     h.close()
 
     w = 8 if args.precision == "fp64" else 4
-    ab = algorithmic_bytes(p.n_nodes, p.n_elems, w)
+    it_steps = last["iters"]
+    f_corr = deferred_fraction(it_steps.cpu().numpy() if hasattr(it_steps, "cpu") else it_steps)
+    ab = algorithmic_bytes(p.n_nodes, p.n_elems, w, f_corr)
     roof = None
     if stats["gather_launches"] and stats["update_launches"]:
         per = {"gather": stats["gather_ms"] / stats["gather_launches"],
@@ -300,7 +316,8 @@ def main():
         roof = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "traffic": committed_traffic(dom, args.precision),
-                "bytes_per_launch": ab[dom], "avg_launch_us": round(per[dom] * 1e3, 3),
+                "bytes_per_launch": int(round(ab[dom])), "avg_launch_us": round(per[dom] * 1e3, 3),
+                "deferred_update_share": round(f_corr, 4),
                 "other_kernels_us": {kname: round(v * 1e3, 3) for kname, v in per.items() if kname != dom}}
 
     line = {

@@ -61,8 +61,9 @@ extern "C" {
 #define FEM_STOP_INITIAL 1   /* continue while r^T P^-1 r > rtol^2 r0^T P^-1 r0    */
 
 #define FEM_DEVICE_PTRS 0x1u /* array arguments are device pointers               */
-#define FEM_TIMING 0x2u      /* time iteration kernels with HIP events (every 8th iteration and every
-                                residual replacement, so the events barely perturb the run) */
+#define FEM_TIMING 0x2u      /* time iteration kernels with HIP events (every 8th iteration launched,
+                                counted across solves, and every residual replacement, so the
+                                events barely perturb the run) */
 
 /* Operators for fem_heat_apply */
 #define FEM_OP_A 0           /* y = (M + theta*dt*K) x                              */
@@ -134,9 +135,10 @@ typedef struct {
 /* Kernel timing (filled when the handle has FEM_TIMING): launches timed and
  * their summed durations, per kernel kind. */
 typedef struct {
-  int64_t gather_launches;   /* search-direction + operator-apply kernel (q = A d, d^T q) */
+  int64_t gather_launches;   /* search-direction + operator-apply kernel (q = A d, d^T q,
+                                and the previous iteration's x += alpha d)                  */
   double gather_ms;
-  int64_t update_launches;   /* x/r update + preconditioned residual norm kernel         */
+  int64_t update_launches;   /* r -= alpha q + preconditioned residual norm kernel        */
   double update_ms;
   int64_t replace_launches;  /* residual-replacement gather kernel                        */
   double replace_ms;

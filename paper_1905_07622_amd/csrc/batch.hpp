@@ -72,7 +72,7 @@ struct BatchArgs {
   int32_t prev;        // PartKind of the partials it reads
   int32_t j;           // iteration index within the current solve
   int32_t xpar;        // replacements so far in this solve, mod 2 (x or e buffer)
-  int32_t inner;       // decide: 1 = inner relay
+  int32_t corr;        // the previous kernel was a plain update: x += alpha d is still due
 };
 
 __device__ inline Relay outer_relay(const SimDev& s, const BatchArgs& a, int32_t mode, bool partials) {
@@ -114,7 +114,7 @@ struct RoleInit {  // x0 by the guess rule, r = b - A x0, r^T P^-1 r (a3)
 };
 
 template <typename V>
-struct RoleDir;  // d = P^-1 r + beta d, q = A d, d^T q (a6 + a4)
+struct RoleDir;  // d = P^-1 r + beta d, q = A d, d^T q (a6 + a4); deferred x += alpha d_old (a5)
 
 template <>
 struct RoleDir<double> {
@@ -123,7 +123,7 @@ struct RoleDir<double> {
   using Epi = EpiQDot<double>;
   static __device__ const GatherArgs<V>& ga(const SimDev& s) { return s.A64; }
   static __device__ Pro pro(const SimDev& s, const BatchArgs& a) {
-    return Pro{s.r64, s.pinv64, s.d64[dir_in(a)], s.d64[dir_out(a)], 0.0};
+    return Pro{s.r64, s.pinv64, s.d64[dir_in(a)], s.d64[dir_out(a)], s.X[a.xpar], a.corr, 0.0, 0.0};
   }
   static __device__ Epi epi(const SimDev& s, const BatchArgs&) { return Epi{s.q64}; }
   static __device__ Relay relay(const SimDev& s, const BatchArgs& a) { return outer_relay(s, a, M_DIR, true); }
@@ -136,7 +136,7 @@ struct RoleDir<float> {
   using Epi = EpiQDot<float>;
   static __device__ const GatherArgs<V>& ga(const SimDev& s) { return s.A32; }
   static __device__ Pro pro(const SimDev& s, const BatchArgs& a) {
-    return Pro{s.r32, s.pinv32, s.d32[dir_in(a)], s.d32[dir_out(a)], 0.0f};
+    return Pro{s.r32, s.pinv32, s.d32[dir_in(a)], s.d32[dir_out(a)], s.e32[a.xpar], a.corr, 0.0f, 0.0f};
   }
   static __device__ Epi epi(const SimDev& s, const BatchArgs&) { return Epi{s.q32}; }
   static __device__ Relay relay(const SimDev& s, const BatchArgs& a) { return inner_relay(s, a, M_DIR, true); }
@@ -208,7 +208,7 @@ __global__ void __launch_bounds__(256) gather_batch_kernel(BatchArgs a) {
   gather_tile<typename Role::V, CUBIC>(ga, Role::pro(s, a), Role::epi(s, a), Role::relay(s, a), local);
 }
 
-// Fused x/r update and preconditioned residual norm (a5), FP64 outer solve
+// Residual update and preconditioned residual norm (a5), FP64 outer solve
 // or FP32 inner solve.
 template <typename V>
 __global__ void __launch_bounds__(256) update_batch_kernel(BatchArgs a) {
@@ -216,11 +216,9 @@ __global__ void __launch_bounds__(256) update_batch_kernel(BatchArgs a) {
   work_item(a, blockIdx.x, sim, local);
   const SimDev& s = a.sims[sim];
   if constexpr (sizeof(V) == 8) {
-    update_body<double>(s.X[a.xpar], s.d64[dir_out(a)], s.r64, s.q64, s.pinv64, s.N,
-                        outer_relay(s, a, M_UPD, true), local, s.nblk[PK_UPD64]);
+    update_body<double>(s.r64, s.q64, s.pinv64, s.N, outer_relay(s, a, M_UPD, true), local, s.nblk[PK_UPD64]);
   } else {
-    update_body<float>(s.e32[a.xpar], s.d32[dir_out(a)], s.r32, s.q32, s.pinv32, s.N,
-                       inner_relay(s, a, M_UPD, true), local, s.nblk[PK_UPD32]);
+    update_body<float>(s.r32, s.q32, s.pinv32, s.N, inner_relay(s, a, M_UPD, true), local, s.nblk[PK_UPD32]);
   }
 }
 
@@ -234,14 +232,29 @@ static __global__ void __launch_bounds__(256) inner_start_batch_kernel(BatchArgs
                    inner_relay(s, a, s.sweep ? M_START : M_IDLE, true), local, s.nblk[PK_START]);
 }
 
-// Settles the pending decision of every simulation (one block each) and
-// copies the settled state to snap[sim] for the host.
-static __global__ void __launch_bounds__(64) decide_batch_kernel(BatchArgs a) {
-  const SimDev& s = a.sims[blockIdx.x];
-  const Relay R = a.inner ? inner_relay(s, a, M_DECIDE, false) : outer_relay(s, a, M_DECIDE, false);
+// Settles the pending decision of every simulation and copies the settled
+// state to snap[sim] for the host.  Blocks follow the update kernel's layout
+// (every block settles the same state; block 0 of a simulation writes it):
+// a solve that finishes here after a plain update still owes the deferred
+// x += alpha d, which the simulation's blocks apply.  V selects the relay
+// and vectors: double the outer (FP64) solve, float the inner one.
+template <typename V>
+__global__ void __launch_bounds__(256) decide_batch_kernel(BatchArgs a) {
+  constexpr bool inner = sizeof(V) == 4;
+  uint32_t sim, local;
+  work_item(a, blockIdx.x, sim, local);
+  const SimDev& s = a.sims[sim];
+  const Relay R = inner ? inner_relay(s, a, M_DECIDE, false) : outer_relay(s, a, M_DECIDE, false);
+  const StageIn in = stage_load(R);
   Scalars st;
-  (void)stage_entry(R, st, true);
-  if (threadIdx.x == 0) a.snap[blockIdx.x] = st;
+  (void)stage_finish(R, in, st, local == 0);
+  if (local == 0 && threadIdx.x == 0) a.snap[sim] = st;
+  if (a.corr && in.pending && st.done && st.status == 0) {
+    if constexpr (inner)
+      axpy_body<float>(s.e32[a.xpar], s.d32[dir_out(a)], (float)st.alpha, s.N, local, s.nblk[PK_UPD32]);
+    else
+      axpy_body<double>(s.X[a.xpar], s.d64[dir_out(a)], st.alpha, s.N, local, s.nblk[PK_UPD64]);
+  }
 }
 
 }  // namespace femheat

@@ -114,16 +114,19 @@ class Engine {
   int compose();
   int upload_simdev();
   void fill_simdev(const Sim& s, SimDev& d) const;
-  BatchArgs args(int cur, int prev, int j, int xpar) const {
-    return BatchArgs{sd_dev_, nullptr, snap_dev_, cur, prev, j, xpar, 0};
+  BatchArgs args(int cur, int prev, int j, int xpar, int corr = 0) const {
+    return BatchArgs{sd_dev_, nullptr, snap_dev_, cur, prev, j, xpar, corr};
   }
+  // Whether the update of iteration jj - 1 was a plain one, whose x += alpha d
+  // the direction kernel of iteration jj (or the decide after it) applies.
+  bool deferred(int jj) const { return jj > 0 && !(R_ > 0 && (jj - 1) % R_ == 0); }
   // Launches; e0/e1 (optional) are recorded at the start of the first and the
   // end of the last kernel of the launch by the dispatch itself.
   template <class Role>
   int gather(BatchArgs a, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
   template <typename V>
   int update(BatchArgs a, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
-  int decide(bool inner);
+  int decide(bool inner, int j_end = 0);
   template <typename V>
   int pcg(int first_chunk);
   int epoch();
@@ -136,6 +139,8 @@ class Engine {
   fem_heat* h_;  // receives error messages
   bool mixed_ = false, timing_ = false;
   int R_ = 50;
+  uint64_t sample_ctr_ = 0;         // iterations launched with timing, across solves
+  std::vector<uint8_t> sampled_;    // per iteration of the current chunk
 
   std::vector<std::unique_ptr<Sim>> sims_;
   std::vector<Sim*> act_;  // simulations of the current epoch, in SimDev order
@@ -408,14 +413,20 @@ int Engine::update(BatchArgs a, hipEvent_t e0, hipEvent_t e1) {
 }
 
 // Settles the pending decision of every simulation of a relay and reads the
-// settled states into snap_host_ (synchronises the stream).
-int Engine::decide(bool inner) {
+// settled states into snap_host_ (synchronises the stream).  j_end > 0: the
+// relay's last kernel was the update of iteration j_end - 1 of a PCG chunk,
+// and a solve that finishes here gets that update's deferred x += alpha d.
+int Engine::decide(bool inner, int j_end) {
   fem_heat* h = h_;
   int& cur = inner ? icur_ : ocur_;
   int& prev = inner ? iprev_ : oprev_;
-  BatchArgs a = args(cur, prev, 0, 0);
-  a.inner = inner ? 1 : 0;
-  hipLaunchKernelGGL(decide_batch_kernel, dim3((uint32_t)act_.size()), dim3(64), 0, stream_, a);
+  const int jl = std::max(0, j_end - 1);
+  BatchArgs a = args(cur, prev, jl, replacements_before(jl, R_) & 1, j_end > 0 && deferred(j_end) ? 1 : 0);
+  a.table = multi_ ? tab_dev_ + (inner ? off_upd32_ : off_upd64_) : nullptr;
+  if (inner)
+    hipLaunchKernelGGL(decide_batch_kernel<float>, dim3(n_upd32_), dim3(kT), 0, stream_, a);
+  else
+    hipLaunchKernelGGL(decide_batch_kernel<double>, dim3(n_upd64_), dim3(kT), 0, stream_, a);
   HIP_TRY(hipGetLastError());
   cur ^= 1;
   HIP_TRY(hipMemcpyAsync(snap_host_, snap_dev_, act_.size() * sizeof(Scalars), hipMemcpyDeviceToHost, stream_));
@@ -432,24 +443,33 @@ int Engine::pcg(int first_chunk) {
   int& cur = inner ? icur_ : ocur_;
   int& prev = inner ? iprev_ : oprev_;
   const int upd_kind = inner ? PK_UPD32 : PK_UPD64;
-  // Timing samples one iteration in kSampleEvery and every replacement, with
-  // events the dispatch itself records at the start and end of each kernel
-  // (marker events between every launch would lengthen the run they time).
+  // Timing samples one iteration in kSampleEvery, counted across solves so
+  // that the sample holds the forms of the direction kernel (with or without
+  // the deferred update) in their overall proportion, and every replacement,
+  // with events the dispatch itself records at the start and end of each
+  // kernel (marker events between every launch would lengthen the run they
+  // time).
   constexpr int kSampleEvery = 8;
-  auto sampled = [&](int jj) { return timing_ && (jj % kSampleEvery == 1 || (R_ > 0 && jj % R_ == 0)); };
+  auto replacing = [&](int jj) { return R_ > 0 && jj % R_ == 0; };
   int j = 0;
   int k = std::max(1, first_chunk);
   for (;;) {
-    if (timing_) RC_TRY(ensure_events(4 * (size_t)k));
+    if (timing_) {
+      RC_TRY(ensure_events(4 * (size_t)k));
+      sampled_.assign((size_t)k, 0);
+    }
     for (int c = 0; c < k; ++c) {
       const int jj = j + c;
-      const bool ev = sampled(jj);
+      const bool pick = timing_ && (sample_ctr_++ % kSampleEvery) == 0;
+      if (pick) sampled_[(size_t)c] = 1;
+      const bool ev = pick || (timing_ && replacing(jj));
       hipEvent_t* e = ev_.data() + 4 * c;
-      RC_TRY(gather<RoleDir<V>>(args(cur, prev, jj, 0), ev ? e[0] : nullptr, ev ? e[1] : nullptr));
+      const int xpar = replacements_before(jj, R_) & 1;
+      RC_TRY(gather<RoleDir<V>>(args(cur, prev, jj, xpar, deferred(jj) ? 1 : 0), ev ? e[0] : nullptr,
+                                ev ? e[1] : nullptr));
       cur ^= 1;
       prev = PK_GATHER;
-      const int xpar = replacements_before(jj, R_) & 1;
-      if (R_ > 0 && jj % R_ == 0) {
+      if (replacing(jj)) {
         RC_TRY(gather<RoleRepl<V>>(args(cur, prev, jj, xpar), ev ? e[2] : nullptr, ev ? e[3] : nullptr));
         prev = PK_GATHER;
       } else {
@@ -458,7 +478,7 @@ int Engine::pcg(int first_chunk) {
       }
       cur ^= 1;
     }
-    RC_TRY(decide(inner));
+    RC_TRY(decide(inner, j + k));
     bool all_done = true;
     int most = j;
     for (size_t q = 0; q < act_.size(); ++q) {
@@ -471,13 +491,16 @@ int Engine::pcg(int first_chunk) {
     if (timing_) {
       const int ran = std::max(0, std::min(most - j, k));
       for (int c = 0; c < ran; ++c) {
-        if (!sampled(j + c)) continue;
+        const bool pick = sampled_[(size_t)c] != 0, rep = replacing(j + c);
+        if (!pick && !rep) continue;
         float g_ms = 0.f, u_ms = 0.f;
-        HIP_TRY(hipEventElapsedTime(&g_ms, ev_[4 * c], ev_[4 * c + 1]));
         HIP_TRY(hipEventElapsedTime(&u_ms, ev_[4 * c + 2], ev_[4 * c + 3]));
-        stats.gather_launches += 1;
-        stats.gather_ms += g_ms;
-        if (R_ > 0 && (j + c) % R_ == 0) {
+        if (pick) {
+          HIP_TRY(hipEventElapsedTime(&g_ms, ev_[4 * c], ev_[4 * c + 1]));
+          stats.gather_launches += 1;
+          stats.gather_ms += g_ms;
+        }
+        if (rep) {
           stats.replace_launches += 1;
           stats.replace_ms += u_ms;
         } else {

@@ -88,6 +88,13 @@ __device__ inline uint32_t xcd_work_item(uint32_t b, uint32_t nblocks) {
   return (b & 7u) * (nblocks >> 3) + (b >> 3);
 }
 
+// A prologue that also owns the iterate: it applies the previous iteration's
+// deferred x += alpha d at the block's own nodes (see ProDirection).
+template <class P>
+struct CarriesIterate {
+  static constexpr bool value = false;
+};
+
 // One block's share of a gather: tile `logical` of the solve that `ga`, the
 // functors and the relay describe.  The block's dot-product partial is
 // stored at index `logical`, and tile 0 publishes the relayed state.
@@ -163,11 +170,13 @@ __device__ inline void gather_tile(const GatherArgs<V>& ga, Pro pro, Epi epi, co
 
     // Two register sets hold the planes l+1 and l+2 (and coefficient layers
     // l and l+1) while layer l computes.
+    constexpr bool XI = CarriesIterate<Pro>::value;
     struct Stage {
       typename Pro::Raw p[kSlots];
       V a[kSlots], b[kSlots];
+      V xo, dold;  // iterate and old direction at this column's node emitted with this stage
     };
-    auto fetch = [&](Stage& S, int z, int l) {  // plane z, coefficient layer l (both clamped)
+    auto fetch = [&](Stage& S, int z, int l, int zown) {  // plane z, coefficient layer l, own node zown (clamped)
       const uint32_t zo = pstride * (uint32_t)min(max(z, 0), pz - 1);
       const uint32_t lo_ = lstride * (uint32_t)min(max(l, 0), nz - 1);
 #pragma unroll
@@ -175,6 +184,11 @@ __device__ inline void gather_tile(const GatherArgs<V>& ga, Pro pro, Epi epi, co
         S.p[k] = pro.fetch(pxy[k] + zo);
         S.a[k] = ga.rhoc[cxy[k] + lo_];
         S.b[k] = ga.kc[cxy[k] + lo_];
+      }
+      if constexpr (XI) {
+        const uint32_t io = col_xy + pstride * (uint32_t)min(max(zown, 0), pz - 1);
+        S.xo = pro.x[io];
+        S.dold = pro.dold[io];
       }
     };
     auto store = [&](const Stage& S, int l, int buf) {  // LDS only
@@ -246,8 +260,9 @@ __device__ inline void gather_tile(const GatherArgs<V>& ga, Pro pro, Epi epi, co
     // here (clamped to the march: past its end they re-read the last ones).
     auto layer = [&](int k, int buf, Stage& S, auto emit) {
       store(S, lay(k), buf);
+      const V xo_k = S.xo, dold_k = S.dold;  // node vis(k), fetched with this stage
       __syncthreads();
-      fetch(S, vis(min(k + 3, n)), lay(min(k + 2, n - 1)));
+      fetch(S, vis(min(k + 3, n)), lay(min(k + 2, n - 1)), vis(min(k + 2, n)));
       read_plane(plane + buf * PW * PH, PW, ltx, lty, hi);
       const V* A = ca + buf * CW * CH;
       const V* B = cb + buf * CW * CH;
@@ -256,6 +271,8 @@ __device__ inline void gather_tile(const GatherArgs<V>& ga, Pro pro, Epi epi, co
       if (decltype(emit)::value) {  // node vis(k) is owned by this block
         const uint32_t i = col_xy + pstride * (uint32_t)vis(k);
         pro.write(i, lo.c, col_ok, ga.sink);
+        if constexpr (XI)
+          if (pro.corr) *(col_ok ? pro.x + i : ga.sink + threadIdx.x) = fma(pro.alpha, dold_k, xo_k);
         dot += epi.store(i, carry + p_lo, lo.c, col_ok, ga.sink);
       }
       carry = p_hi;
@@ -268,10 +285,23 @@ __device__ inline void gather_tile(const GatherArgs<V>& ga, Pro pro, Epi epi, co
     Stage SA, SB;
     {
       Stage S0;
-      fetch(S0, vis(0), lay(0));
-      fetch(SB, vis(1), lay(0));
-      fetch(SA, vis(min(2, n)), lay(min(1, n - 1)));
-      if (!stage_finish(R, in, st, logical == 0)) return;  // uniform
+      fetch(S0, vis(0), lay(0), vis(0));
+      fetch(SB, vis(1), lay(0), vis(0));
+      fetch(SA, vis(min(2, n)), lay(min(1, n - 1)), vis(1));
+      if (!stage_finish(R, in, st, logical == 0)) {  // uniform
+        if constexpr (XI) {
+          // the solve finished in this kernel's evaluation: the last
+          // iteration's deferred iterate update is still due at own nodes
+          if (R.mode == M_DIR && in.pending && st.status == 0 && pro.corr && col_ok) {
+            const V al = (V)st.alpha;
+            for (int z = z0; z < z1; ++z) {
+              const uint32_t i = col_xy + pstride * (uint32_t)z;
+              pro.x[i] = fma(al, pro.dold[i], pro.x[i]);
+            }
+          }
+        }
+        return;
+      }
       pro.init(st);
       epi.init(st);
       store(S0, -1, 0);  // plane vis(0) into buffer 0 (its coefficient slots are rewritten before use)
@@ -318,20 +348,36 @@ struct ProPlain {  // v = src
   __device__ void write(uint32_t, V, bool, V*) const {}
 };
 
+// The iterate update x += alpha d of Algorithm 1 is deferred to the next
+// iteration's direction gather, which reads d_old anyway: at its own nodes it
+// applies x += alpha_prev d_old when `corr` is set (the previous iteration
+// ended with a plain update, not a residual replacement, which updates x
+// itself).  The x/r update kernel then streams r, q and P^-1 only.
 template <typename V>
 struct ProDirection {  // d_new = P^-1 r + beta d_old   (Algorithm 1: s <- P^-1 r, d <- s + beta d)
   const V* r;
   const V* pinv;
   const V* dold;
   V* dnew;
+  V* x;          // iterate, updated in place at own nodes
+  int32_t corr;  // apply the deferred x += alpha d_old
   V beta;
+  V alpha;
   struct Raw {
     V r, p, d;
   };
-  __device__ void init(const Scalars& S) { beta = (V)S.beta; }
+  __device__ void init(const Scalars& S) {
+    beta = (V)S.beta;
+    alpha = (V)S.alpha;
+  }
   __device__ Raw fetch(uint32_t i) const { return Raw{r[i], pinv[i], dold[i]}; }
   __device__ V finish(const Raw& w) const { return fma(beta, w.d, w.p * w.r); }
   __device__ void write(uint32_t i, V v, bool live, V* sink) const { *(live ? dnew + i : sink + threadIdx.x) = v; }
+};
+
+template <typename V>
+struct CarriesIterate<ProDirection<V>> {
+  static constexpr bool value = true;
 };
 
 template <typename V, typename W>

@@ -1,4 +1,4 @@
-// Pointwise kernels of the solver (gfx950): the fused PCG update of
+// Pointwise kernels of the solver (gfx950): the fused PCG residual update of
 // Algorithm 1 (AXPY + DIMVM + VVM + Beta_update of App. A.2 in one pass),
 // the setup kernels (Jacobi diagonal, boundary load vector, Dirichlet
 // values), precision casts for the mixed form and sensor interpolation.
@@ -22,79 +22,88 @@ struct Vec<float> {
   static constexpr int W = 4;
 };
 
-// x += alpha d ; r -= alpha q (0 on Dirichlet rows) ; delta_new = r^T P^-1 r
-// Dirichlet rows are recognised by P^-1 = 0.
+// r -= alpha q (0 on Dirichlet rows) ; delta_new = r^T P^-1 r.  Dirichlet
+// rows are recognised by P^-1 = 0.  (x += alpha d is deferred to the next
+// direction gather.)
 template <typename V>
-__device__ inline void upd1(V& x, V d, V& r, V q, V p, V alpha, double& acc) {
-  x = fma(alpha, d, x);
+__device__ inline void upd1(V& r, V q, V p, V alpha, double& acc) {
   V rr = fma(-alpha, q, r);
   rr = (p == V(0)) ? V(0) : rr;
   r = rr;
   acc += (double)rr * (double)(p * rr);
 }
 
-// Fused update of one solve by block `blk` of its `nblk` blocks (a
+// Residual update of one solve by block `blk` of its `nblk` blocks (a
 // grid-stride loop over the solve's own block count, so the partial sums do
-// not depend on the launch the block belongs to).  Settles alpha = delta /
-// d^T q first -- the block's first loads are already in flight while it sums
-// the partials -- and is a no-op once the solve is done.
+// not depend on the launch the block belongs to).  Each thread loads kU
+// strided vectors before it uses any, and the first kU before it settles
+// alpha = delta / d^T q, so the partial sum runs while they are in flight.
+// A no-op once the solve is done.
 template <typename V>
-__device__ inline void update_body(V* __restrict__ x, const V* __restrict__ d, V* __restrict__ r,
-                                   const V* __restrict__ q, const V* __restrict__ pinv, uint32_t N, const Relay& R,
-                                   uint32_t blk, uint32_t nblk) {
+__device__ inline void update_body(V* __restrict__ r, const V* __restrict__ q, const V* __restrict__ pinv, uint32_t N,
+                                   const Relay& R, uint32_t blk, uint32_t nblk) {
   const StageIn in = stage_load(R);
   if (stage_idle(R, in, blk == 0)) return;
   using VT = typename Vec<V>::T;
   constexpr int W = Vec<V>::W;
+  constexpr int kU = 4;
   const uint32_t nvec = N / W;
   const uint32_t stride = nblk * blockDim.x;
   const uint32_t tid = blk * blockDim.x + threadIdx.x;
-  VT* xv = reinterpret_cast<VT*>(x);
-  const VT* dv = reinterpret_cast<const VT*>(d);
   VT* rv = reinterpret_cast<VT*>(r);
   const VT* qv = reinterpret_cast<const VT*>(q);
   const VT* pv = reinterpret_cast<const VT*>(pinv);
-  // first vector of this thread (clamped: always a valid address)
-  const uint32_t j0 = nvec > 0 ? min(tid, nvec - 1) : 0;
-  VT xx{}, dd{}, rr{}, qq{}, pp{};
-  if (nvec > 0) {
-    xx = xv[j0];
-    dd = dv[j0];
-    rr = rv[j0];
-    qq = qv[j0];
-    pp = pv[j0];
-  }
+  VT rr[kU], qq[kU], pp[kU];
+  auto load = [&](uint32_t base) {
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+      const uint32_t j = base + (uint32_t)u * stride;
+      if (j < nvec) {
+        rr[u] = rv[j];
+        qq[u] = qv[j];
+        pp[u] = pv[j];
+      }
+    }
+  };
+  load(tid);
   Scalars st;
   if (!stage_finish(R, in, st, blk == 0)) return;
   const V alpha = (V)st.alpha;
   double acc = 0.0;
-  for (uint32_t j = tid; j < nvec; j += stride) {
-    if (j != tid) {
-      xx = xv[j];
-      dd = dv[j];
-      rr = rv[j];
-      qq = qv[j];
-      pp = pv[j];
+  for (uint32_t base = tid; base < nvec; base += kU * stride) {
+    if (base != tid) load(base);
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+      const uint32_t j = base + (uint32_t)u * stride;
+      if (j < nvec) {
+        if constexpr (W == 2) {
+          upd1(rr[u].x, qq[u].x, pp[u].x, alpha, acc);
+          upd1(rr[u].y, qq[u].y, pp[u].y, alpha, acc);
+        } else {
+          upd1(rr[u].x, qq[u].x, pp[u].x, alpha, acc);
+          upd1(rr[u].y, qq[u].y, pp[u].y, alpha, acc);
+          upd1(rr[u].z, qq[u].z, pp[u].z, alpha, acc);
+          upd1(rr[u].w, qq[u].w, pp[u].w, alpha, acc);
+        }
+        rv[j] = rr[u];
+      }
     }
-    if constexpr (W == 2) {
-      upd1(xx.x, dd.x, rr.x, qq.x, pp.x, alpha, acc);
-      upd1(xx.y, dd.y, rr.y, qq.y, pp.y, alpha, acc);
-    } else {
-      upd1(xx.x, dd.x, rr.x, qq.x, pp.x, alpha, acc);
-      upd1(xx.y, dd.y, rr.y, qq.y, pp.y, alpha, acc);
-      upd1(xx.z, dd.z, rr.z, qq.z, pp.z, alpha, acc);
-      upd1(xx.w, dd.w, rr.w, qq.w, pp.w, alpha, acc);
-    }
-    xv[j] = xx;
-    rv[j] = rr;
   }
   for (uint32_t i = nvec * W + tid; i < N; i += stride) {
-    V xs = x[i], rs = r[i];
-    upd1(xs, d[i], rs, q[i], pinv[i], alpha, acc);
-    x[i] = xs;
+    V rs = r[i];
+    upd1(rs, q[i], pinv[i], alpha, acc);
     r[i] = rs;
   }
   publish_partial(R, acc, blk);
+}
+
+// x += alpha d over a solve's nodes, by block `blk` of `nblk` (the deferred
+// iterate update of a solve that finished in a decide kernel).
+template <typename V>
+__device__ inline void axpy_body(V* __restrict__ x, const V* __restrict__ d, V alpha, uint32_t N, uint32_t blk,
+                                 uint32_t nblk) {
+  const uint32_t stride = nblk * blockDim.x;
+  for (uint32_t i = blk * blockDim.x + threadIdx.x; i < N; i += stride) x[i] = fma(alpha, d[i], x[i]);
 }
 
 // Start of an inner (FP32) solve of A e = r64 by block `blk` of `nblk`:
