@@ -91,7 +91,6 @@ class Engine {
   ~Engine() {
     (void)hipStreamSynchronize(stream_);
     dfree(sd_dev_);
-    dfree(snap_dev_);
     dfree(tab_dev_);
     for (auto& p : sd_host_)
       if (p) (void)hipHostFree(p);
@@ -115,7 +114,7 @@ class Engine {
   int upload_simdev();
   void fill_simdev(const Sim& s, SimDev& d) const;
   BatchArgs args(int cur, int prev, int j, int xpar, int corr = 0) const {
-    return BatchArgs{sd_dev_, nullptr, snap_dev_, cur, prev, j, xpar, corr};
+    return BatchArgs{sd_dev_, nullptr, snap_map_, cur, prev, j, xpar, corr};
   }
   // Whether the update of iteration jj - 1 was a plain one, whose x += alpha d
   // the direction kernel of iteration jj (or the decide after it) applies.
@@ -151,8 +150,8 @@ class Engine {
   SimDev* sd_host_[2] = {nullptr, nullptr};  // pinned staging, used alternately
   int sd_flip_ = 0;
   size_t sd_cap_ = 0;
-  Scalars* snap_dev_ = nullptr;
-  Scalars* snap_host_ = nullptr;
+  Scalars* snap_host_ = nullptr;  // pinned, coherent: the decide kernel writes it directly
+  Scalars* snap_map_ = nullptr;   // its device address
   size_t snap_cap_ = 0;
   uint2* tab_dev_ = nullptr;
   uint2* tab_host_ = nullptr;
@@ -331,11 +330,12 @@ int Engine::compose() {
     sd_cap_ = n;
   }
   if (snap_cap_ < n) {
-    dfree(snap_dev_);
     if (snap_host_) (void)hipHostFree(snap_host_);
-    snap_host_ = nullptr;
-    RC_TRY(dalloc(h, &snap_dev_, n));
-    HIP_TRY(hipHostMalloc(reinterpret_cast<void**>(&snap_host_), n * sizeof(Scalars), hipHostMallocDefault));
+    snap_host_ = snap_map_ = nullptr;
+    snap_cap_ = 0;
+    HIP_TRY(hipHostMalloc(reinterpret_cast<void**>(&snap_host_), n * sizeof(Scalars),
+                          hipHostMallocMapped | hipHostMallocCoherent));
+    HIP_TRY(hipHostGetDevicePointer(reinterpret_cast<void**>(&snap_map_), snap_host_, 0));
     snap_cap_ = n;
   }
   // launch groups by element class, each with its work table
@@ -429,7 +429,6 @@ int Engine::decide(bool inner, int j_end) {
     hipLaunchKernelGGL(decide_batch_kernel<double>, dim3(n_upd64_), dim3(kT), 0, stream_, a);
   HIP_TRY(hipGetLastError());
   cur ^= 1;
-  HIP_TRY(hipMemcpyAsync(snap_host_, snap_dev_, act_.size() * sizeof(Scalars), hipMemcpyDeviceToHost, stream_));
   HIP_TRY(hipStreamSynchronize(stream_));
   return FEM_OK;
 }
@@ -453,6 +452,7 @@ int Engine::pcg(int first_chunk) {
   auto replacing = [&](int jj) { return R_ > 0 && jj % R_ == 0; };
   int j = 0;
   int k = std::max(1, first_chunk);
+  int chunks = 0;
   for (;;) {
     if (timing_) {
       RC_TRY(ensure_events(4 * (size_t)k));
@@ -511,7 +511,9 @@ int Engine::pcg(int first_chunk) {
     }
     j += k;
     if (all_done) break;
-    k = 4;
+    // the first chunk runs the estimate (the last step's count); a solve
+    // that needs more mostly needs one or two more iterations
+    k = ++chunks == 1 ? 2 : 4;
   }
   return FEM_OK;
 }

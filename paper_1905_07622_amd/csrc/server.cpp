@@ -133,37 +133,47 @@ void Lane::loop() {
     std::vector<Request*> admit, cancelled;
     {
       std::unique_lock<std::mutex> lk(S.mu);
-      // a queued request of this class that admission would take now
-      auto admissible = [&] {
-        if (S.nrunning >= S.o.max_slots) return false;
-        for (Request* r : S.queue) {
-          if (r->st.bytes > S.budget - S.in_use) return false;
-          if (r->key == key) return true;
+      // Admission in arrival order: a request is taken only if it fits
+      // together with every request ahead of it (which other lanes take),
+      // so the first one that does not fit blocks all later ones, of any
+      // class, and a later request never takes the budget or the slot of an
+      // earlier one.  `take` visits the requests of this class that fit.
+      auto scan = [&](auto take) {
+        uint64_t bytes = S.in_use;
+        int32_t slots = S.nrunning;
+        for (auto it = S.queue.begin(); it != S.queue.end();) {
+          Request* r = *it;
+          if (r->st.bytes > S.budget - std::min(S.budget, bytes) || slots >= S.o.max_slots) return;
+          bytes += r->st.bytes;
+          slots += 1;
+          if (r->key == key) {
+            if (!take(it)) return;
+          } else {
+            ++it;
+          }
         }
-        return false;
+      };
+      auto admissible = [&] {
+        bool any = false;
+        scan([&](std::deque<Request*>::iterator&) { return !(any = true); });
+        return any;
       };
       S.cv_work.wait(lk, [&] { return S.stop || !running.empty() || admissible(); });
       if (S.stop)
         for (Request* r : running) r->cancel = true;
       for (Request* r : running)
         if (r->cancel) cancelled.push_back(r);
-      // admission in arrival order; the first request that does not fit
-      // blocks all later ones, of any class
       if (!S.stop) {
-        for (auto it = S.queue.begin(); it != S.queue.end();) {
-          Request* r = *it;
-          if (r->st.bytes > S.budget - S.in_use) break;
-          if (r->key != key) {
-            ++it;
-            continue;
-          }
-          if (S.nrunning + (int32_t)admit.size() >= S.o.max_slots) break;
+        scan([&](std::deque<Request*>::iterator& it) {
+          admit.push_back(*it);
           it = S.queue.erase(it);
-          S.in_use += r->st.bytes;
-          S.peak = std::max(S.peak, S.in_use);
-          admit.push_back(r);
-        }
+          return true;
+        });
+        for (Request* r : admit) S.in_use += r->st.bytes;
+        S.peak = std::max(S.peak, S.in_use);
         S.nrunning += (int32_t)admit.size();
+        // requests of other classes behind these may be admissible now
+        if (!admit.empty()) S.cv_work.notify_all();
       }
     }
     // cancelled simulations leave without outputs

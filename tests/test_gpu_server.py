@@ -117,6 +117,20 @@ def test_cancel_queued_and_running(gpu):
     same_bits(ra, alone[0])
 
 
+def test_one_slot_admits_in_arrival_order_across_classes(gpu):
+    """With one slot, requests of different size classes (different lanes)
+    still run one at a time in arrival order."""
+    probs = [wl.random_problem(20, 20, 20, seed=130, nsteps=6), wl.random_problem(5, 5, 5, seed=131, nsteps=2),
+             wl.random_problem(12, 12, 12, seed=132, nsteps=3), wl.random_problem(5, 6, 5, seed=133, nsteps=2)]
+    with fh.Server(max_slots=1) as srv:
+        ts = [srv.submit(p) for p in probs]
+        got = [srv.wait(t) for t in ts]
+    ds = [d for _, d, _ in got]
+    assert all(d["state"] == fh.FEM_REQ_DONE and d["status"] == 0 for d in ds)
+    for a, b in zip(ds, ds[1:]):
+        assert b["t_admit"] >= a["t_done"]
+
+
 def test_budget_refusal_and_unknown_ticket(gpu):
     with fh.Server(budget_bytes=1000) as srv:
         with pytest.raises(fh.FemError) as e:
