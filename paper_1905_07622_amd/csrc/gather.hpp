@@ -108,9 +108,11 @@ __device__ inline void gather_tile(const GatherArgs<V>& ga, Pro pro, Epi epi, co
   const int TX = ga.s.tx, TY = ga.s.ty, TZ = ga.s.tz;
   const int NW = TX + 2, PH = TY + 2, NC = TX + 1, CH = TY + 1;  // tile widths (nodes, elements)
   const int PW = ga.s.pw, CW = ga.s.cw;                          // LDS row pitches (bank-conflict padding)
+  // Coefficient tiles: cubic elements keep their four class coefficients
+  // (computed once per element when staged), general ones rho*c and k.
+  const int CS = CW * CH;
   V* plane = reinterpret_cast<V*>(smem_raw);  // [2][PH*PW]
-  V* ca = plane + 2 * PW * PH;               // [2][CH*CW]
-  V* cb = ca + 2 * CW * CH;                  // [2][CH*CW]
+  V* coef = plane + 2 * PW * PH;             // [2][4][CH*CW]
 
   const int px = ga.g.px, py = ga.g.py, pz = ga.g.pz;
   const int nx = ga.g.nx, ny = ga.g.ny, nz = ga.g.nz;
@@ -193,16 +195,24 @@ __device__ inline void gather_tile(const GatherArgs<V>& ga, Pro pro, Epi epi, co
     };
     auto store = [&](const Stage& S, int l, int buf) {  // LDS only
       V* P = plane + buf * PW * PH;
-      V* A = ca + buf * CW * CH;
-      V* B = cb + buf * CW * CH;
+      V* C = coef + buf * 4 * CS;
       const bool lin = l >= 0 && l < nz;
 #pragma unroll
       for (int k = 0; k < kSlots; ++k) {
         if (pl[k] >= 0) P[pl[k]] = pro.finish(S.p[k]);
         if (cl[k] >= 0) {
           const bool ok = lin && cin[k];
-          A[cl[k]] = ok ? ga.sa * S.a[k] : V(0);
-          B[cl[k]] = ok ? ga.sb * S.b[k] : V(0);
+          const V a = ok ? ga.sa * S.a[k] : V(0), bk = ok ? ga.sb * S.b[k] : V(0);
+          if (CUBIC) {
+            // classes by popcount: c0 = 8a+4b, c1 = 4a, c2 = 2a-b, c3 = a-b
+            C[cl[k]] = fma(V(8), a, V(4) * bk);
+            C[CS + cl[k]] = V(4) * a;
+            C[2 * CS + cl[k]] = fma(V(2), a, -bk);
+            C[3 * CS + cl[k]] = a - bk;
+          } else {
+            C[cl[k]] = a;
+            C[CS + cl[k]] = bk;
+          }
         }
       }
     };
@@ -220,40 +230,52 @@ __device__ inline void gather_tile(const GatherArgs<V>& ga, Pro pro, Epi epi, co
 
     PlaneQ<V> lo, hi;
     V carry = V(0);
-    // Contribution of one layer's 4 elements to the node of this column on
-    // plane `own`, whose other plane is `oth`.  A node's value is the sum of
-    // the contributions of its two layers, each computed by this function
-    // from zero (explicit FMAs in a fixed order; the library is built without
-    // automatic contraction) -- so it does not depend on the tiling or on the
-    // direction of the march.
-    auto contribution = [&](const PlaneQ<V>& own, const PlaneQ<V>& oth, const V* A, const V* B) {
-      V part[4];
+    // Contributions of one layer's 4 elements to the two nodes of this
+    // column that the layer joins: `lo` on plane `lp` (other plane `hp`) and
+    // `hi` on `hp`.  A node's value is the sum of the contributions of its two
+    // layers, each computed here from zero (explicit FMAs in a fixed order;
+    // the library is built without automatic contraction) -- so it does not
+    // depend on the tiling or on the direction of the march.  Each element's
+    // coefficients serve both nodes and are then dead.
+    auto contributions = [&](const PlaneQ<V>& lp, const PlaneQ<V>& hp, const V* C, V& lo_sum, V& hi_sum) {
+      V plo[4], phi[4];
 #pragma unroll
       for (int sy = 0; sy < 2; ++sy) {
 #pragma unroll
         for (int sx = 0; sx < 2; ++sx) {
           const int e = sy * 2 + sx;
           const int ci = (lty + sy) * CW + ltx + sx;
-          const V a = A[ci], bk = B[ci];
-          const V xo = sx ? own.xp : own.xm, yo = sy ? own.yp : own.ym, bo = own.b[e];
-          const V xt = sx ? oth.xp : oth.xm, yt = sy ? oth.yp : oth.ym, bt = oth.b[e];
+          const V xl = sx ? lp.xp : lp.xm, yl = sy ? lp.yp : lp.ym, bl = lp.b[e];
+          const V xh = sx ? hp.xp : hp.xm, yh = sy ? hp.yp : hp.ym, bh = hp.b[e];
           if (CUBIC) {
-            // classes by popcount: c0 = 8a+4b, c1 = 4a, c2 = 2a-b, c3 = a-b
-            const V c0 = fma(V(8), a, V(4) * bk), c1 = V(4) * a, c2 = fma(V(2), a, -bk), c3 = a - bk;
-            V u = c0 * own.c;
-            u = fma(c1, (xo + yo) + oth.c, u);
-            u = fma(c2, bo + (xt + yt), u);
-            part[e] = fma(c3, bt, u);
+            const V c0 = C[ci], c1 = C[CS + ci], c2 = C[2 * CS + ci], c3 = C[3 * CS + ci];
+            V u = c0 * lp.c;
+            u = fma(c1, (xl + yl) + hp.c, u);
+            u = fma(c2, bl + (xh + yh), u);
+            plo[e] = fma(c3, bh, u);
+            V w = c0 * hp.c;
+            w = fma(c1, (xh + yh) + lp.c, w);
+            w = fma(c2, bh + (xl + yl), w);
+            phi[e] = fma(c3, bl, w);
           } else {
-            const V v[8] = {own.c, xo, yo, bo, oth.c, xt, yt, bt};  // corner differing by class c
-            V u = fma(a, ga.Mc[0], bk * ga.Kc[0]) * v[0];
+            const V a = C[ci], bk = C[CS + ci];
+            const V vl[8] = {lp.c, xl, yl, bl, hp.c, xh, yh, bh};  // corner differing by class c
+            const V vh[8] = {hp.c, xh, yh, bh, lp.c, xl, yl, bl};
+            V c = fma(a, ga.Mc[0], bk * ga.Kc[0]);
+            V u = c * vl[0], w = c * vh[0];
 #pragma unroll
-            for (int c = 1; c < 8; ++c) u = fma(fma(a, ga.Mc[c], bk * ga.Kc[c]), v[c], u);
-            part[e] = u;
+            for (int k = 1; k < 8; ++k) {
+              c = fma(a, ga.Mc[k], bk * ga.Kc[k]);
+              u = fma(c, vl[k], u);
+              w = fma(c, vh[k], w);
+            }
+            plo[e] = u;
+            phi[e] = w;
           }
         }
       }
-      return (part[0] + part[1]) + (part[2] + part[3]);
+      lo_sum = (plo[0] + plo[1]) + (plo[2] + plo[3]);
+      hi_sum = (phi[0] + phi[1]) + (phi[2] + phi[3]);
     };
     // Layer k: completes node vis(k) (its other layer was layer k-1) and
     // starts node vis(k+1).  Loads for plane vis(k+3) and layer k+2 are issued
@@ -264,10 +286,8 @@ __device__ inline void gather_tile(const GatherArgs<V>& ga, Pro pro, Epi epi, co
       __syncthreads();
       fetch(S, vis(min(k + 3, n)), lay(min(k + 2, n - 1)), vis(min(k + 2, n)));
       read_plane(plane + buf * PW * PH, PW, ltx, lty, hi);
-      const V* A = ca + buf * CW * CH;
-      const V* B = cb + buf * CW * CH;
-      const V p_lo = contribution(lo, hi, A, B);
-      const V p_hi = contribution(hi, lo, A, B);
+      V p_lo, p_hi;
+      contributions(lo, hi, coef + buf * 4 * CS, p_lo, p_hi);
       if (decltype(emit)::value) {  // node vis(k) is owned by this block
         const uint32_t i = col_xy + pstride * (uint32_t)vis(k);
         pro.write(i, lo.c, col_ok, ga.sink);

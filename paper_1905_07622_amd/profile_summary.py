@@ -65,24 +65,36 @@ def stats(d: str, out: str, commands):
     print("\n".join(lines))
 
 
-def counter_means(d: str):
+def counter_means(d: str, working: float = 0.0):
+    """Mean counter value per (kernel, counter) over its dispatches.  With
+    working > 0, dispatches below that fraction of the kernel's largest value
+    are left out: iteration kernels launched after their solve finished (a
+    chunk runs a few iterations past the end) exit at once and move almost
+    nothing, and the timing the traffic is compared with skips them too."""
     rows = list(csv.DictReader(open(find_csv(d, "counter_collection.csv"))))
     acc = defaultdict(list)
     for r in rows:
         acc[(short_name(r["Kernel_Name"]), r["Counter_Name"])].append(float(r["Counter_Value"]))
-    return {k: (sum(v) / len(v), len(v)) for k, v in acc.items()}
+    out = {}
+    for k, v in acc.items():
+        if working > 0 and v:
+            top = max(v)
+            v = [x for x in v if x >= working * top] or v
+        out[k] = (sum(v) / len(v), len(v))
+    return out
 
 
 def traffic(fetch_dir, write_dir, copy_fetch_dir, copy_write_dir, out_txt, out_json, kernel_regex, commands,
             algorithmic_bytes=None):
-    fetch = counter_means(fetch_dir)
-    write = counter_means(write_dir)
+    fetch = counter_means(fetch_dir, working=0.25)
+    write = counter_means(write_dir, working=0.25)
     cf = [v for (k, c), v in counter_means(copy_fetch_dir).items() if "copy" in k.lower() and c == "FETCH_SIZE"]
     cw = [v for (k, c), v in counter_means(copy_write_dir).items() if "copy" in k.lower() and c == "WRITE_SIZE"]
     # the copy kernel with the largest count is the 256 MiB calibration copy
     fscale = COPY_BYTES / (max(x[0] for x in cf) * 1024.0)
     wscale = COPY_BYTES / (max(x[0] for x in cw) * 1024.0)
-    lines = ["# HBM traffic per dispatch from rocprofv3 FETCH_SIZE / WRITE_SIZE (KiB), scaled by a plain copy", ""]
+    lines = ["# HBM traffic per dispatch from rocprofv3 FETCH_SIZE / WRITE_SIZE (KiB), scaled by a plain copy",
+             "# (means over working dispatches: those moving at least 25% of the kernel's largest dispatch)", ""]
     lines += [f"command: {c}" for c in commands]
     lines += ["", f"copy calibration: {COPY_BYTES} bytes copied; FETCH_SIZE scale {fscale:.4f}, "
                   f"WRITE_SIZE scale {wscale:.4f}", "",
