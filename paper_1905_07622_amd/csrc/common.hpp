@@ -80,7 +80,7 @@ struct GatherShape {
   uint32_t ntiles;    // ntx*nty*ntz
   uint32_t nblocks;   // ntiles rounded up to a multiple of 8 (one share per XCD)
   size_t smem_bytes(size_t vbytes) const {
-    return vbytes * (2 * (size_t)pw * (ty + 2) + 8 * (size_t)cw * (ty + 1));
+    return vbytes * (2 * (size_t)pw * (ty + 2) + 4 * (size_t)cw * (ty + 1));
   }
 };
 

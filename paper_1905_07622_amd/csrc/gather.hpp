@@ -108,11 +108,12 @@ __device__ inline void gather_tile(const GatherArgs<V>& ga, Pro pro, Epi epi, co
   const int TX = ga.s.tx, TY = ga.s.ty, TZ = ga.s.tz;
   const int NW = TX + 2, PH = TY + 2, NC = TX + 1, CH = TY + 1;  // tile widths (nodes, elements)
   const int PW = ga.s.pw, CW = ga.s.cw;                          // LDS row pitches (bank-conflict padding)
-  // Coefficient tiles: cubic elements keep their four class coefficients
-  // (computed once per element when staged), general ones rho*c and k.
+  // Coefficient tiles: the scaled rho*c and k of each element of a layer.
+  // (Staging the four cubic class coefficients instead saves arithmetic but
+  // doubles these tiles, and measured slower.)
   const int CS = CW * CH;
   V* plane = reinterpret_cast<V*>(smem_raw);  // [2][PH*PW]
-  V* coef = plane + 2 * PW * PH;             // [2][4][CH*CW]
+  V* coef = plane + 2 * PW * PH;             // [2][2][CH*CW]: rho*c, k
 
   const int px = ga.g.px, py = ga.g.py, pz = ga.g.pz;
   const int nx = ga.g.nx, ny = ga.g.ny, nz = ga.g.nz;
@@ -195,7 +196,7 @@ __device__ inline void gather_tile(const GatherArgs<V>& ga, Pro pro, Epi epi, co
     };
     auto store = [&](const Stage& S, int l, int buf) {  // LDS only
       V* P = plane + buf * PW * PH;
-      V* C = coef + buf * 4 * CS;
+      V* C = coef + buf * 2 * CS;
       const bool lin = l >= 0 && l < nz;
 #pragma unroll
       for (int k = 0; k < kSlots; ++k) {
@@ -203,16 +204,8 @@ __device__ inline void gather_tile(const GatherArgs<V>& ga, Pro pro, Epi epi, co
         if (cl[k] >= 0) {
           const bool ok = lin && cin[k];
           const V a = ok ? ga.sa * S.a[k] : V(0), bk = ok ? ga.sb * S.b[k] : V(0);
-          if (CUBIC) {
-            // classes by popcount: c0 = 8a+4b, c1 = 4a, c2 = 2a-b, c3 = a-b
-            C[cl[k]] = fma(V(8), a, V(4) * bk);
-            C[CS + cl[k]] = V(4) * a;
-            C[2 * CS + cl[k]] = fma(V(2), a, -bk);
-            C[3 * CS + cl[k]] = a - bk;
-          } else {
-            C[cl[k]] = a;
-            C[CS + cl[k]] = bk;
-          }
+          C[cl[k]] = a;
+          C[CS + cl[k]] = bk;
         }
       }
     };
@@ -248,7 +241,9 @@ __device__ inline void gather_tile(const GatherArgs<V>& ga, Pro pro, Epi epi, co
           const V xl = sx ? lp.xp : lp.xm, yl = sy ? lp.yp : lp.ym, bl = lp.b[e];
           const V xh = sx ? hp.xp : hp.xm, yh = sy ? hp.yp : hp.ym, bh = hp.b[e];
           if (CUBIC) {
-            const V c0 = C[ci], c1 = C[CS + ci], c2 = C[2 * CS + ci], c3 = C[3 * CS + ci];
+            // classes by popcount: c0 = 8a+4b, c1 = 4a, c2 = 2a-b, c3 = a-b
+            const V a = C[ci], bk = C[CS + ci];
+            const V c0 = fma(V(8), a, V(4) * bk), c1 = V(4) * a, c2 = fma(V(2), a, -bk), c3 = a - bk;
             V u = c0 * lp.c;
             u = fma(c1, (xl + yl) + hp.c, u);
             u = fma(c2, bl + (xh + yh), u);
@@ -287,7 +282,7 @@ __device__ inline void gather_tile(const GatherArgs<V>& ga, Pro pro, Epi epi, co
       fetch(S, vis(min(k + 3, n)), lay(min(k + 2, n - 1)), vis(min(k + 2, n)));
       read_plane(plane + buf * PW * PH, PW, ltx, lty, hi);
       V p_lo, p_hi;
-      contributions(lo, hi, coef + buf * 4 * CS, p_lo, p_hi);
+      contributions(lo, hi, coef + buf * 2 * CS, p_lo, p_hi);
       if (decltype(emit)::value) {  // node vis(k) is owned by this block
         const uint32_t i = col_xy + pstride * (uint32_t)vis(k);
         pro.write(i, lo.c, col_ok, ga.sink);

@@ -52,14 +52,40 @@ def find_csv(d: str, suffix: str) -> str:
     return hits[0]
 
 
+def working_durations(d: str):
+    """Per kernel: durations (ns) of the dispatches that did work -- at least
+    half the kernel's median duration.  Iteration kernels launched after their
+    solve finished exit at once; the benchmark's sampled timing skips them."""
+    try:
+        rows = list(csv.DictReader(open(find_csv(d, "kernel_trace.csv"))))
+    except FileNotFoundError:
+        return {}
+    acc = defaultdict(list)
+    for r in rows:
+        acc[short_name(r["Kernel_Name"])].append(int(r["End_Timestamp"]) - int(r["Start_Timestamp"]))
+    out = {}
+    for k, v in acc.items():
+        med = sorted(v)[len(v) // 2]
+        out[k] = [x for x in v if x >= 0.5 * med]
+    return out
+
+
 def stats(d: str, out: str, commands):
     rows = list(csv.DictReader(open(find_csv(d, "kernel_stats.csv"))))
+    work = working_durations(d)
     lines = ["# rocprofv3 kernel statistics", ""]
     lines += [f"command: {c}" for c in commands]
-    lines += ["", f"{'kernel':90s} {'calls':>7s} {'avg_us':>9s} {'min_us':>8s} {'max_us':>8s} {'share%':>7s}"]
+    lines += ["", "working: dispatches lasting at least half the kernel's median (iteration kernels launched",
+              "after their solve finished exit at once and are left out, as the benchmark's timing does)", "",
+              f"{'kernel':70s} {'calls':>7s} {'avg_us':>9s} {'min_us':>8s} {'max_us':>8s} {'share%':>7s} "
+              f"{'working':>8s} {'work_avg_us':>11s}"]
     for r in rows:
-        lines.append(f"{short_name(r['Name'])[:90]:90s} {int(r['Calls']):7d} {float(r['AverageNs']) / 1e3:9.3f} "
-                     f"{float(r['MinNs']) / 1e3:8.3f} {float(r['MaxNs']) / 1e3:8.3f} {float(r['Percentage']):7.2f}")
+        name = short_name(r["Name"])
+        w = work.get(name, [])
+        wa = f"{sum(w) / len(w) / 1e3:11.3f}" if w else f"{'-':>11s}"
+        lines.append(f"{name[:70]:70s} {int(r['Calls']):7d} {float(r['AverageNs']) / 1e3:9.3f} "
+                     f"{float(r['MinNs']) / 1e3:8.3f} {float(r['MaxNs']) / 1e3:8.3f} {float(r['Percentage']):7.2f} "
+                     f"{len(w):8d} {wa}")
     with open(out, "w") as f:
         f.write("\n".join(lines) + "\n")
     print("\n".join(lines))
