@@ -42,21 +42,24 @@ def deferred_fraction(iters, R: int = 50) -> float:
     return corr / total if total else 0.0
 
 
-def algorithmic_bytes(N: int, E: int, w: int, f_corr: float) -> dict:
+def algorithmic_bytes(N: int, E: int, w: int, f_corr: float, one_reduction: bool = False) -> dict:
     """Bytes each kernel must move per launch (no re-reads counted), averaged
     over the launches the timing samples.
     gather (direction + apply): read r, P^-1, d_old, rho*c_e, k_e; write d_new,
-    q; in the share f_corr of launches also read and write x.
-    update: read r, q, P^-1; write r."""
-    return {"gather": (5 * N + 2 * E) * w + 2 * N * w * f_corr, "update": 4 * N * w}
+    q; in the share f_corr of launches also read and write x (and, in the
+    one-reduction form, read the previous q and write the advanced r).
+    update (two-kernel form only): read r, q, P^-1; write r."""
+    per_corr = 4 if one_reduction else 2
+    return {"gather": (5 * N + 2 * E) * w + per_corr * N * w * f_corr, "update": 0 if one_reduction else 4 * N * w}
 
 
-def committed_traffic(kernel: str, precision: str):
+def committed_traffic(kernel: str, precision: str, form: str = "two-kernel"):
     """HBM bytes per launch of `kernel` from the committed rocprofv3 FETCH_SIZE /
     WRITE_SIZE summary of this workload, or None when there is none or the
     kernel sources changed since it was taken."""
     from paper_1905_07622_amd.profile_summary import kernel_source_hash
-    path = os.path.join(ROOT, "profiles", f"traffic_{kernel}_lognormal100_{precision}.json")
+    tag = "" if form == "two-kernel" else "_one_reduction"
+    path = os.path.join(ROOT, "profiles", f"traffic_{kernel}{tag}_lognormal100_{precision}.json")
     if not os.path.exists(path):
         return None
     with open(path) as f:
@@ -224,6 +227,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-timing", action="store_true", help="time without per-kernel HIP events")
     ap.add_argument("--tile", type=int, nargs=3, default=(0, 0, 0))
+    ap.add_argument("--pcg-form", choices=["two-kernel", "one-reduction"], default="two-kernel",
+                    help="Algorithm 1 with two kernels (and reductions) per iteration, or the one-reduction form")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched-proposals measurement")
     ap.add_argument("--no-served", action="store_true", help="skip the serving measurement")
     ap.add_argument("--only-extra", action="store_true", help="skip the 1M-DOF headline run")
@@ -276,7 +281,8 @@ def main():
     prec = fh.FEM_FP64 if args.precision == "fp64" else fh.FEM_FP32_FP64DOT
     h = fh.Heat(p.nx, p.ny, p.nz, p.hx, p.hy, p.hz, k, rc, dirichlet_mask=p.dirichlet_mask,
                 flux_mask=p.flux_mask, flux=p.flux, precision=prec, device_ptrs=True,
-                timing=not args.no_timing, tile=tuple(args.tile), stream=stream)
+                timing=not args.no_timing, tile=tuple(args.tile), stream=stream,
+                one_reduction=args.pcg_form == "one-reduction")
     run_kw = dict(dt=p.dt, theta=p.theta, nsteps=p.nsteps, rtol=p.rtol)
     for w in range(args.warmup):
         h.run(T0, **run_kw)
@@ -306,16 +312,18 @@ def main():
     w = 8 if args.precision == "fp64" else 4
     it_steps = last["iters"]
     f_corr = deferred_fraction(it_steps.cpu().numpy() if hasattr(it_steps, "cpu") else it_steps)
-    ab = algorithmic_bytes(p.n_nodes, p.n_elems, w, f_corr)
+    one_red = args.pcg_form == "one-reduction"
+    ab = algorithmic_bytes(p.n_nodes, p.n_elems, w, f_corr, one_red)
     roof = None
-    if stats["gather_launches"] and stats["update_launches"]:
-        per = {"gather": stats["gather_ms"] / stats["gather_launches"],
-               "update": stats["update_ms"] / stats["update_launches"]}
-        dom = max(("gather", "update"), key=lambda kname: stats[kname + "_ms"])
+    if stats["gather_launches"] and (stats["update_launches"] or one_red):
+        per = {"gather": stats["gather_ms"] / stats["gather_launches"]}
+        if stats["update_launches"]:
+            per["update"] = stats["update_ms"] / stats["update_launches"]
+        dom = max(per, key=lambda kname: stats[kname + "_ms"])
         achieved = ab[dom] / (per[dom] * 1e-3) / 1e9
         roof = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": committed_traffic(dom, args.precision),
+                "traffic": committed_traffic(dom, args.precision, args.pcg_form),
                 "bytes_per_launch": int(round(ab[dom])), "avg_launch_us": round(per[dom] * 1e3, 3),
                 "deferred_update_share": round(f_corr, 4),
                 "other_kernels_us": {kname: round(v * 1e3, 3) for kname, v in per.items() if kname != dom}}
@@ -335,7 +343,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"log-normal k, {p.nx}^3 hex Q1 ({p.n_nodes} DOF), Crank-Nicolson dt=5e-4, "
                                f"{p.nsteps} steps, rtol 1e-8, Jacobi-PCG", "seed": 2,
-                   "precision": args.precision, "iterations_per_run": int(last["total_iters"]),
+                   "precision": args.precision, "pcg_form": args.pcg_form,
+                   "iterations_per_run": int(last["total_iters"]),
                    "tile": [shape["tile_x"], shape["tile_y"], shape["tile_z"]],
                    "grid_blocks": shape["grid_blocks"]},
         "roofline": roof,

@@ -64,6 +64,14 @@ extern "C" {
 #define FEM_TIMING 0x2u      /* time iteration kernels with HIP events (every 8th iteration launched,
                                 counted across solves, and every residual replacement, so the
                                 events barely perturb the run) */
+#define FEM_ONE_REDUCTION 0x4u /* FP64 PCG in one kernel and one reduction per iteration: the direction
+                                  kernel also completes the previous update (r -= alpha q, x += alpha d)
+                                  and sums d^T q, q^T P^-1 r, q^T P^-1 q and r^T P^-1 r; alpha and the stop
+                                  test are Algorithm 1's, beta uses r'^T P^-1 r' = delta - 2 alpha
+                                  q^T P^-1 r + alpha^2 q^T P^-1 q (restarted from the summed delta every
+                                  iteration), so the iterates agree with Algorithm 1 to rounding.  One
+                                  extra direction kernel per solve; the inner FP32 solves of the mixed
+                                  form keep two kernels per iteration */
 
 /* Operators for fem_heat_apply */
 #define FEM_OP_A 0           /* y = (M + theta*dt*K) x                              */

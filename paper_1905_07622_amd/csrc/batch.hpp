@@ -39,6 +39,8 @@ struct SimDev {
   double* b64;
   double* r64;
   double* q64;
+  double* r64b;  // one-reduction form: second residual and apply buffers (ping-pong with r64, q64)
+  double* q64b;
   double* d64[2];
   const double* T1;  // T^{n-1}
   const double* T2;  // T^{n-2}
@@ -56,6 +58,7 @@ struct SimDev {
   Ctl octl, ictl;
   uint32_t N;
   uint32_t nblk[4];    // blocks of each PartKind
+  uint32_t ldp;        // capacity of each partial component (one-reduction form: four per block)
   double fs;           // dt * s_n of the current step
   int32_t guess_prev;  // 1: x0 = T^{n-1}
   int32_t xc;          // mixed form: X buffer of the current FP64 iterate
@@ -77,11 +80,11 @@ struct BatchArgs {
 
 __device__ inline Relay outer_relay(const SimDev& s, const BatchArgs& a, int32_t mode, bool partials) {
   return Relay{s.oS[a.cur], s.oS[a.cur ^ 1], s.oP[a.cur], s.nblk[a.prev], partials ? s.oP[a.cur ^ 1] : nullptr,
-               mode, s.octl};
+               mode, s.octl, s.ldp};
 }
 __device__ inline Relay inner_relay(const SimDev& s, const BatchArgs& a, int32_t mode, bool partials) {
   return Relay{s.iS[a.cur], s.iS[a.cur ^ 1], s.iP[a.cur], s.nblk[a.prev], partials ? s.iP[a.cur ^ 1] : nullptr,
-               mode, s.ictl};
+               mode, s.ictl, s.ldp};
 }
 
 // The direction ping-pongs every iteration: iteration j reads d[j&1] and
@@ -171,6 +174,39 @@ struct RoleRepl<float> {
   static __device__ Relay relay(const SimDev& s, const BatchArgs& a) { return inner_relay(s, a, M_UPD, true); }
 };
 
+// One-reduction form (FP64): iteration j's residual lives in buffer j&1 of
+// (r64, r64b) and its q = A d in buffer j&1 of (q64, q64b); the initial
+// residual is in r64 (buffer 0).
+__device__ inline double* rbuf(const SimDev& s, int k) { return (k & 1) ? s.r64b : s.r64; }
+__device__ inline double* qbuf(const SimDev& s, int k) { return (k & 1) ? s.q64b : s.q64; }
+
+struct RoleFused {  // (r -= alpha q, x += alpha d_old,) d = P^-1 r + beta d, q = A d, four sums (a4-a6)
+  using V = double;
+  using Pro = ProFused<double>;
+  using Epi = EpiQ<double>;
+  static __device__ const GatherArgs<V>& ga(const SimDev& s) { return s.A64; }
+  static __device__ Pro pro(const SimDev& s, const BatchArgs& a) {
+    return Pro{rbuf(s, a.corr ? a.j + 1 : a.j), qbuf(s, a.j + 1), s.pinv64, s.d64[dir_in(a)], s.d64[dir_out(a)],
+               s.X[a.xpar], rbuf(s, a.j), a.corr, 0.0, 0.0};
+  }
+  static __device__ Epi epi(const SimDev& s, const BatchArgs& a) { return Epi{qbuf(s, a.j)}; }
+  static __device__ Relay relay(const SimDev& s, const BatchArgs& a) {
+    return outer_relay(s, a, a.corr ? M_FUPD : M_FDIR, true);
+  }
+};
+
+struct RoleReplFused {  // one-reduction form: x += alpha d, r = b - A x into the next residual buffer
+  using V = double;
+  using Pro = ProAxpy<double, double>;
+  using Epi = EpiResidual<double>;
+  static __device__ const GatherArgs<V>& ga(const SimDev& s) { return s.A64; }
+  static __device__ Pro pro(const SimDev& s, const BatchArgs& a) {
+    return Pro{s.X[a.xpar], s.d64[dir_out(a)], s.X[a.xpar ^ 1], 0, 0.0};
+  }
+  static __device__ Epi epi(const SimDev& s, const BatchArgs& a) { return Epi{s.b64, s.pinv64, rbuf(s, a.j + 1)}; }
+  static __device__ Relay relay(const SimDev& s, const BatchArgs& a) { return outer_relay(s, a, M_FREPL, true); }
+};
+
 struct RoleCorr {  // mixed form: x64 += e, r64 = b - A x64, FP64 residual norm (a9)
   using V = double;
   using Pro = ProAxpy<double, float>;
@@ -200,7 +236,7 @@ __device__ inline void work_item(const BatchArgs& a, uint32_t w, uint32_t& sim, 
 // One gather role over every simulation of a launch group (grid = the sum
 // of the group's per-simulation block counts, each a multiple of 8).
 template <bool CUBIC, class Role>
-__global__ void __launch_bounds__(256) gather_batch_kernel(BatchArgs a) {
+__global__ void __launch_bounds__(256, 2) gather_batch_kernel(BatchArgs a) {
   uint32_t sim, local;
   work_item(a, xcd_work_item(blockIdx.x, gridDim.x), sim, local);
   const SimDev& s = a.sims[sim];

@@ -31,12 +31,13 @@ struct Scalars {
   double dq;         // d^T q
   double alpha;
   double beta;
+  double mu, nu;     // one-reduction form: q^T P^-1 r and q^T P^-1 q of the last direction
   int32_t iter;      // completed iterations of the current solve
   int32_t done;      // 1: every further iteration kernel is a no-op
   int32_t status;    // 0 or a negative status (breakdown)
   int32_t zero_rhs;  // b^T P^-1 b == 0 with the RHS stop rule
   int32_t phase;     // which scalar update the latest partials complete
-  int32_t pad;
+  int32_t fresh;     // one-reduction form: the last direction kernel also advanced r
 };
 
 // Controls of one solve.
@@ -51,7 +52,8 @@ enum Phase : int32_t {
   PH_AFTER_INIT = 1,   // partials hold r0^T P^-1 r0
   PH_AFTER_UPD = 2,    // partials hold r^T P^-1 r after an update
   PH_AFTER_CHECK = 3,  // partials hold the FP64 residual norm of a refinement sweep
-  PH_DECIDED = 4
+  PH_DECIDED = 4,
+  PH_AFTER_FUSED = 5   // partials hold d^T q, q^T P^-1 r, q^T P^-1 q, r^T P^-1 r (one-reduction form)
 };
 
 // Role of a kernel in the relay.
@@ -65,7 +67,11 @@ enum Mode : int32_t {
   M_CORR = 6,    // FP64 correction of a refinement sweep
   M_DECIDE = 7,  // settles the pending decision only
   M_SKIP = 8,    // relays the state unchanged and does no work
-  M_IDLE = 9     // an inner solve that is not needed: starts done, zero iterations
+  M_IDLE = 9,    // an inner solve that is not needed: starts done, zero iterations
+  // one-reduction form: settle the pending update, then
+  M_FDIR = 10,   //   direction + apply with the residual as it is (after the initial residual or a replacement)
+  M_FUPD = 11,   //   r -= alpha q, x += alpha d, then direction + apply
+  M_FREPL = 12   //   residual replacement x += alpha d, r = b - A x
 };
 
 constexpr int32_t kStatusBreakdown = -4;
@@ -79,8 +85,10 @@ struct GatherShape {
   int32_t pw, cw;     // LDS row pitches of the plane tile (>= TX+2) and coefficient tile (>= TX+1)
   uint32_t ntiles;    // ntx*nty*ntz
   uint32_t nblocks;   // ntiles rounded up to a multiple of 8 (one share per XCD)
-  size_t smem_bytes(size_t vbytes) const {
-    return vbytes * (2 * (size_t)pw * (ty + 2) + 4 * (size_t)cw * (ty + 1));
+  // LDS of a gather: `planes` double-buffered node planes and two
+  // double-buffered coefficient tiles.
+  size_t smem_bytes(size_t vbytes, int planes = 1) const {
+    return vbytes * (2 * (size_t)planes * pw * (ty + 2) + 4 * (size_t)cw * (ty + 1));
   }
 };
 

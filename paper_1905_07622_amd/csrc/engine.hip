@@ -26,6 +26,7 @@
 #include <cmath>
 #include <cstring>
 #include <memory>
+#include <type_traits>
 #include <vector>
 
 #include <hip/hip_ext.h>
@@ -76,7 +77,7 @@ namespace {
 struct Group {
   bool cubic = true;
   uint32_t off = 0, nwork = 0, nthreads = 64;
-  size_t smem64 = 0, smem32 = 0;
+  size_t smem64 = 0, smem32 = 0, smem64f = 0;  // smem64f: one-reduction direction kernel (three planes)
 };
 
 }  // namespace
@@ -86,6 +87,7 @@ class Engine {
   Engine(hipStream_t stream, const fem_opts& o, fem_heat* err) : stream_(stream), opts_(o), h_(err) {
     mixed_ = o.precision == FEM_FP32_FP64DOT;
     timing_ = (o.flags & FEM_TIMING) != 0;
+    fused_ = !mixed_ && (o.flags & FEM_ONE_REDUCTION) != 0;
     R_ = o.replace_every;
   }
   ~Engine() {
@@ -137,6 +139,7 @@ class Engine {
   fem_opts opts_;
   fem_heat* h_;  // receives error messages
   bool mixed_ = false, timing_ = false;
+  bool fused_ = false;  // FP64 PCG in the one-reduction form
   int R_ = 50;
   uint64_t sample_ctr_ = 0;         // iterations launched with timing, across solves
   std::vector<uint8_t> sampled_;    // per iteration of the current chunk
@@ -251,6 +254,9 @@ void Engine::fill_simdev(const Sim& s, SimDev& d) const {
   d.b64 = h->b64;
   d.r64 = h->r64;
   d.q64 = h->q64;
+  d.r64b = h->r64b ? h->r64b : h->r64;
+  d.q64b = h->q64b ? h->q64b : h->q64;
+  d.ldp = h->n_partials;
   d.d64[0] = h->d64[0];
   d.d64[1] = h->d64[1];
   d.T1 = s.T1;
@@ -352,6 +358,7 @@ int Engine::compose() {
       g.nthreads = std::max<uint32_t>(g.nthreads, (uint32_t)sh->shape.nthreads);
       g.smem64 = std::max(g.smem64, sh->shape.smem_bytes(8));
       g.smem32 = std::max(g.smem32, sh->shape.smem_bytes(4));
+      g.smem64f = std::max(g.smem64f, sh->shape.smem_bytes(8, 3));
     }
     g.nwork = (uint32_t)tab.size() - g.off;
     if (g.nwork > 0) groups_[ngroups_++] = g;
@@ -388,7 +395,9 @@ int Engine::gather(BatchArgs a, hipEvent_t e0, hipEvent_t e1) {
   for (int gi = 0; gi < ngroups_; ++gi) {
     const Group& g = groups_[gi];
     a.table = multi_ ? tab_dev_ + g.off : nullptr;
-    const size_t smem = sizeof(typename Role::V) == 8 ? g.smem64 : g.smem32;
+    const size_t smem = std::is_same<Role, RoleFused>::value ? g.smem64f
+                        : sizeof(typename Role::V) == 8        ? g.smem64
+                                                               : g.smem32;
     hipEvent_t s0 = gi == 0 ? e0 : nullptr, s1 = gi == ngroups_ - 1 ? e1 : nullptr;
     if (g.cubic)
       hipExtLaunchKernelGGL((gather_batch_kernel<true, Role>), dim3(g.nwork), dim3(g.nthreads), smem, stream_, s0, s1,
@@ -421,7 +430,10 @@ int Engine::decide(bool inner, int j_end) {
   int& cur = inner ? icur_ : ocur_;
   int& prev = inner ? iprev_ : oprev_;
   const int jl = std::max(0, j_end - 1);
-  BatchArgs a = args(cur, prev, jl, replacements_before(jl, R_) & 1, j_end > 0 && deferred(j_end) ? 1 : 0);
+  // (the one-reduction form owes nothing when a solve ends: its direction
+  // kernel completes each update before the stop test)
+  BatchArgs a = args(cur, prev, jl, replacements_before(jl, R_) & 1,
+                     !(fused_ && !inner) && j_end > 0 && deferred(j_end) ? 1 : 0);
   a.table = multi_ ? tab_dev_ + (inner ? off_upd32_ : off_upd64_) : nullptr;
   if (inner)
     hipLaunchKernelGGL(decide_batch_kernel<float>, dim3(n_upd32_), dim3(kT), 0, stream_, a);
@@ -442,6 +454,7 @@ int Engine::pcg(int first_chunk) {
   int& cur = inner ? icur_ : ocur_;
   int& prev = inner ? iprev_ : oprev_;
   const int upd_kind = inner ? PK_UPD32 : PK_UPD64;
+  const bool one_red = fused_ && !inner;  // one kernel per iteration (plus replacements)
   // Timing samples one iteration in kSampleEvery, counted across solves so
   // that the sample holds the forms of the direction kernel (with or without
   // the deferred update) in their overall proportion, and every replacement,
@@ -465,18 +478,27 @@ int Engine::pcg(int first_chunk) {
       const bool ev = pick || (timing_ && replacing(jj));
       hipEvent_t* e = ev_.data() + 4 * c;
       const int xpar = replacements_before(jj, R_) & 1;
-      RC_TRY(gather<RoleDir<V>>(args(cur, prev, jj, xpar, deferred(jj) ? 1 : 0), ev ? e[0] : nullptr,
-                                ev ? e[1] : nullptr));
+      if (one_red) {
+        RC_TRY(gather<RoleFused>(args(cur, prev, jj, xpar, deferred(jj) ? 1 : 0), ev ? e[0] : nullptr,
+                                 ev ? e[1] : nullptr));
+      } else {
+        RC_TRY(gather<RoleDir<V>>(args(cur, prev, jj, xpar, deferred(jj) ? 1 : 0), ev ? e[0] : nullptr,
+                                  ev ? e[1] : nullptr));
+      }
       cur ^= 1;
       prev = PK_GATHER;
       if (replacing(jj)) {
-        RC_TRY(gather<RoleRepl<V>>(args(cur, prev, jj, xpar), ev ? e[2] : nullptr, ev ? e[3] : nullptr));
+        if (one_red)
+          RC_TRY(gather<RoleReplFused>(args(cur, prev, jj, xpar), ev ? e[2] : nullptr, ev ? e[3] : nullptr));
+        else
+          RC_TRY(gather<RoleRepl<V>>(args(cur, prev, jj, xpar), ev ? e[2] : nullptr, ev ? e[3] : nullptr));
         prev = PK_GATHER;
-      } else {
+        cur ^= 1;
+      } else if (!one_red) {
         RC_TRY(update<V>(args(cur, prev, jj, xpar), ev ? e[2] : nullptr, ev ? e[3] : nullptr));
         prev = upd_kind;
+        cur ^= 1;
       }
-      cur ^= 1;
     }
     RC_TRY(decide(inner, j + k));
     bool all_done = true;
@@ -492,18 +514,18 @@ int Engine::pcg(int first_chunk) {
       const int ran = std::max(0, std::min(most - j, k));
       for (int c = 0; c < ran; ++c) {
         const bool pick = sampled_[(size_t)c] != 0, rep = replacing(j + c);
-        if (!pick && !rep) continue;
         float g_ms = 0.f, u_ms = 0.f;
-        HIP_TRY(hipEventElapsedTime(&u_ms, ev_[4 * c + 2], ev_[4 * c + 3]));
         if (pick) {
           HIP_TRY(hipEventElapsedTime(&g_ms, ev_[4 * c], ev_[4 * c + 1]));
           stats.gather_launches += 1;
           stats.gather_ms += g_ms;
         }
         if (rep) {
+          HIP_TRY(hipEventElapsedTime(&u_ms, ev_[4 * c + 2], ev_[4 * c + 3]));
           stats.replace_launches += 1;
           stats.replace_ms += u_ms;
-        } else {
+        } else if (pick && !one_red) {
+          HIP_TRY(hipEventElapsedTime(&u_ms, ev_[4 * c + 2], ev_[4 * c + 3]));
           stats.update_launches += 1;
           stats.update_ms += u_ms;
         }

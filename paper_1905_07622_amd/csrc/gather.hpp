@@ -95,6 +95,13 @@ struct CarriesIterate {
   static constexpr bool value = false;
 };
 
+// A prologue of the one-reduction form: it also advances the residual and
+// stages it (and P^-1) for the node's own dot products.
+template <class P>
+struct AdvancesResidual {
+  static constexpr bool value = false;
+};
+
 // One block's share of a gather: tile `logical` of the solve that `ga`, the
 // functors and the relay describe.  The block's dot-product partial is
 // stored at index `logical`, and tile 0 publishes the relayed state.
@@ -114,16 +121,27 @@ __device__ inline void gather_tile(const GatherArgs<V>& ga, Pro pro, Epi epi, co
   const int CS = CW * CH;
   V* plane = reinterpret_cast<V*>(smem_raw);  // [2][PH*PW]
   V* coef = plane + 2 * PW * PH;             // [2][2][CH*CW]: rho*c, k
+  constexpr bool FU = AdvancesResidual<Pro>::value;
+  V* rpl = coef + 4 * CS;    // one-reduction form: [2][PH*PW] advanced residual
+  V* ppl = rpl + 2 * PW * PH;  //                    [2][PH*PW] P^-1
 
   const int px = ga.g.px, py = ga.g.py, pz = ga.g.pz;
   const int nx = ga.g.nx, ny = ga.g.ny, nz = ga.g.nz;
   const uint32_t pstride = (uint32_t)px * (uint32_t)py, lstride = (uint32_t)nx * (uint32_t)ny;
 
   if (logical >= ga.s.ntiles) {  // a padding block: partial 0 (never the writer)
-    if (stage_finish(R, in, st, false) && R.pout) publish_partial(R, 0.0, logical);
+    if (stage_finish(R, in, st, false) && R.pout) {
+      if constexpr (AdvancesResidual<Pro>::value) {
+        const double z[4] = {0.0, 0.0, 0.0, 0.0};
+        publish_partial4(R, z, logical);
+      } else {
+        publish_partial(R, 0.0, logical);
+      }
+    }
     return;
   }
   double dot = 0.0;
+  double dots[4] = {0.0, 0.0, 0.0, 0.0};  // one-reduction form: d^T q, q^T P^-1 r, q^T P^-1 q, r^T P^-1 r
   {
     // tile order: z-chunk fastest, then x, then y -- the tiles that split a
     // row in x are neighbours in the order and so share an XCD (and its L2),
@@ -200,7 +218,16 @@ __device__ inline void gather_tile(const GatherArgs<V>& ga, Pro pro, Epi epi, co
       const bool lin = l >= 0 && l < nz;
 #pragma unroll
       for (int k = 0; k < kSlots; ++k) {
-        if (pl[k] >= 0) P[pl[k]] = pro.finish(S.p[k]);
+        if constexpr (FU) {
+          if (pl[k] >= 0) {
+            const V rn = pro.residual(S.p[k]);
+            P[pl[k]] = pro.direction(S.p[k], rn);
+            rpl[buf * PW * PH + pl[k]] = rn;
+            ppl[buf * PW * PH + pl[k]] = S.p[k].p;
+          }
+        } else {
+          if (pl[k] >= 0) P[pl[k]] = pro.finish(S.p[k]);
+        }
         if (cl[k] >= 0) {
           const bool ok = lin && cin[k];
           const V a = ok ? ga.sa * S.a[k] : V(0), bk = ok ? ga.sb * S.b[k] : V(0);
@@ -223,6 +250,7 @@ __device__ inline void gather_tile(const GatherArgs<V>& ga, Pro pro, Epi epi, co
 
     PlaneQ<V> lo, hi;
     V carry = V(0);
+    V rn_lo = V(0), pp_lo = V(0), rn_hi = V(0), pp_hi = V(0);  // one-reduction form: own node's r, P^-1
     // Contributions of one layer's 4 elements to the two nodes of this
     // column that the layer joins: `lo` on plane `lp` (other plane `hp`) and
     // `hi` on `hp`.  A node's value is the sum of the contributions of its two
@@ -281,6 +309,11 @@ __device__ inline void gather_tile(const GatherArgs<V>& ga, Pro pro, Epi epi, co
       __syncthreads();
       fetch(S, vis(min(k + 3, n)), lay(min(k + 2, n - 1)), vis(min(k + 2, n)));
       read_plane(plane + buf * PW * PH, PW, ltx, lty, hi);
+      if constexpr (FU) {  // the new plane's centre: this column's node vis(k+1)
+        const int c = (lty + 1) * PW + ltx + 1;
+        rn_hi = rpl[buf * PW * PH + c];
+        pp_hi = ppl[buf * PW * PH + c];
+      }
       V p_lo, p_hi;
       contributions(lo, hi, coef + buf * 2 * CS, p_lo, p_hi);
       if (decltype(emit)::value) {  // node vis(k) is owned by this block
@@ -288,10 +321,26 @@ __device__ inline void gather_tile(const GatherArgs<V>& ga, Pro pro, Epi epi, co
         pro.write(i, lo.c, col_ok, ga.sink);
         if constexpr (XI)
           if (pro.corr) *(col_ok ? pro.x + i : ga.sink + threadIdx.x) = fma(pro.alpha, dold_k, xo_k);
-        dot += epi.store(i, carry + p_lo, lo.c, col_ok, ga.sink);
+        if constexpr (FU) {
+          if (pro.corr) *(col_ok ? pro.rnew + i : ga.sink + threadIdx.x) = rn_lo;
+          const V qv = carry + p_lo;
+          *(col_ok ? epi.q + i : ga.sink + threadIdx.x) = qv;
+          if (col_ok) {
+            dots[0] += (double)lo.c * (double)qv;
+            dots[1] += (double)qv * (double)(pp_lo * rn_lo);
+            dots[2] += (double)qv * (double)(pp_lo * qv);
+            dots[3] += (double)rn_lo * (double)(pp_lo * rn_lo);
+          }
+        } else {
+          dot += epi.store(i, carry + p_lo, lo.c, col_ok, ga.sink);
+        }
       }
       carry = p_hi;
       lo = hi;
+      if constexpr (FU) {
+        rn_lo = rn_hi;
+        pp_lo = pp_hi;
+      }
     };
 
     // Prologue: the first three planes and the first two coefficient layers
@@ -323,6 +372,11 @@ __device__ inline void gather_tile(const GatherArgs<V>& ga, Pro pro, Epi epi, co
     }
     __syncthreads();
     read_plane(plane, PW, ltx, lty, lo);
+    if constexpr (FU) {
+      const int c = (lty + 1) * PW + ltx + 1;
+      rn_lo = rpl[c];
+      pp_lo = ppl[c];
+    }
     using no = std::integral_constant<bool, false>;
     using yes = std::integral_constant<bool, true>;
     layer(0, 1, SB, no{});  // node vis(0) belongs to the neighbouring chunk
@@ -333,7 +387,11 @@ __device__ inline void gather_tile(const GatherArgs<V>& ga, Pro pro, Epi epi, co
     }
     if (k < n) layer(k, 0, SA, yes{});
   }
-  if (R.pout) publish_partial(R, dot, logical);
+  if constexpr (FU) {
+    if (R.pout) publish_partial4(R, dots, logical);
+  } else {
+    if (R.pout) publish_partial(R, dot, logical);
+  }
 }
 
 // A gather of one solve: one block per tile (grid = ga.s.nblocks).
@@ -392,6 +450,53 @@ struct ProDirection {  // d_new = P^-1 r + beta d_old   (Algorithm 1: s <- P^-1 
 
 template <typename V>
 struct CarriesIterate<ProDirection<V>> {
+  static constexpr bool value = true;
+};
+
+// One-reduction form of an iteration (one kernel, one set of partial sums):
+// when `corr` is set the kernel first completes the previous iteration's
+// update, r -= alpha q (0 on Dirichlet rows, as in the update kernel) and
+// x += alpha d_old (own nodes), then forms d = P^-1 r + beta d_old and
+// q = A d.  Its partials are d^T q, q^T P^-1 r, q^T P^-1 q and r^T P^-1 r of
+// the advanced r (see PH_AFTER_FUSED).  The residual ping-pongs (the halo of
+// a tile reads r values that another tile advances).
+template <typename V>
+struct ProFused {
+  const V* r;     // residual this kernel starts from
+  const V* qold;  // q of the previous iteration (read always; used when corr)
+  const V* pinv;
+  const V* dold;
+  V* dnew;
+  V* x;           // iterate, updated in place at own nodes
+  V* rnew;        // advanced residual, written at own nodes when corr
+  int32_t corr;
+  V beta;
+  V alpha;
+  struct Raw {
+    V r, q, p, d;
+  };
+  __device__ void init(const Scalars& S) {
+    beta = (V)S.beta;
+    alpha = (V)S.alpha;
+  }
+  __device__ Raw fetch(uint32_t i) const { return Raw{r[i], qold[i], pinv[i], dold[i]}; }
+  __device__ V residual(const Raw& w) const {
+    if (!corr) return w.r;
+    const V rr = fma(-alpha, w.q, w.r);
+    return (w.p == V(0)) ? V(0) : rr;
+  }
+  __device__ V direction(const Raw& w, V rn) const { return fma(beta, w.d, w.p * rn); }
+  __device__ V finish(const Raw& w) const { return direction(w, residual(w)); }
+  __device__ void write(uint32_t i, V v, bool live, V* sink) const { *(live ? dnew + i : sink + threadIdx.x) = v; }
+};
+
+template <typename V>
+struct CarriesIterate<ProFused<V>> {
+  static constexpr bool value = true;
+};
+
+template <typename V>
+struct AdvancesResidual<ProFused<V>> {
   static constexpr bool value = true;
 };
 
@@ -458,6 +563,12 @@ struct EpiQDot {  // q = A d ; contribution d_i q_i to d^T q
     *(live ? q + i : sink + threadIdx.x) = acc;
     return live ? (double)v * (double)acc : 0.0;
   }
+};
+
+template <typename V>
+struct EpiQ {  // q = A d (one-reduction form: the kernel forms its four dot products itself)
+  V* q;
+  __device__ void init(const Scalars&) {}
 };
 
 template <typename V>

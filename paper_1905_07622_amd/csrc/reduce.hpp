@@ -33,6 +33,7 @@ struct Relay {
   double* pout;        // this kernel's partials (one per block), or nullptr
   int32_t mode;
   Ctl ctl;
+  uint32_t ld;         // distance between the components of multi-valued partials
 };
 
 // Sum of n partials in one canonical order that does not depend on the block
@@ -62,6 +63,36 @@ __device__ inline double canonical_sum(const double* p, uint32_t n, double* red4
   return ((red4[0] + red4[1]) + red4[2]) + red4[3];
 }
 
+// Four canonical sums at once (components c at p + c*ld), in the order of
+// canonical_sum, with every load issued before the first reduction.
+__device__ inline void canonical_sum4(const double* p, uint32_t ld, uint32_t n, double* out, double* red16) {
+  const uint32_t lane = threadIdx.x & 63u, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  for (uint32_t vw = wid; vw < 4; vw += nw) {
+    const uint32_t slot = vw * 64 + lane;
+    double v[4][8];
+#pragma unroll
+    for (int c = 0; c < 4; ++c)
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const uint32_t k = slot + 256u * u;
+        v[c][u] = k < n ? p[c * ld + k] : 0.0;
+      }
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      double s = v[c][0];
+#pragma unroll
+      for (int u = 1; u < 8; ++u) s += v[c][u];
+      for (uint32_t k = slot + 2048u; k < n; k += 256u) s += p[c * ld + k];
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+      if (lane == 0) red16[c * 4 + vw] = s;
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int c = 0; c < 4; ++c) out[c] = ((red16[c * 4 + 0] + red16[c * 4 + 1]) + red16[c * 4 + 2]) + red16[c * 4 + 3];
+}
+
 // Sum over the block (blockDim.x a multiple of 64, at most 1024); valid in thread 0.
 __device__ inline double block_sum(double v, double* wsum) {
 #pragma unroll
@@ -78,8 +109,10 @@ __device__ inline double block_sum(double v, double* wsum) {
   return s;
 }
 
-// The scalar update that the previous kernel's partial sum x completes.
-__device__ inline void evaluate_pending(Scalars& s, double x, const Ctl& c) {
+// The scalar update that the previous kernel's partial sums x complete
+// (x[0] only, except after a one-reduction direction kernel: x[0..3]).
+__device__ inline void evaluate_pending(Scalars& s, const double* xs, const Ctl& c) {
+  const double x = xs[0];
   switch (s.phase) {
     case PH_AFTER_INIT: {  // r0^T P^-1 r0: tolerance and the test before the first iteration
       s.delta = x;
@@ -116,6 +149,40 @@ __device__ inline void evaluate_pending(Scalars& s, double x, const Ctl& c) {
         s.done = !(x > s.tol) ? 1 : 0;
       }
       break;
+    case PH_AFTER_FUSED: {
+      // One-reduction form.  The direction kernel that produced these sums
+      // also advanced r (when `fresh`): its r^T P^-1 r is Algorithm 1's
+      // delta_new, and the stop test is taken on it exactly as there.  If the
+      // solve goes on, alpha = delta / d^T q is Algorithm 1's, the next update
+      // is counted, and the next beta comes from the delta that update will
+      // produce, r'^T P^-1 r' = delta - 2 alpha q^T P^-1 r + alpha^2 q^T P^-1 q
+      // (restarted from the directly summed delta every iteration).
+      const double gq = xs[0], mu = xs[1], nu = xs[2];
+      if (s.fresh) {
+        s.delta_old = s.delta;
+        s.delta = xs[3];
+      }
+      s.dq = gq;
+      s.mu = mu;
+      s.nu = nu;
+      if (!isfinite(s.delta)) {
+        s.status = kStatusBreakdown;
+        s.done = 1;
+      } else if (!(s.delta > s.tol) || s.iter >= c.max_iter) {
+        s.done = 1;
+      } else {
+        const double a = s.delta / gq;
+        if (!(gq > 0.0) || !isfinite(gq) || !isfinite(a)) {
+          s.status = kStatusBreakdown;
+          s.done = 1;
+        } else {
+          s.alpha = a;
+          s.iter += 1;
+          const double next = (s.delta - 2.0 * a * mu) + (a * a) * nu;
+          s.beta = next / s.delta;
+        }
+      }
+    } break;
     default:
       break;
   }
@@ -138,14 +205,14 @@ __device__ inline StageIn stage_load(const Relay& R) {
   if (R.sin) in.t = *R.sin;
   in.pending = !in.t.done && in.t.phase != PH_DECIDED && in.t.phase != PH_NONE;
   in.need = R.mode == M_INIT || (R.mode == M_UPD && !in.t.done) ||
-            ((R.mode == M_DIR || R.mode == M_DECIDE) && in.pending);
+            ((R.mode == M_DIR || R.mode == M_DECIDE || R.mode >= M_FDIR) && in.pending);
   return in;
 }
 
 // A search-direction or update kernel of a finished solve has no work and
 // leaves the state unchanged: only the writer relays it.  Uniform.
 __device__ inline bool stage_idle(const Relay& R, const StageIn& in, bool writer) {
-  if ((R.mode == M_DIR || R.mode == M_UPD) && in.t.done) {
+  if ((R.mode == M_DIR || R.mode == M_UPD || R.mode >= M_FDIR) && in.t.done) {
     if (writer && threadIdx.x == 0 && R.sout) *R.sout = in.t;
     return true;
   }
@@ -158,10 +225,17 @@ __device__ inline bool stage_idle(const Relay& R, const StageIn& in, bool writer
 __device__ inline bool stage_finish(const Relay& R, const StageIn& in, Scalars& out, bool writer) {
   __shared__ Scalars sh;
   __shared__ int go;
-  __shared__ double red4[4];
+  __shared__ double red16[16];
   Scalars t = in.t;
   const bool pending = in.pending;
-  const double x = in.need ? canonical_sum(R.pin, R.npin, red4) : 0.0;
+  double xs[4] = {0.0, 0.0, 0.0, 0.0};
+  if (in.need) {  // uniform
+    if (pending && in.t.phase == PH_AFTER_FUSED)
+      canonical_sum4(R.pin, R.ld, R.npin, xs, red16);
+    else
+      xs[0] = canonical_sum(R.pin, R.npin, red16);
+  }
+  const double x = xs[0];
   if (threadIdx.x == 0) {
     int g = 1;
     switch (R.mode) {
@@ -186,8 +260,22 @@ __device__ inline bool stage_finish(const Relay& R, const StageIn& in, Scalars& 
         break;
       case M_DIR:
       case M_DECIDE:
-        if (pending) evaluate_pending(t, x, R.ctl);
+        if (pending) evaluate_pending(t, xs, R.ctl);
         g = (R.mode == M_DIR && !t.done) ? 1 : 0;
+        break;
+      case M_FDIR:
+      case M_FUPD:  // one-reduction direction kernel: publishes the four sums
+        if (pending) evaluate_pending(t, xs, R.ctl);
+        g = t.done ? 0 : 1;
+        if (g) {
+          t.phase = PH_AFTER_FUSED;
+          t.fresh = R.mode == M_FUPD ? 1 : 0;
+        }
+        break;
+      case M_FREPL:  // one-reduction residual replacement: publishes r^T P^-1 r
+        if (pending) evaluate_pending(t, xs, R.ctl);
+        g = t.done ? 0 : 1;
+        if (g) t.phase = PH_AFTER_UPD;
         break;
       case M_UPD:
         if (t.done) {
@@ -244,6 +332,27 @@ __device__ inline void publish_partial(const Relay& R, double v, uint32_t slot) 
   __shared__ double wsum[16];
   const double bs = block_sum(v, wsum);
   if (threadIdx.x == 0 && R.pout) R.pout[slot] = bs;
+}
+
+// Four partials per block (component c at pout[c*ld + slot]), each summed in
+// the order of block_sum.
+__device__ inline void publish_partial4(const Relay& R, const double* v, uint32_t slot) {
+  __shared__ double wsum4[4][16];
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    double x = v[c];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
+    if (lane == 0) wsum4[c][wid] = x;
+  }
+  __syncthreads();
+  if (threadIdx.x < 4 && R.pout) {
+    const int c = threadIdx.x, nw = blockDim.x >> 6;
+    double s = 0.0;
+    for (int w = 0; w < nw; ++w) s += wsum4[c][w];
+    R.pout[c * R.ld + slot] = s;
+  }
 }
 
 }  // namespace femheat

@@ -162,7 +162,7 @@ void fill_classes(const Geom& g, GatherArgs<V>& ga, double cm, double ck, bool c
   ga.sb = (V)ck;
 }
 
-Relay no_relay() { return Relay{nullptr, nullptr, nullptr, 0, nullptr, M_NONE, Ctl{0.0, 0, 0}}; }
+Relay no_relay() { return Relay{nullptr, nullptr, nullptr, 0, nullptr, M_NONE, Ctl{0.0, 0, 0}, 0}; }
 
 }  // namespace
 
@@ -313,18 +313,24 @@ int solver_init(fem_heat* h, const fem_grid* grid, const double* k_e, const doub
   RC_TRY(dalloc(h, &h->b64, N));
   RC_TRY(dalloc(h, &h->r64, N));
   RC_TRY(dalloc(h, &h->q64, N));
+  const bool one_red = (h->opts.flags & FEM_ONE_REDUCTION) != 0;
+  if (one_red) {
+    RC_TRY(dalloc(h, &h->r64b, N));
+    RC_TRY(dalloc(h, &h->q64b, N));
+  }
   RC_TRY(dalloc(h, &h->d64[0], N));
   RC_TRY(dalloc(h, &h->d64[1], N));
   for (auto& p : h->pool) RC_TRY(dalloc(h, &p, N));
   if (h->nonzero_dirichlet) RC_TRY(dalloc(h, &h->lift64, N));
   RC_TRY(dalloc(h, &h->sink, 256));
   h->n_partials = std::max({h->shape.nblocks, h->upd_blocks64, h->upd_blocks32, h->start_blocks});
+  const size_t ncomp = one_red ? 4 : 1;  // the one-reduction direction kernel publishes four sums per block
   for (RelayCtx* c : {&h->outer, &h->inner})
     for (int k = 0; k < 2; ++k) {
       RC_TRY(dalloc(h, &c->S[k], 1));
-      RC_TRY(dalloc(h, &c->P[k], h->n_partials));
+      RC_TRY(dalloc(h, &c->P[k], ncomp * h->n_partials));
       HIP_TRY(hipMemsetAsync(c->S[k], 0, sizeof(Scalars), h->stream));
-      HIP_TRY(hipMemsetAsync(c->P[k], 0, h->n_partials * sizeof(double), h->stream));
+      HIP_TRY(hipMemsetAsync(c->P[k], 0, ncomp * h->n_partials * sizeof(double), h->stream));
     }
   RC_TRY(copy_in(h, h->rhoc64, rhoc_e, E));
   RC_TRY(copy_in(h, h->k64, k_e, E));
@@ -402,12 +408,14 @@ size_t handle_device_bytes(const fem_grid& grid, const fem_opts& opts, const fem
   if (bc)
     for (int f = 0; f < 6; ++f)
       if (((bc->dirichlet_mask >> f) & 1u) && bc->dirichlet_value[f] != 0.0) lift = true;
-  // FP64: coefficients; F, pinv, b, r, q, two directions, four fields (+ lift)
-  size_t bytes = 8 * (2 * E + (11 + (lift ? 1 : 0)) * N);
+  // FP64: coefficients; F, pinv, b, r, q, two directions, four fields (+ lift; + r, q ping-pong buffers of
+  // the one-reduction form)
+  const bool one_red = (opts.flags & FEM_ONE_REDUCTION) != 0;
+  size_t bytes = 8 * (2 * E + (11 + (lift ? 1 : 0) + (one_red ? 2 : 0)) * N);
   if (opts.precision == FEM_FP32_FP64DOT) bytes += 4 * (2 * E + 8 * N);  // FP32 set
   // relay state and partials (at most max(tiles, update blocks) per buffer) and the sink
   const size_t tiles_bound = N / 32 + 1024;
-  bytes += 4 * (sizeof(Scalars) + 8 * tiles_bound) + 8 * 256;
+  bytes += 4 * (sizeof(Scalars) + 8 * tiles_bound * (one_red ? 4 : 1)) + 8 * 256;
   if (n_sensors > 0) bytes += 8 * (3 * (size_t)n_sensors + (size_t)std::max(nsteps, 1) * n_sensors);
   return bytes;
 }
@@ -423,6 +431,8 @@ void solver_free(fem_heat* h) {
   dfree(h->b64);
   dfree(h->r64);
   dfree(h->q64);
+  dfree(h->r64b);
+  dfree(h->q64b);
   for (auto& p : h->d64) dfree(p);
   for (auto& p : h->pool) dfree(p);
   dfree(h->lift64);

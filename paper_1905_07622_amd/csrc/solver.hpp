@@ -44,6 +44,8 @@ struct fem_heat {
   double* b64 = nullptr;
   double* r64 = nullptr;
   double* q64 = nullptr;
+  double* r64b = nullptr;  // one-reduction form: second residual and apply buffers
+  double* q64b = nullptr;
   double* d64[2] = {nullptr, nullptr};
   double* pool[4] = {nullptr, nullptr, nullptr, nullptr};  // T^{n-1}, T^{n-2}, x ping-pong
   double* lift64 = nullptr;   // A_fD g (only with non-zero Dirichlet values)

@@ -21,7 +21,7 @@ FEM_OK, FEM_EINVAL, FEM_ENOMEM, FEM_ENOCONV, FEM_EBREAKDOWN, FEM_EDEVICE, FEM_EB
 FEM_FP64, FEM_FP32_FP64DOT = 0, 1
 FEM_GUESS_EXTRAP, FEM_GUESS_PREV = 0, 1
 FEM_STOP_RHS, FEM_STOP_INITIAL = 0, 1
-FEM_DEVICE_PTRS, FEM_TIMING = 0x1, 0x2
+FEM_DEVICE_PTRS, FEM_TIMING, FEM_ONE_REDUCTION = 0x1, 0x2, 0x4
 FEM_OP_A, FEM_OP_L, FEM_OP_JACOBI, FEM_OP_LOAD, FEM_OP_FP32 = 0, 1, 2, 3, 0x100
 
 _dp = ctypes.POINTER(ctypes.c_double)
@@ -277,11 +277,12 @@ class _Arrays:
 
 def make_opts(*, precision=FEM_FP64, max_iter=10000, replace_every=50, guess=FEM_GUESS_EXTRAP,
               stop_rule=FEM_STOP_RHS, max_refine=4, inner_rtol=1e-5, device_ptrs=False, timing=False,
-              tile=(0, 0, 0), stream=None, device=0) -> fem_opts:
+              one_reduction=False, tile=(0, 0, 0), stream=None, device=0) -> fem_opts:
     o = fem_heat_default_opts()
     o.precision, o.max_iter, o.replace_every = precision, max_iter, replace_every
     o.guess, o.stop_rule, o.max_refine, o.inner_rtol = guess, stop_rule, max_refine, inner_rtol
-    o.flags = (FEM_DEVICE_PTRS if device_ptrs else 0) | (FEM_TIMING if timing else 0)
+    o.flags = ((FEM_DEVICE_PTRS if device_ptrs else 0) | (FEM_TIMING if timing else 0)
+               | (FEM_ONE_REDUCTION if one_reduction else 0))
     o.hip_stream = stream
     o.device = device
     o.tile_x, o.tile_y, o.tile_z = tile
@@ -447,7 +448,8 @@ class Heat:
     def __init__(self, nx, ny, nz, hx, hy, hz, k_e, rhoc_e, *, dirichlet_mask=0, dirichlet_value=None,
                  flux_mask=0, flux=None, flux_schedule=None, precision=FEM_FP64, max_iter=10000,
                  replace_every=50, guess=FEM_GUESS_EXTRAP, stop_rule=FEM_STOP_RHS, max_refine=4,
-                 inner_rtol=1e-5, device_ptrs=False, timing=False, tile=(0, 0, 0), stream=None, device=0):
+                 inner_rtol=1e-5, device_ptrs=False, timing=False, one_reduction=False, tile=(0, 0, 0), stream=None,
+                 device=0):
         self.h = None
         self.device_ptrs = device_ptrs
         self.N = (nx + 1) * (ny + 1) * (nz + 1)
@@ -464,7 +466,8 @@ class Heat:
         o = fem_heat_default_opts()
         o.precision, o.max_iter, o.replace_every = precision, max_iter, replace_every
         o.guess, o.stop_rule, o.max_refine, o.inner_rtol = guess, stop_rule, max_refine, inner_rtol
-        o.flags = (FEM_DEVICE_PTRS if device_ptrs else 0) | (FEM_TIMING if timing else 0)
+        o.flags = ((FEM_DEVICE_PTRS if device_ptrs else 0) | (FEM_TIMING if timing else 0)
+                   | (FEM_ONE_REDUCTION if one_reduction else 0))
         o.hip_stream = stream
         o.device = device
         o.tile_x, o.tile_y, o.tile_z = tile

@@ -32,3 +32,12 @@ def test_byte_model_per_node():
     assert ab0["gather"] == (5 * N + 2 * E) * 8
     assert ab1["gather"] - ab0["gather"] == 16 * N  # x read and written once
     assert ab0["update"] == ab1["update"] == 32 * N  # r, q, P^-1 read; r written
+
+
+def test_byte_model_one_reduction():
+    N, E = 1000, 729
+    ab0 = bench.algorithmic_bytes(N, E, 8, 0.0, True)
+    ab1 = bench.algorithmic_bytes(N, E, 8, 1.0, True)
+    assert ab0["gather"] == (5 * N + 2 * E) * 8  # as the two-kernel direction kernel
+    assert ab1["gather"] - ab0["gather"] == 32 * N  # + q read, r written, x read and written
+    assert ab1["update"] == 0

@@ -1,0 +1,114 @@
+"""GPU parity of the one-reduction PCG form (FEM_ONE_REDUCTION).
+
+The form runs one direction kernel per iteration that also completes the
+previous update and publishes d^T q, q^T P^-1 r, q^T P^-1 q and r^T P^-1 r;
+alpha and the stop test are Algorithm 1's, beta comes from the recurrence for
+the next r^T P^-1 r.  So it must meet the same gates as the two-kernel form:
+the FP64 oracle iteration-locked to the GPU's counts (relative L2 <= 1e-10),
+iteration counts within one of the two-kernel form, residual replacements
+(forced often here) and max_iter handled the same way, and batches whose
+members are bit-identical alone and in the mix.
+"""
+import numpy as np
+import pytest
+
+from _util import rel_l2, say
+from oracle import oracle
+from paper_1905_07622_amd import femheat as fh
+from paper_1905_07622_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+GATE64 = 1e-10
+
+
+def problems():
+    return [
+        wl.random_problem(13, 9, 11, seed=51, nsteps=5, rtol=1e-10),
+        wl.random_problem(20, 7, 5, seed=52, nsteps=4, theta=0.5, rtol=1e-9, flux_mask=1 << wl.FACE_ZP,
+                          flux=[0, 0, 0, 0, 0, 2.0]),
+        wl.random_problem(9, 12, 8, seed=53, nsteps=5, hx=0.05, hy=0.08, hz=0.03, rtol=1e-10),
+        wl.random_problem(17, 15, 16, seed=54, nsteps=4, dt=2e-3, rtol=1e-11,
+                          dirichlet_mask=(1 << wl.FACE_ZM) | (1 << wl.FACE_XP),
+                          dirichlet_value=[0, 1.5, 0, 0, -0.5, 0]),
+        wl.two_phase_sphere_cube().replace(nsteps=6),
+    ]
+
+
+def run_heat(p, **kw):
+    with fh.Heat.from_problem(p, **{k: v for k, v in kw.items() if k in ("one_reduction", "replace_every",
+                                                                        "max_iter", "timing")}) as h:
+        out = h.run(p.T0, dt=p.dt, theta=p.theta, nsteps=p.nsteps, rtol=p.rtol, save_every=1,
+                    check=kw.get("check", True))
+        st = h.stats()
+    return out, st
+
+
+@pytest.mark.parametrize("replace_every", [50, 4])
+def test_single_handle_matches_locked_oracle(gpu, replace_every):
+    for p in problems():
+        one, _ = run_heat(p, one_reduction=True, replace_every=replace_every)
+        two, _ = run_heat(p, one_reduction=False, replace_every=replace_every)
+        ref = oracle.run(p, save_every=1, locked_iters=one["iters"], replace_every=replace_every)
+        err = max(rel_l2(one["T_saved"][n], ref["T_saved"][n]) for n in range(p.nsteps))
+        say(f"  {p.name} R={replace_every}: iters {list(one['iters'])} (two-kernel {list(two['iters'])}) "
+            f"max rel L2 vs locked oracle {err:.2e}")
+        assert err <= GATE64
+        assert np.all(one["relres"] <= p.rtol)
+        assert np.abs(np.asarray(one["iters"]) - np.asarray(two["iters"])).max() <= 1
+        assert rel_l2(one["T_final"], two["T_final"]) <= GATE64
+
+
+def test_max_iter_and_statuses(gpu):
+    hard = wl.random_problem(12, 12, 12, seed=42, nsteps=2, rtol=1e-30)  # below FP64 reach
+    with fh.Heat.from_problem(hard, one_reduction=True, max_iter=40) as h:
+        out = h.run(hard.T0, dt=hard.dt, theta=hard.theta, nsteps=2, rtol=hard.rtol, check=False)
+    assert out["status"] == fh.FEM_ENOCONV and list(out["iters"]) == [40, 40]
+    ref = oracle.run(hard, nsteps=2, max_iter=40)
+    assert rel_l2(out["T_final"], ref["T_final"]) <= GATE64
+
+
+def test_batch_alone_and_mix_bitwise(gpu):
+    probs = problems() + [wl.random_problem(6, 6, 6, seed=55, nsteps=0)]
+    st, res = fh.run_batch(probs, save_every=1, one_reduction=True)
+    assert st == fh.FEM_OK
+    for p, r in zip(probs, res):
+        if p.nsteps == 0:
+            continue
+        _, alone = fh.run_batch([p], save_every=1, one_reduction=True)
+        for key in ("T_final", "T_saved", "iters", "relres"):
+            assert np.array_equal(np.asarray(r[key]), np.asarray(alone[0][key])), (p.name, key)
+        ref = oracle.run(p, save_every=1, locked_iters=r["iters"])
+        assert max(rel_l2(r["T_saved"][n], ref["T_saved"][n]) for n in range(p.nsteps)) <= GATE64
+
+
+def test_timing_counts_direction_kernels_only(gpu):
+    p = wl.random_problem(14, 12, 10, seed=12, nsteps=4, rtol=1e-11)
+    a, _ = run_heat(p, one_reduction=True)
+    b, st = run_heat(p, one_reduction=True, timing=True)
+    assert np.array_equal(a["T_final"], b["T_final"]) and np.array_equal(a["iters"], b["iters"])
+    assert st["gather_launches"] > 0 and st["gather_ms"] > 0
+    assert st["update_launches"] == 0 and st["replace_launches"] >= p.nsteps
+
+
+def test_mixed_form_ignores_the_flag(gpu):
+    p = wl.sphere_proposal(1, n=20, nsteps=3)
+    with fh.Heat.from_problem(p, precision=fh.FEM_FP32_FP64DOT) as h:
+        a = h.run(p.T0, dt=p.dt, theta=p.theta, nsteps=p.nsteps, rtol=p.rtol)
+    with fh.Heat.from_problem(p, precision=fh.FEM_FP32_FP64DOT, one_reduction=True) as h:
+        b = h.run(p.T0, dt=p.dt, theta=p.theta, nsteps=p.nsteps, rtol=p.rtol)
+    assert np.array_equal(a["T_final"], b["T_final"]) and np.array_equal(a["iters"], b["iters"])
+
+
+def test_benchmark_workload_sampled(gpu):
+    """The 1,030,301-node Crank-Nicolson workload in the benchmark's launch
+    shape, a few steps: the one-reduction form against the two-kernel form
+    (itself checked against the oracle at this size elsewhere)."""
+    p = wl.lognormal_cube(100, seed=2, nsteps=3)
+    one, _ = run_heat(p, one_reduction=True)
+    two, _ = run_heat(p, one_reduction=False)
+    say(f"  lognormal100: iters {list(one['iters'])} vs {list(two['iters'])}, "
+        f"rel L2 {rel_l2(one['T_final'], two['T_final']):.2e}")
+    assert np.abs(np.asarray(one["iters"]) - np.asarray(two["iters"])).max() <= 1
+    for n in range(p.nsteps):
+        assert rel_l2(one["T_saved"][n], two["T_saved"][n]) <= GATE64
