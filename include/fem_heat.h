@@ -61,8 +61,8 @@ extern "C" {
 #define FEM_STOP_INITIAL 1   /* continue while r^T P^-1 r > rtol^2 r0^T P^-1 r0    */
 
 #define FEM_DEVICE_PTRS 0x1u /* array arguments are device pointers               */
-#define FEM_TIMING 0x2u      /* time iteration kernels with HIP events (every 8th iteration launched,
-                                counted across solves, and every residual replacement, so the
+#define FEM_TIMING 0x2u      /* time iteration kernels with HIP events (every 64th iteration and every
+                                8th residual replacement launched, counted across solves, so the
                                 events barely perturb the run) */
 #define FEM_ONE_REDUCTION 0x4u /* FP64 PCG in one kernel and one reduction per iteration: the direction
                                   kernel also completes the previous update (r -= alpha q, x += alpha d)

@@ -99,6 +99,9 @@ class Engine {
     if (snap_host_) (void)hipHostFree(snap_host_);
     if (tab_host_) (void)hipHostFree(tab_host_);
     for (auto e : ev_) (void)hipEventDestroy(e);
+    for (const Timed& t : pending_)
+      for (hipEvent_t e : t.e)
+        if (e) (void)hipEventDestroy(e);
     for (auto e : ev_run_)
       if (e) (void)hipEventDestroy(e);
   }
@@ -133,7 +136,17 @@ class Engine {
   int epoch();
   int mixed_sweeps();
   int finish_step(Sim& s);
-  int ensure_events(size_t n);
+  // Timing of sampled iterations: events come from a pool; a chunk's records
+  // are read while the GPU runs a later chunk (reading them at the chunk
+  // boundary, where the GPU waits for the host, cost ~3% of the run).
+  struct Timed {
+    hipEvent_t e[4];  // direction kernel start/end, update or replacement start/end
+    bool gather;      // the direction kernel is in the sample
+    int kind;         // 0: no second kernel timed, 1: update, 2: replacement
+  };
+  hipEvent_t take_event();
+  int flush_timing();
+  std::vector<Timed> pending_;
 
   hipStream_t stream_;
   fem_opts opts_;
@@ -142,7 +155,7 @@ class Engine {
   bool fused_ = false;  // FP64 PCG in the one-reduction form
   int R_ = 50;
   uint64_t sample_ctr_ = 0;         // iterations launched with timing, across solves
-  std::vector<uint8_t> sampled_;    // per iteration of the current chunk
+  uint64_t replace_ctr_ = 0;        // residual replacements launched with timing
 
   std::vector<std::unique_ptr<Sim>> sims_;
   std::vector<Sim*> act_;  // simulations of the current epoch, in SimDev order
@@ -171,13 +184,42 @@ class Engine {
   hipEvent_t ev_run_[2] = {nullptr, nullptr};
 };
 
-int Engine::ensure_events(size_t n) {
-  fem_heat* h = h_;
-  while (ev_.size() < n) {
-    hipEvent_t e;
-    HIP_TRY(hipEventCreate(&e));
-    ev_.push_back(e);
+hipEvent_t Engine::take_event() {
+  hipEvent_t e = nullptr;
+  if (!ev_.empty()) {
+    e = ev_.back();
+    ev_.pop_back();
+  } else if (hipEventCreate(&e) != hipSuccess) {
+    e = nullptr;
   }
+  return e;
+}
+
+// Reads every pending record (their events have completed: each was followed
+// by a decide the host has waited for) and returns the events to the pool.
+int Engine::flush_timing() {
+  fem_heat* h = h_;
+  for (const Timed& t : pending_) {
+    float ms = 0.f;
+    if (t.gather) {
+      HIP_TRY(hipEventElapsedTime(&ms, t.e[0], t.e[1]));
+      stats.gather_launches += 1;
+      stats.gather_ms += ms;
+    }
+    if (t.kind != 0) {
+      HIP_TRY(hipEventElapsedTime(&ms, t.e[2], t.e[3]));
+      if (t.kind == 2) {
+        stats.replace_launches += 1;
+        stats.replace_ms += ms;
+      } else {
+        stats.update_launches += 1;
+        stats.update_ms += ms;
+      }
+    }
+    for (hipEvent_t e : t.e)
+      if (e) ev_.push_back(e);
+  }
+  pending_.clear();
   return FEM_OK;
 }
 
@@ -455,51 +497,65 @@ int Engine::pcg(int first_chunk) {
   int& prev = inner ? iprev_ : oprev_;
   const int upd_kind = inner ? PK_UPD32 : PK_UPD64;
   const bool one_red = fused_ && !inner;  // one kernel per iteration (plus replacements)
-  // Timing samples one iteration in kSampleEvery, counted across solves so
-  // that the sample holds the forms of the direction kernel (with or without
-  // the deferred update) in their overall proportion, and every replacement,
-  // with events the dispatch itself records at the start and end of each
-  // kernel (marker events between every launch would lengthen the run they
-  // time).
-  constexpr int kSampleEvery = 8;
+  // Timing samples one iteration in kSampleEvery and one residual replacement
+  // in kReplaceEvery, counted across solves so that the sample holds the
+  // forms of the direction kernel (with or without the deferred update) in
+  // their overall proportion, with events the dispatch itself records at the
+  // start and end of each kernel.  Each timed launch still costs ~5 us of
+  // GPU time between kernels (sampling every 8th iteration slowed the 1M-DOF
+  // run by 4%), hence the sparse sample; marker events between every launch
+  // would lengthen the run they time far more.
+  constexpr int kSampleEvery = 64, kReplaceEvery = 8;
   auto replacing = [&](int jj) { return R_ > 0 && jj % R_ == 0; };
   int j = 0;
   int k = std::max(1, first_chunk);
   int chunks = 0;
+  std::vector<Timed> recs;  // this chunk's sampled iterations (index c)
+  std::vector<int> rec_c;
   for (;;) {
-    if (timing_) {
-      RC_TRY(ensure_events(4 * (size_t)k));
-      sampled_.assign((size_t)k, 0);
-    }
+    recs.clear();
+    rec_c.clear();
     for (int c = 0; c < k; ++c) {
       const int jj = j + c;
       const bool pick = timing_ && (sample_ctr_++ % kSampleEvery) == 0;
-      if (pick) sampled_[(size_t)c] = 1;
-      const bool ev = pick || (timing_ && replacing(jj));
-      hipEvent_t* e = ev_.data() + 4 * c;
+      const bool rep = replacing(jj);
+      const bool pick_rep = rep && timing_ && (replace_ctr_++ % kReplaceEvery) == 0;
+      Timed t{{nullptr, nullptr, nullptr, nullptr}, pick, pick_rep ? 2 : (pick && !rep && !one_red ? 1 : 0)};
+      if (timing_ && (t.gather || t.kind != 0)) {
+        for (int q = 0; q < 4; ++q)
+          if ((q < 2 && t.gather) || (q >= 2 && t.kind != 0)) {
+            t.e[q] = take_event();
+            if (!t.e[q]) return fail(h, FEM_EDEVICE, "hipEventCreate failed");
+          }
+        recs.push_back(t);
+        rec_c.push_back(c);
+      }
+      const Timed* tr = recs.empty() || rec_c.back() != c ? nullptr : &recs.back();
+      hipEvent_t e0 = tr ? tr->e[0] : nullptr, e1 = tr ? tr->e[1] : nullptr;
+      hipEvent_t e2 = tr ? tr->e[2] : nullptr, e3 = tr ? tr->e[3] : nullptr;
       const int xpar = replacements_before(jj, R_) & 1;
       if (one_red) {
-        RC_TRY(gather<RoleFused>(args(cur, prev, jj, xpar, deferred(jj) ? 1 : 0), ev ? e[0] : nullptr,
-                                 ev ? e[1] : nullptr));
+        RC_TRY(gather<RoleFused>(args(cur, prev, jj, xpar, deferred(jj) ? 1 : 0), e0, e1));
       } else {
-        RC_TRY(gather<RoleDir<V>>(args(cur, prev, jj, xpar, deferred(jj) ? 1 : 0), ev ? e[0] : nullptr,
-                                  ev ? e[1] : nullptr));
+        RC_TRY(gather<RoleDir<V>>(args(cur, prev, jj, xpar, deferred(jj) ? 1 : 0), e0, e1));
       }
       cur ^= 1;
       prev = PK_GATHER;
-      if (replacing(jj)) {
+      if (rep) {
         if (one_red)
-          RC_TRY(gather<RoleReplFused>(args(cur, prev, jj, xpar), ev ? e[2] : nullptr, ev ? e[3] : nullptr));
+          RC_TRY(gather<RoleReplFused>(args(cur, prev, jj, xpar), e2, e3));
         else
-          RC_TRY(gather<RoleRepl<V>>(args(cur, prev, jj, xpar), ev ? e[2] : nullptr, ev ? e[3] : nullptr));
+          RC_TRY(gather<RoleRepl<V>>(args(cur, prev, jj, xpar), e2, e3));
         prev = PK_GATHER;
         cur ^= 1;
       } else if (!one_red) {
-        RC_TRY(update<V>(args(cur, prev, jj, xpar), ev ? e[2] : nullptr, ev ? e[3] : nullptr));
+        RC_TRY(update<V>(args(cur, prev, jj, xpar), e2, e3));
         prev = upd_kind;
         cur ^= 1;
       }
     }
+    // the GPU is busy with this chunk: read the earlier chunks' samples now
+    if (timing_) RC_TRY(flush_timing());
     RC_TRY(decide(inner, j + k));
     bool all_done = true;
     int most = j;
@@ -511,23 +567,14 @@ int Engine::pcg(int first_chunk) {
       most = std::max(most, (int)t.iter);
     }
     if (timing_) {
+      // iterations past the end of every solve ran idle: not in the sample
       const int ran = std::max(0, std::min(most - j, k));
-      for (int c = 0; c < ran; ++c) {
-        const bool pick = sampled_[(size_t)c] != 0, rep = replacing(j + c);
-        float g_ms = 0.f, u_ms = 0.f;
-        if (pick) {
-          HIP_TRY(hipEventElapsedTime(&g_ms, ev_[4 * c], ev_[4 * c + 1]));
-          stats.gather_launches += 1;
-          stats.gather_ms += g_ms;
-        }
-        if (rep) {
-          HIP_TRY(hipEventElapsedTime(&u_ms, ev_[4 * c + 2], ev_[4 * c + 3]));
-          stats.replace_launches += 1;
-          stats.replace_ms += u_ms;
-        } else if (pick && !one_red) {
-          HIP_TRY(hipEventElapsedTime(&u_ms, ev_[4 * c + 2], ev_[4 * c + 3]));
-          stats.update_launches += 1;
-          stats.update_ms += u_ms;
+      for (size_t q = 0; q < recs.size(); ++q) {
+        if (rec_c[q] < ran) {
+          pending_.push_back(recs[q]);
+        } else {
+          for (hipEvent_t e : recs[q].e)
+            if (e) ev_.push_back(e);
         }
       }
     }
@@ -719,6 +766,7 @@ int Engine::run() {
   }
   HIP_TRY(hipEventRecord(ev_run_[1], stream_));
   HIP_TRY(hipEventSynchronize(ev_run_[1]));
+  RC_TRY(flush_timing());
   float ms = 0.f;
   HIP_TRY(hipEventElapsedTime(&ms, ev_run_[0], ev_run_[1]));
   for (auto& s : sims_) RC_TRY(write_outputs(*s, ms));

@@ -88,7 +88,7 @@ def test_timing_counts_direction_kernels_only(gpu):
     b, st = run_heat(p, one_reduction=True, timing=True)
     assert np.array_equal(a["T_final"], b["T_final"]) and np.array_equal(a["iters"], b["iters"])
     assert st["gather_launches"] > 0 and st["gather_ms"] > 0
-    assert st["update_launches"] == 0 and st["replace_launches"] >= p.nsteps
+    assert st["update_launches"] == 0 and 1 <= st["replace_launches"] <= p.nsteps
 
 
 def test_mixed_form_ignores_the_flag(gpu):

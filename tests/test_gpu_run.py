@@ -180,4 +180,5 @@ def test_timing_changes_nothing_and_samples(gpu):
     assert np.array_equal(a["T_final"], b["T_final"]) and np.array_equal(a["iters"], b["iters"])
     total = int(np.sum(b["iters"]))
     assert 0 < st["gather_launches"] < total and st["gather_ms"] > 0
-    assert st["replace_launches"] >= p.nsteps  # iteration 0 of every step is a replacement
+    # iteration 0 of every step is a replacement; one in eight is timed, the first included
+    assert 1 <= st["replace_launches"] <= p.nsteps
