@@ -79,6 +79,13 @@ __device__ inline void read_plane(const V* P, int pw, int lx, int ly, PlaneQ<V>&
 // tile (and of a coefficient tile); the launch guarantees both tiles fit.
 constexpr int kSlots = 2;
 
+// Layers between issuing a plane's global loads and staging it in LDS: 2
+// keeps two register sets of loads in flight, 1 one set (fewer registers).
+#ifndef FEMHEAT_GATHER_DEPTH
+#define FEMHEAT_GATHER_DEPTH 2
+#endif
+constexpr int kDepth = FEMHEAT_GATHER_DEPTH;
+
 // XCD-aware tile order: blocks are dispatched round-robin over the 8 XCDs,
 // so block b runs on XCD b%8.  Work item (b%8)*share + b/8 gives every XCD a
 // contiguous range of tiles (z fastest, then x, then y), so the halo planes,
@@ -307,7 +314,7 @@ __device__ inline void gather_tile(const GatherArgs<V>& ga, Pro pro, Epi epi, co
       store(S, lay(k), buf);
       const V xo_k = S.xo, dold_k = S.dold;  // node vis(k), fetched with this stage
       __syncthreads();
-      fetch(S, vis(min(k + 3, n)), lay(min(k + 2, n - 1)), vis(min(k + 2, n)));
+      fetch(S, vis(min(k + 1 + kDepth, n)), lay(min(k + kDepth, n - 1)), vis(min(k + kDepth, n)));
       read_plane(plane + buf * PW * PH, PW, ltx, lty, hi);
       if constexpr (FU) {  // the new plane's centre: this column's node vis(k+1)
         const int c = (lty + 1) * PW + ltx + 1;
@@ -345,13 +352,14 @@ __device__ inline void gather_tile(const GatherArgs<V>& ga, Pro pro, Epi epi, co
 
     // Prologue: the first three planes and the first two coefficient layers
     // are requested at once, before the relayed partial sum, so that sum and
-    // the fill of the plane pipeline overlap.
+    // the fill of the plane pipeline overlap.  (Issuing them before the
+    // relayed state is read as well measured slower.)
     Stage SA, SB;
     {
       Stage S0;
       fetch(S0, vis(0), lay(0), vis(0));
       fetch(SB, vis(1), lay(0), vis(0));
-      fetch(SA, vis(min(2, n)), lay(min(1, n - 1)), vis(1));
+      if constexpr (kDepth == 2) fetch(SA, vis(min(2, n)), lay(min(1, n - 1)), vis(1));
       if (!stage_finish(R, in, st, logical == 0)) {  // uniform
         if constexpr (XI) {
           // the solve finished in this kernel's evaluation: the last
@@ -380,12 +388,16 @@ __device__ inline void gather_tile(const GatherArgs<V>& ga, Pro pro, Epi epi, co
     using no = std::integral_constant<bool, false>;
     using yes = std::integral_constant<bool, true>;
     layer(0, 1, SB, no{});  // node vis(0) belongs to the neighbouring chunk
-    int k = 1;
-    for (; k + 1 < n; k += 2) {  // two register sets alternate: indices stay compile-time
-      layer(k, 0, SA, yes{});
-      layer(k + 1, 1, SB, yes{});
+    if constexpr (kDepth == 2) {
+      int k = 1;
+      for (; k + 1 < n; k += 2) {  // two register sets alternate: indices stay compile-time
+        layer(k, 0, SA, yes{});
+        layer(k + 1, 1, SB, yes{});
+      }
+      if (k < n) layer(k, 0, SA, yes{});
+    } else {
+      for (int k = 1; k < n; ++k) layer(k, (k + 1) & 1, SB, yes{});
     }
-    if (k < n) layer(k, 0, SA, yes{});
   }
   if constexpr (FU) {
     if (R.pout) publish_partial4(R, dots, logical);

@@ -36,14 +36,12 @@ __device__ inline void upd1(V& r, V q, V p, V alpha, double& acc) {
 // Residual update of one solve by block `blk` of its `nblk` blocks (a
 // grid-stride loop over the solve's own block count, so the partial sums do
 // not depend on the launch the block belongs to).  Each thread loads kU
-// strided vectors before it uses any, and the first kU before it settles
-// alpha = delta / d^T q, so the partial sum runs while they are in flight.
-// A no-op once the solve is done.
+// strided vectors before it uses any, and the first kU before it reads the
+// relayed state and settles alpha = delta / d^T q, so those reads run while
+// the loads are in flight.  A no-op once the solve is done.
 template <typename V>
 __device__ inline void update_body(V* __restrict__ r, const V* __restrict__ q, const V* __restrict__ pinv, uint32_t N,
                                    const Relay& R, uint32_t blk, uint32_t nblk) {
-  const StageIn in = stage_load(R);
-  if (stage_idle(R, in, blk == 0)) return;
   using VT = typename Vec<V>::T;
   constexpr int W = Vec<V>::W;
   constexpr int kU = 4;
@@ -66,6 +64,8 @@ __device__ inline void update_body(V* __restrict__ r, const V* __restrict__ q, c
     }
   };
   load(tid);
+  const StageIn in = stage_load(R);
+  if (stage_idle(R, in, blk == 0)) return;
   Scalars st;
   if (!stage_finish(R, in, st, blk == 0)) return;
   const V alpha = (V)st.alpha;
