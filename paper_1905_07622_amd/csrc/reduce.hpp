@@ -63,6 +63,24 @@ __device__ inline double canonical_sum(const double* p, uint32_t n, double* red4
   return ((red4[0] + red4[1]) + red4[2]) + red4[3];
 }
 
+// canonical_sum with each thread's first 8 partials already loaded (v, by
+// waves 0..3: blocks of at least 4 waves): the same order, so the same value.
+__device__ inline double canonical_sum_pre(const double* p, uint32_t n, const double* v, double* red4) {
+  const uint32_t lane = threadIdx.x & 63u, wid = threadIdx.x >> 6;
+  if (wid < 4) {
+    const uint32_t slot = wid * 64 + lane;
+    double s = v[0];
+#pragma unroll
+    for (int u = 1; u < 8; ++u) s += v[u];
+    for (uint32_t k = slot + 2048u; k < n; k += 256u) s += p[k];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+    if (lane == 0) red4[wid] = s;
+  }
+  __syncthreads();
+  return ((red4[0] + red4[1]) + red4[2]) + red4[3];
+}
+
 // Four canonical sums at once (components c at p + c*ld), in the order of
 // canonical_sum, with every load issued before the first reduction.
 __device__ inline void canonical_sum4(const double* p, uint32_t ld, uint32_t n, double* out, double* red16) {
@@ -194,6 +212,8 @@ struct StageIn {
   Scalars t;
   bool pending;  // the previous kernel's partials complete a scalar update
   bool need;     // this kernel sums those partials
+  bool pre;      // pv holds this thread's first partials (blocks of >= 4 waves)
+  double pv[8];
 };
 
 // First half of a relayed kernel's entry: reads the state (one uniform load).
@@ -201,6 +221,19 @@ struct StageIn {
 // stage_finish, whose partial sum then overlaps them.
 __device__ inline StageIn stage_load(const Relay& R) {
   StageIn in;
+  // The partials are read together with the state (before it is known
+  // whether they are needed: a wasted read costs less than a second memory
+  // round trip), in canonical_sum's slot order: wave w < 4 holds virtual
+  // wave w.
+  in.pre = (blockDim.x >> 6) >= 4 && R.pin != nullptr;  // uniform
+  if (in.pre) {
+    const uint32_t slot = threadIdx.x;  // only waves 0..3 use theirs
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const uint32_t k = slot + 256u * u;
+      in.pv[u] = (slot < 256u && k < R.npin) ? R.pin[k] : 0.0;
+    }
+  }
   in.t = Scalars{};
   if (R.sin) in.t = *R.sin;
   in.pending = !in.t.done && in.t.phase != PH_DECIDED && in.t.phase != PH_NONE;
@@ -232,6 +265,8 @@ __device__ inline bool stage_finish(const Relay& R, const StageIn& in, Scalars& 
   if (in.need) {  // uniform
     if (pending && in.t.phase == PH_AFTER_FUSED)
       canonical_sum4(R.pin, R.ld, R.npin, xs, red16);
+    else if (in.pre)
+      xs[0] = canonical_sum_pre(R.pin, R.npin, in.pv, red16);
     else
       xs[0] = canonical_sum(R.pin, R.npin, red16);
   }
