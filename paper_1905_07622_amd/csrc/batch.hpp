@@ -66,6 +66,18 @@ struct SimDev {
   int32_t sweep;       // mixed form: this sweep runs an inner solve and a correction
 };
 
+// What the update kernel of a launch with a single simulation needs, passed
+// with the launch itself: it then starts without first reading the
+// simulation's SimDev (one dependent memory read less on its critical path).
+struct UpdView {
+  int32_t on;       // 0: read the SimDev array as usual
+  uint32_t N, nblk;
+  void* r;
+  const void* q;
+  const void* pinv;
+  Relay R;
+};
+
 // Uniform arguments of one batched launch.
 struct BatchArgs {
   const SimDev* sims;
@@ -76,6 +88,7 @@ struct BatchArgs {
   int32_t j;           // iteration index within the current solve
   int32_t xpar;        // replacements so far in this solve, mod 2 (x or e buffer)
   int32_t corr;        // the previous kernel was a plain update: x += alpha d is still due
+  UpdView uv;          // update launches of a single simulation
 };
 
 __device__ inline Relay outer_relay(const SimDev& s, const BatchArgs& a, int32_t mode, bool partials) {
@@ -248,6 +261,11 @@ __global__ void __launch_bounds__(256, 2) gather_batch_kernel(BatchArgs a) {
 // or FP32 inner solve.
 template <typename V>
 __global__ void __launch_bounds__(256) update_batch_kernel(BatchArgs a) {
+  if (a.uv.on) {  // uniform
+    update_body<V>(static_cast<V*>(a.uv.r), static_cast<const V*>(a.uv.q), static_cast<const V*>(a.uv.pinv), a.uv.N,
+                   a.uv.R, blockIdx.x, a.uv.nblk);
+    return;
+  }
   uint32_t sim, local;
   work_item(a, blockIdx.x, sim, local);
   const SimDev& s = a.sims[sim];

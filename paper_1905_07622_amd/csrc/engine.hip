@@ -119,7 +119,8 @@ class Engine {
   int upload_simdev();
   void fill_simdev(const Sim& s, SimDev& d) const;
   BatchArgs args(int cur, int prev, int j, int xpar, int corr = 0) const {
-    return BatchArgs{sd_dev_, nullptr, snap_map_, cur, prev, j, xpar, corr};
+    BatchArgs a{sd_dev_, nullptr, snap_map_, cur, prev, j, xpar, corr, UpdView{}};
+    return a;
   }
   // Whether the update of iteration jj - 1 was a plain one, whose x += alpha d
   // the direction kernel of iteration jj (or the decide after it) applies.
@@ -163,6 +164,7 @@ class Engine {
   bool multi_ = false;     // more than one simulation: launches go through work tables
 
   SimDev* sd_dev_ = nullptr;
+  SimDev sd_one_{};  // host copy of the uploaded SimDev when the batch holds one simulation
   SimDev* sd_host_[2] = {nullptr, nullptr};  // pinned staging, used alternately
   int sd_flip_ = 0;
   size_t sd_cap_ = 0;
@@ -350,6 +352,7 @@ int Engine::upload_simdev() {
   SimDev* stage = sd_host_[sd_flip_];
   sd_flip_ ^= 1;
   for (size_t k = 0; k < act_.size(); ++k) fill_simdev(*act_[k], stage[k]);
+  if (act_.size() == 1) sd_one_ = stage[0];
   HIP_TRY(hipMemcpyAsync(sd_dev_, stage, act_.size() * sizeof(SimDev), hipMemcpyHostToDevice, stream_));
   return FEM_OK;
 }
@@ -457,6 +460,25 @@ int Engine::update(BatchArgs a, hipEvent_t e0, hipEvent_t e1) {
   fem_heat* h = h_;
   const bool f64 = sizeof(V) == 8;
   a.table = multi_ ? tab_dev_ + (f64 ? off_upd64_ : off_upd32_) : nullptr;
+  if (!multi_) {  // the same relay and vectors as outer_relay / inner_relay would give
+    const SimDev& s = sd_one_;
+    UpdView& u = a.uv;
+    u.on = 1;
+    u.N = s.N;
+    if (f64) {
+      u.nblk = s.nblk[PK_UPD64];
+      u.r = s.r64;
+      u.q = s.q64;
+      u.pinv = s.pinv64;
+      u.R = Relay{s.oS[a.cur], s.oS[a.cur ^ 1], s.oP[a.cur], s.nblk[a.prev], s.oP[a.cur ^ 1], M_UPD, s.octl, s.ldp};
+    } else {
+      u.nblk = s.nblk[PK_UPD32];
+      u.r = s.r32;
+      u.q = s.q32;
+      u.pinv = s.pinv32;
+      u.R = Relay{s.iS[a.cur], s.iS[a.cur ^ 1], s.iP[a.cur], s.nblk[a.prev], s.iP[a.cur ^ 1], M_UPD, s.ictl, s.ldp};
+    }
+  }
   hipExtLaunchKernelGGL((update_batch_kernel<V>), dim3(f64 ? n_upd64_ : n_upd32_), dim3(kT), 0, stream_, e0, e1, 0,
                         a);
   HIP_TRY(hipGetLastError());
