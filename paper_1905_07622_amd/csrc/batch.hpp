@@ -89,6 +89,9 @@ struct BatchArgs {
   int32_t xpar;        // replacements so far in this solve, mod 2 (x or e buffer)
   int32_t corr;        // the previous kernel was a plain update: x += alpha d is still due
   UpdView uv;          // update launches of a single simulation
+  int32_t next_xc;     // next-step launches: iterate buffer the current solve is assumed to end in
+  int32_t next_R;      //                     replacement period
+  double next_fs;      //                     dt * s of the next step
 };
 
 __device__ inline Relay outer_relay(const SimDev& s, const BatchArgs& a, int32_t mode, bool partials) {
@@ -127,6 +130,43 @@ struct RoleInit {  // x0 by the guess rule, r = b - A x0, r^T P^-1 r (a3)
   }
   static __device__ Epi epi(const SimDev& s, const BatchArgs&) { return Epi{s.b64, s.pinv64, s.r64}; }
   static __device__ Relay relay(const SimDev& s, const BatchArgs& a) { return outer_relay(s, a, M_INIT, true); }
+};
+
+// The next step's RHS and initial residual, launched right after a decide
+// and before the host has read it (the host would otherwise leave the GPU
+// idle for its round trip).  They see the fields as the step's end will
+// rotate them -- T^n = X[next_xc], T^{n-1} = T1, the guess into T2's buffer --
+// and run only if the solve has ended well in X[next_xc]; otherwise they
+// pass the state through and the host carries on (see M_RHS_NEXT).
+__device__ inline Relay next_relay(const SimDev& s, const BatchArgs& a, int32_t mode) {
+  Relay R = outer_relay(s, a, mode, true);
+  R.next_xc = a.next_xc;
+  R.next_R = a.next_R;
+  return R;
+}
+
+struct RoleRhsNext {
+  using V = double;
+  using Pro = ProPlain<double>;
+  using Epi = EpiRhs<double>;
+  static __device__ const GatherArgs<V>& ga(const SimDev& s) { return s.L64; }
+  static __device__ Pro pro(const SimDev& s, const BatchArgs& a) { return Pro{s.X[a.next_xc]}; }
+  static __device__ Epi epi(const SimDev& s, const BatchArgs& a) {
+    return Epi{s.b64, s.F64, s.pinv64, s.lift64, a.next_fs};
+  }
+  static __device__ Relay relay(const SimDev& s, const BatchArgs& a) { return next_relay(s, a, M_RHS_NEXT); }
+};
+
+struct RoleInitNext {
+  using V = double;
+  using Pro = ProGuess<double>;
+  using Epi = EpiResidual<double>;
+  static __device__ const GatherArgs<V>& ga(const SimDev& s) { return s.A64; }
+  static __device__ Pro pro(const SimDev& s, const BatchArgs& a) {
+    return Pro{s.X[a.next_xc], s.T1, s.pinv64, const_cast<double*>(s.T2), s.guess_prev, 0};
+  }
+  static __device__ Epi epi(const SimDev& s, const BatchArgs&) { return Epi{s.b64, s.pinv64, s.r64}; }
+  static __device__ Relay relay(const SimDev& s, const BatchArgs& a) { return next_relay(s, a, M_INIT_NEXT); }
 };
 
 template <typename V>

@@ -71,7 +71,11 @@ enum Mode : int32_t {
   // one-reduction form: settle the pending update, then
   M_FDIR = 10,   //   direction + apply with the residual as it is (after the initial residual or a replacement)
   M_FUPD = 11,   //   r -= alpha q, x += alpha d, then direction + apply
-  M_FREPL = 12   //   residual replacement x += alpha d, r = b - A x
+  M_FREPL = 12,  //   residual replacement x += alpha d, r = b - A x
+  // the next step's right-hand side and initial residual, launched before the
+  // host knows whether the current solve has finished: they run only if it has
+  M_RHS_NEXT = 13,   // as M_RHS if the solve ended well with the iterate buffer predicted
+  M_INIT_NEXT = 14   // as M_INIT if the M_RHS_NEXT before it ran
 };
 
 constexpr int32_t kStatusBreakdown = -4;

@@ -99,6 +99,7 @@ class Engine {
     if (snap_host_) (void)hipHostFree(snap_host_);
     if (tab_host_) (void)hipHostFree(tab_host_);
     for (auto e : ev_) (void)hipEventDestroy(e);
+    if (ev_decide_) (void)hipEventDestroy(ev_decide_);
     for (const Timed& t : pending_)
       for (hipEvent_t e : t.e)
         if (e) (void)hipEventDestroy(e);
@@ -119,7 +120,7 @@ class Engine {
   int upload_simdev();
   void fill_simdev(const Sim& s, SimDev& d) const;
   BatchArgs args(int cur, int prev, int j, int xpar, int corr = 0) const {
-    BatchArgs a{sd_dev_, nullptr, snap_map_, cur, prev, j, xpar, corr, UpdView{}};
+    BatchArgs a{sd_dev_, nullptr, snap_map_, cur, prev, j, xpar, corr, UpdView{}, 0, R_, 0.0};
     return a;
   }
   // Whether the update of iteration jj - 1 was a plain one, whose x += alpha d
@@ -131,7 +132,12 @@ class Engine {
   int gather(BatchArgs a, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
   template <typename V>
   int update(BatchArgs a, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
-  int decide(bool inner, int j_end = 0);
+  int decide(bool inner, int j_end = 0, bool launch_next = false);
+  // The next step's RHS and initial residual launched behind a decide (one
+  // simulation): set when they ran, so the next epoch does not launch them.
+  bool next_ran_ = false;
+  const Sim* next_sim_ = nullptr;
+  hipEvent_t ev_decide_ = nullptr;  // the host waits for the decide only, not what follows it
   template <typename V>
   int pcg(int first_chunk);
   int epoch();
@@ -345,8 +351,8 @@ void Engine::fill_simdev(const Sim& s, SimDev& d) const {
 }
 
 // Copies the SimDev array of the current epoch to the device.  Callers only
-// do so after the stream has been synchronised since the previous copy, so
-// the staging buffer being written is never still in use.
+// do so after waiting for a decide launched after the previous copy, so the
+// staging buffer being written is never still in use.
 int Engine::upload_simdev() {
   fem_heat* h = h_;
   SimDev* stage = sd_host_[sd_flip_];
@@ -489,7 +495,8 @@ int Engine::update(BatchArgs a, hipEvent_t e0, hipEvent_t e1) {
 // settled states into snap_host_ (synchronises the stream).  j_end > 0: the
 // relay's last kernel was the update of iteration j_end - 1 of a PCG chunk,
 // and a solve that finishes here gets that update's deferred x += alpha d.
-int Engine::decide(bool inner, int j_end) {
+// launch_next: see below.
+int Engine::decide(bool inner, int j_end, bool launch_next) {
   fem_heat* h = h_;
   int& cur = inner ? icur_ : ocur_;
   int& prev = inner ? iprev_ : oprev_;
@@ -505,7 +512,33 @@ int Engine::decide(bool inner, int j_end) {
     hipLaunchKernelGGL(decide_batch_kernel<double>, dim3(n_upd64_), dim3(kT), 0, stream_, a);
   HIP_TRY(hipGetLastError());
   cur ^= 1;
-  HIP_TRY(hipStreamSynchronize(stream_));
+  if (!ev_decide_) HIP_TRY(hipEventCreateWithFlags(&ev_decide_, hipEventDisableTiming));
+  HIP_TRY(hipEventRecord(ev_decide_, stream_));
+  // The next step's RHS and initial residual go in behind the decide, so the
+  // GPU has work while the host waits for it and prepares the next launches;
+  // on the device they run only if the solve ended well in the iterate
+  // buffer assumed here (the one its iteration count so far gives).
+  int next_xc = -1;
+  if (launch_next) {
+    const Sim& s = *act_[0];
+    next_xc = replacements_before(j_end, R_) & 1;
+    BatchArgs b = args(ocur_, oprev_, 0, 0);
+    b.next_xc = next_xc;
+    b.next_fs = s.rq.dt * schedule_value(s.rq.h, (int64_t)s.first + s.step + 2);
+    RC_TRY(gather<RoleRhsNext>(b));
+    ocur_ ^= 1;
+    oprev_ = PK_GATHER;
+    b.cur = ocur_;
+    b.prev = oprev_;
+    RC_TRY(gather<RoleInitNext>(b));
+    ocur_ ^= 1;
+  }
+  HIP_TRY(hipEventSynchronize(ev_decide_));
+  if (launch_next) {
+    const Scalars& t = snap_host_[0];
+    next_ran_ = t.done && t.status == 0 && (replacements_before(t.iter, R_) & 1) == next_xc;
+    next_sim_ = act_[0];
+  }
   return FEM_OK;
 }
 
@@ -578,7 +611,8 @@ int Engine::pcg(int first_chunk) {
     }
     // the GPU is busy with this chunk: read the earlier chunks' samples now
     if (timing_) RC_TRY(flush_timing());
-    RC_TRY(decide(inner, j + k));
+    const bool launch_next = !inner && !mixed_ && act_.size() == 1 && act_[0]->step + 1 < act_[0]->rq.nsteps;
+    RC_TRY(decide(inner, j + k, launch_next));
     bool all_done = true;
     int most = j;
     for (size_t q = 0; q < act_.size(); ++q) {
@@ -680,12 +714,20 @@ int Engine::epoch() {
     s.sweeping = s.broke = false;
   }
   RC_TRY(upload_simdev());
-  RC_TRY(gather<RoleRhs>(args(ocur_, oprev_, 0, 0)));
-  ocur_ ^= 1;
-  oprev_ = PK_GATHER;
-  RC_TRY(gather<RoleInit>(args(ocur_, oprev_, 0, 0)));
-  ocur_ ^= 1;
-  oprev_ = PK_GATHER;
+  // the RHS and initial residual of this step already ran behind the last
+  // decide of the previous one (one simulation, same batch); running them
+  // again would give the same values
+  const bool prepared = next_ran_ && act_.size() == 1 && next_sim_ == act_[0];
+  next_ran_ = false;
+  next_sim_ = nullptr;
+  if (!prepared) {
+    RC_TRY(gather<RoleRhs>(args(ocur_, oprev_, 0, 0)));
+    ocur_ ^= 1;
+    oprev_ = PK_GATHER;
+    RC_TRY(gather<RoleInit>(args(ocur_, oprev_, 0, 0)));
+    ocur_ ^= 1;
+    oprev_ = PK_GATHER;
+  }
   if (mixed_) {
     RC_TRY(mixed_sweeps());
   } else {

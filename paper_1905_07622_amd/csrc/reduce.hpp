@@ -34,6 +34,8 @@ struct Relay {
   int32_t mode;
   Ctl ctl;
   uint32_t ld;         // distance between the components of multi-valued partials
+  int32_t next_xc;     // M_RHS_NEXT: iterate buffer the launch assumed (replacements mod 2)
+  int32_t next_R;      //             replacement period
 };
 
 // Sum of n partials in one canonical order that does not depend on the block
@@ -207,6 +209,8 @@ __device__ inline void evaluate_pending(Scalars& s, const double* xs, const Ctl&
   s.phase = PH_DECIDED;
 }
 
+__device__ inline bool is_fused_mode(int32_t m) { return m == M_FDIR || m == M_FUPD || m == M_FREPL; }
+
 // The relayed state as a kernel finds it, before the pending update.
 struct StageIn {
   Scalars t;
@@ -237,15 +241,15 @@ __device__ inline StageIn stage_load(const Relay& R) {
   in.t = Scalars{};
   if (R.sin) in.t = *R.sin;
   in.pending = !in.t.done && in.t.phase != PH_DECIDED && in.t.phase != PH_NONE;
-  in.need = R.mode == M_INIT || (R.mode == M_UPD && !in.t.done) ||
-            ((R.mode == M_DIR || R.mode == M_DECIDE || R.mode >= M_FDIR) && in.pending);
+  in.need = R.mode == M_INIT || R.mode == M_INIT_NEXT || (R.mode == M_UPD && !in.t.done) ||
+            ((R.mode == M_DIR || R.mode == M_DECIDE || is_fused_mode(R.mode)) && in.pending);
   return in;
 }
 
 // A search-direction or update kernel of a finished solve has no work and
 // leaves the state unchanged: only the writer relays it.  Uniform.
 __device__ inline bool stage_idle(const Relay& R, const StageIn& in, bool writer) {
-  if ((R.mode == M_DIR || R.mode == M_UPD || R.mode >= M_FDIR) && in.t.done) {
+  if ((R.mode == M_DIR || R.mode == M_UPD || is_fused_mode(R.mode)) && in.t.done) {
     if (writer && threadIdx.x == 0 && R.sout) *R.sout = in.t;
     return true;
   }
@@ -273,7 +277,16 @@ __device__ inline bool stage_finish(const Relay& R, const StageIn& in, Scalars& 
   const double x = xs[0];
   if (threadIdx.x == 0) {
     int g = 1;
-    switch (R.mode) {
+    int mode = R.mode;
+    if (mode == M_RHS_NEXT) {
+      // the solve must have ended without breakdown, with its iterate in the
+      // buffer the launch assumed; otherwise the state passes unchanged
+      const int xc = (R.next_R <= 0 || t.iter <= 0) ? 0 : ((t.iter - 1) / R.next_R + 1) & 1;
+      mode = (t.done && t.status == 0 && xc == R.next_xc) ? M_RHS : M_SKIP;
+    } else if (mode == M_INIT_NEXT) {
+      mode = (t.phase == PH_NONE && !t.done) ? M_INIT : M_SKIP;  // the M_RHS_NEXT before it ran
+    }
+    switch (mode) {
       case M_RHS:  // a new step: b and b^T P^-1 b
         t.done = 0;
         t.status = 0;

@@ -147,3 +147,24 @@ def test_proposal_batch_sampled_parity(gpu):
         errs = [rel_l2(res[s]["T_saved"][n], ref["T_saved"][n]) for n in range(5)]
         say(f"  sim {s}: iters {list(res[s]['iters'])} max rel L2 {max(errs):.2e}")
         assert max(errs) <= GATE_MIXED
+
+
+@pytest.mark.parametrize("replace_every,rtol", [(50, 1e-10), (3, 1e-10), (4, 1e-9), (50, 0.5)])
+def test_single_simulation_overlap_matches_batch(gpu, replace_every, rtol):
+    """A simulation alone starts each step's RHS and initial residual behind
+    the previous step's last decide, before the host has read it (and on the
+    device only if the solve ended in the iterate buffer assumed); in a batch
+    of two it does not.  Both must give the same bits -- also when the
+    assumption fails (frequent replacements move the iterate between buffers)
+    and when solves take zero or one iteration (loose tolerance)."""
+    p = wl.random_problem(13, 9, 11, seed=31, nsteps=6, rtol=rtol)
+    partner = wl.random_problem(6, 6, 6, seed=34, nsteps=6)
+    _, alone = fh.run_batch([p], save_every=1, replace_every=replace_every)
+    _, pair = fh.run_batch([p, partner], save_every=1, replace_every=replace_every)
+    say(f"  R={replace_every} rtol={rtol}: iters {list(alone[0]['iters'])}")
+    same_bits(alone[0], pair[0])
+    with fh.Heat.from_problem(p, replace_every=replace_every) as h:
+        one = h.run(p.T0, dt=p.dt, theta=p.theta, nsteps=p.nsteps, rtol=p.rtol, save_every=1)
+    assert np.array_equal(one["iters"], alone[0]["iters"])
+    ref = oracle.run(p, save_every=1, locked_iters=one["iters"], replace_every=replace_every)
+    assert max(rel_l2(one["T_saved"][n], ref["T_saved"][n]) for n in range(p.nsteps)) <= GATE64
