@@ -4,19 +4,24 @@
 // right-hand side b = L T^{n-1} + dt*s_n*F (one gather, RHS epilogue), the
 // initial guess and residual (one gather), then the iterations of
 // Algorithm 1, two kernels each: the search-direction update fused into the
-// operator apply (q = A d, d^T q -> alpha on the device) and the fused x/r
-// update with the preconditioned residual norm (delta, beta and the stop
-// test on the device).  When i mod replace_every == 0 (50 in Algorithm 1)
-// the update is a gather computing r = b - A x instead.  The mixed form runs
-// that loop in FP32 on A e = r64 inside FP64 refinement sweeps.
+// operator apply (q = A d, d^T q -> alpha on the device; it also applies the
+// previous iteration's x += alpha d at its own nodes) and the residual update
+// with the preconditioned residual norm (delta, beta and the stop test on
+// the device).  When i mod replace_every == 0 (50 in Algorithm 1) the update
+// is a gather computing x += alpha d, r = b - A x instead.  The mixed form
+// runs that loop in FP32 on A e = r64 inside FP64 refinement sweeps; the
+// option FEM_ONE_REDUCTION runs the FP64 loop with one kernel per iteration.
 //
 // The paper's host read the residual back every iteration (App. A.3).  Here
 // the scalars of Algorithm 1 and the convergence decision live on the device
 // and are relayed from kernel to kernel (reduce.hpp): once a solve is done,
 // every further iteration kernel returns immediately.  The host enqueues
-// iterations in chunks, ends a chunk with a decide kernel and reads one small
-// pinned state block per simulation, sizing the first chunk of a step from
-// the previous step's iteration count.
+// iterations in chunks (the previous step's count, then 2, then 4), ends a
+// chunk with a decide kernel that writes one pinned, mapped state block per
+// simulation, and waits for that kernel alone: with one simulation, the next
+// step's RHS and initial residual are already queued behind it and run on
+// the device if the solve has ended, so the GPU works through the host's
+// round trip.
 //
 // The engine advances every simulation it holds in lockstep, one step per
 // epoch, with batched launches (batch.hpp): one launch of each kernel serves

@@ -23,17 +23,18 @@
 // 3x3 neighbourhood of the new plane (9 LDS reads) with the 4 elements of the
 // layer (8 LDS reads) for the two nodes of its column that the layer touches.
 // Plane quantities are kept in registers for the next layer.  Out-of-grid
-// nodes are staged as 0 and out-of-grid elements carry zero coefficients, so
-// boundaries need no branches in the arithmetic.
+// nodes are staged from clamped addresses and out-of-grid elements carry zero
+// coefficients, so boundaries need no branches in the arithmetic.
 //
 // Neighbouring z-chunks march in opposite directions, so they read the halo
 // planes they share at the same time, from the same L2.
 //
 // A prologue functor produces the input value at every staged node (and
-// writes it back for owned nodes: fused search-direction or x updates), an
-// epilogue functor consumes the result at owned nodes (q, residual, RHS) and
-// returns the node's contribution to a block dot product that is reduced on
-// the device.
+// writes it back for owned nodes: fused search-direction or x updates, the
+// deferred x += alpha d of the previous iteration, or the advanced residual
+// of the one-reduction form), an epilogue functor consumes the result at
+// owned nodes (q, residual, RHS) and returns the node's contribution to a
+// block dot product that is reduced on the device.
 #pragma once
 
 #include <type_traits>

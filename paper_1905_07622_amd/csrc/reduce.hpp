@@ -3,10 +3,11 @@
 // The VVM_A / VVM_reduce / VVM_C / Beta_update kernels of App. A.2 become:
 //  * every kernel that produces a dot product writes one FP64 partial per
 //    block (plain stores);
-//  * the NEXT kernel in stream order reads those partials at its start: wave 0
-//    of every block sums them in one fixed order (so every block obtains the
-//    bit-identical value), evaluates the pending scalar update of Algorithm 1
-//    (alpha, or delta/beta and the stop test) and broadcasts it to the block;
+//  * the NEXT kernel in stream order reads those partials at its start,
+//    together with the relayed state (one memory round trip), sums them in
+//    one fixed order (so every block obtains the bit-identical value),
+//    evaluates the pending scalar update of Algorithm 1 (alpha, or
+//    delta/beta and the stop test) and broadcasts it to the block;
 //  * the solve state is relayed through a ping-pong pair of Scalars: a kernel
 //    reads Sin and one block of the solve (its tile 0) writes the updated
 //    state to Sout, so no block ever reads a value another block of the same
