@@ -104,6 +104,66 @@ def _rel(a, b, torch):
     return float(torch.linalg.norm(a - b) / torch.linalg.norm(b))
 
 
+def _timed_runs(h, T0, run_kw, nruns):
+    """Times nruns full runs after one warm-up; returns (MDOF*iter/s, iterations per run, last result)."""
+    h.run(T0, **run_kw)
+    import torch
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    iters, last = 0, None
+    for _ in range(nruns):
+        last = h.run(T0, **run_kw)
+        iters += last["total_iters"]
+    torch.cuda.synchronize()
+    return iters / (time.perf_counter() - t0) / 1e6, last["total_iters"], last
+
+
+def bench_mixed(args, torch, p, k, rc, T0, T_fp64):
+    """The headline workload in the mixed form (FP32 inner PCG with FP64 dot products and scalars inside
+    FP64 refinement): MDOF*iter/s counting inner iterations, and the final field against the FP64 run."""
+    from paper_1905_07622_amd import femheat as fh
+    stream = torch.cuda.current_stream().cuda_stream
+    h = fh.Heat(p.nx, p.ny, p.nz, p.hx, p.hy, p.hz, k, rc, dirichlet_mask=p.dirichlet_mask,
+                flux_mask=p.flux_mask, flux=p.flux, precision=fh.FEM_FP32_FP64DOT, device_ptrs=True,
+                stream=stream)
+    run_kw = dict(dt=p.dt, theta=p.theta, nsteps=p.nsteps, rtol=p.rtol)
+    rate, its, last = _timed_runs(h, T0, run_kw, 2)
+    h.close()
+    diff = torch.linalg.vector_norm(last["T_final"] - T_fp64) / torch.linalg.vector_norm(T_fp64)
+    print(f"mixed: {rate * p.n_nodes:.1f} MDOF*iter/s", file=sys.stderr, flush=True)
+    return {"workload": "the headline workload in the mixed form", "value": round(rate * p.n_nodes, 1),
+            "unit": "MDOF*iter/s", "iterations_per_run": int(its),
+            "sweeps_per_step_max": int(last["refine_sweeps"].max()),
+            "rel_l2_vs_fp64_final_field": float(diff)}
+
+
+def bench_above_mall(args, torch):
+    """The headline field rules at (mall_n+1)^3 nodes, whose FP64 working set (~100 B per node) exceeds
+    the 256 MB Infinity Cache: the rate when HBM, not the cache, serves the vectors."""
+    from paper_1905_07622_amd import femheat as fh
+    from paper_1905_07622_amd import workloads as wl
+    p = wl.lognormal_cube(args.mall_n, seed=2, nsteps=args.mall_nsteps)
+    dev = "cuda"
+    k = torch.tensor(p.k_e, device=dev)
+    rc = torch.tensor(p.rhoc_e, device=dev)
+    T0 = torch.tensor(p.T0, device=dev)
+    h = fh.Heat(p.nx, p.ny, p.nz, p.hx, p.hy, p.hz, k, rc, dirichlet_mask=p.dirichlet_mask,
+                flux_mask=p.flux_mask, flux=p.flux, device_ptrs=True,
+                stream=torch.cuda.current_stream().cuda_stream)
+    run_kw = dict(dt=p.dt, theta=p.theta, nsteps=p.nsteps, rtol=p.rtol)
+    t0 = time.perf_counter()
+    rate, its, last = _timed_runs(h, T0, run_kw, 2)
+    h.close()
+    f_corr = deferred_fraction(last["iters"].cpu().numpy())
+    ab = algorithmic_bytes(p.n_nodes, p.n_elems, 8, f_corr)
+    mdof = rate * p.n_nodes
+    print(f"above MALL: {mdof:.1f} MDOF*iter/s ({time.perf_counter() - t0:.1f} s)", file=sys.stderr, flush=True)
+    return {"workload": f"log-normal k, {p.nx}^3 hex Q1 ({p.n_nodes} DOF), Crank-Nicolson dt=5e-4, "
+                        f"{p.nsteps} steps, rtol 1e-8, FP64", "value": round(mdof, 1), "unit": "MDOF*iter/s",
+            "iterations_per_run": int(its),
+            "effective_gbs": round((ab["gather"] + ab["update"]) * rate * 1e6 / 1e9, 1)}
+
+
 def bench_batched(args, torch):
     """Batched proposals: S simulations on 48^3 random-sphere fields, 100
     backward-Euler steps each, in one fem_heat_run_batch call (mixed form),
@@ -219,7 +279,7 @@ def bench_served(args, torch):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--precision", choices=["fp64", "mixed"], default="fp64")
     ap.add_argument("--nsteps", type=int, default=200, help="time steps per run (the workload has 200)")
@@ -232,6 +292,10 @@ def main():
     ap.add_argument("--no-batched", action="store_true", help="skip the batched-proposals measurement")
     ap.add_argument("--no-served", action="store_true", help="skip the serving measurement")
     ap.add_argument("--only-extra", action="store_true", help="skip the 1M-DOF headline run")
+    ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-form run of the headline workload")
+    ap.add_argument("--no-above-mall", action="store_true", help="skip the 201^3-node (DRAM-bound) run")
+    ap.add_argument("--mall-n", type=int, default=200)
+    ap.add_argument("--mall-nsteps", type=int, default=20)
     ap.add_argument("--batch-sims", type=int, default=64)
     ap.add_argument("--batch-n", type=int, default=48)
     ap.add_argument("--batch-nsteps", type=int, default=100)
@@ -294,8 +358,11 @@ def main():
     stats = {"gather_launches": 0, "gather_ms": 0.0, "update_launches": 0, "update_ms": 0.0,
              "replace_launches": 0, "replace_ms": 0.0}
     last = None
+    run_ms = []
     for s in range(args.steps):
+        tr = time.perf_counter()
         last = h.run(T0, **run_kw)
+        run_ms.append((time.perf_counter() - tr) * 1e3)  # run() returns once its stream has drained
         iters += last["total_iters"]
         st = h.stats()
         for key in stats:
@@ -328,6 +395,18 @@ def main():
                 "deferred_update_share": round(f_corr, 4),
                 "other_kernels_us": {kname: round(v * 1e3, 3) for kname, v in per.items() if kname != dom}}
 
+    per_iter = algorithmic_bytes(p.n_nodes, p.n_elems, w, f_corr, one_red)
+    iter_bytes = per_iter["gather"] + per_iter["update"]
+    runs = {"n": len(run_ms), "median_ms": round(float(np.median(run_ms)), 2),
+            "min_ms": round(min(run_ms), 2), "max_ms": round(max(run_ms), 2),
+            "effective_gbs": round(iter_bytes * iters / secs / 1e9, 1),
+            "effective_gbs_note": "algorithmic bytes of the iteration kernels (direction gather + update) x "
+                                  "iterations / wall time; per-step RHS and initial-residual bytes not counted"}
+    if args.precision == "fp64" and not args.no_mixed:
+        extra["mixed"] = bench_mixed(args, torch, p, k, rc, T0, last["T_final"])
+    if not args.no_above_mall:
+        extra["above_mall"] = bench_above_mall(args, torch)
+
     line = {
         "metric": "PCG MDOF*iter/s at 1M DOF",
         "value": round(value, 1),
@@ -348,6 +427,7 @@ def main():
                    "tile": [shape["tile_x"], shape["tile_y"], shape["tile_z"]],
                    "grid_blocks": shape["grid_blocks"]},
         "roofline": roof,
+        "runs": runs,
     }
     line.update(extra)
     if not args.no_cpu_baseline:
