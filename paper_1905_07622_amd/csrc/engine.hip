@@ -149,8 +149,8 @@ class Engine {
   int mixed_sweeps();
   int finish_step(Sim& s);
   // Timing of sampled iterations: events come from a pool; a chunk's records
-  // are read while the GPU runs a later chunk (reading them at the chunk
-  // boundary, where the GPU waits for the host, cost ~3% of the run).
+  // are read while the GPU runs a later chunk, not at the chunk boundary,
+  // where the GPU waits for the host.
   struct Timed {
     hipEvent_t e[4];  // direction kernel start/end, update or replacement start/end
     bool gather;      // the direction kernel is in the sample
@@ -288,6 +288,8 @@ int Engine::add(const RunRequest& r, Sim** out) {
 }
 
 void Engine::remove(Sim* s) {
+  next_ran_ = false;  // a later simulation may be allocated where this one was
+  next_sim_ = nullptr;
   for (size_t i = 0; i < sims_.size(); ++i)
     if (sims_[i].get() == s) {
       sims_.erase(sims_.begin() + (long)i);
