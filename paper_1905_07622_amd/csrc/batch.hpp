@@ -66,7 +66,7 @@ struct SimDev {
   int32_t sweep;       // mixed form: this sweep runs an inner solve and a correction
 };
 
-// What the update kernel of a launch with a single simulation needs, passed
+// What the FP64 update kernel of a launch with a single simulation needs, passed
 // with the launch itself: it then starts without first reading the
 // simulation's SimDev (one dependent memory read less on its critical path).
 struct UpdView {
@@ -250,6 +250,7 @@ struct RoleFused {  // (r -= alpha q, x += alpha d_old,) d = P^-1 r + beta d, q 
 
 struct RoleReplFused {  // one-reduction form: x += alpha d, r = b - A x into the next residual buffer
   using V = double;
+  static constexpr bool kFour = true;  // follows a one-reduction direction kernel
   using Pro = ProAxpy<double, double>;
   using Epi = EpiResidual<double>;
   static __device__ const GatherArgs<V>& ga(const SimDev& s) { return s.A64; }
@@ -276,6 +277,13 @@ struct RoleCorr {  // mixed form: x64 += e, r64 = b - A x64, FP64 residual norm 
 
 // ---- kernels -----------------------------------------------------------------
 
+// Whether a role's kernel may follow a one-reduction direction kernel (and so
+// sum four partials): roles that say so with kFour.
+template <class Role>
+constexpr auto reads_four(int) -> decltype(Role::kFour, bool()) { return Role::kFour; }
+template <class Role>
+constexpr bool reads_four(long) { return false; }
+
 __device__ inline void work_item(const BatchArgs& a, uint32_t w, uint32_t& sim, uint32_t& local) {
   sim = 0;
   local = w;
@@ -294,17 +302,21 @@ __global__ void __launch_bounds__(256, 2) gather_batch_kernel(BatchArgs a) {
   work_item(a, xcd_work_item(blockIdx.x, gridDim.x), sim, local);
   const SimDev& s = a.sims[sim];
   const GatherArgs<typename Role::V> ga = Role::ga(s);
-  gather_tile<typename Role::V, CUBIC>(ga, Role::pro(s, a), Role::epi(s, a), Role::relay(s, a), local);
+  using Pro = typename Role::Pro;
+  gather_tile<typename Role::V, CUBIC, Pro, typename Role::Epi, reads_four<Role>(0) || AdvancesResidual<Pro>::value>(
+      ga, Role::pro(s, a), Role::epi(s, a), Role::relay(s, a), local);
 }
 
 // Residual update and preconditioned residual norm (a5), FP64 outer solve
 // or FP32 inner solve.
 template <typename V>
 __global__ void __launch_bounds__(256) update_batch_kernel(BatchArgs a) {
-  if (a.uv.on) {  // uniform
-    update_body<V>(static_cast<V*>(a.uv.r), static_cast<const V*>(a.uv.q), static_cast<const V*>(a.uv.pinv), a.uv.N,
-                   a.uv.R, blockIdx.x, a.uv.nblk);
-    return;
+  if constexpr (sizeof(V) == 8) {  // FP64 only: the FP32 kernel keeps its register count low
+    if (a.uv.on) {  // uniform
+      update_body<V, true>(static_cast<V*>(a.uv.r), static_cast<const V*>(a.uv.q),
+                           static_cast<const V*>(a.uv.pinv), a.uv.N, a.uv.R, blockIdx.x, a.uv.nblk);
+      return;
+    }
   }
   uint32_t sim, local;
   work_item(a, blockIdx.x, sim, local);
@@ -312,7 +324,8 @@ __global__ void __launch_bounds__(256) update_batch_kernel(BatchArgs a) {
   if constexpr (sizeof(V) == 8) {
     update_body<double>(s.r64, s.q64, s.pinv64, s.N, outer_relay(s, a, M_UPD, true), local, s.nblk[PK_UPD64]);
   } else {
-    update_body<float>(s.r32, s.q32, s.pinv32, s.N, inner_relay(s, a, M_UPD, true), local, s.nblk[PK_UPD32]);
+    update_body<float>(s.r32, s.q32, s.pinv32, s.N, inner_relay(s, a, M_UPD, true), local, s.nblk[PK_UPD32],
+                       s.e32[a.xpar], s.d32[dir_out(a)]);
   }
 }
 
@@ -332,7 +345,7 @@ static __global__ void __launch_bounds__(256) inner_start_batch_kernel(BatchArgs
 // a solve that finishes here after a plain update still owes the deferred
 // x += alpha d, which the simulation's blocks apply.  V selects the relay
 // and vectors: double the outer (FP64) solve, float the inner one.
-template <typename V>
+template <typename V, bool kFour>
 __global__ void __launch_bounds__(256) decide_batch_kernel(BatchArgs a) {
   constexpr bool inner = sizeof(V) == 4;
   uint32_t sim, local;
@@ -341,7 +354,7 @@ __global__ void __launch_bounds__(256) decide_batch_kernel(BatchArgs a) {
   const Relay R = inner ? inner_relay(s, a, M_DECIDE, false) : outer_relay(s, a, M_DECIDE, false);
   const StageIn in = stage_load(R);
   Scalars st;
-  (void)stage_finish(R, in, st, local == 0);
+  (void)stage_finish<kFour>(R, in, st, local == 0);
   if (local == 0 && threadIdx.x == 0) a.snap[sim] = st;
   if (a.corr && in.pending && st.done && st.status == 0) {
     if constexpr (inner)

@@ -188,7 +188,7 @@ class Engine {
 
   Group groups_[2];
   int ngroups_ = 0;
-  uint32_t off_upd64_ = 0, n_upd64_ = 0, off_upd32_ = 0, n_upd32_ = 0, off_start_ = 0, n_start_ = 0;
+  uint32_t off_upd64_ = 0, n_upd64_ = 0, off_upd32_ = 0, n_upd32_ = 0, off_start_ = 0, n_start_ = 0, off_one_ = 0;
 
   // relay parity and the kind of partials the next kernel reads, per relay
   int ocur_ = 0, oprev_ = PK_GATHER, icur_ = 0, iprev_ = PK_GATHER;
@@ -432,6 +432,8 @@ int Engine::compose() {
   add_kind(&fem_heat::upd_blocks64, off_upd64_, n_upd64_);
   add_kind(&fem_heat::upd_blocks32, off_upd32_, n_upd32_);
   add_kind(&fem_heat::start_blocks, off_start_, n_start_);
+  off_one_ = (uint32_t)tab.size();  // one block per simulation (decides that owe no x += alpha d)
+  for (size_t k = 0; k < n; ++k) tab.push_back(make_uint2((uint32_t)k, 0u));
   if (multi_) {
     if (tab_cap_ < tab.size()) {
       dfree(tab_dev_);
@@ -473,24 +475,16 @@ int Engine::update(BatchArgs a, hipEvent_t e0, hipEvent_t e1) {
   fem_heat* h = h_;
   const bool f64 = sizeof(V) == 8;
   a.table = multi_ ? tab_dev_ + (f64 ? off_upd64_ : off_upd32_) : nullptr;
-  if (!multi_) {  // the same relay and vectors as outer_relay / inner_relay would give
+  if (!multi_ && f64) {  // the same relay and vectors as outer_relay would give
     const SimDev& s = sd_one_;
     UpdView& u = a.uv;
     u.on = 1;
     u.N = s.N;
-    if (f64) {
-      u.nblk = s.nblk[PK_UPD64];
-      u.r = s.r64;
-      u.q = s.q64;
-      u.pinv = s.pinv64;
-      u.R = Relay{s.oS[a.cur], s.oS[a.cur ^ 1], s.oP[a.cur], s.nblk[a.prev], s.oP[a.cur ^ 1], M_UPD, s.octl, s.ldp};
-    } else {
-      u.nblk = s.nblk[PK_UPD32];
-      u.r = s.r32;
-      u.q = s.q32;
-      u.pinv = s.pinv32;
-      u.R = Relay{s.iS[a.cur], s.iS[a.cur ^ 1], s.iP[a.cur], s.nblk[a.prev], s.iP[a.cur ^ 1], M_UPD, s.ictl, s.ldp};
-    }
+    u.nblk = s.nblk[PK_UPD64];
+    u.r = s.r64;
+    u.q = s.q64;
+    u.pinv = s.pinv64;
+    u.R = Relay{s.oS[a.cur], s.oS[a.cur ^ 1], s.oP[a.cur], s.nblk[a.prev], s.oP[a.cur ^ 1], M_UPD, s.octl, s.ldp};
   }
   hipExtLaunchKernelGGL((update_batch_kernel<V>), dim3(f64 ? n_upd64_ : n_upd32_), dim3(kT), 0, stream_, e0, e1, 0,
                         a);
@@ -508,15 +502,27 @@ int Engine::decide(bool inner, int j_end, bool launch_next) {
   int& cur = inner ? icur_ : ocur_;
   int& prev = inner ? iprev_ : oprev_;
   const int jl = std::max(0, j_end - 1);
-  // (the one-reduction form owes nothing when a solve ends: its direction
-  // kernel completes each update before the stop test)
+  // (nothing is owed by the one-reduction form, whose direction kernel
+  // completes each update before the stop test, nor by the FP32 inner
+  // solves, whose update kernel applies x += alpha d itself)
   BatchArgs a = args(cur, prev, jl, replacements_before(jl, R_) & 1,
-                     !(fused_ && !inner) && j_end > 0 && deferred(j_end) ? 1 : 0);
-  a.table = multi_ ? tab_dev_ + (inner ? off_upd32_ : off_upd64_) : nullptr;
+                     !inner && !fused_ && j_end > 0 && deferred(j_end) ? 1 : 0);
+  // a decide that may owe x += alpha d runs over the update kernel's blocks,
+  // which then share that work; otherwise one block per simulation settles it
+  uint32_t grid;
+  if (a.corr) {
+    a.table = multi_ ? tab_dev_ + (inner ? off_upd32_ : off_upd64_) : nullptr;
+    grid = inner ? n_upd32_ : n_upd64_;
+  } else {
+    a.table = multi_ ? tab_dev_ + off_one_ : nullptr;
+    grid = (uint32_t)act_.size();
+  }
   if (inner)
-    hipLaunchKernelGGL(decide_batch_kernel<float>, dim3(n_upd32_), dim3(kT), 0, stream_, a);
+    hipLaunchKernelGGL((decide_batch_kernel<float, false>), dim3(grid), dim3(kT), 0, stream_, a);
+  else if (fused_)
+    hipLaunchKernelGGL((decide_batch_kernel<double, true>), dim3(grid), dim3(kT), 0, stream_, a);
   else
-    hipLaunchKernelGGL(decide_batch_kernel<double>, dim3(n_upd64_), dim3(kT), 0, stream_, a);
+    hipLaunchKernelGGL((decide_batch_kernel<double, false>), dim3(grid), dim3(kT), 0, stream_, a);
   HIP_TRY(hipGetLastError());
   cur ^= 1;
   if (!ev_decide_) HIP_TRY(hipEventCreateWithFlags(&ev_decide_, hipEventDisableTiming));
@@ -599,7 +605,7 @@ int Engine::pcg(int first_chunk) {
       if (one_red) {
         RC_TRY(gather<RoleFused>(args(cur, prev, jj, xpar, deferred(jj) ? 1 : 0), e0, e1));
       } else {
-        RC_TRY(gather<RoleDir<V>>(args(cur, prev, jj, xpar, deferred(jj) ? 1 : 0), e0, e1));
+        RC_TRY(gather<RoleDir<V>>(args(cur, prev, jj, xpar, !inner && deferred(jj) ? 1 : 0), e0, e1));
       }
       cur ^= 1;
       prev = PK_GATHER;

@@ -113,9 +113,9 @@ struct AdvancesResidual {
 // One block's share of a gather: tile `logical` of the solve that `ga`, the
 // functors and the relay describe.  The block's dot-product partial is
 // stored at index `logical`, and tile 0 publishes the relayed state.
-template <typename V, bool CUBIC, class Pro, class Epi>
+template <typename V, bool CUBIC, class Pro, class Epi, bool kFour = AdvancesResidual<Pro>::value>
 __device__ inline void gather_tile(const GatherArgs<V>& ga, Pro pro, Epi epi, const Relay& R, uint32_t logical) {
-  const StageIn in = stage_load(R);
+  const StageIn in = stage_load<sizeof(V) == 8>(R);
   if (stage_idle(R, in, logical == 0)) return;  // uniform: a finished solve
   Scalars st;
 
@@ -138,7 +138,7 @@ __device__ inline void gather_tile(const GatherArgs<V>& ga, Pro pro, Epi epi, co
   const uint32_t pstride = (uint32_t)px * (uint32_t)py, lstride = (uint32_t)nx * (uint32_t)ny;
 
   if (logical >= ga.s.ntiles) {  // a padding block: partial 0 (never the writer)
-    if (stage_finish(R, in, st, false) && R.pout) {
+    if (stage_finish<kFour>(R, in, st, false) && R.pout) {
       if constexpr (AdvancesResidual<Pro>::value) {
         const double z[4] = {0.0, 0.0, 0.0, 0.0};
         publish_partial4(R, z, logical);
@@ -361,7 +361,7 @@ __device__ inline void gather_tile(const GatherArgs<V>& ga, Pro pro, Epi epi, co
       fetch(S0, vis(0), lay(0), vis(0));
       fetch(SB, vis(1), lay(0), vis(0));
       if constexpr (kDepth == 2) fetch(SA, vis(min(2, n)), lay(min(1, n - 1)), vis(1));
-      if (!stage_finish(R, in, st, logical == 0)) {  // uniform
+      if (!stage_finish<kFour>(R, in, st, logical == 0)) {  // uniform
         if constexpr (XI) {
           // the solve finished in this kernel's evaluation: the last
           // iteration's deferred iterate update is still due at own nodes
@@ -461,8 +461,11 @@ struct ProDirection {  // d_new = P^-1 r + beta d_old   (Algorithm 1: s <- P^-1 
   __device__ void write(uint32_t i, V v, bool live, V* sink) const { *(live ? dnew + i : sink + threadIdx.x) = v; }
 };
 
-template <typename V>
-struct CarriesIterate<ProDirection<V>> {
+// Only the FP64 direction kernel carries the iterate: in the FP32 inner
+// solves of the mixed form the update kernel keeps x += alpha d (moving those
+// bytes into the gather measured slower there, in batches above all).
+template <>
+struct CarriesIterate<ProDirection<double>> {
   static constexpr bool value = true;
 };
 

@@ -224,13 +224,15 @@ struct StageIn {
 // First half of a relayed kernel's entry: reads the state (one uniform load).
 // Kernels can issue their first global loads after it and before
 // stage_finish, whose partial sum then overlaps them.
+template <bool kPre = false>
 __device__ inline StageIn stage_load(const Relay& R) {
   StageIn in;
-  // The partials are read together with the state (before it is known
+  // kPre: the partials are read together with the state (before it is known
   // whether they are needed: a wasted read costs less than a second memory
   // round trip), in canonical_sum's slot order: wave w < 4 holds virtual
-  // wave w.
-  in.pre = (blockDim.x >> 6) >= 4 && R.pin != nullptr;  // uniform
+  // wave w.  It costs registers, so only the FP64 kernels do it (the FP32
+  // inner solves run in batches, where occupancy matters more).
+  in.pre = kPre && (blockDim.x >> 6) >= 4 && R.pin != nullptr;  // uniform
   if (in.pre) {
     const uint32_t slot = threadIdx.x;  // only waves 0..3 use theirs
 #pragma unroll
@@ -259,7 +261,10 @@ __device__ inline bool stage_idle(const Relay& R, const StageIn& in, bool writer
 
 // Second half: sums the partials if needed, evaluates the state this kernel
 // works with, has the writer block publish it to Sout, and returns whether
-// the kernel has work.  Called by all threads of the block.
+// the kernel has work.  Called by all threads of the block.  kFour: the
+// kernel may follow a one-reduction direction kernel and sum its four
+// partials (only those kernels carry that code: it needs many registers).
+template <bool kFour = false>
 __device__ inline bool stage_finish(const Relay& R, const StageIn& in, Scalars& out, bool writer) {
   __shared__ Scalars sh;
   __shared__ int go;
@@ -268,9 +273,13 @@ __device__ inline bool stage_finish(const Relay& R, const StageIn& in, Scalars& 
   const bool pending = in.pending;
   double xs[4] = {0.0, 0.0, 0.0, 0.0};
   if (in.need) {  // uniform
-    if (pending && in.t.phase == PH_AFTER_FUSED)
-      canonical_sum4(R.pin, R.ld, R.npin, xs, red16);
-    else if (in.pre)
+    bool four = false;
+    if constexpr (kFour) {
+      four = pending && in.t.phase == PH_AFTER_FUSED;
+      if (four) canonical_sum4(R.pin, R.ld, R.npin, xs, red16);
+    }
+    if (four) {
+    } else if (in.pre)
       xs[0] = canonical_sum_pre(R.pin, R.npin, in.pv, red16);
     else
       xs[0] = canonical_sum(R.pin, R.npin, red16);

@@ -23,8 +23,8 @@ struct Vec<float> {
 };
 
 // r -= alpha q (0 on Dirichlet rows) ; delta_new = r^T P^-1 r.  Dirichlet
-// rows are recognised by P^-1 = 0.  (x += alpha d is deferred to the next
-// direction gather.)
+// rows are recognised by P^-1 = 0.  (In the FP64 solve x += alpha d is
+// deferred to the next direction gather.)
 template <typename V>
 __device__ inline void upd1(V& r, V q, V p, V alpha, double& acc) {
   V rr = fma(-alpha, q, r);
@@ -36,22 +36,38 @@ __device__ inline void upd1(V& r, V q, V p, V alpha, double& acc) {
 // Residual update of one solve by block `blk` of its `nblk` blocks (a
 // grid-stride loop over the solve's own block count, so the partial sums do
 // not depend on the launch the block belongs to).  Each thread loads kU
-// strided vectors before it uses any, and the first kU before it reads the
-// relayed state and settles alpha = delta / d^T q, so those reads run while
-// the loads are in flight.  A no-op once the solve is done.
-template <typename V>
+// strided vectors before it uses any, and the first kU before it settles
+// alpha = delta / d^T q, so the partial sum runs while they are in flight.
+// With kEarly (a launch for one simulation) those loads are issued even
+// before the relayed state is read; otherwise the state comes first, so a
+// finished solve loads nothing (in a lockstep batch most members are often
+// finished).  When x and d are given (FP32 inner solves) the kernel also
+// applies x += alpha d.
+template <typename V, bool kEarly = false>
 __device__ inline void update_body(V* __restrict__ r, const V* __restrict__ q, const V* __restrict__ pinv, uint32_t N,
-                                   const Relay& R, uint32_t blk, uint32_t nblk) {
+                                   const Relay& R, uint32_t blk, uint32_t nblk, V* __restrict__ x = nullptr,
+                                   const V* __restrict__ d = nullptr) {
+  StageIn in;
+  if constexpr (!kEarly) {
+    in = stage_load<sizeof(V) == 8>(R);
+    if (stage_idle(R, in, blk == 0)) return;
+  }
   using VT = typename Vec<V>::T;
   constexpr int W = Vec<V>::W;
-  constexpr int kU = 4;
+  // vectors in flight per thread: 4 in FP64 (the 1M-DOF solve launches one
+  // round of blocks); 1 in FP32, whose batched launches run many rounds and
+  // need the occupancy of a small register count instead
+  constexpr int kU = sizeof(V) == 8 ? 4 : 1;
   const uint32_t nvec = N / W;
   const uint32_t stride = nblk * blockDim.x;
   const uint32_t tid = blk * blockDim.x + threadIdx.x;
   VT* rv = reinterpret_cast<VT*>(r);
   const VT* qv = reinterpret_cast<const VT*>(q);
   const VT* pv = reinterpret_cast<const VT*>(pinv);
-  VT rr[kU], qq[kU], pp[kU];
+  const bool withx = x != nullptr;  // uniform
+  VT* xv = reinterpret_cast<VT*>(x);
+  const VT* dv = reinterpret_cast<const VT*>(d);
+  VT rr[kU], qq[kU], pp[kU], xx[kU], dd[kU];
   auto load = [&](uint32_t base) {
 #pragma unroll
     for (int u = 0; u < kU; ++u) {
@@ -60,12 +76,18 @@ __device__ inline void update_body(V* __restrict__ r, const V* __restrict__ q, c
         rr[u] = rv[j];
         qq[u] = qv[j];
         pp[u] = pv[j];
+        if (withx) {
+          xx[u] = xv[j];
+          dd[u] = dv[j];
+        }
       }
     }
   };
   load(tid);
-  const StageIn in = stage_load(R);
-  if (stage_idle(R, in, blk == 0)) return;
+  if constexpr (kEarly) {
+    in = stage_load<sizeof(V) == 8>(R);
+    if (stage_idle(R, in, blk == 0)) return;
+  }
   Scalars st;
   if (!stage_finish(R, in, st, blk == 0)) return;
   const V alpha = (V)st.alpha;
@@ -86,6 +108,18 @@ __device__ inline void update_body(V* __restrict__ r, const V* __restrict__ q, c
           upd1(rr[u].w, qq[u].w, pp[u].w, alpha, acc);
         }
         rv[j] = rr[u];
+        if (withx) {
+          if constexpr (W == 2) {
+            xx[u].x = fma(alpha, dd[u].x, xx[u].x);
+            xx[u].y = fma(alpha, dd[u].y, xx[u].y);
+          } else {
+            xx[u].x = fma(alpha, dd[u].x, xx[u].x);
+            xx[u].y = fma(alpha, dd[u].y, xx[u].y);
+            xx[u].z = fma(alpha, dd[u].z, xx[u].z);
+            xx[u].w = fma(alpha, dd[u].w, xx[u].w);
+          }
+          xv[j] = xx[u];
+        }
       }
     }
   }
@@ -93,6 +127,7 @@ __device__ inline void update_body(V* __restrict__ r, const V* __restrict__ q, c
     V rs = r[i];
     upd1(rs, q[i], pinv[i], alpha, acc);
     r[i] = rs;
+    if (withx) x[i] = fma(alpha, d[i], x[i]);
   }
   publish_partial(R, acc, blk);
 }
