@@ -90,7 +90,7 @@ struct BatchArgs {
   int32_t corr;        // the previous kernel was a plain update: x += alpha d is still due
   UpdView uv;          // update launches of a single simulation
   int32_t next_xc;     // next-step launches: iterate buffer the current solve is assumed to end in
-  int32_t next_R;      //                     replacement period
+  int32_t next_R;      //                     replacement period (< 0: mixed form, buffer known)
   double next_fs;      //                     dt * s of the next step
 };
 

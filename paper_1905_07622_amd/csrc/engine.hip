@@ -68,7 +68,10 @@ struct Sim {
   std::vector<int32_t> iters, sweeps;
   std::vector<double> relres;
   int64_t total = 0;
-  int est = 8;
+  int est = 8;  // FP64 solve: first chunk of the next step (this step's count)
+  // mixed form: first chunk of refinement sweep k of the next step (sweep k's
+  // count in the latest step that ran it; the last entry serves later sweeps)
+  int est_sw[4] = {8, 2, 2, 2};
   // within the current step
   int32_t it = 0, nsw = 0, xc = 0, exc = 0;
   bool sweeping = false, broke = false;
@@ -534,9 +537,12 @@ int Engine::decide(bool inner, int j_end, bool launch_next) {
   int next_xc = -1;
   if (launch_next) {
     const Sim& s = *act_[0];
-    next_xc = replacements_before(j_end, R_) & 1;
+    // FP64 solve: the buffer its iteration count gives (replacements mod 2);
+    // mixed form: the one the sweep's correction just wrote
+    next_xc = mixed_ ? s.xc : replacements_before(j_end, R_) & 1;
     BatchArgs b = args(ocur_, oprev_, 0, 0);
     b.next_xc = next_xc;
+    if (mixed_) b.next_R = -1;
     b.next_fs = s.rq.dt * schedule_value(s.rq.h, (int64_t)s.first + s.step + 2);
     RC_TRY(gather<RoleRhsNext>(b));
     ocur_ ^= 1;
@@ -549,7 +555,7 @@ int Engine::decide(bool inner, int j_end, bool launch_next) {
   HIP_TRY(hipEventSynchronize(ev_decide_));
   if (launch_next) {
     const Scalars& t = snap_host_[0];
-    next_ran_ = t.done && t.status == 0 && (replacements_before(t.iter, R_) & 1) == next_xc;
+    next_ran_ = t.done && t.status == 0 && (mixed_ || (replacements_before(t.iter, R_) & 1) == next_xc);
     next_sim_ = act_[0];
   }
   return FEM_OK;
@@ -675,7 +681,7 @@ int Engine::mixed_sweeps() {
       s.sweeping = !s.broke && !s.so.done && s.nsw < opts_.max_refine;
       if (s.sweeping) {
         any = true;
-        est = std::max(est, s.nsw == 0 ? s.est : std::max(1, s.est / 4));
+        est = std::max(est, s.est_sw[std::min(s.nsw, 3)]);
       }
     }
     if (!any) break;
@@ -696,6 +702,7 @@ int Engine::mixed_sweeps() {
         continue;
       }
       s.it += s.si.iter;
+      s.est_sw[std::min(s.nsw, 3)] = std::max(1, (int)s.si.iter);
       s.exc = replacements_before(s.si.iter, R_) & 1;
     }
     RC_TRY(upload_simdev());
@@ -708,7 +715,10 @@ int Engine::mixed_sweeps() {
       s.xc ^= 1;
       s.nsw += 1;
     }
-    RC_TRY(decide(false));
+    // with one simulation, the next step's RHS and initial residual go in
+    // behind this decide (they run if this sweep ended the step)
+    const bool launch_next = act_.size() == 1 && act_[0]->step + 1 < act_[0]->rq.nsteps;
+    RC_TRY(decide(false, 0, launch_next));
     for (size_t q = 0; q < act_.size(); ++q) {
       Sim& s = *act_[q];
       s.so = snap_host_[q];

@@ -36,7 +36,7 @@ struct Relay {
   Ctl ctl;
   uint32_t ld;         // distance between the components of multi-valued partials
   int32_t next_xc;     // M_RHS_NEXT: iterate buffer the launch assumed (replacements mod 2)
-  int32_t next_R;      //             replacement period
+  int32_t next_R;      //             replacement period (< 0: refinement sweep, no buffer test)
 };
 
 // Sum of n partials in one canonical order that does not depend on the block
@@ -291,8 +291,9 @@ __device__ inline bool stage_finish(const Relay& R, const StageIn& in, Scalars& 
     if (mode == M_RHS_NEXT) {
       // the solve must have ended without breakdown, with its iterate in the
       // buffer the launch assumed; otherwise the state passes unchanged
+      // (next_R < 0: a refinement sweep's correction, whose buffer is known)
       const int xc = (R.next_R <= 0 || t.iter <= 0) ? 0 : ((t.iter - 1) / R.next_R + 1) & 1;
-      mode = (t.done && t.status == 0 && xc == R.next_xc) ? M_RHS : M_SKIP;
+      mode = (t.done && t.status == 0 && (R.next_R < 0 || xc == R.next_xc)) ? M_RHS : M_SKIP;
     } else if (mode == M_INIT_NEXT) {
       mode = (t.phase == PH_NONE && !t.done) ? M_INIT : M_SKIP;  // the M_RHS_NEXT before it ran
     }

@@ -168,3 +168,29 @@ def test_single_simulation_overlap_matches_batch(gpu, replace_every, rtol):
     assert np.array_equal(one["iters"], alone[0]["iters"])
     ref = oracle.run(p, save_every=1, locked_iters=one["iters"], replace_every=replace_every)
     assert max(rel_l2(one["T_saved"][n], ref["T_saved"][n]) for n in range(p.nsteps)) <= GATE64
+
+
+@pytest.mark.parametrize("rtol,max_refine,inner_rtol", [(1e-8, 4, 1e-5), (1e-11, 4, 1e-3), (1e-11, 1, 1e-3),
+                                                        (0.5, 4, 1e-5)])
+def test_mixed_single_simulation_overlap_matches_batch(gpu, rtol, max_refine, inner_rtol):
+    """The mixed form alone also starts the next step's RHS and initial
+    residual behind the decide of each refinement sweep, before the host
+    knows whether that sweep ended the step; on the device they run only if
+    it did.  Alone and in a batch of two (no overlap) must give the same bits:
+    one sweep per step, several (a loose inner tolerance against a tight
+    outer one), steps cut off unconverged by max_refine, and steps that need
+    no sweep at all."""
+    p = wl.random_problem(13, 9, 11, seed=37, nsteps=6, rtol=rtol)
+    partner = wl.random_problem(6, 6, 6, seed=38, nsteps=6)
+    kw = dict(save_every=1, precision=fh.FEM_FP32_FP64DOT, max_refine=max_refine, inner_rtol=inner_rtol,
+              check=False)
+    _, alone = fh.run_batch([p], **kw)
+    _, pair = fh.run_batch([p, partner], **kw)
+    st = alone[0]["status"]
+    say(f"  rtol={rtol} max_refine={max_refine} inner_rtol={inner_rtol}: iters {list(alone[0]['iters'])} "
+        f"sweeps {list(alone[0]['refine_sweeps'])} status {st}")
+    assert st == pair[0]["status"] and st in (fh.FEM_OK, fh.FEM_ENOCONV)
+    same_bits(alone[0], pair[0])
+    if st == fh.FEM_OK and rtol <= 1e-8:  # (at rtol 0.5 neither field is near the converged one)
+        ref = oracle.run(p, save_every=1)
+        assert max(rel_l2(alone[0]["T_saved"][n], ref["T_saved"][n]) for n in range(p.nsteps)) <= GATE_MIXED
