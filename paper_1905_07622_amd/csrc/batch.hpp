@@ -66,15 +66,16 @@ struct SimDev {
   int32_t sweep;       // mixed form: this sweep runs an inner solve and a correction
 };
 
-// What the FP64 update kernel of a launch with a single simulation needs, passed
+// What the update kernel of a launch with a single simulation needs, passed
 // with the launch itself: it then starts without first reading the
 // simulation's SimDev (one dependent memory read less on its critical path).
 struct UpdView {
-  int32_t on;       // 0: read the SimDev array as usual
   uint32_t N, nblk;
   void* r;
   const void* q;
   const void* pinv;
+  void* x;          // FP32 inner solves: x += alpha d here (nullptr in FP64)
+  const void* d;
   Relay R;
 };
 
@@ -308,15 +309,20 @@ __global__ void __launch_bounds__(256, 2) gather_batch_kernel(BatchArgs a) {
 }
 
 // Residual update and preconditioned residual norm (a5), FP64 outer solve
-// or FP32 inner solve.
-template <typename V>
+// or FP32 inner solve; kOne: the launch serves one simulation (UpdView).
+template <typename V, bool kOne>
 __global__ void __launch_bounds__(256) update_batch_kernel(BatchArgs a) {
-  if constexpr (sizeof(V) == 8) {  // FP64 only: the FP32 kernel keeps its register count low
-    if (a.uv.on) {  // uniform
-      update_body<V, true>(static_cast<V*>(a.uv.r), static_cast<const V*>(a.uv.q),
-                           static_cast<const V*>(a.uv.pinv), a.uv.N, a.uv.R, blockIdx.x, a.uv.nblk);
-      return;
+  if constexpr (kOne) {  // one simulation, its vectors and relay in the launch arguments
+    V* x = nullptr;  // (a literal null in FP64, so that kernel has no x path)
+    const V* d = nullptr;
+    if constexpr (sizeof(V) == 4) {
+      x = static_cast<V*>(a.uv.x);
+      d = static_cast<const V*>(a.uv.d);
     }
+    update_body<V, true, sizeof(V) == 8 ? 4 : 2>(static_cast<V*>(a.uv.r), static_cast<const V*>(a.uv.q),
+                                                 static_cast<const V*>(a.uv.pinv), a.uv.N, a.uv.R, blockIdx.x,
+                                                 a.uv.nblk, x, d);
+    return;
   }
   uint32_t sim, local;
   work_item(a, blockIdx.x, sim, local);

@@ -478,19 +478,30 @@ int Engine::update(BatchArgs a, hipEvent_t e0, hipEvent_t e1) {
   fem_heat* h = h_;
   const bool f64 = sizeof(V) == 8;
   a.table = multi_ ? tab_dev_ + (f64 ? off_upd64_ : off_upd32_) : nullptr;
-  if (!multi_ && f64) {  // the same relay and vectors as outer_relay would give
+  const dim3 grid(f64 ? n_upd64_ : n_upd32_);
+  if (multi_) {
+    hipExtLaunchKernelGGL((update_batch_kernel<V, false>), grid, dim3(kT), 0, stream_, e0, e1, 0, a);
+  } else {  // the same vectors and relay as the SimDev would give (outer_relay, inner_relay)
     const SimDev& s = sd_one_;
     UpdView& u = a.uv;
-    u.on = 1;
     u.N = s.N;
-    u.nblk = s.nblk[PK_UPD64];
-    u.r = s.r64;
-    u.q = s.q64;
-    u.pinv = s.pinv64;
-    u.R = Relay{s.oS[a.cur], s.oS[a.cur ^ 1], s.oP[a.cur], s.nblk[a.prev], s.oP[a.cur ^ 1], M_UPD, s.octl, s.ldp};
+    if (f64) {
+      u.nblk = s.nblk[PK_UPD64];
+      u.r = s.r64;
+      u.q = s.q64;
+      u.pinv = s.pinv64;
+      u.R = Relay{s.oS[a.cur], s.oS[a.cur ^ 1], s.oP[a.cur], s.nblk[a.prev], s.oP[a.cur ^ 1], M_UPD, s.octl, s.ldp};
+    } else {
+      u.nblk = s.nblk[PK_UPD32];
+      u.r = s.r32;
+      u.q = s.q32;
+      u.pinv = s.pinv32;
+      u.x = s.e32[a.xpar];
+      u.d = s.d32[(a.j + 1) & 1];  // the direction this iteration's gather wrote
+      u.R = Relay{s.iS[a.cur], s.iS[a.cur ^ 1], s.iP[a.cur], s.nblk[a.prev], s.iP[a.cur ^ 1], M_UPD, s.ictl, s.ldp};
+    }
+    hipExtLaunchKernelGGL((update_batch_kernel<V, true>), grid, dim3(kT), 0, stream_, e0, e1, 0, a);
   }
-  hipExtLaunchKernelGGL((update_batch_kernel<V>), dim3(f64 ? n_upd64_ : n_upd32_), dim3(kT), 0, stream_, e0, e1, 0,
-                        a);
   HIP_TRY(hipGetLastError());
   return FEM_OK;
 }

@@ -42,8 +42,11 @@ __device__ inline void upd1(V& r, V q, V p, V alpha, double& acc) {
 // before the relayed state is read; otherwise the state comes first, so a
 // finished solve loads nothing (in a lockstep batch most members are often
 // finished).  When x and d are given (FP32 inner solves) the kernel also
-// applies x += alpha d.
-template <typename V, bool kEarly = false>
+// applies x += alpha d.  Vectors in flight per thread (kU): 4 in FP64, whose
+// 1M-DOF launch is one round of blocks; 2 in FP32 for one simulation; 1 in
+// FP32 batches, which run many rounds and need the occupancy of a small
+// register count instead.
+template <typename V, bool kEarly = false, int kU = (sizeof(V) == 8 ? 4 : 1)>
 __device__ inline void update_body(V* __restrict__ r, const V* __restrict__ q, const V* __restrict__ pinv, uint32_t N,
                                    const Relay& R, uint32_t blk, uint32_t nblk, V* __restrict__ x = nullptr,
                                    const V* __restrict__ d = nullptr) {
@@ -54,10 +57,6 @@ __device__ inline void update_body(V* __restrict__ r, const V* __restrict__ q, c
   }
   using VT = typename Vec<V>::T;
   constexpr int W = Vec<V>::W;
-  // vectors in flight per thread: 4 in FP64 (the 1M-DOF solve launches one
-  // round of blocks); 1 in FP32, whose batched launches run many rounds and
-  // need the occupancy of a small register count instead
-  constexpr int kU = sizeof(V) == 8 ? 4 : 1;
   const uint32_t nvec = N / W;
   const uint32_t stride = nblk * blockDim.x;
   const uint32_t tid = blk * blockDim.x + threadIdx.x;
