@@ -164,6 +164,40 @@ def bench_above_mall(args, torch):
             "effective_gbs": round((ab["gather"] + ab["update"]) * rate * 1e6 / 1e9, 1)}
 
 
+def bench_apply_ab(args, torch, p, k, rc, calls=20):
+    """The operator apply y = A x of the headline workload two ways: the node-centred gather of the PCG
+    path, and the two-pass element-by-element form after the paper's coalesced element-by-element method
+    (FEM_OP_ELEMENTWISE).  Device time of the operator kernels per call (HIP events inside the library),
+    and the effective rate on the operator's own bytes (read x and the two coefficient arrays, write y)."""
+    from paper_1905_07622_amd import femheat as fh
+    h = fh.Heat(p.nx, p.ny, p.nz, p.hx, p.hy, p.hz, k, rc, dirichlet_mask=p.dirichlet_mask,
+                flux_mask=p.flux_mask, flux=p.flux, device_ptrs=True, timing=True,
+                stream=torch.cuda.current_stream().cuda_stream)
+    x = torch.rand(p.n_nodes, dtype=torch.float64, device="cuda", generator=torch.Generator("cuda").manual_seed(3))
+    own = (2 * p.n_nodes + 2 * p.n_elems) * 8
+    res = {}
+    ys = {}
+    for name, ew in (("gather", False), ("elementwise_two_pass", True)):
+        for _ in range(3):
+            h.apply(fh.FEM_OP_A, x, dt=p.dt, theta=p.theta, elementwise=ew)
+        s0 = h.stats()
+        for _ in range(calls):
+            ys[name] = h.apply(fh.FEM_OP_A, x, dt=p.dt, theta=p.theta, elementwise=ew)
+        s1 = h.stats()
+        us = (s1["apply_ms"] - s0["apply_ms"]) / (s1["apply_calls"] - s0["apply_calls"]) * 1e3
+        res[name] = {"us_per_apply": round(us, 2), "operator_gbs": round(own / us / 1e3, 1)}
+    h.close()
+    res["elementwise_two_pass"]["design_bytes"] = (13 * p.n_nodes + 2 * p.n_elems) * 8
+    res["gather"]["design_bytes"] = own
+    diff = torch.linalg.vector_norm(ys["gather"] - ys["elementwise_two_pass"]) / torch.linalg.vector_norm(ys["gather"])
+    res["rel_l2_between_forms"] = float(diff)
+    res["calls"] = calls
+    res["workload"] = "y = (M + theta dt K) x on the headline grid and coefficients, x ~ U[0,1)"
+    print(f"apply A/B: gather {res['gather']['us_per_apply']} us, elementwise "
+          f"{res['elementwise_two_pass']['us_per_apply']} us", file=sys.stderr, flush=True)
+    return res
+
+
 def bench_batched(args, torch):
     """Batched proposals: S simulations on 48^3 random-sphere fields, 100
     backward-Euler steps each, in one fem_heat_run_batch call (mixed form),
@@ -294,6 +328,8 @@ def main():
     ap.add_argument("--only-extra", action="store_true", help="skip the 1M-DOF headline run")
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-form run of the headline workload")
     ap.add_argument("--no-above-mall", action="store_true", help="skip the 201^3-node (DRAM-bound) run")
+    ap.add_argument("--no-apply-ab", action="store_true",
+                    help="skip the gather vs element-by-element operator comparison")
     ap.add_argument("--mall-n", type=int, default=200)
     ap.add_argument("--mall-nsteps", type=int, default=20)
     ap.add_argument("--batch-sims", type=int, default=64)
@@ -406,6 +442,8 @@ def main():
         extra["mixed"] = bench_mixed(args, torch, p, k, rc, T0, last["T_final"])
     if not args.no_above_mall:
         extra["above_mall"] = bench_above_mall(args, torch)
+    if args.precision == "fp64" and not args.no_apply_ab:
+        extra["apply_ab"] = bench_apply_ab(args, torch, p, k, rc)
 
     line = {
         "metric": "PCG MDOF*iter/s at 1M DOF",

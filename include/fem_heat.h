@@ -79,6 +79,14 @@ extern "C" {
 #define FEM_OP_JACOBI 2      /* y = P^-1 x, P = diag(M + theta*dt*K); 0 on Dirichlet */
 #define FEM_OP_LOAD 3        /* y = F (boundary load vector); x is ignored          */
 #define FEM_OP_FP32 0x100    /* OR-ed in: use the FP32 operator (x rounded to FP32) */
+#define FEM_OP_ELEMENTWISE 0x200 /* OR-ed in (FEM_OP_A or FEM_OP_L, FP64 only): apply element by element in
+                                    two passes instead of the node-centred gather, after the structure of
+                                    the paper's coalesced element-by-element method (Section 4.3, third
+                                    implementation): each wavefront integrates a row of elements from the
+                                    four node rows along its x-edges and sums neighbouring contributions,
+                                    a second pass adds the up to four partial sums per node.  Kept for
+                                    comparison; the first use allocates 4 N doubles of partial sums, held
+                                    by the handle until fem_heat_destroy */
 
 typedef struct fem_heat fem_heat;
 
@@ -152,6 +160,9 @@ typedef struct {
   double replace_ms;
   int32_t grid_blocks;       /* blocks of the gather launch                                */
   int32_t tile_x, tile_y, tile_z;
+  int64_t apply_calls;       /* fem_heat_apply calls on a handle created with FEM_TIMING,  */
+  double apply_ms;           /* and the device time of their operator kernels (HIP events;
+                                the copies of x and y are outside)                          */
 } fem_stats;
 
 /* Create a solver for one grid, coefficient field and set of boundary

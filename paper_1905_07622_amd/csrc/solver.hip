@@ -10,6 +10,7 @@
 #include <cmath>
 #include <cstring>
 
+#include "ebe.hpp"
 #include "engine.hpp"
 #include "runtime.hpp"
 #include "vector_kernels.hpp"
@@ -345,11 +346,41 @@ int solver_apply(fem_heat* h, int32_t which, double dt, double theta, const doub
   HIP_TRY(hipSetDevice(h->opts.device));
   const uint32_t N = h->g.N;
   const bool fp32 = (which & FEM_OP_FP32) != 0;
+  const bool ebe = (which & FEM_OP_ELEMENTWISE) != 0;
   const int op = which & 0xff;
   double* xd = h->pool[0];
   double* yd = h->pool[1];
   if (op != FEM_OP_LOAD) RC_TRY(copy_in(h, xd, x, N));
-  if (op == FEM_OP_A || op == FEM_OP_L) {
+  if (ebe && !h->ebe_part) RC_TRY(dalloc(h, &h->ebe_part, 4 * (size_t)N));
+  if (h->timing) {
+    for (auto& e : h->ev_apply)
+      if (!e) HIP_TRY(hipEventCreate(&e));
+    HIP_TRY(hipEventRecord(h->ev_apply[0], h->stream));
+  }
+  if ((op == FEM_OP_A || op == FEM_OP_L) && ebe) {
+    const double ck = op == FEM_OP_A ? theta * dt : -(1.0 - theta) * dt;
+    GatherArgs<double> ga{};
+    fill_classes(h->g, ga, 1.0, ck, false);  // the general class entries hold for any box
+    EbeArgs ea{};
+    ea.nx = h->g.nx;
+    ea.ny = h->g.ny;
+    ea.nz = h->g.nz;
+    ea.px = h->g.px;
+    ea.py = h->g.py;
+    ea.N = N;
+    ea.nseg = (uint32_t)((h->g.nx + kEbeStore - 1) / kEbeStore);
+    ea.x = xd;
+    ea.rhoc = h->rhoc64;
+    ea.kc = h->k64;
+    ea.part = h->ebe_part;
+    for (int c = 0; c < 8; ++c) {
+      ea.Mc[c] = ga.sa * ga.Mc[c];
+      ea.Kc[c] = ga.sb * ga.Kc[c];
+    }
+    const uint64_t waves = (uint64_t)ea.nseg * (uint64_t)h->g.ny * (uint64_t)h->g.nz;
+    hipLaunchKernelGGL(ebe_elements_kernel, dim3((uint32_t)((waves + 3) / 4)), dim3(256), 0, h->stream, ea);
+    hipLaunchKernelGGL(ebe_sum_kernel, dim3(std::min<uint32_t>(nblk(N), 4096)), dim3(kT), 0, h->stream, ea, yd);
+  } else if (op == FEM_OP_A || op == FEM_OP_L) {
     const double ck = op == FEM_OP_A ? theta * dt : -(1.0 - theta) * dt;
     if (fp32) {
       RC_TRY(ensure_fp32(h));
@@ -375,8 +406,15 @@ int solver_apply(fem_heat* h, int32_t which, double dt, double theta, const doub
     return fail(h, FEM_EINVAL, "unknown operator");
   }
   HIP_TRY(hipGetLastError());
+  if (h->timing) HIP_TRY(hipEventRecord(h->ev_apply[1], h->stream));
   RC_TRY(copy_out(h, y, yd, (size_t)N * sizeof(double)));
   HIP_TRY(hipStreamSynchronize(h->stream));
+  if (h->timing) {
+    float ms = 0.0f;
+    HIP_TRY(hipEventElapsedTime(&ms, h->ev_apply[0], h->ev_apply[1]));
+    h->stats.apply_calls += 1;
+    h->stats.apply_ms += ms;
+  }
   return FEM_OK;
 }
 
@@ -450,6 +488,9 @@ void solver_free(fem_heat* h) {
     }
   dfree(h->xyz_dev);
   dfree(h->traces_dev);
+  dfree(h->ebe_part);
+  for (auto& e : h->ev_apply)
+    if (e) (void)hipEventDestroy(e);
   if (h->own_stream && h->stream) (void)hipStreamDestroy(h->stream);
   h->stream = nullptr;
 }

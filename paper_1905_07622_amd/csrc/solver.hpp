@@ -73,6 +73,10 @@ struct fem_heat {
   femheat::GatherShape shape{};
   uint32_t upd_blocks64 = 0, upd_blocks32 = 0, start_blocks = 0;
 
+  // element-by-element apply (test hook): 4 N partial sums, allocated on first use
+  double* ebe_part = nullptr;
+  hipEvent_t ev_apply[2] = {nullptr, nullptr};  // FEM_TIMING: around an apply's operator kernels
+
   fem_stats stats{};
 
   std::string err;

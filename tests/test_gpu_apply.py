@@ -111,3 +111,66 @@ def test_device_pointer_apply(gpu):
         assert np.array_equal(y.cpu().numpy(), ref)
     finally:
         h.close()
+
+
+# ---- element-by-element two-pass apply (FEM_OP_ELEMENTWISE), kept for comparison ----
+
+EBE_CASES = CASES + [
+    ("seg_61x3x2", (61, 3, 2), {}),
+    ("seg_62x2x3", (62, 2, 3), {}),
+    ("seg_63x3x2", (63, 3, 2), {}),
+    ("seg_124x2x2", (124, 2, 2), {}),
+    ("seg_125x4x3", (125, 4, 3), dict(hx=0.01, hy=0.02, hz=0.015)),
+]
+
+
+@pytest.mark.parametrize("name,dims,kw", EBE_CASES, ids=[c[0] for c in EBE_CASES])
+@pytest.mark.parametrize("theta,dt", [(1.0, 1e-3), (0.5, 5e-4)])
+def test_elementwise_apply_matches_oracle(gpu, name, dims, kw, theta, dt):
+    """Both operators by the two-pass element-by-element form, against the
+    oracle's assembled product to the same FP64 bound as the gather, across
+    x-segment boundaries (62 stored nodes per wavefront) and ragged grids."""
+    say(f"elementwise apply case {name} theta={theta} dt={dt}")
+    prob = wl.random_problem(*dims, seed=sum(dims), **kw)
+    x = wl.random_vector(prob.n_nodes, 11)
+    with fh.Heat.from_problem(prob) as h:
+        yA = h.apply(fh.FEM_OP_A, x, dt=dt, theta=theta, elementwise=True)
+        yL = h.apply(fh.FEM_OP_L, x, dt=dt, theta=theta, elementwise=True)
+        gA = h.apply(fh.FEM_OP_A, x, dt=dt, theta=theta)
+    assert_apply_close(yA, prob, 1.0, theta * dt, x, 1e-13)
+    assert_apply_close(yL, prob, 1.0, -(1 - theta) * dt, x, 1e-13)
+    np.testing.assert_allclose(yA, gA, rtol=0, atol=1e-13 * np.abs(gA).max())
+
+
+def test_elementwise_matches_brute_force_element_loop(gpu):
+    prob = wl.random_problem(7, 4, 3, seed=8, hx=0.3, hy=0.2, hz=0.45)
+    x = wl.random_vector(prob.n_nodes, 3)
+    with fh.Heat.from_problem(prob) as h:
+        y = h.apply(fh.FEM_OP_A, x, dt=0.1, theta=0.7, elementwise=True)
+    ref = oracle.element_loop(prob, 1.0, 0.07, x)
+    np.testing.assert_allclose(y, ref, atol=1e-13 * np.abs(ref).max())
+
+
+def test_elementwise_full_size_100cubed_and_timing(gpu):
+    """The 1,030,301-node log-normal operator in both forms, with the apply
+    timing of FEM_TIMING handles (one event pair per call)."""
+    prob = wl.lognormal_cube()
+    x = wl.random_vector(prob.n_nodes, 9)
+    with fh.Heat.from_problem(prob, timing=True) as h:
+        y = h.apply(fh.FEM_OP_A, x, dt=prob.dt, theta=prob.theta, elementwise=True)
+        g = h.apply(fh.FEM_OP_A, x, dt=prob.dt, theta=prob.theta)
+        st = h.stats()
+    assert_apply_close(y, prob, 1.0, prob.theta * prob.dt, x, 1e-13)
+    np.testing.assert_allclose(y, g, rtol=0, atol=1e-13 * np.abs(g).max())
+    assert st["apply_calls"] == 2 and st["apply_ms"] > 0
+
+
+def test_elementwise_rejects_fp32_and_other_operators(gpu):
+    prob = wl.random_problem(4, 4, 4, seed=2)
+    x = wl.random_vector(prob.n_nodes, 1)
+    with fh.Heat.from_problem(prob) as h:
+        for which, fp32 in ((fh.FEM_OP_A, True), (fh.FEM_OP_JACOBI, False), (fh.FEM_OP_LOAD, False)):
+            with pytest.raises(fh.FemError):
+                h.apply(which, x, dt=1e-3, theta=1.0, fp32=fp32, elementwise=True)
+        st = h.stats()
+    assert st["apply_calls"] == 0  # a handle without FEM_TIMING keeps no apply times
