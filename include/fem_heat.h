@@ -87,6 +87,10 @@ extern "C" {
                                     a second pass adds the up to four partial sums per node.  Kept for
                                     comparison; the first use allocates 4 N doubles of partial sums, held
                                     by the handle until fem_heat_destroy */
+#define FEM_OP_ROWWAVE 0x400 /* OR-ed in (FEM_OP_A or FEM_OP_L, FP64 only): node-centred apply with one
+                                wavefront per node row and no block barrier (x-neighbours through lane
+                                shuffles, y- and z-neighbours from nine coalesced row loads), instead of
+                                the LDS-tiled z-marching gather.  Kept for comparison */
 
 typedef struct fem_heat fem_heat;
 

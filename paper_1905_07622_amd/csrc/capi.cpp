@@ -266,12 +266,14 @@ int fem_heat_apply(fem_heat* h, int32_t which, double dt, double theta, const do
   if (!h) return FEM_EINVAL;
   h->err.clear();
   const int op = which & 0xff;
-  if ((which & ~(0xff | FEM_OP_FP32 | FEM_OP_ELEMENTWISE)) || op > FEM_OP_LOAD) {
+  if ((which & ~(0xff | FEM_OP_FP32 | FEM_OP_ELEMENTWISE | FEM_OP_ROWWAVE)) || op > FEM_OP_LOAD) {
     h->err = "unknown operator";
     return FEM_EINVAL;
   }
-  if ((which & FEM_OP_ELEMENTWISE) && ((which & FEM_OP_FP32) || (op != FEM_OP_A && op != FEM_OP_L))) {
-    h->err = "the element-by-element apply takes FEM_OP_A or FEM_OP_L in FP64";
+  const int32_t form = which & (FEM_OP_ELEMENTWISE | FEM_OP_ROWWAVE);
+  if (form && (form == (FEM_OP_ELEMENTWISE | FEM_OP_ROWWAVE) || (which & FEM_OP_FP32) ||
+               (op != FEM_OP_A && op != FEM_OP_L))) {
+    h->err = "the element-by-element and row-wavefront applies take one of FEM_OP_A, FEM_OP_L in FP64";
     return FEM_EINVAL;
   }
   if (!y || (op != FEM_OP_LOAD && !x)) {

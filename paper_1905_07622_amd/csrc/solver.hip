@@ -12,6 +12,7 @@
 
 #include "ebe.hpp"
 #include "engine.hpp"
+#include "rowwave.hpp"
 #include "runtime.hpp"
 #include "vector_kernels.hpp"
 
@@ -347,6 +348,7 @@ int solver_apply(fem_heat* h, int32_t which, double dt, double theta, const doub
   const uint32_t N = h->g.N;
   const bool fp32 = (which & FEM_OP_FP32) != 0;
   const bool ebe = (which & FEM_OP_ELEMENTWISE) != 0;
+  const bool rows = (which & FEM_OP_ROWWAVE) != 0;
   const int op = which & 0xff;
   double* xd = h->pool[0];
   double* yd = h->pool[1];
@@ -380,6 +382,30 @@ int solver_apply(fem_heat* h, int32_t which, double dt, double theta, const doub
     const uint64_t waves = (uint64_t)ea.nseg * (uint64_t)h->g.ny * (uint64_t)h->g.nz;
     hipLaunchKernelGGL(ebe_elements_kernel, dim3((uint32_t)((waves + 3) / 4)), dim3(256), 0, h->stream, ea);
     hipLaunchKernelGGL(ebe_sum_kernel, dim3(std::min<uint32_t>(nblk(N), 4096)), dim3(kT), 0, h->stream, ea, yd);
+  } else if ((op == FEM_OP_A || op == FEM_OP_L) && rows) {
+    const double ck = op == FEM_OP_A ? theta * dt : -(1.0 - theta) * dt;
+    GatherArgs<double> ga{};
+    fill_classes(h->g, ga, 1.0, ck, false);
+    RowArgs ra{};
+    ra.nx = h->g.nx;
+    ra.ny = h->g.ny;
+    ra.nz = h->g.nz;
+    ra.px = h->g.px;
+    ra.py = h->g.py;
+    ra.pz = h->g.pz;
+    ra.nseg = (uint32_t)((h->g.px + kRowOwn - 1) / kRowOwn);
+    ra.nwave = ra.nseg * (uint32_t)h->g.py * (uint32_t)h->g.pz;
+    ra.nblk = (ra.nwave + 3) / 4;
+    ra.share = (ra.nblk + 7) / 8;
+    ra.x = xd;
+    ra.rhoc = h->rhoc64;
+    ra.kc = h->k64;
+    ra.y = yd;
+    for (int c = 0; c < 8; ++c) {
+      ra.Mc[c] = ga.sa * ga.Mc[c];
+      ra.Kc[c] = ga.sb * ga.Kc[c];
+    }
+    hipLaunchKernelGGL(rowwave_apply_kernel, dim3(8 * ra.share), dim3(256), 0, h->stream, ra);
   } else if (op == FEM_OP_A || op == FEM_OP_L) {
     const double ck = op == FEM_OP_A ? theta * dt : -(1.0 - theta) * dt;
     if (fp32) {

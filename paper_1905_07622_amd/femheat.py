@@ -22,7 +22,8 @@ FEM_FP64, FEM_FP32_FP64DOT = 0, 1
 FEM_GUESS_EXTRAP, FEM_GUESS_PREV = 0, 1
 FEM_STOP_RHS, FEM_STOP_INITIAL = 0, 1
 FEM_DEVICE_PTRS, FEM_TIMING, FEM_ONE_REDUCTION = 0x1, 0x2, 0x4
-FEM_OP_A, FEM_OP_L, FEM_OP_JACOBI, FEM_OP_LOAD, FEM_OP_FP32, FEM_OP_ELEMENTWISE = 0, 1, 2, 3, 0x100, 0x200
+FEM_OP_A, FEM_OP_L, FEM_OP_JACOBI, FEM_OP_LOAD, FEM_OP_FP32, FEM_OP_ELEMENTWISE, FEM_OP_ROWWAVE = (
+    0, 1, 2, 3, 0x100, 0x200, 0x400)
 
 _dp = ctypes.POINTER(ctypes.c_double)
 _ip = ctypes.POINTER(ctypes.c_int32)
@@ -512,12 +513,13 @@ class Heat:
         return dict(status=st, T_final=T_final, T_saved=T_saved, traces=traces, iters=iters, relres=relres,
                     refine_sweeps=sweeps, total_iters=int(out.total_iters), device_ms=float(out.device_ms))
 
-    def apply(self, which, x=None, *, dt, theta, fp32=False, elementwise=False):
+    def apply(self, which, x=None, *, dt, theta, fp32=False, elementwise=False, rowwave=False):
         a = _Arrays(self.device_ptrs)
         y, yp = a.out((self.N,))
         if x is None:
             x = np.zeros(self.N) if not self.device_ptrs else __import__("torch").zeros(self.N, dtype=__import__("torch").float64, device="cuda")
-        which = which | (FEM_OP_FP32 if fp32 else 0) | (FEM_OP_ELEMENTWISE if elementwise else 0)
+        which = (which | (FEM_OP_FP32 if fp32 else 0) | (FEM_OP_ELEMENTWISE if elementwise else 0)
+                 | (FEM_OP_ROWWAVE if rowwave else 0))
         st = fem_heat_apply(self.h, which, dt, theta, a.inp(x), yp)
         if st != FEM_OK:
             raise FemError(st, fem_last_error(self.h))

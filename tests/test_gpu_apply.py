@@ -113,7 +113,10 @@ def test_device_pointer_apply(gpu):
         h.close()
 
 
-# ---- element-by-element two-pass apply (FEM_OP_ELEMENTWISE), kept for comparison ----
+# ---- comparison forms of the apply, kept beside the gather: element by element in two passes
+# (FEM_OP_ELEMENTWISE) and node-centred with one wavefront per node row (FEM_OP_ROWWAVE) ----
+
+FORMS = ["elementwise", "rowwave"]
 
 EBE_CASES = CASES + [
     ("seg_61x3x2", (61, 3, 2), {}),
@@ -124,53 +127,60 @@ EBE_CASES = CASES + [
 ]
 
 
+@pytest.mark.parametrize("form", FORMS)
 @pytest.mark.parametrize("name,dims,kw", EBE_CASES, ids=[c[0] for c in EBE_CASES])
 @pytest.mark.parametrize("theta,dt", [(1.0, 1e-3), (0.5, 5e-4)])
-def test_elementwise_apply_matches_oracle(gpu, name, dims, kw, theta, dt):
-    """Both operators by the two-pass element-by-element form, against the
-    oracle's assembled product to the same FP64 bound as the gather, across
-    x-segment boundaries (62 stored nodes per wavefront) and ragged grids."""
-    say(f"elementwise apply case {name} theta={theta} dt={dt}")
+def test_comparison_forms_match_oracle(gpu, form, name, dims, kw, theta, dt):
+    """Both operators by each comparison form, against the oracle's assembled
+    product to the same FP64 bound as the gather, across x-segment boundaries
+    (62 nodes per wavefront) and ragged and non-cubic grids."""
+    say(f"{form} apply case {name} theta={theta} dt={dt}")
     prob = wl.random_problem(*dims, seed=sum(dims), **kw)
     x = wl.random_vector(prob.n_nodes, 11)
+    f = {form: True}
     with fh.Heat.from_problem(prob) as h:
-        yA = h.apply(fh.FEM_OP_A, x, dt=dt, theta=theta, elementwise=True)
-        yL = h.apply(fh.FEM_OP_L, x, dt=dt, theta=theta, elementwise=True)
+        yA = h.apply(fh.FEM_OP_A, x, dt=dt, theta=theta, **f)
+        yL = h.apply(fh.FEM_OP_L, x, dt=dt, theta=theta, **f)
         gA = h.apply(fh.FEM_OP_A, x, dt=dt, theta=theta)
     assert_apply_close(yA, prob, 1.0, theta * dt, x, 1e-13)
     assert_apply_close(yL, prob, 1.0, -(1 - theta) * dt, x, 1e-13)
     np.testing.assert_allclose(yA, gA, rtol=0, atol=1e-13 * np.abs(gA).max())
 
 
-def test_elementwise_matches_brute_force_element_loop(gpu):
+@pytest.mark.parametrize("form", FORMS)
+def test_comparison_forms_match_brute_force_element_loop(gpu, form):
     prob = wl.random_problem(7, 4, 3, seed=8, hx=0.3, hy=0.2, hz=0.45)
     x = wl.random_vector(prob.n_nodes, 3)
     with fh.Heat.from_problem(prob) as h:
-        y = h.apply(fh.FEM_OP_A, x, dt=0.1, theta=0.7, elementwise=True)
+        y = h.apply(fh.FEM_OP_A, x, dt=0.1, theta=0.7, **{form: True})
     ref = oracle.element_loop(prob, 1.0, 0.07, x)
     np.testing.assert_allclose(y, ref, atol=1e-13 * np.abs(ref).max())
 
 
-def test_elementwise_full_size_100cubed_and_timing(gpu):
-    """The 1,030,301-node log-normal operator in both forms, with the apply
-    timing of FEM_TIMING handles (one event pair per call)."""
+def test_comparison_forms_full_size_100cubed_and_timing(gpu):
+    """The 1,030,301-node log-normal operator in all three forms, with the
+    apply timing of FEM_TIMING handles (one event pair per call)."""
     prob = wl.lognormal_cube()
     x = wl.random_vector(prob.n_nodes, 9)
     with fh.Heat.from_problem(prob, timing=True) as h:
-        y = h.apply(fh.FEM_OP_A, x, dt=prob.dt, theta=prob.theta, elementwise=True)
+        ys = [h.apply(fh.FEM_OP_A, x, dt=prob.dt, theta=prob.theta, **{f: True}) for f in FORMS]
         g = h.apply(fh.FEM_OP_A, x, dt=prob.dt, theta=prob.theta)
         st = h.stats()
-    assert_apply_close(y, prob, 1.0, prob.theta * prob.dt, x, 1e-13)
-    np.testing.assert_allclose(y, g, rtol=0, atol=1e-13 * np.abs(g).max())
-    assert st["apply_calls"] == 2 and st["apply_ms"] > 0
+    for y in ys:
+        assert_apply_close(y, prob, 1.0, prob.theta * prob.dt, x, 1e-13)
+        np.testing.assert_allclose(y, g, rtol=0, atol=1e-13 * np.abs(g).max())
+    assert st["apply_calls"] == 3 and st["apply_ms"] > 0
 
 
-def test_elementwise_rejects_fp32_and_other_operators(gpu):
+def test_comparison_forms_reject_fp32_other_operators_and_both_flags(gpu):
     prob = wl.random_problem(4, 4, 4, seed=2)
     x = wl.random_vector(prob.n_nodes, 1)
     with fh.Heat.from_problem(prob) as h:
-        for which, fp32 in ((fh.FEM_OP_A, True), (fh.FEM_OP_JACOBI, False), (fh.FEM_OP_LOAD, False)):
-            with pytest.raises(fh.FemError):
-                h.apply(which, x, dt=1e-3, theta=1.0, fp32=fp32, elementwise=True)
+        for form in FORMS:
+            for which, fp32 in ((fh.FEM_OP_A, True), (fh.FEM_OP_JACOBI, False), (fh.FEM_OP_LOAD, False)):
+                with pytest.raises(fh.FemError):
+                    h.apply(which, x, dt=1e-3, theta=1.0, fp32=fp32, **{form: True})
+        with pytest.raises(fh.FemError):
+            h.apply(fh.FEM_OP_A, x, dt=1e-3, theta=1.0, elementwise=True, rowwave=True)
         st = h.stats()
     assert st["apply_calls"] == 0  # a handle without FEM_TIMING keeps no apply times
