@@ -64,6 +64,7 @@ struct SimDev {
   int32_t xc;          // mixed form: X buffer of the current FP64 iterate
   int32_t exc;         // mixed form: e buffer of the last inner solution
   int32_t sweep;       // mixed form: this sweep runs an inner solve and a correction
+  double inner_rtol;   // mixed form: floor of the inner relative tolerance
 };
 
 // What the update kernel of a launch with a single simulation needs, passed
@@ -90,6 +91,7 @@ struct BatchArgs {
   int32_t xpar;        // replacements so far in this solve, mod 2 (x or e buffer)
   int32_t corr;        // the previous kernel was a plain update: x += alpha d is still due
   UpdView uv;          // update launches of a single simulation
+  int32_t ocur;        // inner start: parity of the settled outer state
   int32_t next_xc;     // next-step launches: iterate buffer the current solve is assumed to end in
   int32_t next_R;      //                     replacement period (< 0: mixed form, buffer known)
   double next_fs;      //                     dt * s of the next step
@@ -335,14 +337,29 @@ __global__ void __launch_bounds__(256) update_batch_kernel(BatchArgs a) {
   }
 }
 
-// Start of the inner solves of a refinement sweep (a9); simulations that do
-// not sweep this time get an idle, already finished inner solve.
+// Start of the inner solves of a refinement sweep (a9).  A simulation sweeps
+// if the host asked for it and its settled outer state (read here, so the
+// host need not have seen it) is neither done nor broken down; the others get
+// an idle, already finished inner solve.  The inner tolerance is half the
+// reduction the FP64 stop rule still needs, never tighter than inner_rtol
+// (FP32 arithmetic bounds what the inner solve can reach) nor looser than
+// 0.5; it goes to the first evaluation with the relayed state.
 static __global__ void __launch_bounds__(256) inner_start_batch_kernel(BatchArgs a) {
   uint32_t sim, local;
   work_item(a, blockIdx.x, sim, local);
   const SimDev& s = a.sims[sim];
-  inner_start_body(s.r64, s.rhs32, s.r32, s.e32[0], s.pinv32, s.N,
-                   inner_relay(s, a, s.sweep ? M_START : M_IDLE, true), local, s.nblk[PK_START]);
+  Relay R = inner_relay(s, a, M_IDLE, true);
+  if (s.sweep) {
+    const Scalars& o = *s.oS[a.ocur];
+    if (!o.done && o.status == 0) {
+      const double ref = s.octl.stop_rule == 1 ? o.delta0 : o.delta_b;
+      const double need = o.delta > 0.0 ? 0.5 * sqrt(s.octl.rtol2 * ref / o.delta) : 1.0;
+      const double irt = fmin(0.5, fmax(s.inner_rtol, need));
+      R.mode = M_START;
+      R.ctl.rtol2 = irt * irt;
+    }
+  }
+  inner_start_body(s.r64, s.rhs32, s.r32, s.e32[0], s.pinv32, s.N, R, local, s.nblk[PK_START]);
 }
 
 // Settles the pending decision of every simulation and copies the settled

@@ -128,7 +128,7 @@ class Engine {
   int upload_simdev();
   void fill_simdev(const Sim& s, SimDev& d) const;
   BatchArgs args(int cur, int prev, int j, int xpar, int corr = 0) const {
-    BatchArgs a{sd_dev_, nullptr, snap_map_, cur, prev, j, xpar, corr, UpdView{}, 0, R_, 0.0};
+    BatchArgs a{sd_dev_, nullptr, snap_map_, cur, prev, j, xpar, corr, UpdView{}, ocur_, 0, R_, 0.0};
     return a;
   }
   // Whether the update of iteration jj - 1 was a plain one, whose x += alpha d
@@ -140,7 +140,7 @@ class Engine {
   int gather(BatchArgs a, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
   template <typename V>
   int update(BatchArgs a, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
-  int decide(bool inner, int j_end = 0, bool launch_next = false);
+  int decide(bool inner, int j_end = 0, bool launch_next = false, bool wait = true, int slot = 0);
   // The next step's RHS and initial residual launched behind a decide (one
   // simulation): set when they ran, so the next epoch does not launch them.
   bool next_ran_ = false;
@@ -338,16 +338,10 @@ void Engine::fill_simdev(const Sim& s, SimDev& d) const {
     d.iP[k] = h->inner.P[k];
   }
   d.octl = Ctl{s.rq.rtol * s.rq.rtol, opts_.max_iter, opts_.stop_rule};
-  double irt = opts_.inner_rtol;
-  if (s.sweeping) {
-    // Inner tolerance: half the reduction the FP64 stop rule still needs,
-    // never tighter than inner_rtol (FP32 arithmetic bounds what the inner
-    // solve can reach); one sweep then usually suffices.
-    const double ref = opts_.stop_rule == FEM_STOP_INITIAL ? s.so.delta0 : s.so.delta_b;
-    const double need = s.so.delta > 0 ? 0.5 * std::sqrt(d.octl.rtol2 * ref / s.so.delta) : 1.0;
-    irt = std::min(0.5, std::max(opts_.inner_rtol, need));
-  }
-  d.ictl = Ctl{irt * irt, opts_.max_iter, FEM_STOP_INITIAL};
+  // the inner tolerance comes from the settled outer state, in the inner
+  // start kernel (see inner_start_batch_kernel): one sweep then usually suffices
+  d.ictl = Ctl{-1.0, opts_.max_iter, FEM_STOP_INITIAL};
+  d.inner_rtol = opts_.inner_rtol;
   d.N = h->g.N;
   d.nblk[PK_GATHER] = h->shape.nblocks;
   d.nblk[PK_UPD64] = h->upd_blocks64;
@@ -396,11 +390,11 @@ int Engine::compose() {
     for (auto& p : sd_host_) HIP_TRY(hipHostMalloc(reinterpret_cast<void**>(&p), n * sizeof(SimDev), hipHostMallocDefault));
     sd_cap_ = n;
   }
-  if (snap_cap_ < n) {
+  if (snap_cap_ < n) {  // two slots per simulation (see decide)
     if (snap_host_) (void)hipHostFree(snap_host_);
     snap_host_ = snap_map_ = nullptr;
     snap_cap_ = 0;
-    HIP_TRY(hipHostMalloc(reinterpret_cast<void**>(&snap_host_), n * sizeof(Scalars),
+    HIP_TRY(hipHostMalloc(reinterpret_cast<void**>(&snap_host_), 2 * n * sizeof(Scalars),
                           hipHostMallocMapped | hipHostMallocCoherent));
     HIP_TRY(hipHostGetDevicePointer(reinterpret_cast<void**>(&snap_map_), snap_host_, 0));
     snap_cap_ = n;
@@ -510,8 +504,10 @@ int Engine::update(BatchArgs a, hipEvent_t e0, hipEvent_t e1) {
 // settled states into snap_host_ (synchronises the stream).  j_end > 0: the
 // relay's last kernel was the update of iteration j_end - 1 of a PCG chunk,
 // and a solve that finishes here gets that update's deferred x += alpha d.
-// launch_next: see below.
-int Engine::decide(bool inner, int j_end, bool launch_next) {
+// launch_next: see below.  wait = false: the host does not wait (it reads
+// the snapshot after a later decide); slot 1 writes the states to the second
+// snapshot slot (snap_host_[n + q]), which later decides leave alone.
+int Engine::decide(bool inner, int j_end, bool launch_next, bool wait, int slot) {
   fem_heat* h = h_;
   int& cur = inner ? icur_ : ocur_;
   int& prev = inner ? iprev_ : oprev_;
@@ -521,6 +517,7 @@ int Engine::decide(bool inner, int j_end, bool launch_next) {
   // solves, whose update kernel applies x += alpha d itself)
   BatchArgs a = args(cur, prev, jl, replacements_before(jl, R_) & 1,
                      !inner && !fused_ && j_end > 0 && deferred(j_end) ? 1 : 0);
+  if (slot) a.snap += act_.size();
   // a decide that may owe x += alpha d runs over the update kernel's blocks,
   // which then share that work; otherwise one block per simulation settles it
   uint32_t grid;
@@ -563,7 +560,7 @@ int Engine::decide(bool inner, int j_end, bool launch_next) {
     RC_TRY(gather<RoleInitNext>(b));
     ocur_ ^= 1;
   }
-  HIP_TRY(hipEventSynchronize(ev_decide_));
+  if (wait) HIP_TRY(hipEventSynchronize(ev_decide_));
   if (launch_next) {
     const Scalars& t = snap_host_[0];
     next_ran_ = t.done && t.status == 0 && (mixed_ || (replacements_before(t.iter, R_) & 1) == next_xc);
@@ -678,18 +675,27 @@ int Engine::pcg(int first_chunk) {
 // the FP64 stop rule holds or max_refine sweeps are spent.
 int Engine::mixed_sweeps() {
   fem_heat* h = h_;
-  RC_TRY(decide(false));
-  for (size_t q = 0; q < act_.size(); ++q) {
-    Sim& s = *act_[q];
-    s.so = snap_host_[q];
-    if (s.so.status != 0) s.broke = true;
-  }
+  const size_t n = act_.size();
+  // The first sweep does not wait for the decide after the initial residual:
+  // the inner start kernel reads the settled outer state itself (it starts
+  // the inner solve only where that solve is neither done nor broken down,
+  // with the inner tolerance taken from it), and the host reads the state
+  // from the second snapshot slot once the inner solve's first decide is back.
+  const bool early = opts_.max_refine > 0;
+  RC_TRY(decide(false, 0, false, !early, early ? 1 : 0));
+  if (!early)
+    for (size_t q = 0; q < n; ++q) {
+      Sim& s = *act_[q];
+      s.so = snap_host_[q];
+      if (s.so.status != 0) s.broke = true;
+    }
+  bool first = early;
   for (;;) {
     bool any = false;
     int est = 1;
     for (Sim* sp : act_) {
       Sim& s = *sp;
-      s.sweeping = !s.broke && !s.so.done && s.nsw < opts_.max_refine;
+      s.sweeping = !s.broke && (first || !s.so.done) && s.nsw < opts_.max_refine;
       if (s.sweeping) {
         any = true;
         est = std::max(est, s.est_sw[std::min(s.nsw, 3)]);
@@ -704,6 +710,18 @@ int Engine::mixed_sweeps() {
     icur_ ^= 1;
     iprev_ = PK_START;
     RC_TRY(pcg<float>(est));
+    if (first) {  // the outer state the inner start kernel went by
+      first = false;
+      bool swept = false;
+      for (size_t q = 0; q < n; ++q) {
+        Sim& s = *act_[q];
+        s.so = snap_host_[n + q];
+        if (s.so.status != 0) s.broke = true;
+        if (s.so.done || s.broke) s.sweeping = false;  // its inner solve ran idle
+        swept = swept || s.sweeping;
+      }
+      if (!swept) break;
+    }
     for (Sim* sp : act_) {
       Sim& s = *sp;
       if (!s.sweeping) continue;

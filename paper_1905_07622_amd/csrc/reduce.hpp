@@ -136,12 +136,15 @@ __device__ inline void evaluate_pending(Scalars& s, const double* xs, const Ctl&
   const double x = xs[0];
   switch (s.phase) {
     case PH_AFTER_INIT: {  // r0^T P^-1 r0: tolerance and the test before the first iteration
+      // (rtol2 < 0: the squared tolerance came with the state, in tol, from
+      // the kernel that started the solve)
+      const double rt2 = c.rtol2 < 0.0 ? s.tol : c.rtol2;
       s.delta = x;
       s.delta0 = x;
       s.delta_old = x;
       s.beta = 0.0;
       s.iter = 0;
-      s.tol = c.stop_rule == 1 ? c.rtol2 * x : c.rtol2 * s.delta_b;
+      s.tol = c.stop_rule == 1 ? rt2 * x : rt2 * s.delta_b;
       if (!isfinite(x)) {
         s.status = kStatusBreakdown;
         s.done = 1;
@@ -315,6 +318,7 @@ __device__ inline bool stage_finish(const Relay& R, const StageIn& in, Scalars& 
         t.status = 0;
         t.delta_b = 0.0;
         t.zero_rhs = 0;
+        t.tol = R.ctl.rtol2;  // its squared tolerance, for a Ctl that defers it (rtol2 < 0)
         t.phase = PH_AFTER_INIT;
         break;
       case M_DIR:
