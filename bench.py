@@ -203,6 +203,39 @@ def bench_apply_ab(args, torch, p, k, rc, calls=20):
     return res
 
 
+def bench_inverse(args, torch, chains=32, iters=48, n=64):
+    """The paper's motivating use (Section 5.4) through the batched path: Metropolis-Hastings chains over
+    the corrosion depth of the plate stand-in, every proposal a forward solve (mixed form), all chains'
+    proposals of an iteration in one fem_heat_run_batch call.  The observed frame is the FP64 GPU solve at
+    the true depth through the camera model.  Throughput = forward solves / wall time of the sampling."""
+    from paper_1905_07622_amd import femheat as fh
+    from paper_1905_07622_amd import inverse as inv
+    from paper_1905_07622_amd import workloads as wl
+
+    def make(d):
+        return wl.corroded_plate(d, n=n)
+
+    truth = 0.03125
+    f_true = inv.batched_frames(make, precision=fh.FEM_FP64)(np.array([truth]))[0]
+    obs = inv.camera(f_true, wl.camera_noise(21, f_true.size))
+    normals, uniforms = wl.mh_draws(22, iters, chains)
+    ll = inv.likelihood_of(inv.batched_frames(make, precision=fh.FEM_FP32_FP64DOT), obs)
+    t0 = time.perf_counter()
+    out = inv.metropolis(np.linspace(0.01, 0.08, chains), normals, uniforms, 0.004, ll, 0.0, 0.125)
+    secs = time.perf_counter() - t0
+    late = out["samples"][iters // 2:].ravel()
+    p = make(truth)
+    print(f"inverse: {out['evaluated'] / secs:.1f} forward solves/s", file=sys.stderr, flush=True)
+    return {"workload": f"{chains} Metropolis-Hastings chains x {iters} iterations over the corrosion depth of a "
+                        f"{p.nx}x{p.ny}x{p.nz}-element plate ({p.n_nodes} DOF, {p.nsteps} backward-Euler steps, "
+                        f"{p.sensors.shape[0]}-pixel camera, noise 0.1 rounded to 0.1), proposals solved in the "
+                        "mixed form, one batched call per iteration",
+            "forward_solves_per_s": round(out["evaluated"] / secs, 1), "seconds": round(secs, 3),
+            "forward_solves": out["evaluated"], "acceptance": round(float(out["accepted"].mean()), 3),
+            "true_depth": truth, "second_half_mean": round(float(late.mean()), 5),
+            "second_half_std": round(float(late.std()), 5)}
+
+
 def bench_batched(args, torch):
     """Batched proposals: S simulations on 48^3 random-sphere fields, 100
     backward-Euler steps each, in one fem_heat_run_batch call (mixed form),
@@ -335,6 +368,7 @@ def main():
     ap.add_argument("--no-above-mall", action="store_true", help="skip the 201^3-node (DRAM-bound) run")
     ap.add_argument("--no-apply-ab", action="store_true",
                     help="skip the gather vs element-by-element operator comparison")
+    ap.add_argument("--no-inverse", action="store_true", help="skip the coefficient-inverse sampling run")
     ap.add_argument("--mall-n", type=int, default=200)
     ap.add_argument("--mall-nsteps", type=int, default=20)
     ap.add_argument("--batch-sims", type=int, default=64)
@@ -449,6 +483,8 @@ def main():
         extra["above_mall"] = bench_above_mall(args, torch)
     if args.precision == "fp64" and not args.no_apply_ab:
         extra["apply_ab"] = bench_apply_ab(args, torch, p, k, rc)
+    if args.precision == "fp64" and not args.no_inverse:
+        extra["inverse"] = bench_inverse(args, torch)
 
     line = {
         "metric": "PCG MDOF*iter/s at 1M DOF",

@@ -286,3 +286,55 @@ def random_problem(nx, ny, nz, seed, *, hx=None, hy=None, hz=None, theta=1.0, dt
 
 def random_vector(n: int, seed: int) -> np.ndarray:
     return np.random.Generator(np.random.PCG64(seed)).uniform(-1.0, 1.0, n)
+
+
+# ----------------------------------------------------------------------------
+# coefficient-inverse stand-in (Section 5.4): corroded plate, camera, draws
+# ----------------------------------------------------------------------------
+
+PLATE_L = (1.0, 0.5, 0.125)      # plate extent; the front (heated, observed) face is z = 0.125
+CHANNEL_Y, CHANNEL_W = 0.25, 0.15  # corrosion channel: apex line y = 0.25, zero depth at 0.25 +- 0.15
+K_CORRODED = 0.01                # k and rho*c of corroded material (steel: 1)
+
+
+def corroded_plate(depth: float, n: int = 32, nsteps: int = 30, pulse_steps: int = 15, flux: float = 40.0,
+                   camera=(16, 8)) -> Problem:
+    """Stand-in for the paper's corroded plate (its gusset geometry exists only in a missing figure):
+    the plate [0,1] x [0,0.5] x [0,0.125] on n x n/2 x n/8 cubic elements, k = rho*c = 1, corroded from
+    the back face z = 0 along a channel that is constant in x and parabolic in y, penetrating `depth` at
+    its apex (y = 0.25) and nothing at |y - 0.25| >= 0.15.  Corroded material has k = rho*c = 0.01; an
+    element mixes the two by the share of its z-extent below the profile at its centroid, so the
+    coefficients move continuously with depth.  The front face is heated with q = `flux` for the first
+    `pulse_steps` steps (insulated otherwise, like every other face); backward Euler, dt = 1e-3,
+    rtol 1e-8; camera pixels (mx x my) centred on the front face."""
+    nx, ny, nz = n, n // 2, max(1, n // 8)
+    h = PLATE_L[0] / nx
+    cx, cy, cz = element_centroids(nx, ny, nz, h, h, h)
+    prof = depth * np.maximum(0.0, 1.0 - ((cy - CHANNEL_Y) / CHANNEL_W) ** 2)
+    frac = np.clip((prof - (cz - 0.5 * h)) / h, 0.0, 1.0)
+    k = (1.0 - frac) * 1.0 + frac * K_CORRODED
+    flux_v = np.zeros(6)
+    flux_v[FACE_ZP] = flux
+    sched = np.zeros(nsteps)
+    sched[:pulse_steps] = 1.0
+    mx, my = camera
+    j, i = np.meshgrid(np.arange(my), np.arange(mx), indexing="ij")
+    cam = np.stack([((i + 0.5) / mx * PLATE_L[0]).ravel(), ((j + 0.5) / my * PLATE_L[1]).ravel(),
+                    np.full(mx * my, nz * h)], axis=1)
+    return Problem(name=f"plate{nx}x{ny}x{nz}_d{depth:.4f}", nx=nx, ny=ny, nz=nz, hx=h, hy=h, hz=h,
+                   k_e=k.ravel().astype(np.float64), rhoc_e=k.ravel().astype(np.float64).copy(),
+                   T0=np.zeros((nx + 1) * (ny + 1) * (nz + 1)), dt=1e-3, theta=1.0, nsteps=nsteps,
+                   rtol=1e-8, flux_mask=face_bit(FACE_ZP), flux=flux_v, flux_schedule=sched,
+                   sensors=np.ascontiguousarray(cam, dtype=np.float64))
+
+
+def mh_draws(seed: int, n_iter: int, n_chains: int):
+    """Random numbers of n_chains Metropolis-Hastings chains over n_iter iterations: standard normals for
+    the random-walk proposals and U[0,1) for the acceptance tests, each (n_iter, n_chains)."""
+    g1, g2 = _streams(seed, 2)
+    return g1.standard_normal((n_iter, n_chains)), g2.uniform(0.0, 1.0, (n_iter, n_chains))
+
+
+def camera_noise(seed: int, n_pixels: int) -> np.ndarray:
+    """Standard normal draws for the camera's per-pixel noise."""
+    return np.random.Generator(np.random.PCG64(seed)).standard_normal(n_pixels)
