@@ -113,7 +113,10 @@ struct AdvancesResidual {
 // One block's share of a gather: tile `logical` of the solve that `ga`, the
 // functors and the relay describe.  The block's dot-product partial is
 // stored at index `logical`, and tile 0 publishes the relayed state.
-template <typename V, bool CUBIC, class Pro, class Epi, bool kFour = AdvancesResidual<Pro>::value>
+// kD: prefetch depth in layers.  The one-reduction direction kernel stages a fourth vector and keeps
+// four accumulators; with one layer of prefetch it fits 164 VGPRs instead of 256 with a spill.
+template <typename V, bool CUBIC, class Pro, class Epi, bool kFour = AdvancesResidual<Pro>::value,
+          int kD = (AdvancesResidual<Pro>::value ? 1 : kDepth)>
 __device__ inline void gather_tile(const GatherArgs<V>& ga, Pro pro, Epi epi, const Relay& R, uint32_t logical) {
   const StageIn in = stage_load<sizeof(V) == 8>(R);
   if (stage_idle(R, in, logical == 0)) return;  // uniform: a finished solve
@@ -315,7 +318,7 @@ __device__ inline void gather_tile(const GatherArgs<V>& ga, Pro pro, Epi epi, co
       store(S, lay(k), buf);
       const V xo_k = S.xo, dold_k = S.dold;  // node vis(k), fetched with this stage
       __syncthreads();
-      fetch(S, vis(min(k + 1 + kDepth, n)), lay(min(k + kDepth, n - 1)), vis(min(k + kDepth, n)));
+      fetch(S, vis(min(k + 1 + kD, n)), lay(min(k + kD, n - 1)), vis(min(k + kD, n)));
       read_plane(plane + buf * PW * PH, PW, ltx, lty, hi);
       if constexpr (FU) {  // the new plane's centre: this column's node vis(k+1)
         const int c = (lty + 1) * PW + ltx + 1;
@@ -360,7 +363,7 @@ __device__ inline void gather_tile(const GatherArgs<V>& ga, Pro pro, Epi epi, co
       Stage S0;
       fetch(S0, vis(0), lay(0), vis(0));
       fetch(SB, vis(1), lay(0), vis(0));
-      if constexpr (kDepth == 2) fetch(SA, vis(min(2, n)), lay(min(1, n - 1)), vis(1));
+      if constexpr (kD == 2) fetch(SA, vis(min(2, n)), lay(min(1, n - 1)), vis(1));
       if (!stage_finish<kFour>(R, in, st, logical == 0)) {  // uniform
         if constexpr (XI) {
           // the solve finished in this kernel's evaluation: the last
@@ -389,7 +392,7 @@ __device__ inline void gather_tile(const GatherArgs<V>& ga, Pro pro, Epi epi, co
     using no = std::integral_constant<bool, false>;
     using yes = std::integral_constant<bool, true>;
     layer(0, 1, SB, no{});  // node vis(0) belongs to the neighbouring chunk
-    if constexpr (kDepth == 2) {
+    if constexpr (kD == 2) {
       int k = 1;
       for (; k + 1 < n; k += 2) {  // two register sets alternate: indices stay compile-time
         layer(k, 0, SA, yes{});
