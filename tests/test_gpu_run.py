@@ -168,6 +168,19 @@ def test_full_size_lognormal_first_steps(gpu):
     assert err <= 1e-10
 
 
+def test_above_cache_size_first_steps(gpu):
+    """The largest grid the benchmark runs: the log-normal workload at 201^3
+    nodes (8,120,601 DOF, beyond the 256 MB Infinity Cache), first 2 steps
+    against the iteration-locked oracle, in the benchmark's launch shape."""
+    say("run 201^3 lognormal, 2 steps")
+    p = wl.lognormal_cube(200, seed=2, nsteps=2)
+    out, ref = run_both(p, nsteps=2, oracle_kw=dict(nthreads=16))
+    assert out["status"] == 0 and ref["status"] == 0
+    err = rel_l2(out["T_final"], ref["T_final"])
+    say(f"  iters {list(out['iters'])}, rel L2 {err:.3e}")
+    assert err <= 1e-10
+
+
 def test_timing_changes_nothing_and_samples(gpu):
     """FEM_TIMING records events around a sample of the iterations; the
     results are bit-identical to an untimed run."""
