@@ -468,7 +468,12 @@ def main():
                 "traffic": committed_traffic(dom, args.precision, args.pcg_form),
                 "bytes_per_launch": int(round(ab[dom])), "avg_launch_us": round(per[dom] * 1e3, 3),
                 "deferred_update_share": round(f_corr, 4),
-                "other_kernels_us": {kname: round(v * 1e3, 3) for kname, v in per.items() if kname != dom}}
+                "other_kernels_us": {kname: round(v * 1e3, 3) for kname, v in per.items() if kname != dom},
+                # the other iteration kernels on the same footing (algorithmic bytes / event-timed launch)
+                "other_kernels": {kname: {"achieved": round(ab[kname] / (v * 1e-3) / 1e9, 1),
+                                          "frac": round(ab[kname] / (v * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                                          "bytes_per_launch": int(round(ab[kname]))}
+                                  for kname, v in per.items() if kname != dom and ab.get(kname)}}
 
     per_iter = algorithmic_bytes(p.n_nodes, p.n_elems, w, f_corr, one_red)
     iter_bytes = per_iter["gather"] + per_iter["update"]
