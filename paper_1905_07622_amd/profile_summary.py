@@ -148,6 +148,53 @@ def traffic(fetch_dir, write_dir, copy_fetch_dir, copy_write_dir, out_txt, out_j
         print("wrote", out_json)
 
 
+def counters(dirs, out, kernel_regex, commands):
+    """Means of the SQ counters of one kernel over its working dispatches (per pass: those whose first
+    present reference counter, SQ_WAVE_CYCLES or SQ_INSTS_VALU, is at least 25% of its largest value),
+    with the ratios of same-unit counters: wait shares of the wave cycles, LDS bank-conflict share of the
+    LDS-active cycles, and instructions per wave."""
+    means = {}
+    for d in dirs:
+        rows = list(csv.DictReader(open(find_csv(d, "counter_collection.csv"))))
+        disp = defaultdict(dict)
+        for r in rows:
+            k = short_name(r["Kernel_Name"])
+            if re.search(kernel_regex, k):
+                disp[r.get("Dispatch_Id") or r["Correlation_Id"]][r["Counter_Name"]] = float(r["Counter_Value"])
+        if not disp:
+            continue
+        ref = next((c for c in ("SQ_WAVE_CYCLES", "SQ_INSTS_VALU") if c in next(iter(disp.values()))), None)
+        vals = list(disp.values())
+        if ref:
+            top = max(v.get(ref, 0.0) for v in vals)
+            vals = [v for v in vals if v.get(ref, 0.0) >= 0.25 * top] or vals
+        for c in vals[0]:
+            means[c] = (sum(v.get(c, 0.0) for v in vals) / len(vals), len(vals))
+    lines = [f"# rocprofv3 SQ counters of {kernel_regex!r}: means over working dispatches", ""]
+    lines += [f"command: {c}" for c in commands]
+    lines += ["", f"{'counter':28s} {'mean':>16s} {'dispatches':>10s}"]
+    lines += [f"{c:28s} {v:16.1f} {n:10d}" for c, (v, n) in sorted(means.items())]
+
+    def m(c):
+        return means.get(c, (None, 0))[0]
+
+    ratios = [("wait (any) / wave cycles", "SQ_WAIT_ANY", "SQ_WAVE_CYCLES"),
+              ("wait (instruction) / wave cycles", "SQ_WAIT_INST_ANY", "SQ_WAVE_CYCLES"),
+              ("wait (LDS) / wave cycles", "SQ_WAIT_INST_LDS", "SQ_WAVE_CYCLES"),
+              ("LDS bank conflict / LDS active", "SQ_LDS_BANK_CONFLICT", "SQ_ACTIVE_INST_LDS"),
+              ("VALU instructions / wave", "SQ_INSTS_VALU", "SQ_WAVES"),
+              ("vector-memory reads / wave", "SQ_INSTS_VMEM_RD", "SQ_WAVES"),
+              ("vector-memory writes / wave", "SQ_INSTS_VMEM_WR", "SQ_WAVES"),
+              ("LDS instructions / wave", "SQ_INSTS_LDS", "SQ_WAVES")]
+    lines += [""]
+    for label, a, b in ratios:
+        if m(a) is not None and m(b):
+            lines.append(f"{label:36s} {m(a) / m(b):10.3f}")
+    with open(out, "w") as f:
+        f.write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+
+
 def main():
     ap = argparse.ArgumentParser()
     sub = ap.add_subparsers(dest="cmd", required=True)
@@ -161,9 +208,16 @@ def main():
     b.add_argument("--kernel-regex", required=True)
     b.add_argument("--command", action="append", default=[])
     b.add_argument("--algorithmic-bytes", type=float, default=None)
+    c = sub.add_parser("counters")
+    c.add_argument("out")
+    c.add_argument("dirs", nargs="+")
+    c.add_argument("--kernel-regex", required=True)
+    c.add_argument("--command", action="append", default=[])
     args = ap.parse_args()
     if args.cmd == "stats":
         stats(args.dir, args.out, args.command)
+    elif args.cmd == "counters":
+        counters(args.dirs, args.out, args.kernel_regex, args.command)
     else:
         traffic(args.fetch_dir, args.write_dir, args.copy_fetch_dir, args.copy_write_dir, args.out_txt,
                 args.out_json, args.kernel_regex, args.command, args.algorithmic_bytes)
