@@ -236,6 +236,33 @@ def bench_inverse(args, torch, chains=32, iters=48, n=64):
             "second_half_std": round(float(late.std()), 5)}
 
 
+def bench_context(torch, gather_bytes):
+    """Reference points for the kernel figures, measured with torch on the same GPU: a device copy moving the
+    gather's bytes (half read, half written), and the rate of a 256 MiB copy."""
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+
+    def copy_us(nbytes, reps=20):
+        src = torch.empty(nbytes // 16, dtype=torch.float64, device="cuda").fill_(1.0)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(reps):
+            dst.copy_(src)
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) * 1e3 / reps
+
+    g_us = copy_us(int(gather_bytes))
+    big = 2 * 256 * 1024 * 1024
+    b_us = copy_us(big, reps=5)
+    return {"copy_of_gather_bytes_us": round(g_us, 2),
+            "copy_of_gather_bytes_gbs": round(gather_bytes / g_us / 1e3, 1),
+            "copy_256MiB_gbs": round(big / b_us / 1e3, 1),
+            "note": "torch device copies on the same GPU, (read + write bytes) / time between events"}
+
+
 def bench_batched(args, torch):
     """Batched proposals: S simulations on 48^3 random-sphere fields, 100
     backward-Euler steps each, in one fem_heat_run_batch call (mixed form),
@@ -490,6 +517,8 @@ def main():
         extra["apply_ab"] = bench_apply_ab(args, torch, p, k, rc)
     if args.precision == "fp64" and not args.no_inverse:
         extra["inverse"] = bench_inverse(args, torch)
+    if args.precision == "fp64" and not args.no_apply_ab:
+        extra["context"] = bench_context(torch, per_iter["gather"])
 
     line = {
         "metric": "PCG MDOF*iter/s at 1M DOF",
