@@ -34,6 +34,7 @@
 #ifndef FEM_HEAT_H
 #define FEM_HEAT_H
 
+#include <stddef.h>
 #include <stdint.h>
 
 #ifdef __cplusplus
@@ -118,6 +119,22 @@ typedef struct {
   int32_t n_schedule;
 } fem_bc;
 
+/* Device memory of a handle (or of a server's simulations) through the
+ * caller's allocator.  alloc returns 0 and sets *ptr to `bytes` of device
+ * memory on the handle's device, usable by work enqueued on `stream` after
+ * the call (stream-ordered); release hands back a block once the work
+ * enqueued on `stream` before the call is done with it.  The library calls
+ * them from the thread that uses the handle (a server: from its worker
+ * threads, one stream per thread), never concurrently for one stream.  With
+ * no allocator, handles use hipMalloc / hipFree; a server uses its own
+ * stream-ordered memory pool, so retiring a simulation never synchronises
+ * the device. */
+typedef struct {
+  void *ctx;
+  int (*alloc)(void *ctx, void **ptr, size_t bytes, void *stream);
+  void (*release)(void *ctx, void *ptr, void *stream);
+} fem_allocator;
+
 typedef struct {
   int32_t precision;      /* FEM_FP64 | FEM_FP32_FP64DOT                          */
   int32_t max_iter;       /* i_max of Algorithm 1 (per step; inner per sweep in mixed form); default 10000 */
@@ -130,7 +147,16 @@ typedef struct {
   uint32_t flags;         /* FEM_DEVICE_PTRS | FEM_TIMING                          */
   void *hip_stream;       /* hipStream_t to run on; NULL = the library's own stream */
   int32_t device;         /* HIP device ordinal                                    */
-  int32_t tile_x, tile_y, tile_z; /* gather tile overrides; 0 = automatic         */
+  int32_t tile_x, tile_y, tile_z; /* gather tile overrides; 0 = automatic.  tile_x <= 256,
+                             tile_x*tile_y <= 256, and the (tile_x+2)*(tile_y+2) plane tile must
+                             fit two staging slots per thread: FEM_EINVAL otherwise            */
+  const fem_allocator *allocator; /* device memory (NULL: see fem_allocator); must outlive
+                             every handle and server created with these options          */
+  const char *tune_cache; /* path of the autotuner's tile cache (JSON), or NULL.  When set and no
+                             tile override is given, a handle takes the gather tile recorded
+                             there for its node grid, precision, element class and launch kind
+                             (alone or batch member) on this GPU architecture and HIP runtime;
+                             fem_heat_tune records into it.  Results do not depend on the tile. */
 } fem_opts;
 
 /* Outputs of a run (inputs marked "in").  Every pointer may be NULL.
@@ -299,6 +325,33 @@ int fem_server_info_get(fem_server *s, fem_server_info *info);
 
 /* Cancel everything outstanding, stop the worker and release the server. */
 void fem_server_destroy(fem_server *s);
+
+/* Autotuner (the project's own; the paper tunes nothing).  Times the
+ * hot gather of the PCG iteration -- search-direction update fused with the
+ * operator apply q = A d and the previous iteration's x += alpha d, in the
+ * handle's precision (FP32 for the mixed form) -- on this handle's grid and
+ * coefficients for a set of candidate tiles (x pieces of the node row, block
+ * heights, z-chunk lengths for 1 to 4 resident blocks per CU), each with
+ * device events over repeated launches, and installs the fastest on the
+ * handle.  With FEM_TUNE_BATCH the candidates and the timing are those of a
+ * batch member: chunks of 8 to 32 planes, timed with enough copies of the
+ * simulation in one launch to fill the device, per simulation.  When the
+ * handle's options name a tune_cache, the result is recorded there under
+ * the key of this grid, precision, element class and launch kind, and later
+ * handles (fem_heat_create, fem_heat_run_batch, servers) with the same
+ * options take it.  Results of a run do not depend on the tile (the gather's
+ * sums are formed in a fixed order).  The handle's vectors are overwritten:
+ * tune before a run, not between the two halves of a resumed run.  out may
+ * be NULL. */
+#define FEM_TUNE_BATCH 0x1
+typedef struct {
+  int32_t tile_x, tile_y, tile_z; /* installed tile                                         */
+  int32_t candidates;             /* tiles timed                                            */
+  double best_us;                 /* its time per launch (per simulation with FEM_TUNE_BATCH) */
+  double rule_us;                 /* the same for the tile the handle had before            */
+  int32_t recorded;               /* 1: written to the tune_cache                           */
+} fem_tune_result;
+int fem_heat_tune(fem_heat *h, double dt, double theta, uint32_t flags, fem_tune_result *out);
 
 /* Kernel timing and launch shape of the last run (FEM_TIMING). */
 int fem_heat_stats(const fem_heat *h, fem_stats *out);

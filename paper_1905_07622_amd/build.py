@@ -17,7 +17,7 @@ BUILD = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libfemheat.so")
 INCLUDE = os.path.join(ROOT, "include")
 
-SOURCES = ["solver.hip", "engine.hip", "server.cpp", "capi.cpp"]
+SOURCES = ["solver.hip", "engine.hip", "server.cpp", "capi.cpp", "tune_cache.cpp"]
 ARCH = "gfx950"
 
 

@@ -10,6 +10,7 @@
 #include <string>
 #include <vector>
 
+#include "engine.hpp"
 #include "server.hpp"
 #include "solver.hpp"
 
@@ -43,6 +44,17 @@ int check_opts(const fem_opts* opts, fem_opts& o, std::string& why) {
   if (o.precision == FEM_FP32_FP64DOT && !finite_pos(o.inner_rtol)) return bad("inner_rtol must be > 0");
   if (o.tile_x < 0 || o.tile_y < 0 || o.tile_z < 0 || o.tile_x > 256 || o.tile_x * std::max(o.tile_y, 1) > 256)
     return bad("tile overrides out of range");
+  // each thread of a gather block stages two entries of the (tx+2) x (ty+2)
+  // plane tile and of the (tx+1) x (ty+1) coefficient tile; with tile_x given
+  // and tile_y automatic, tile_y can shrink to 1, so that case must fit
+  if (o.tile_x > 0) {
+    const int tx = o.tile_x, ty = std::max(o.tile_y, 1);
+    const int nthreads = ((tx * ty + 63) / 64) * 64;
+    if ((tx + 2) * (ty + 2) > 2 * nthreads || (tx + 1) * (ty + 1) > 2 * nthreads)
+      return bad("tile overrides too thin: the gather stages two plane entries per thread");
+  } else if (o.tile_y > 0) {
+    return bad("tile_y needs tile_x");
+  }
   return FEM_OK;
 }
 
@@ -286,6 +298,24 @@ int fem_heat_apply(fem_heat* h, int32_t which, double dt, double theta, const do
   }
   try {
     return femheat::solver_apply(h, which, dt, theta, x, y);
+  } catch (...) {
+    h->err = "unexpected exception";
+    return FEM_EDEVICE;
+  }
+}
+
+int fem_heat_tune(fem_heat* h, double dt, double theta, uint32_t flags, fem_tune_result* out) {
+  if (!h) return FEM_EINVAL;
+  h->err.clear();
+  if (!finite_pos(dt) || !(theta >= 0.0 && theta <= 1.0) || (flags & ~(uint32_t)FEM_TUNE_BATCH)) {
+    h->err = "dt must be > 0, theta in [0, 1], flags FEM_TUNE_BATCH or 0";
+    return FEM_EINVAL;
+  }
+  try {
+    return femheat::engine_tune(h, dt, theta, flags, out);
+  } catch (const std::bad_alloc&) {
+    h->err = "host allocation failed";
+    return FEM_ENOMEM;
   } catch (...) {
     h->err = "unexpected exception";
     return FEM_EDEVICE;

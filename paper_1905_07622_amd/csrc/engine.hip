@@ -39,6 +39,7 @@
 #include "batch.hpp"
 #include "engine.hpp"
 #include "runtime.hpp"
+#include "tune.hpp"
 
 namespace femheat {
 namespace {
@@ -88,6 +89,15 @@ struct Group {
   size_t smem64 = 0, smem32 = 0, smem64f = 0;  // smem64f: one-reduction direction kernel (three planes)
 };
 
+// Work-table layout of a batched launch: where each kernel kind's entries
+// start in the table and how many there are.
+struct Layout {
+  Group groups[2];
+  int ngroups = 0;
+  uint32_t off_upd64 = 0, n_upd64 = 0, off_upd32 = 0, n_upd32 = 0, off_start = 0, n_start = 0, off_one = 0,
+           n_one = 0;
+};
+
 }  // namespace
 
 class Engine {
@@ -100,8 +110,8 @@ class Engine {
   }
   ~Engine() {
     (void)hipStreamSynchronize(stream_);
-    dfree(sd_dev_);
-    dfree(tab_dev_);
+    efree(sd_dev_);
+    efree(tab_dev_);
     for (auto& p : sd_host_)
       if (p) (void)hipHostFree(p);
     if (snap_host_) (void)hipHostFree(snap_host_);
@@ -116,6 +126,23 @@ class Engine {
   }
 
   int add(const RunRequest& r, Sim** out = nullptr);
+  int tune(fem_heat* h, double dt, double theta, bool batch, fem_tune_result* out);
+  // The engine's own device buffers, on its stream and through its allocator.
+  template <typename T>
+  int ealloc(T** p, size_t n) {
+    void* v = nullptr;
+    if (!dev_alloc(opts_.allocator, stream_, &v, std::max<size_t>(n, 1) * sizeof(T))) {
+      *p = nullptr;
+      return fail(h_, FEM_ENOMEM, "device allocation of the engine's tables failed");
+    }
+    *p = static_cast<T*>(v);
+    return FEM_OK;
+  }
+  template <typename T>
+  void efree(T*& p) {
+    dev_free(opts_.allocator, stream_, p);
+    p = nullptr;
+  }
   int run();
   int step(int* active);
   int write_outputs(Sim& s, float ms);
@@ -189,9 +216,21 @@ class Engine {
   uint2* tab_host_ = nullptr;
   size_t tab_cap_ = 0;
 
-  Group groups_[2];
-  int ngroups_ = 0;
-  uint32_t off_upd64_ = 0, n_upd64_ = 0, off_upd32_ = 0, n_upd32_ = 0, off_start_ = 0, n_start_ = 0, off_one_ = 0;
+  // The table of the epoch (region 0 of tab_dev_) and, within a PCG solve of
+  // a batch, compactions of it that leave out the simulations whose solve is
+  // done (regions 1 and 2, used alternately): a lockstep batch then stops
+  // launching blocks for members that only wait for the slowest one.
+  Layout full_, lay_;
+  const uint2* tab_cur_ = nullptr;
+  int ctab_flip_ = 0;
+  size_t live_count_ = 0;
+  void build_layout(const std::vector<char>& live, std::vector<uint2>& tab, Layout& L) const;
+  int compact(const std::vector<char>& live);
+  void uncompact() {
+    lay_ = full_;
+    tab_cur_ = tab_dev_;
+    live_count_ = act_.size();
+  }
 
   // relay parity and the kind of partials the next kernel reads, per relay
   int ocur_ = 0, oprev_ = PK_GATHER, icur_ = 0, iprev_ = PK_GATHER;
@@ -267,14 +306,14 @@ int Engine::add(const RunRequest& r, Sim** out) {
   s.nsens = (o && o->sensor_xyz && o->n_sensors > 0) ? o->n_sensors : 0;
   if (s.nsens > 0) {
     if (h->xyz_cap < (size_t)s.nsens) {
-      dfree(h->xyz_dev);
+      dfree(h, h->xyz_dev);
       RC_TRY(dalloc(h, &h->xyz_dev, 3 * (size_t)s.nsens));
       h->xyz_cap = s.nsens;
     }
     RC_TRY(copy_in(h, h->xyz_dev, o->sensor_xyz, 3 * (size_t)s.nsens));
     const size_t need = (size_t)std::max(r.nsteps, 1) * s.nsens;
     if (h->traces_cap < need) {
-      dfree(h->traces_dev);
+      dfree(h, h->traces_dev);
       RC_TRY(dalloc(h, &h->traces_dev, need));
       h->traces_cap = need;
     }
@@ -374,34 +413,66 @@ int Engine::compose() {
   std::vector<Sim*> next;
   for (auto& sp : sims_)
     if (!sp->finished) next.push_back(sp.get());
-  if (!dirty_ && next == act_ && ngroups_ > 0) return FEM_OK;
+  if (!dirty_ && next == act_ && full_.ngroups > 0) return FEM_OK;
   dirty_ = false;
   HIP_TRY(hipStreamSynchronize(stream_));  // buffers below may be freed or rewritten
   act_ = next;
   const size_t n = act_.size();
   if (n == 0) return FEM_OK;
   multi_ = n > 1;
+  // capacities grow geometrically: freeing pinned host memory synchronises
+  // the whole device (every stream, other servers' lanes included)
+  auto grow = [](size_t cap, size_t need) { return std::max<size_t>({need, 2 * cap, 16}); };
   if (sd_cap_ < n) {
-    dfree(sd_dev_);
+    const size_t cap = grow(sd_cap_, n);
+    efree(sd_dev_);
     for (auto& p : sd_host_)
       if (p) (void)hipHostFree(p);
     sd_host_[0] = sd_host_[1] = nullptr;
-    RC_TRY(dalloc(h, &sd_dev_, n));
-    for (auto& p : sd_host_) HIP_TRY(hipHostMalloc(reinterpret_cast<void**>(&p), n * sizeof(SimDev), hipHostMallocDefault));
-    sd_cap_ = n;
+    sd_cap_ = 0;
+    RC_TRY(ealloc(&sd_dev_, cap));
+    for (auto& p : sd_host_) HIP_TRY(hipHostMalloc(reinterpret_cast<void**>(&p), cap * sizeof(SimDev), hipHostMallocDefault));
+    sd_cap_ = cap;
   }
   if (snap_cap_ < n) {  // two slots per simulation (see decide)
+    const size_t cap = grow(snap_cap_, n);
     if (snap_host_) (void)hipHostFree(snap_host_);
     snap_host_ = snap_map_ = nullptr;
     snap_cap_ = 0;
-    HIP_TRY(hipHostMalloc(reinterpret_cast<void**>(&snap_host_), 2 * n * sizeof(Scalars),
+    HIP_TRY(hipHostMalloc(reinterpret_cast<void**>(&snap_host_), 2 * cap * sizeof(Scalars),
                           hipHostMallocMapped | hipHostMallocCoherent));
     HIP_TRY(hipHostGetDevicePointer(reinterpret_cast<void**>(&snap_map_), snap_host_, 0));
-    snap_cap_ = n;
+    snap_cap_ = cap;
   }
-  // launch groups by element class, each with its work table
-  ngroups_ = 0;
   std::vector<uint2> tab;
+  build_layout(std::vector<char>(n, 1), tab, full_);
+  lay_ = full_;
+  live_count_ = n;
+  if (multi_) {
+    // region 0: this table; regions 1 and 2: compactions (at most as long)
+    if (tab_cap_ < tab.size()) {
+      const size_t cap = grow(tab_cap_, tab.size());
+      efree(tab_dev_);
+      if (tab_host_) (void)hipHostFree(tab_host_);
+      tab_host_ = nullptr;
+      tab_cap_ = 0;
+      RC_TRY(ealloc(&tab_dev_, 3 * cap));
+      HIP_TRY(hipHostMalloc(reinterpret_cast<void**>(&tab_host_), 3 * cap * sizeof(uint2), hipHostMallocDefault));
+      tab_cap_ = cap;
+    }
+    std::memcpy(tab_host_, tab.data(), tab.size() * sizeof(uint2));
+    HIP_TRY(hipMemcpyAsync(tab_dev_, tab_host_, tab.size() * sizeof(uint2), hipMemcpyHostToDevice, stream_));
+  }
+  tab_cur_ = tab_dev_;
+  return FEM_OK;
+}
+
+// Launch groups by element class and the entries of every kernel kind, for
+// the simulations of the epoch marked live (table entries name a simulation
+// by its index in the epoch, so a compaction keeps the SimDev array).
+void Engine::build_layout(const std::vector<char>& live, std::vector<uint2>& tab, Layout& L) const {
+  const size_t n = act_.size();
+  L = Layout{};
   for (int cls = 0; cls < 2; ++cls) {
     Group g;
     g.cubic = cls == 0;
@@ -409,53 +480,71 @@ int Engine::compose() {
     for (size_t k = 0; k < n; ++k) {
       const fem_heat* sh = act_[k]->rq.h;
       if (sh->cubic != g.cubic) continue;
-      for (uint32_t b = 0; b < sh->shape.nblocks; ++b) tab.push_back(make_uint2((uint32_t)k, b));
+      // launch parameters from every member of the class, live or not, so a
+      // compaction launches the same block shape and LDS size
       g.nthreads = std::max<uint32_t>(g.nthreads, (uint32_t)sh->shape.nthreads);
       g.smem64 = std::max(g.smem64, sh->shape.smem_bytes(8));
       g.smem32 = std::max(g.smem32, sh->shape.smem_bytes(4));
       g.smem64f = std::max(g.smem64f, sh->shape.smem_bytes(8, 3));
+      if (!live[k]) continue;
+      for (uint32_t b = 0; b < sh->shape.nblocks; ++b) tab.push_back(make_uint2((uint32_t)k, b));
     }
     g.nwork = (uint32_t)tab.size() - g.off;
-    if (g.nwork > 0) groups_[ngroups_++] = g;
+    if (g.nwork > 0) L.groups[L.ngroups++] = g;
   }
   auto add_kind = [&](uint32_t fem_heat::*count, uint32_t& off, uint32_t& total) {
     off = (uint32_t)tab.size();
     for (size_t k = 0; k < n; ++k) {
+      if (!live[k]) continue;
       const fem_heat* sh = act_[k]->rq.h;
       for (uint32_t b = 0; b < sh->*count; ++b) tab.push_back(make_uint2((uint32_t)k, b));
     }
     total = (uint32_t)tab.size() - off;
   };
-  add_kind(&fem_heat::upd_blocks64, off_upd64_, n_upd64_);
-  add_kind(&fem_heat::upd_blocks32, off_upd32_, n_upd32_);
-  add_kind(&fem_heat::start_blocks, off_start_, n_start_);
-  off_one_ = (uint32_t)tab.size();  // one block per simulation (decides that owe no x += alpha d)
-  for (size_t k = 0; k < n; ++k) tab.push_back(make_uint2((uint32_t)k, 0u));
-  if (multi_) {
-    if (tab_cap_ < tab.size()) {
-      dfree(tab_dev_);
-      if (tab_host_) (void)hipHostFree(tab_host_);
-      tab_host_ = nullptr;
-      RC_TRY(dalloc(h, &tab_dev_, tab.size()));
-      HIP_TRY(hipHostMalloc(reinterpret_cast<void**>(&tab_host_), tab.size() * sizeof(uint2), hipHostMallocDefault));
-      tab_cap_ = tab.size();
-    }
-    std::memcpy(tab_host_, tab.data(), tab.size() * sizeof(uint2));
-    HIP_TRY(hipMemcpyAsync(tab_dev_, tab_host_, tab.size() * sizeof(uint2), hipMemcpyHostToDevice, stream_));
-  }
+  add_kind(&fem_heat::upd_blocks64, L.off_upd64, L.n_upd64);
+  add_kind(&fem_heat::upd_blocks32, L.off_upd32, L.n_upd32);
+  add_kind(&fem_heat::start_blocks, L.off_start, L.n_start);
+  L.off_one = (uint32_t)tab.size();  // one block per simulation (decides that owe no x += alpha d)
+  for (size_t k = 0; k < n; ++k)
+    if (live[k]) tab.push_back(make_uint2((uint32_t)k, 0u));
+  L.n_one = (uint32_t)tab.size() - L.off_one;
+}
+
+// Launches from here on serve only the live simulations.  The others' relay
+// state is left as their last kernel wrote it: they take no part until the
+// layout is restored, and the next kernel that does serve them starts a new
+// solve (the right-hand side of a step, the start of an inner solve, a
+// refinement correction), which resets what it reads.  Their settled state
+// stays in the host snapshot, which later decides do not rewrite.
+int Engine::compact(const std::vector<char>& live) {
+  fem_heat* h = h_;
+  std::vector<uint2> tab;
+  Layout L;
+  build_layout(live, tab, L);
+  ctab_flip_ ^= 1;
+  const size_t region = (size_t)(1 + ctab_flip_) * tab_cap_;
+  // the staging region was last copied two compactions ago, before a decide
+  // the host has waited for since
+  std::memcpy(tab_host_ + region, tab.data(), tab.size() * sizeof(uint2));
+  HIP_TRY(hipMemcpyAsync(tab_dev_ + region, tab_host_ + region, tab.size() * sizeof(uint2), hipMemcpyHostToDevice,
+                         stream_));
+  lay_ = L;
+  tab_cur_ = tab_dev_ + region;
+  live_count_ = 0;
+  for (char c : live) live_count_ += c ? 1 : 0;
   return FEM_OK;
 }
 
 template <class Role>
 int Engine::gather(BatchArgs a, hipEvent_t e0, hipEvent_t e1) {
   fem_heat* h = h_;
-  for (int gi = 0; gi < ngroups_; ++gi) {
-    const Group& g = groups_[gi];
-    a.table = multi_ ? tab_dev_ + g.off : nullptr;
+  for (int gi = 0; gi < lay_.ngroups; ++gi) {
+    const Group& g = lay_.groups[gi];
+    a.table = multi_ ? tab_cur_ + g.off : nullptr;
     const size_t smem = std::is_same<Role, RoleFused>::value ? g.smem64f
                         : sizeof(typename Role::V) == 8        ? g.smem64
                                                                : g.smem32;
-    hipEvent_t s0 = gi == 0 ? e0 : nullptr, s1 = gi == ngroups_ - 1 ? e1 : nullptr;
+    hipEvent_t s0 = gi == 0 ? e0 : nullptr, s1 = gi == lay_.ngroups - 1 ? e1 : nullptr;
     if (g.cubic)
       hipExtLaunchKernelGGL((gather_batch_kernel<true, Role>), dim3(g.nwork), dim3(g.nthreads), smem, stream_, s0, s1,
                             0, a);
@@ -471,8 +560,8 @@ template <typename V>
 int Engine::update(BatchArgs a, hipEvent_t e0, hipEvent_t e1) {
   fem_heat* h = h_;
   const bool f64 = sizeof(V) == 8;
-  a.table = multi_ ? tab_dev_ + (f64 ? off_upd64_ : off_upd32_) : nullptr;
-  const dim3 grid(f64 ? n_upd64_ : n_upd32_);
+  a.table = multi_ ? tab_cur_ + (f64 ? lay_.off_upd64 : lay_.off_upd32) : nullptr;
+  const dim3 grid(f64 ? lay_.n_upd64 : lay_.n_upd32);
   if (multi_) {
     hipExtLaunchKernelGGL((update_batch_kernel<V, false>), grid, dim3(kT), 0, stream_, e0, e1, 0, a);
   } else {  // the same vectors and relay as the SimDev would give (outer_relay, inner_relay)
@@ -522,11 +611,11 @@ int Engine::decide(bool inner, int j_end, bool launch_next, bool wait, int slot)
   // which then share that work; otherwise one block per simulation settles it
   uint32_t grid;
   if (a.corr) {
-    a.table = multi_ ? tab_dev_ + (inner ? off_upd32_ : off_upd64_) : nullptr;
-    grid = inner ? n_upd32_ : n_upd64_;
+    a.table = multi_ ? tab_cur_ + (inner ? lay_.off_upd32 : lay_.off_upd64) : nullptr;
+    grid = inner ? lay_.n_upd32 : lay_.n_upd64;
   } else {
-    a.table = multi_ ? tab_dev_ + off_one_ : nullptr;
-    grid = (uint32_t)act_.size();
+    a.table = multi_ ? tab_cur_ + lay_.off_one : nullptr;
+    grid = lay_.n_one;
   }
   if (inner)
     hipLaunchKernelGGL((decide_batch_kernel<float, false>), dim3(grid), dim3(kT), 0, stream_, a);
@@ -663,10 +752,21 @@ int Engine::pcg(int first_chunk) {
     }
     j += k;
     if (all_done) break;
+    if (multi_) {  // later chunks serve only the simulations still iterating
+      std::vector<char> live(act_.size(), 0);
+      size_t nlive = 0;
+      for (size_t q = 0; q < act_.size(); ++q) {
+        const Scalars& t = inner ? act_[q]->si : act_[q]->so;
+        live[q] = t.done ? 0 : 1;
+        nlive += live[q];
+      }
+      if (nlive < live_count_) RC_TRY(compact(live));
+    }
     // the first chunk runs the estimate (the last step's count); a solve
     // that needs more mostly needs one or two more iterations
     k = ++chunks == 1 ? 2 : 4;
   }
+  if (live_count_ != act_.size()) uncompact();
   return FEM_OK;
 }
 
@@ -704,8 +804,8 @@ int Engine::mixed_sweeps() {
     if (!any) break;
     RC_TRY(upload_simdev());
     BatchArgs a = args(icur_, iprev_, 0, 0);
-    a.table = multi_ ? tab_dev_ + off_start_ : nullptr;
-    hipLaunchKernelGGL(inner_start_batch_kernel, dim3(n_start_), dim3(kT), 0, stream_, a);
+    a.table = multi_ ? tab_cur_ + lay_.off_start : nullptr;
+    hipLaunchKernelGGL(inner_start_batch_kernel, dim3(lay_.n_start), dim3(kT), 0, stream_, a);
     HIP_TRY(hipGetLastError());
     icur_ ^= 1;
     iprev_ = PK_START;
@@ -888,6 +988,115 @@ int Engine::run() {
   for (auto& s : sims_) RC_TRY(write_outputs(*s, ms));
   HIP_TRY(hipStreamSynchronize(stream_));
   return FEM_OK;
+}
+
+// Autotuner (fem_heat_tune): times the hot gather of the PCG iteration of
+// `h` -- the search direction fused with q = A d, d^T q and the deferred
+// x += alpha d, in the handle's precision -- through the batched launch the
+// engine uses, for every candidate shape.  The timed launches work on zeroed
+// vectors of the handle with a relayed state that is never done (so every
+// block does its full work) and never read back.  A batch member is timed
+// with enough copies of the simulation in one launch to fill the device
+// (the copies share the handle's buffers; their identical stores race
+// harmlessly), per copy.
+int Engine::tune(fem_heat* h, double dt, double theta, bool batch, fem_tune_result* out) {
+  fem_heat* eh = h_;
+  const uint32_t N = h->g.N;
+  RC_TRY(prepare_operator(h, theta * dt, mixed_));
+  for (double* p : {h->r64, h->q64, h->d64[0], h->d64[1], h->pool[0], h->pool[1], h->pool[2], h->pool[3]})
+    hipLaunchKernelGGL((fill_kernel<double>), dim3(nblk(N)), dim3(kT), 0, stream_, p, 0.0, N);
+  if (mixed_)
+    for (float* p : {h->r32, h->q32, h->d32[0], h->d32[1], h->e32[0], h->e32[1]})
+      hipLaunchKernelGGL((fill_kernel<float>), dim3(nblk(N)), dim3(kT), 0, stream_, p, 0.0f, N);
+  for (RelayCtx* c : {&h->outer, &h->inner})
+    for (int k = 0; k < 2; ++k) HIP_TRY(hipMemsetAsync(c->S[k], 0, sizeof(Scalars), stream_));
+  HIP_TRY(hipGetLastError());
+  int cus = 0;
+  HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, h->opts.device));
+  const GatherShape before = h->shape;
+  const bool was_batched = h->batched;
+  h->batched = batch;
+  const std::vector<GatherShape> cands = tune_candidates(h, std::max(cus, 1));
+  h->batched = was_batched;
+  hipEvent_t ev[2] = {nullptr, nullptr};
+  for (auto& x : ev) HIP_TRY(hipEventCreate(&x));
+  constexpr int kReps = 6;
+  double best = 0.0, rule = 0.0;
+  size_t bi = 0;
+  int rc = FEM_OK;
+  for (size_t i = 0; i < cands.size() && rc == FEM_OK; ++i) {
+    const GatherShape& c = cands[i];
+    rc = set_shape(h, c);
+    if (rc != FEM_OK) break;
+    const int copies = batch ? std::min<int>(64, std::max<int>(1, (4 * cus + (int)c.nblocks - 1) / (int)c.nblocks)) : 1;
+    sims_.clear();
+    for (int q = 0; q < copies; ++q) {
+      auto sp = std::make_unique<Sim>();
+      sp->rq = RunRequest{h, nullptr, nullptr, dt, theta, 1.0, 1, nullptr};
+      sp->T1 = h->pool[0];
+      sp->T2 = h->pool[1];
+      sp->X[0] = h->pool[2];
+      sp->X[1] = h->pool[3];
+      sims_.push_back(std::move(sp));
+    }
+    dirty_ = true;
+    if ((rc = compose()) != FEM_OK || (rc = upload_simdev()) != FEM_OK) break;
+    auto launch = [&]() {
+      return mixed_ ? gather<RoleDir<float>>(args(0, PK_GATHER, 1, 0, 0))
+                    : gather<RoleDir<double>>(args(0, PK_GATHER, 1, 0, 1));
+    };
+    for (int w = 0; w < 2 && rc == FEM_OK; ++w) rc = launch();
+    if (rc == FEM_OK && hipEventRecord(ev[0], stream_) != hipSuccess) rc = fail(eh, FEM_EDEVICE, "hipEventRecord");
+    for (int r = 0; r < kReps && rc == FEM_OK; ++r) rc = launch();
+    if (rc == FEM_OK && (hipEventRecord(ev[1], stream_) != hipSuccess || hipEventSynchronize(ev[1]) != hipSuccess))
+      rc = fail(eh, FEM_EDEVICE, "timing events failed");
+    float ms = 0.f;
+    if (rc == FEM_OK && hipEventElapsedTime(&ms, ev[0], ev[1]) != hipSuccess) rc = fail(eh, FEM_EDEVICE, "hipEventElapsedTime");
+    if (rc != FEM_OK) break;
+    const double us = (double)ms * 1e3 / kReps / copies;
+    if (i == 0) rule = us;
+    if (i == 0 || us < best) {
+      best = us;
+      bi = i;
+    }
+  }
+  for (auto& x : ev) (void)hipEventDestroy(x);
+  (void)hipStreamSynchronize(stream_);
+  sims_.clear();
+  act_.clear();
+  dirty_ = true;
+  RC_TRY(rc);
+  // a simulation alone runs with the tile found; a batch member's tile is
+  // only recorded (this handle itself runs alone)
+  RC_TRY(set_shape(h, batch ? before : cands[bi]));
+  if (!batch) h->tuned = true;
+  const GatherShape& b = cands[bi];
+  int rec = 0;
+  if (h->opts.tune_cache) {
+    const int t[3] = {b.tx, b.ty, b.tz};
+    rec = tune_store(h->opts.tune_cache, tune_key(h->opts.device, mixed_, h->cubic, batch, h->g.px, h->g.py, h->g.pz),
+                     t, best, rule, (int)cands.size())
+              ? 1
+              : 0;
+  }
+  if (out) {
+    out->tile_x = b.tx;
+    out->tile_y = b.ty;
+    out->tile_z = b.tz;
+    out->candidates = (int32_t)cands.size();
+    out->best_us = best;
+    out->rule_us = rule;
+    out->recorded = rec;
+  }
+  return FEM_OK;
+}
+
+int engine_tune(fem_heat* h, double dt, double theta, uint32_t flags, fem_tune_result* out) {
+  HIP_TRY(hipSetDevice(h->opts.device));
+  fem_opts o = h->opts;
+  o.flags &= ~(uint32_t)FEM_TIMING;
+  Engine e(h->stream, o, h);
+  return e.tune(h, dt, theta, (flags & FEM_TUNE_BATCH) != 0, out);
 }
 
 // ---- opaque interface for the server ------------------------------------------

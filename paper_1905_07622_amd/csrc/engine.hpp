@@ -27,6 +27,9 @@ int engine_finish(Engine* e, Sim* s, double ms);
 // Removes a simulation without outputs.
 void engine_drop(Engine* e, Sim* s);
 
+// Autotuner of the gather launch shape (fem_heat_tune).
+int engine_tune(fem_heat* h, double dt, double theta, uint32_t flags, fem_tune_result* out);
+
 // Device bytes a handle for this problem holds while it runs.
 size_t handle_device_bytes(const fem_grid& grid, const fem_opts& opts, const fem_bc* bc, int32_t nsteps,
                            int32_t n_sensors);

@@ -33,19 +33,42 @@ inline int fail(fem_heat* h, int code, const std::string& msg) {
     if (rc_ != FEM_OK) return rc_; \
   } while (0)
 
-template <typename T>
-int dalloc(fem_heat* h, T** p, size_t n) {
-  if (hipMalloc(reinterpret_cast<void**>(p), std::max<size_t>(n, 1) * sizeof(T)) != hipSuccess) {
+// Device memory: through a caller's allocator (stream-ordered on `s`) when
+// one is given, else hipMalloc / hipFree (hipFree synchronises the device).
+inline bool dev_alloc(const fem_allocator* a, hipStream_t s, void** p, size_t bytes) {
+  *p = nullptr;
+  if (a && a->alloc) return a->alloc(a->ctx, p, bytes, s) == 0 && *p != nullptr;
+  if (hipMalloc(p, bytes) != hipSuccess) {
     (void)hipGetLastError();
     *p = nullptr;
-    return fail(h, FEM_ENOMEM, "hipMalloc of " + std::to_string(n * sizeof(T)) + " bytes failed");
+    return false;
   }
+  return true;
+}
+inline void dev_free(const fem_allocator* a, hipStream_t s, void* p) {
+  if (!p) return;
+  if (a && a->release)
+    a->release(a->ctx, p, s);
+  else
+    (void)hipFree(p);
+}
+
+// Buffers of a handle, on its stream and through its allocator.
+template <typename T>
+int dalloc(fem_heat* h, T** p, size_t n) {
+  const size_t bytes = std::max<size_t>(n, 1) * sizeof(T);
+  void* v = nullptr;
+  if (!dev_alloc(h->opts.allocator, h->stream, &v, bytes)) {
+    *p = nullptr;
+    return fail(h, FEM_ENOMEM, "device allocation of " + std::to_string(bytes) + " bytes failed");
+  }
+  *p = static_cast<T*>(v);
   return FEM_OK;
 }
 
 template <typename T>
-void dfree(T*& p) {
-  if (p) (void)hipFree(p);
+void dfree(fem_heat* h, T*& p) {
+  dev_free(h->opts.allocator, h->stream, p);
   p = nullptr;
 }
 

@@ -21,6 +21,7 @@
 #include <map>
 #include <memory>
 #include <mutex>
+#include <string>
 #include <thread>
 #include <vector>
 
@@ -62,6 +63,14 @@ struct Lane;
 
 struct fem_server {
   fem_server_opts o{};
+  // Device memory of admitted simulations: a stream-ordered pool of the
+  // server (or the caller's allocator).  Each lane allocates and releases on
+  // its own stream, so a retirement never synchronises the device -- hipFree
+  // would wait for every lane's kernels -- and released blocks are reused by
+  // later admissions without returning to the driver.
+  hipMemPool_t pool = nullptr;
+  fem_allocator pool_alloc{};
+  std::string tune_cache;  // own copy of the options' tile-cache path
 
   std::mutex mu;
   std::condition_variable cv_work, cv_done;
@@ -100,6 +109,18 @@ struct Lane {
 
 namespace {
 
+int pool_alloc_fn(void* ctx, void** ptr, size_t bytes, void* stream) {
+  auto* srv = static_cast<fem_server*>(ctx);
+  if (hipMallocFromPoolAsync(ptr, bytes, srv->pool, static_cast<hipStream_t>(stream)) != hipSuccess) {
+    (void)hipGetLastError();
+    *ptr = nullptr;
+    return -1;
+  }
+  return 0;
+}
+
+void pool_release_fn(void*, void* ptr, void* stream) { (void)hipFreeAsync(ptr, static_cast<hipStream_t>(stream)); }
+
 void free_handle(Request* r) {
   if (r->h) {
     femheat::solver_free(r->h);
@@ -131,6 +152,7 @@ void Lane::loop() {
   (void)hipSetDevice(S.o.opts.device);
   for (;;) {
     std::vector<Request*> admit, cancelled;
+    bool stopping = false;
     {
       std::unique_lock<std::mutex> lk(S.mu);
       // Admission in arrival order: a request is taken only if it fits
@@ -159,7 +181,8 @@ void Lane::loop() {
         return any;
       };
       S.cv_work.wait(lk, [&] { return S.stop || !running.empty() || admissible(); });
-      if (S.stop)
+      stopping = S.stop;
+      if (stopping)
         for (Request* r : running) r->cancel = true;
       for (Request* r : running)
         if (r->cancel) cancelled.push_back(r);
@@ -169,7 +192,13 @@ void Lane::loop() {
           it = S.queue.erase(it);
           return true;
         });
-        for (Request* r : admit) S.in_use += r->st.bytes;
+        // admitted requests leave the queue as RUNNING: a cancel from now on
+        // is taken at the next epoch boundary, after their set-up below
+        for (Request* r : admit) {
+          r->st.state = FEM_REQ_RUNNING;
+          r->st.t_admit = S.now();
+          S.in_use += r->st.bytes;
+        }
         S.peak = std::max(S.peak, S.in_use);
         S.nrunning += (int32_t)admit.size();
         // requests of other classes behind these may be admissible now
@@ -186,7 +215,7 @@ void Lane::loop() {
       S.finish(r, FEM_REQ_CANCELED, FEM_ECANCELED, true);
       S.cv_done.notify_all();
     }
-    if (S.stop) {
+    if (stopping) {
       std::lock_guard<std::mutex> lk(S.mu);
       if (running.empty()) return;
     }
@@ -211,8 +240,6 @@ void Lane::loop() {
         S.cv_done.notify_all();
         continue;
       }
-      r->st.state = FEM_REQ_RUNNING;
-      r->st.t_admit = S.now();
       running.push_back(r);
     }
     if (running.empty()) continue;
@@ -322,6 +349,27 @@ int server_create(const fem_server_opts& o, fem_server** out, std::string* err) 
     }
     s->budget = free_b / 4 * 3;
   }
+  if (!o.opts.allocator) {
+    hipMemPoolProps props{};
+    props.allocType = hipMemAllocationTypePinned;
+    props.handleTypes = hipMemHandleTypeNone;
+    props.location.type = hipMemLocationTypeDevice;
+    props.location.id = o.opts.device;
+    if (hipMemPoolCreate(&s->pool, &props) != hipSuccess) {
+      (void)hipGetLastError();
+      *err = "hipMemPoolCreate failed";
+      return FEM_EDEVICE;
+    }
+    // keep released blocks in the pool (at most what the budget admits at once)
+    uint64_t keep = UINT64_MAX;
+    (void)hipMemPoolSetAttribute(s->pool, hipMemPoolAttrReleaseThreshold, &keep);
+    s->pool_alloc = fem_allocator{s.get(), pool_alloc_fn, pool_release_fn};
+    s->o.opts.allocator = &s->pool_alloc;
+  }
+  if (o.opts.tune_cache) {
+    s->tune_cache = o.opts.tune_cache;
+    s->o.opts.tune_cache = s->tune_cache.c_str();
+  }
   s->t0 = Clock::now();
   *out = s.release();
   return FEM_OK;
@@ -420,8 +468,9 @@ int server_cancel(fem_server* s, uint64_t ticket) {
   auto it = s->reqs.find(ticket);
   if (it == s->reqs.end()) return FEM_EINVAL;
   Request* r = it->second.get();
-  if (r->st.state == FEM_REQ_QUEUED) {
-    s->queue.erase(std::find(s->queue.begin(), s->queue.end(), r));
+  auto qi = std::find(s->queue.begin(), s->queue.end(), r);
+  if (r->st.state == FEM_REQ_QUEUED && qi != s->queue.end()) {
+    s->queue.erase(qi);
     s->finish(r, FEM_REQ_CANCELED, FEM_ECANCELED, false);
     s->cv_done.notify_all();
   } else if (r->st.state == FEM_REQ_RUNNING) {
@@ -463,6 +512,7 @@ void server_destroy(fem_server* s) {
     (void)hipStreamDestroy(ln.stream);
   }
   s->cv_done.notify_all();
+  if (s->pool) (void)hipMemPoolDestroy(s->pool);
   delete s;
 }
 

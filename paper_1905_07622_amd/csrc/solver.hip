@@ -14,6 +14,7 @@
 #include "engine.hpp"
 #include "rowwave.hpp"
 #include "runtime.hpp"
+#include "tune.hpp"
 #include "vector_kernels.hpp"
 
 namespace femheat {
@@ -189,10 +190,12 @@ template GatherArgs<float> gather_args<float>(const fem_heat*, double, double);
 
 namespace {
 
-// One gather of one handle outside the time stepping (set-up, test hook).
+// One gather of one handle outside the time stepping (set-up, test hook);
+// `sink` (>= 256 values) replaces the handle's sink when given.
 template <typename V, class Pro, class Epi>
-int launch_gather(fem_heat* h, double cm, double ck, Pro pro, Epi epi, const Relay& R) {
-  const GatherArgs<V> ga = gather_args<V>(h, cm, ck);
+int launch_gather(fem_heat* h, double cm, double ck, Pro pro, Epi epi, const Relay& R, V* sink = nullptr) {
+  GatherArgs<V> ga = gather_args<V>(h, cm, ck);
+  if (sink) ga.sink = sink;
   const size_t smem = h->shape.smem_bytes(sizeof(V));
   if (h->cubic)
     hipLaunchKernelGGL((gather_kernel<V, true, Pro, Epi>), dim3(h->shape.nblocks), dim3(h->shape.nthreads), smem,
@@ -202,6 +205,33 @@ int launch_gather(fem_heat* h, double cm, double ck, Pro pro, Epi epi, const Rel
                        h->stream, ga, pro, epi, R);
   HIP_TRY(hipGetLastError());
   return FEM_OK;
+}
+
+// Element-by-element apply y = (M + ck K) x in two passes (comparison form)
+// with its 4 N partial sums in `part`.
+void launch_ebe(fem_heat* h, double ck, const double* x, double* part, double* y) {
+  const uint32_t N = h->g.N;
+  GatherArgs<double> ga{};
+  fill_classes(h->g, ga, 1.0, ck, false);  // the general class entries hold for any box
+  EbeArgs ea{};
+  ea.nx = h->g.nx;
+  ea.ny = h->g.ny;
+  ea.nz = h->g.nz;
+  ea.px = h->g.px;
+  ea.py = h->g.py;
+  ea.N = N;
+  ea.nseg = (uint32_t)((h->g.nx + kEbeStore - 1) / kEbeStore);
+  ea.x = x;
+  ea.rhoc = h->rhoc64;
+  ea.kc = h->k64;
+  ea.part = part;
+  for (int c = 0; c < 8; ++c) {
+    ea.Mc[c] = ga.sa * ga.Mc[c];
+    ea.Kc[c] = ga.sb * ga.Kc[c];
+  }
+  const uint64_t waves = (uint64_t)ea.nseg * (uint64_t)h->g.ny * (uint64_t)h->g.nz;
+  hipLaunchKernelGGL(ebe_elements_kernel, dim3((uint32_t)((waves + 3) / 4)), dim3(256), 0, h->stream, ea);
+  hipLaunchKernelGGL(ebe_sum_kernel, dim3(std::min<uint32_t>(nblk(N), 4096)), dim3(kT), 0, h->stream, ea, y);
 }
 
 }  // namespace
@@ -277,8 +307,26 @@ int solver_init(fem_heat* h, const fem_grid* grid, const double* k_e, const doub
   h->cubic = (g.hx == g.hy && g.hy == g.hz);
   HIP_TRY(hipSetDevice(h->opts.device));
   {
+    // a tile the autotuner recorded for this grid, precision, element class
+    // and launch kind (alone or in a batch) replaces the rule
+    fem_opts so = h->opts;
+    if (so.tune_cache && so.tile_x == 0 && so.tile_y == 0 && so.tile_z == 0) {
+      int t[3];
+      if (tune_lookup(so.tune_cache, tune_key(so.device, so.precision == FEM_FP32_FP64DOT, h->cubic, h->batched,
+                                              g.px, g.py, g.pz),
+                      t)) {
+        fem_opts probe_o = so;
+        probe_o.tile_x = t[0];
+        probe_o.tile_y = t[1];
+        probe_o.tile_z = t[2];
+        if (shape_stages(choose_shape(g, probe_o, 1))) {
+          so = probe_o;
+          h->tuned = true;
+        }
+      }
+    }
     // the x-y tiling does not depend on the capacity: size the block first
-    const GatherShape probe = choose_shape(g, h->opts, 1);
+    const GatherShape probe = choose_shape(g, so, 1);
     const bool fp32 = h->opts.precision == FEM_FP32_FP64DOT;
     int cus = 0;
     HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, h->opts.device));
@@ -286,7 +334,8 @@ int solver_init(fem_heat* h, const fem_grid* grid, const double* k_e, const doub
     // plane pipeline's fill more often than the extra blocks hide latency
     // (measured for the FP32 gather, which could hold four)
     const int per_cu = std::min(2, resident_blocks(h->cubic, fp32, probe.nthreads, probe.smem_bytes(fp32 ? 4 : 8)));
-    h->shape = choose_shape(g, h->opts, h->batched ? 0 : std::max(1, cus) * per_cu);
+    h->shape = choose_shape(g, so, h->batched ? 0 : std::max(1, cus) * per_cu);
+    h->capacity = std::max(1, cus) * per_cu;
   }
   {
     const GatherShape& s = h->shape;
@@ -361,27 +410,7 @@ int solver_apply(fem_heat* h, int32_t which, double dt, double theta, const doub
   }
   if ((op == FEM_OP_A || op == FEM_OP_L) && ebe) {
     const double ck = op == FEM_OP_A ? theta * dt : -(1.0 - theta) * dt;
-    GatherArgs<double> ga{};
-    fill_classes(h->g, ga, 1.0, ck, false);  // the general class entries hold for any box
-    EbeArgs ea{};
-    ea.nx = h->g.nx;
-    ea.ny = h->g.ny;
-    ea.nz = h->g.nz;
-    ea.px = h->g.px;
-    ea.py = h->g.py;
-    ea.N = N;
-    ea.nseg = (uint32_t)((h->g.nx + kEbeStore - 1) / kEbeStore);
-    ea.x = xd;
-    ea.rhoc = h->rhoc64;
-    ea.kc = h->k64;
-    ea.part = h->ebe_part;
-    for (int c = 0; c < 8; ++c) {
-      ea.Mc[c] = ga.sa * ga.Mc[c];
-      ea.Kc[c] = ga.sb * ga.Kc[c];
-    }
-    const uint64_t waves = (uint64_t)ea.nseg * (uint64_t)h->g.ny * (uint64_t)h->g.nz;
-    hipLaunchKernelGGL(ebe_elements_kernel, dim3((uint32_t)((waves + 3) / 4)), dim3(256), 0, h->stream, ea);
-    hipLaunchKernelGGL(ebe_sum_kernel, dim3(std::min<uint32_t>(nblk(N), 4096)), dim3(kT), 0, h->stream, ea, yd);
+    launch_ebe(h, ck, xd, h->ebe_part, yd);
   } else if ((op == FEM_OP_A || op == FEM_OP_L) && rows) {
     const double ck = op == FEM_OP_A ? theta * dt : -(1.0 - theta) * dt;
     GatherArgs<double> ga{};
@@ -444,6 +473,98 @@ int solver_apply(fem_heat* h, int32_t which, double dt, double theta, const doub
   return FEM_OK;
 }
 
+// ---------------------------------------------------------------------------
+// launch shapes for the autotuner
+
+bool shape_stages(const GatherShape& s) {
+  return s.tx >= 1 && s.ty >= 1 && s.tz >= 1 && s.tx * s.ty <= 256 &&
+         (s.tx + 2) * (s.ty + 2) <= kSlots * s.nthreads && (s.tx + 1) * (s.ty + 1) <= kSlots * s.nthreads;
+}
+
+GatherShape shape_with_tile(const fem_heat* h, int tx, int ty, int tz) {
+  fem_opts o = h->opts;
+  o.tile_x = tx;
+  o.tile_y = ty;
+  o.tile_z = tz;
+  return choose_shape(h->g, o, h->batched ? 0 : h->capacity);
+}
+
+// Candidates: x pieces of the node row (1 to 4 equal pieces, and 16/32/64
+// wide), block heights that the staging scheme holds (the largest, the one
+// that splits the y-rows evenly, and half of it), and for each x-y tile a
+// z-chunk length per target of resident blocks (1 to 4 per CU for a
+// simulation alone; 8 to 32 planes or the whole column for batch members).
+std::vector<GatherShape> tune_candidates(const fem_heat* h, int cus) {
+  std::vector<GatherShape> out;
+  out.push_back(h->shape);  // the rule's (or the cached) shape first
+  const int px = h->g.px, py = h->g.py, pz = h->g.pz;
+  std::vector<int> txs;
+  for (int pieces = 1; pieces <= 4; ++pieces) {
+    const int tx = (px + pieces - 1) / pieces;
+    if (tx <= 128) txs.push_back(tx);
+  }
+  for (int tx : {16, 32, 64})
+    if (tx < px) txs.push_back(tx);
+  auto seen = [&](const GatherShape& s) {
+    for (const GatherShape& o : out)
+      if (o.tx == s.tx && o.ty == s.ty && o.tz == s.tz) return true;
+    return false;
+  };
+  for (int tx : txs) {
+    const int tymax = std::max(1, 256 / tx);
+    int fit = 0;
+    for (int ty = std::min(tymax, py); ty >= 1; --ty) {
+      const int nt = ((tx * ty + 63) / 64) * 64;
+      if ((tx + 2) * (ty + 2) <= kSlots * nt && (tx + 1) * (ty + 1) <= kSlots * nt) {
+        fit = ty;
+        break;
+      }
+    }
+    if (fit == 0) continue;
+    const int even = (py + ((py + fit - 1) / fit) - 1) / ((py + fit - 1) / fit);
+    std::vector<int> tys = {fit, even, std::max(1, even / 2)};
+    for (int ty : tys) {
+      const int cols = ((px + tx - 1) / tx) * ((py + ty - 1) / ty);
+      std::vector<int> tzs;
+      if (h->batched) {
+        tzs = {8, 12, 16, 24, 32, pz};
+      } else {
+        for (int per_cu = 1; per_cu <= 4; ++per_cu) {
+          const int ntz = std::max(1, per_cu * cus / cols);
+          tzs.push_back(std::max(2, (pz + ntz - 1) / ntz));
+        }
+      }
+      for (int tz : tzs) {
+        GatherShape s = shape_with_tile(h, tx, ty, std::min(std::max(tz, 1), pz));
+        if (shape_stages(s) && !seen(s)) out.push_back(s);
+      }
+    }
+  }
+  return out;
+}
+
+int set_shape(fem_heat* h, const GatherShape& s) {
+  if (!shape_stages(s)) return fail(h, FEM_EINVAL, "tile shape too thin for the staging scheme");
+  if (s.nblocks > h->n_partials) {
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    const uint32_t n = s.nblocks;
+    const size_t ncomp = (h->opts.flags & FEM_ONE_REDUCTION) ? 4 : 1;
+    for (RelayCtx* c : {&h->outer, &h->inner})
+      for (int k = 0; k < 2; ++k) {
+        dfree(h, c->P[k]);
+        RC_TRY(dalloc(h, &c->P[k], ncomp * n));
+        HIP_TRY(hipMemsetAsync(c->P[k], 0, ncomp * n * sizeof(double), h->stream));
+      }
+    h->n_partials = n;
+  }
+  h->shape = s;
+  h->stats.tile_x = s.tx;
+  h->stats.tile_y = s.ty;
+  h->stats.tile_z = s.tz;
+  h->stats.grid_blocks = (int32_t)s.nblocks;
+  return FEM_OK;
+}
+
 int make_handle(const fem_grid* grid, const double* k_e, const double* rhoc_e, const fem_bc* bc, const fem_opts& o,
                 bool batched, fem_heat** out, std::string* why) {
   fem_heat* h = new (std::nothrow) fem_heat();
@@ -486,35 +607,35 @@ size_t handle_device_bytes(const fem_grid& grid, const fem_opts& opts, const fem
 
 void solver_free(fem_heat* h) {
   if (h->stream) (void)hipStreamSynchronize(h->stream);
-  dfree(h->rhoc64);
-  dfree(h->k64);
-  dfree(h->rhoc32);
-  dfree(h->k32);
-  dfree(h->F64);
-  dfree(h->pinv64);
-  dfree(h->b64);
-  dfree(h->r64);
-  dfree(h->q64);
-  dfree(h->r64b);
-  dfree(h->q64b);
-  for (auto& p : h->d64) dfree(p);
-  for (auto& p : h->pool) dfree(p);
-  dfree(h->lift64);
-  dfree(h->sink);
-  dfree(h->pinv32);
-  for (auto& p : h->e32) dfree(p);
-  dfree(h->r32);
-  dfree(h->q32);
-  for (auto& p : h->d32) dfree(p);
-  dfree(h->rhs32);
+  dfree(h, h->rhoc64);
+  dfree(h, h->k64);
+  dfree(h, h->rhoc32);
+  dfree(h, h->k32);
+  dfree(h, h->F64);
+  dfree(h, h->pinv64);
+  dfree(h, h->b64);
+  dfree(h, h->r64);
+  dfree(h, h->q64);
+  dfree(h, h->r64b);
+  dfree(h, h->q64b);
+  for (auto& p : h->d64) dfree(h, p);
+  for (auto& p : h->pool) dfree(h, p);
+  dfree(h, h->lift64);
+  dfree(h, h->sink);
+  dfree(h, h->pinv32);
+  for (auto& p : h->e32) dfree(h, p);
+  dfree(h, h->r32);
+  dfree(h, h->q32);
+  for (auto& p : h->d32) dfree(h, p);
+  dfree(h, h->rhs32);
   for (RelayCtx* c : {&h->outer, &h->inner})
     for (int k = 0; k < 2; ++k) {
-      dfree(c->S[k]);
-      dfree(c->P[k]);
+      dfree(h, c->S[k]);
+      dfree(h, c->P[k]);
     }
-  dfree(h->xyz_dev);
-  dfree(h->traces_dev);
-  dfree(h->ebe_part);
+  dfree(h, h->xyz_dev);
+  dfree(h, h->traces_dev);
+  dfree(h, h->ebe_part);
   for (auto& e : h->ev_apply)
     if (e) (void)hipEventDestroy(e);
   if (h->own_stream && h->stream) (void)hipStreamDestroy(h->stream);

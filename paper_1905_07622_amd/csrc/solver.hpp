@@ -71,6 +71,8 @@ struct fem_heat {
   size_t xyz_cap = 0;
 
   femheat::GatherShape shape{};
+  int32_t capacity = 1;   // blocks of the hot gather the device holds at once (tile rule of a simulation alone)
+  bool tuned = false;     // the shape came from the autotuner's cache
   uint32_t upd_blocks64 = 0, upd_blocks32 = 0, start_blocks = 0;
 
   // element-by-element apply (test hook): 4 N partial sums, allocated on first use

@@ -46,7 +46,8 @@ class fem_opts(ctypes.Structure):
                 ("stop_rule", ctypes.c_int32), ("max_refine", ctypes.c_int32),
                 ("inner_rtol", ctypes.c_double), ("flags", ctypes.c_uint32),
                 ("hip_stream", ctypes.c_void_p), ("device", ctypes.c_int32),
-                ("tile_x", ctypes.c_int32), ("tile_y", ctypes.c_int32), ("tile_z", ctypes.c_int32)]
+                ("tile_x", ctypes.c_int32), ("tile_y", ctypes.c_int32), ("tile_z", ctypes.c_int32),
+                ("allocator", ctypes.c_void_p), ("tune_cache", ctypes.c_char_p)]
 
 
 class fem_out(ctypes.Structure):
@@ -64,6 +65,15 @@ class fem_stats(ctypes.Structure):
                 ("grid_blocks", ctypes.c_int32), ("tile_x", ctypes.c_int32),
                 ("tile_y", ctypes.c_int32), ("tile_z", ctypes.c_int32),
                 ("apply_calls", ctypes.c_int64), ("apply_ms", ctypes.c_double)]
+
+
+FEM_TUNE_BATCH = 0x1
+
+
+class fem_tune_result(ctypes.Structure):
+    _fields_ = [("tile_x", ctypes.c_int32), ("tile_y", ctypes.c_int32), ("tile_z", ctypes.c_int32),
+                ("candidates", ctypes.c_int32), ("best_us", ctypes.c_double), ("rule_us", ctypes.c_double),
+                ("recorded", ctypes.c_int32)]
 
 
 class fem_request(ctypes.Structure):
@@ -98,7 +108,8 @@ class FemError(RuntimeError):
         self.status = status
 
 
-EXPORTS = ("fem_heat_create", "fem_heat_run", "fem_heat_apply", "fem_heat_stats", "fem_heat_destroy",
+EXPORTS = ("fem_heat_create", "fem_heat_run", "fem_heat_apply", "fem_heat_stats", "fem_heat_tune",
+           "fem_heat_destroy",
            "fem_heat_default_opts", "fem_strerror", "fem_last_error", "fem_heat_run_batch",
            "fem_server_create", "fem_server_submit", "fem_server_poll", "fem_server_wait", "fem_server_cancel",
            "fem_server_info_get", "fem_server_destroy")
@@ -120,6 +131,8 @@ def lib():
                                    ctypes.c_double, ctypes.POINTER(fem_out)]
         L.fem_heat_apply.argtypes = [vp, ctypes.c_int32, ctypes.c_double, ctypes.c_double, _dp, _dp]
         L.fem_heat_stats.argtypes = [vp, ctypes.POINTER(fem_stats)]
+        L.fem_heat_tune.argtypes = [vp, ctypes.c_double, ctypes.c_double, ctypes.c_uint32,
+                                    ctypes.POINTER(fem_tune_result)]
         L.fem_heat_run_batch.argtypes = [ctypes.POINTER(fem_request), ctypes.c_int32, ctypes.POINTER(fem_opts), _ip]
         L.fem_heat_run_batch.restype = ctypes.c_int
         L.fem_server_create.argtypes = [ctypes.POINTER(fem_server_opts), ctypes.POINTER(vp)]
@@ -141,7 +154,7 @@ def lib():
         L.fem_strerror.restype = ctypes.c_char_p
         L.fem_last_error.argtypes = [vp]
         L.fem_last_error.restype = ctypes.c_char_p
-        for n in ("fem_heat_create", "fem_heat_run", "fem_heat_apply", "fem_heat_stats"):
+        for n in ("fem_heat_create", "fem_heat_run", "fem_heat_apply", "fem_heat_stats", "fem_heat_tune"):
             getattr(L, n).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -180,6 +193,12 @@ def fem_heat_run(h, T0_ptr, T_prev_ptr, dt, theta, nsteps, rtol, out: Optional[f
 
 def fem_heat_apply(h, which, dt, theta, x_ptr, y_ptr) -> int:
     return lib().fem_heat_apply(h, which, dt, theta, x_ptr, y_ptr)
+
+
+def fem_heat_tune(h, dt, theta, flags=0):
+    r = fem_tune_result()
+    st = lib().fem_heat_tune(h, dt, theta, flags, ctypes.byref(r))
+    return st, r
 
 
 def fem_heat_stats(h) -> fem_stats:
@@ -279,7 +298,7 @@ class _Arrays:
 
 def make_opts(*, precision=FEM_FP64, max_iter=10000, replace_every=50, guess=FEM_GUESS_EXTRAP,
               stop_rule=FEM_STOP_RHS, max_refine=4, inner_rtol=1e-5, device_ptrs=False, timing=False,
-              one_reduction=False, tile=(0, 0, 0), stream=None, device=0) -> fem_opts:
+              one_reduction=False, tile=(0, 0, 0), stream=None, device=0, tune_cache=None) -> fem_opts:
     o = fem_heat_default_opts()
     o.precision, o.max_iter, o.replace_every = precision, max_iter, replace_every
     o.guess, o.stop_rule, o.max_refine, o.inner_rtol = guess, stop_rule, max_refine, inner_rtol
@@ -288,6 +307,7 @@ def make_opts(*, precision=FEM_FP64, max_iter=10000, replace_every=50, guess=FEM
     o.hip_stream = stream
     o.device = device
     o.tile_x, o.tile_y, o.tile_z = tile
+    o.tune_cache = None if tune_cache is None else os.fsencode(tune_cache)
     return o
 
 
@@ -451,7 +471,7 @@ class Heat:
                  flux_mask=0, flux=None, flux_schedule=None, precision=FEM_FP64, max_iter=10000,
                  replace_every=50, guess=FEM_GUESS_EXTRAP, stop_rule=FEM_STOP_RHS, max_refine=4,
                  inner_rtol=1e-5, device_ptrs=False, timing=False, one_reduction=False, tile=(0, 0, 0), stream=None,
-                 device=0):
+                 device=0, tune_cache=None):
         self.h = None
         self.device_ptrs = device_ptrs
         self.N = (nx + 1) * (ny + 1) * (nz + 1)
@@ -473,6 +493,8 @@ class Heat:
         o.hip_stream = stream
         o.device = device
         o.tile_x, o.tile_y, o.tile_z = tile
+        self._tune_cache = None if tune_cache is None else os.fsencode(tune_cache)
+        o.tune_cache = self._tune_cache
         self.opts = o
         arrs = _Arrays(device_ptrs)
         st, h = fem_heat_create(self.grid, arrs.inp(k_e), arrs.inp(rhoc_e), bc, o)
@@ -524,6 +546,13 @@ class Heat:
         if st != FEM_OK:
             raise FemError(st, fem_last_error(self.h))
         return y
+
+    def tune(self, *, dt, theta, batch=False) -> dict:
+        """fem_heat_tune: installs (or, with batch=True, records) the fastest gather tile."""
+        st, r = fem_heat_tune(self.h, dt, theta, FEM_TUNE_BATCH if batch else 0)
+        if st != FEM_OK:
+            raise FemError(st, fem_last_error(self.h))
+        return {k: getattr(r, k) for k, _ in fem_tune_result._fields_}
 
     def stats(self) -> dict:
         s = fem_heat_stats(self.h)

@@ -142,7 +142,8 @@ def test_run_batch_argument_checks(lib):
     assert fh.fem_heat_run_batch(reqs, 1, bad_opts, None) == fh.FEM_EINVAL
 
 
-STRUCTS = ("fem_grid", "fem_bc", "fem_opts", "fem_out", "fem_stats", "fem_request", "fem_server_opts",
+STRUCTS = ("fem_grid", "fem_bc", "fem_opts", "fem_out", "fem_stats", "fem_tune_result", "fem_request",
+           "fem_server_opts",
            "fem_status", "fem_server_info")
 
 
@@ -187,3 +188,14 @@ def test_server_rejects_invalid_options_before_device_work(lib):
     assert fh.fem_server_cancel(None, 1) == fh.FEM_EINVAL
     r = fh.fem_request()
     assert fh.fem_server_submit(None, r)[0] == fh.FEM_EINVAL
+
+
+@pytest.mark.parametrize("tile", [(128, 2, 4), (1, 64, 4), (200, 0, 0), (0, 4, 0), (257, 1, 1), (64, 5, 1)])
+def test_create_rejects_tiles_the_gather_cannot_stage(lib, tile):
+    """Tile overrides whose (tx+2)(ty+2) plane tile needs more than two staging
+    slots per thread (or out of range) are refused before any device work."""
+    k = np.ones(8)
+    st, h = fh.fem_heat_create(fh.fem_grid(2, 2, 2, 0.5, 0.5, 0.5), k.ctypes.data_as(fh._dp),
+                               k.ctypes.data_as(fh._dp), fh.fem_bc(), fh.make_opts(tile=tile))
+    assert st == fh.FEM_EINVAL and not h.value
+    assert "tile" in fh.fem_last_error(None)

@@ -1,0 +1,77 @@
+"""The autotuner (fem_heat_tune) and its tile cache.
+
+Tuning changes only the launch shape of the gather: the sums of every node
+are formed in a fixed order whatever the tile, so runs with the tuned tile
+must be bit-identical to runs with the library's rule -- alone, in a batch,
+in FP64 and in the mixed form.  The cache makes later handles (single,
+batch members) take the recorded tile.
+"""
+import json
+
+import numpy as np
+import pytest
+
+from _util import say
+from paper_1905_07622_amd import femheat as fh
+from paper_1905_07622_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+
+def _run(h, p, nsteps=4):
+    return h.run(p.T0, dt=p.dt, theta=p.theta, nsteps=nsteps, rtol=p.rtol)
+
+
+@pytest.mark.parametrize("precision", [fh.FEM_FP64, fh.FEM_FP32_FP64DOT])
+def test_tuned_single_run_bitwise_equal_and_cached(gpu, tmp_path, precision):
+    p = wl.lognormal_cube(36, seed=5, nsteps=4)
+    cache = str(tmp_path / "tune.json")
+    with fh.Heat.from_problem(p, precision=precision) as h0:
+        ref = _run(h0, p)
+        rule_tile = [h0.stats()[k] for k in ("tile_x", "tile_y", "tile_z")]
+    with fh.Heat.from_problem(p, precision=precision, tune_cache=cache) as h1:
+        res = h1.tune(dt=p.dt, theta=p.theta)
+        say(f"tuned {res} (rule tile {rule_tile})")
+        assert res["candidates"] > 3 and res["recorded"] == 1
+        assert res["best_us"] <= res["rule_us"]
+        st = h1.stats()
+        assert [st["tile_x"], st["tile_y"], st["tile_z"]] == [res["tile_x"], res["tile_y"], res["tile_z"]]
+        out = _run(h1, p)
+    assert np.array_equal(out["T_final"], ref["T_final"]) and np.array_equal(out["iters"], ref["iters"])
+    rec = json.load(open(cache))["entries"]
+    assert len(rec) == 1 and rec[0]["tile"] == [res["tile_x"], res["tile_y"], res["tile_z"]]
+    assert "|single|37x37x37" in rec[0]["key"]
+    # a later handle with the same options takes the recorded tile
+    with fh.Heat.from_problem(p, precision=precision, tune_cache=cache) as h2:
+        st = h2.stats()
+        assert [st["tile_x"], st["tile_y"], st["tile_z"]] == rec[0]["tile"]
+        again = _run(h2, p)
+    assert np.array_equal(again["T_final"], ref["T_final"])
+
+
+def test_tuned_batch_members_bitwise_equal(gpu, tmp_path):
+    cache = str(tmp_path / "tune.json")
+    probs = [wl.sphere_proposal(s, n=20, nsteps=3) for s in range(5)]
+    st0, ref = fh.run_batch(probs, precision=fh.FEM_FP32_FP64DOT)
+    p = probs[0]
+    with fh.Heat.from_problem(p, precision=fh.FEM_FP32_FP64DOT, tune_cache=cache) as h:
+        before = h.stats()
+        res = h.tune(dt=p.dt, theta=p.theta, batch=True)
+        after = h.stats()
+    say(f"batch-member tile {res}")
+    assert res["recorded"] == 1
+    # with FEM_TUNE_BATCH the handle keeps its own tile; the batch tile is recorded
+    assert [before[k] for k in ("tile_x", "tile_y", "tile_z")] == [after[k] for k in ("tile_x", "tile_y", "tile_z")]
+    assert "|batch|21x21x21" in json.load(open(cache))["entries"][0]["key"]
+    st1, out = fh.run_batch(probs, precision=fh.FEM_FP32_FP64DOT, tune_cache=cache)
+    assert st0 == st1 == fh.FEM_OK
+    for a, b in zip(out, ref):
+        assert np.array_equal(a["T_final"], b["T_final"]) and np.array_equal(a["iters"], b["iters"])
+
+
+def test_tune_rejects_bad_arguments(gpu):
+    p = wl.random_problem(5, 4, 3, seed=2)
+    with fh.Heat.from_problem(p) as h:
+        assert fh.fem_heat_tune(h.h, -1.0, 1.0)[0] == fh.FEM_EINVAL
+        assert fh.fem_heat_tune(h.h, 1e-3, 2.0)[0] == fh.FEM_EINVAL
+        assert fh.fem_heat_tune(h.h, 1e-3, 1.0, 0x8)[0] == fh.FEM_EINVAL
