@@ -317,12 +317,104 @@ static void diag_of(const oracle_csr *A, double *P) {
 }
 
 /* ------------------------------------------------------------------------- */
+/* Chebyshev-accelerated Jacobi preconditioner (not in the paper, whose GPU   */
+/* method uses Jacobi only, Sec. 3.3; a polynomial preconditioner is the kind */
+/* that stays element-wise and matrix-free on the device)                     */
+/* ------------------------------------------------------------------------- */
+
+/* Largest eigenvalue of the symmetric 8x8 matrix D^-1/2 X D^-1/2 (D = diag X)
+ * by power iteration from a fixed generic start: plain and slow, 8x8 only. */
+static double scaled_top_eigenvalue(const double *X) {
+  double v[8], w[8], lam = 0.0;
+  for (int a = 0; a < 8; ++a) v[a] = 1.0 + 0.1 * a + 0.01 * a * a;
+  for (int it = 0; it < 2000; ++it) {
+    double n = 0.0;
+    for (int a = 0; a < 8; ++a) {
+      double t = 0.0;
+      for (int b = 0; b < 8; ++b) t += X[a * 8 + b] / sqrt(X[a * 8 + a] * X[b * 8 + b]) * v[b];
+      w[a] = t;
+      n += t * t;
+    }
+    n = sqrt(n);
+    lam = 0.0;
+    for (int a = 0; a < 8; ++a) {
+      lam += v[a] * w[a];
+      v[a] = w[a] / n;
+    }
+  }
+  return lam;
+}
+
+/* For A = sum_e (rho_e M_e + c k_e K_e) with rho_e > 0, c k_e >= 0 and D its
+ * diagonal, the Rayleigh quotient x^T A x / x^T D x is a weighted mean of the
+ * element quotients x_e^T M_e x_e / x_e^T diag(M_e) x_e and the same for K_e,
+ * so the spectrum of D^-1 A lies below the larger of the two element maxima,
+ * for every coefficient field (Dirichlet elimination keeps it below). */
+double oracle_cheb_upper(double hx, double hy, double hz) {
+  double M[64], K[64];
+  oracle_element_matrices(hx, hy, hz, M, K);
+  const double lm = scaled_top_eigenvalue(M), lk = scaled_top_eigenvalue(K);
+  return lm > lk ? lm : lk;
+}
+
+/* s = M^-1 r for the preconditioner defined by m steps of the Chebyshev
+ * iteration for D^-1 A x = D^-1 r from x = 0 on the interval [lo, hi]:
+ * with c = (hi+lo)/2, w = (hi-lo)/2 and sigma = c/w,
+ *   x = 0, res = r, rho = 1/sigma, d = D^-1 res / c;
+ *   repeat m times: x += d; stop after the m-th; res -= A d;
+ *                   rho' = 1/(2 sigma - rho); d = rho' rho d + (2 rho'/w) D^-1 res; rho = rho'.
+ * The result is q(D^-1 A) D^-1 r where 1 - lambda q(lambda) is the Chebyshev
+ * polynomial of degree m shifted to [lo, hi] and scaled to 1 at 0: it lies in
+ * (0, 2) on [lo, hi] and in (0, 1] below lo, so M^-1 is symmetric positive
+ * definite whenever hi bounds the spectrum.  Rows with P = 0 give s = 0. */
+void oracle_cheb_apply(const oracle_csr *A, const double *P, int32_t m, double lo, double hi, const double *r,
+                       double *s, int nthreads) {
+  const int64_t n = A->n;
+  double *res = (double *)malloc((size_t)n * sizeof(double));
+  double *d = (double *)malloc((size_t)n * sizeof(double));
+  double *w = (double *)malloc((size_t)n * sizeof(double));
+  const double c = 0.5 * (hi + lo), wd = 0.5 * (hi - lo), sigma = c / wd;
+  double rho = 1.0 / sigma;
+  for (int64_t i = 0; i < n; ++i) {
+    s[i] = 0.0;
+    res[i] = r[i];
+    d[i] = P[i] > 0.0 ? res[i] / P[i] / c : 0.0;
+  }
+  for (int32_t k = 1; k <= m; ++k) {
+    for (int64_t i = 0; i < n; ++i) s[i] += d[i];
+    if (k == m) break;
+    oracle_spmv(A, d, w, nthreads);
+    const double rn = 1.0 / (2.0 * sigma - rho);
+    for (int64_t i = 0; i < n; ++i) {
+      res[i] -= w[i];
+      d[i] = rn * rho * d[i] + (2.0 * rn / wd) * (P[i] > 0.0 ? res[i] / P[i] : 0.0);
+    }
+    rho = rn;
+  }
+  free(res);
+  free(d);
+  free(w);
+}
+
+/* ------------------------------------------------------------------------- */
 /* Algorithm 1: preconditioned conjugate gradient                             */
 /* ------------------------------------------------------------------------- */
 
-int oracle_pcg(const oracle_csr *A, const double *b, double *x, int32_t max_iter, double tol_scale,
-               int32_t relative_to_initial, int32_t replace_every, int32_t locked, double *delta_out,
-               double *tol_out, int nthreads) {
+/* s = preconditioner applied to r: P^-1 r (Jacobi, Sec. 3.3) or the
+ * Chebyshev polynomial above (pc != NULL).  Rows with P = 0 (eliminated
+ * Dirichlet rows of a caller that marks them so) give 0. */
+static void precondition(const oracle_csr *A, const double *P, const oracle_precond *pc, const double *r, double *s,
+                         int nthreads) {
+  if (pc && pc->kind == ORACLE_PRECOND_CHEBYSHEV) {
+    oracle_cheb_apply(A, P, pc->degree, pc->lo, pc->hi, r, s, nthreads);
+  } else {
+    for (int64_t k = 0; k < A->n; ++k) s[k] = P[k] > 0.0 ? r[k] / P[k] : 0.0;
+  }
+}
+
+int oracle_pcg_prec(const oracle_csr *A, const double *b, double *x, int32_t max_iter, double tol_scale,
+                    int32_t relative_to_initial, int32_t replace_every, int32_t locked, const oracle_precond *pc,
+                    const double *Pdiag, double *delta_out, double *tol_out, int nthreads) {
   const int64_t n = A->n;
   double *P = (double *)malloc((size_t)n * sizeof(double));
   double *r = (double *)malloc((size_t)n * sizeof(double));
@@ -333,13 +425,16 @@ int oracle_pcg(const oracle_csr *A, const double *b, double *x, int32_t max_iter
     free(P); free(r); free(d); free(q); free(s);
     return ORACLE_ENOMEM;
   }
-  diag_of(A, P);
+  if (Pdiag)
+    memcpy(P, Pdiag, (size_t)n * sizeof(double));
+  else
+    diag_of(A, P);
   int status = 0;
   int32_t i = 0;
-  /* r <- b - A x ; d <- P^-1 r ; delta_new <- r^T d */
+  /* r <- b - A x ; d <- M^-1 r ; delta_new <- r^T d */
   oracle_spmv(A, x, r, nthreads);
   for (int64_t k = 0; k < n; ++k) r[k] = b[k] - r[k];
-  for (int64_t k = 0; k < n; ++k) d[k] = r[k] / P[k];
+  precondition(A, P, pc, r, d, nthreads);
   double delta_new = dot(r, d, n, nthreads);
   const double tol = relative_to_initial ? tol_scale * delta_new : tol_scale;
   *tol_out = tol;
@@ -363,7 +458,7 @@ int oracle_pcg(const oracle_csr *A, const double *b, double *x, int32_t max_iter
     } else {
       for (int64_t k = 0; k < n; ++k) r[k] -= alpha * q[k];
     }
-    for (int64_t k = 0; k < n; ++k) s[k] = r[k] / P[k];
+    precondition(A, P, pc, r, s, nthreads);         /* s <- M^-1 r */
     const double delta_old = delta_new;             /* delta_old is not assigned in the listing */
     delta_new = dot(r, s, n, nthreads);
     if (!isfinite(delta_new)) {
@@ -377,6 +472,13 @@ int oracle_pcg(const oracle_csr *A, const double *b, double *x, int32_t max_iter
   *delta_out = delta_new;
   free(P); free(r); free(d); free(q); free(s);
   return status ? status : i;
+}
+
+int oracle_pcg(const oracle_csr *A, const double *b, double *x, int32_t max_iter, double tol_scale,
+               int32_t relative_to_initial, int32_t replace_every, int32_t locked, double *delta_out,
+               double *tol_out, int nthreads) {
+  return oracle_pcg_prec(A, b, x, max_iter, tol_scale, relative_to_initial, replace_every, locked, NULL, NULL,
+                         delta_out, tol_out, nthreads);
 }
 
 /* ------------------------------------------------------------------------- */
@@ -394,6 +496,8 @@ static int valid(const oracle_problem *p, const oracle_controls *c) {
   if (c) {
     if (!(c->dt > 0) || !(c->theta >= 0 && c->theta <= 1) || !(c->rtol > 0) || c->nsteps < 0) return 0;
     if (c->max_iter < 0 || c->replace_every < 0) return 0;
+    if (c->precond != ORACLE_PRECOND_JACOBI && c->precond != ORACLE_PRECOND_CHEBYSHEV) return 0;
+    if (c->precond == ORACLE_PRECOND_CHEBYSHEV && (c->cheb_degree < 2 || !(c->cheb_ratio > 1.0))) return 0;
   }
   return 1;
 }
@@ -428,6 +532,7 @@ int oracle_run(const oracle_problem *p, const double *T0, const double *T_prev, 
   double *x = (double *)malloc((size_t)N * sizeof(double));
   double *b = (double *)malloc((size_t)N * sizeof(double));
   double *w = (double *)malloc((size_t)N * sizeof(double));
+  double *Pm = NULL, *bf = NULL;
   if (!F || !g || !dir || !lift || !P || !T1 || !T2 || !x || !b || !w) {
     status = ORACLE_ENOMEM;
     goto done;
@@ -448,6 +553,24 @@ int oracle_run(const oracle_problem *p, const double *T0, const double *T_prev, 
       }
     }
   diag_of(&A, P);
+  /* Chebyshev preconditioner: interval [hi/ratio, hi] from the bound of the
+   * spectrum of D^-1 A; the diagonal it scales by is 0 on Dirichlet rows, so
+   * they stay out of every preconditioned vector */
+  const int cheb = c->precond == ORACLE_PRECOND_CHEBYSHEV;
+  oracle_precond pc = {ORACLE_PRECOND_JACOBI, 0, 0.0, 0.0};
+  if (cheb) {
+    Pm = (double *)malloc((size_t)N * sizeof(double));
+    bf = (double *)malloc((size_t)N * sizeof(double));
+    if (!Pm || !bf) {
+      status = ORACLE_ENOMEM;
+      goto done;
+    }
+    pc.kind = ORACLE_PRECOND_CHEBYSHEV;
+    pc.degree = c->cheb_degree;
+    pc.hi = oracle_cheb_upper(p->hx, p->hy, p->hz);
+    pc.lo = pc.hi / c->cheb_ratio;
+    for (int64_t i = 0; i < N; ++i) Pm[i] = dir[i] ? 0.0 : P[i];
+  }
 
   for (int64_t i = 0; i < N; ++i) {
     T1[i] = dir[i] ? g[i] : T0[i];
@@ -463,7 +586,14 @@ int oracle_run(const oracle_problem *p, const double *T0, const double *T_prev, 
       b[i] = dir[i] ? g[i] : b[i] - lift[i];
       w[i] = dir[i] ? 0.0 : b[i] / P[i];
     }
-    const double delta_b = dot(b, w, N, nt);
+    double delta_b;
+    if (cheb) {  /* b^T M^-1 b over the free rows, M^-1 the Chebyshev preconditioner */
+      for (int64_t i = 0; i < N; ++i) bf[i] = dir[i] ? 0.0 : b[i];
+      oracle_cheb_apply(&A, Pm, pc.degree, pc.lo, pc.hi, bf, w, nt);
+      delta_b = dot(bf, w, N, nt);
+    } else {
+      delta_b = dot(b, w, N, nt);
+    }
     for (int64_t i = 0; i < N; ++i)
       x[i] = (c->guess == ORACLE_GUESS_PREV) ? T1[i] : 2.0 * T1[i] - T2[i];
     int it;
@@ -474,8 +604,9 @@ int oracle_run(const oracle_problem *p, const double *T0, const double *T_prev, 
       it = 0;
     } else {
       const double rt2 = c->rtol * c->rtol;
-      it = oracle_pcg(&A, b, x, c->max_iter, c->stop_rule == ORACLE_STOP_RHS ? rt2 * delta_b : rt2,
-                      c->stop_rule == ORACLE_STOP_INITIAL, c->replace_every, locked, &delta, &tol, nt);
+      it = oracle_pcg_prec(&A, b, x, c->max_iter, c->stop_rule == ORACLE_STOP_RHS ? rt2 * delta_b : rt2,
+                           c->stop_rule == ORACLE_STOP_INITIAL, c->replace_every, locked, cheb ? &pc : NULL,
+                           cheb ? Pm : NULL, &delta, &tol, nt);
       if (it < 0) {
         status = it;
         goto done;
@@ -499,5 +630,6 @@ done:
   oracle_csr_free(&A);
   oracle_csr_free(&L);
   free(F); free(g); free(dir); free(lift); free(P); free(T1); free(T2); free(x); free(b); free(w);
+  free(Pm); free(bf);
   return status;
 }

@@ -38,6 +38,15 @@ enum {
 
 enum { ORACLE_GUESS_EXTRAP = 0, ORACLE_GUESS_PREV = 1 };
 enum { ORACLE_STOP_RHS = 0, ORACLE_STOP_INITIAL = 1 };
+enum { ORACLE_PRECOND_JACOBI = 0, ORACLE_PRECOND_CHEBYSHEV = 1 };
+
+/* A preconditioner for oracle_pcg_prec: Jacobi (Sec. 3.3), or the Chebyshev
+ * polynomial of `degree` on [lo, hi] in the Jacobi-scaled operator. */
+typedef struct {
+  int32_t kind;
+  int32_t degree;
+  double lo, hi;
+} oracle_precond;
 
 typedef struct {
   int32_t nx, ny, nz;
@@ -62,6 +71,9 @@ typedef struct {
   int32_t first_step;     /* global index of the step before the first one of this run */
   const int32_t *locked_iters; /* NULL: stop by the tolerance; else run exactly these counts */
   int32_t nthreads;
+  int32_t precond;        /* ORACLE_PRECOND_*; the stop rule's norm is the preconditioner's */
+  int32_t cheb_degree;    /* Chebyshev: polynomial degree m >= 2 (m - 1 operator applies) */
+  double cheb_ratio;      /* Chebyshev: interval [hi/ratio, hi], hi = oracle_cheb_upper */
 } oracle_controls;
 
 typedef struct {
@@ -121,6 +133,22 @@ int oracle_run(const oracle_problem *p, const double *T0, const double *T_prev,
 int oracle_pcg(const oracle_csr *A, const double *b, double *x, int32_t max_iter,
                double tol_scale, int32_t relative_to_initial, int32_t replace_every,
                int32_t locked, double *delta_out, double *tol_out, int nthreads);
+
+/* Upper bound of the spectrum of D^-1 A (D = diag A) for every coefficient
+ * field on this element box: the larger of the element maxima for the mass
+ * and the stiffness block, each by power iteration on the 8x8 block. */
+double oracle_cheb_upper(double hx, double hy, double hz);
+
+/* s = q(D^-1 A) D^-1 r: m steps of the Chebyshev iteration on [lo, hi] from 0
+ * (m - 1 products with A); rows with P[i] = 0 give s[i] = 0. */
+void oracle_cheb_apply(const oracle_csr *A, const double *P, int32_t m, double lo, double hi, const double *r,
+                       double *s, int nthreads);
+
+/* oracle_pcg with a preconditioner (pc NULL: Jacobi) and optionally the
+ * diagonal it scales by (Pdiag NULL: diag A).  delta = r^T M^-1 r. */
+int oracle_pcg_prec(const oracle_csr *A, const double *b, double *x, int32_t max_iter, double tol_scale,
+                    int32_t relative_to_initial, int32_t replace_every, int32_t locked, const oracle_precond *pc,
+                    const double *Pdiag, double *delta_out, double *tol_out, int nthreads);
 
 #ifdef __cplusplus
 }

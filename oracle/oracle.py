@@ -22,6 +22,7 @@ SRC_PATH = os.path.join(_HERE, "fem_oracle.c")
 OK, EINVAL, ENOMEM, ENOCONV, EBREAKDOWN = 0, -1, -2, -3, -4
 GUESS_EXTRAP, GUESS_PREV = 0, 1
 STOP_RHS, STOP_INITIAL = 0, 1
+PRECOND_JACOBI, PRECOND_CHEBYSHEV = 0, 1
 
 _dp = ctypes.POINTER(ctypes.c_double)
 _ip = ctypes.POINTER(ctypes.c_int32)
@@ -50,7 +51,13 @@ class _Controls(ctypes.Structure):
                 ("nsteps", ctypes.c_int32), ("max_iter", ctypes.c_int32),
                 ("replace_every", ctypes.c_int32), ("guess", ctypes.c_int32),
                 ("stop_rule", ctypes.c_int32), ("first_step", ctypes.c_int32),
-                ("locked_iters", _ip), ("nthreads", ctypes.c_int32)]
+                ("locked_iters", _ip), ("nthreads", ctypes.c_int32), ("precond", ctypes.c_int32),
+                ("cheb_degree", ctypes.c_int32), ("cheb_ratio", ctypes.c_double)]
+
+
+class _Precond(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("degree", ctypes.c_int32), ("lo", ctypes.c_double),
+                ("hi", ctypes.c_double)]
 
 
 class _Outputs(ctypes.Structure):
@@ -86,7 +93,15 @@ def lib():
                                  ctypes.POINTER(_Outputs)]
         L.oracle_pcg.argtypes = [ctypes.POINTER(_CSR), _dp, _dp, ctypes.c_int32, ctypes.c_double,
                                  ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _dp, _dp, ctypes.c_int]
-        for name in ("oracle_assemble", "oracle_run", "oracle_pcg"):
+        L.oracle_pcg_prec.argtypes = [ctypes.POINTER(_CSR), _dp, _dp, ctypes.c_int32, ctypes.c_double,
+                                      ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(_Precond), _dp,
+                                      _dp, _dp, ctypes.c_int]
+        L.oracle_cheb_upper.argtypes = [ctypes.c_double] * 3
+        L.oracle_cheb_upper.restype = ctypes.c_double
+        L.oracle_cheb_apply.argtypes = [ctypes.POINTER(_CSR), _dp, ctypes.c_int32, ctypes.c_double, ctypes.c_double,
+                                        _dp, _dp, ctypes.c_int]
+        L.oracle_cheb_apply.restype = None
+        for name in ("oracle_assemble", "oracle_run", "oracle_pcg", "oracle_pcg_prec"):
             getattr(L, name).restype = ctypes.c_int
         _lib_handle = L
     return _lib_handle
@@ -177,6 +192,34 @@ class CSR:
                               _ptr(tol_used), self.nthreads)
         return x, it, float(delta[0])
 
+    def diagonal(self) -> np.ndarray:
+        rowptr, col, val = self.to_arrays()
+        P = np.zeros(self.n)
+        for i in range(self.n):
+            row = slice(rowptr[i], rowptr[i + 1])
+            P[i] = val[row][col[row] == i].sum()
+        return P
+
+    def cheb_apply(self, r, degree, lo, hi, P=None) -> np.ndarray:
+        """s = q(D^-1 A) D^-1 r, the Chebyshev preconditioner (P: the diagonal, 0 on rows left out)."""
+        r = _f64(r)
+        P = self.diagonal() if P is None else _f64(P)
+        s = np.zeros(self.n)
+        lib().oracle_cheb_apply(ctypes.byref(self._c), _ptr(P), degree, lo, hi, _ptr(r), _ptr(s), self.nthreads)
+        return s
+
+    def pcg_cheb(self, b, x0, *, degree, lo, hi, max_iter=10000, tol=0.0, relative_to_initial=False,
+                 replace_every=50, locked=-1):
+        b = _f64(b)
+        x = _f64(x0).copy()
+        delta = np.zeros(1)
+        tol_used = np.zeros(1)
+        pc = _Precond(PRECOND_CHEBYSHEV, degree, lo, hi)
+        it = lib().oracle_pcg_prec(ctypes.byref(self._c), _ptr(b), _ptr(x), max_iter, tol, int(relative_to_initial),
+                                   replace_every, locked, ctypes.byref(pc), None, _ptr(delta), _ptr(tol_used),
+                                   self.nthreads)
+        return x, it, float(delta[0])
+
     def close(self):
         if self._c.rowptr:
             lib().oracle_csr_free(ctypes.byref(self._c))
@@ -195,6 +238,11 @@ def operator_apply(prob, cm: float, ck: float, x, nthreads: int = 1) -> np.ndarr
         return A.matvec(x)
     finally:
         A.close()
+
+
+def cheb_upper(hx: float, hy: float, hz: float) -> float:
+    """The oracle's bound of the spectrum of D^-1 A on boxes of this shape."""
+    return float(lib().oracle_cheb_upper(hx, hy, hz))
 
 
 def element_loop(prob, cm: float, ck: float, x) -> np.ndarray:
@@ -231,7 +279,8 @@ def sensors(prob, T, xyz) -> np.ndarray:
 
 def run(prob, T0=None, T_prev=None, *, nsteps=None, dt=None, theta=None, rtol=None,
         max_iter=10000, replace_every=50, guess=GUESS_EXTRAP, stop_rule=STOP_RHS, first_step=0,
-        locked_iters=None, save_every=0, sensor_xyz=None, nthreads=1) -> dict:
+        locked_iters=None, save_every=0, sensor_xyz=None, nthreads=1, precond=PRECOND_JACOBI, cheb_degree=3,
+        cheb_ratio=30.0) -> dict:
     """Run the theta-scheme with the problem's controls unless overridden."""
     p = _ProblemRef(prob)
     N = p.N
@@ -250,6 +299,7 @@ def run(prob, T0=None, T_prev=None, *, nsteps=None, dt=None, theta=None, rtol=No
         assert len(locked) >= nsteps
         c.locked_iters = locked.ctypes.data_as(_ip)
     c.nthreads = nthreads
+    c.precond, c.cheb_degree, c.cheb_ratio = precond, cheb_degree, cheb_ratio
     xyz = prob.sensors if sensor_xyz is None else sensor_xyz
     xyz = None if xyz is None else _f64(xyz).reshape(-1, 3)
     S = 0 if xyz is None else len(xyz)
