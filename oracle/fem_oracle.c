@@ -94,6 +94,82 @@ void oracle_element_matrices(double hx, double hy, double hz, double *M, double 
       }
 }
 
+/* The paper's element (Sec. 4.1): every box of the fixed grid split into six
+ * linear tetrahedra.  Which six is not stated; the split taken here is the one
+ * around the box diagonal from corner 0 to corner 7, tetrahedron
+ * 0 -> 0 + e_i -> 0 + e_i + e_j -> 7 for each order (i, j, k) of the axes,
+ * which gives the same diagonal on the shared face of every two neighbouring
+ * boxes, so the mesh is conforming. */
+static const int kTet6[6][4] = {{0, 1, 3, 7}, {0, 1, 5, 7}, {0, 2, 3, 7}, {0, 2, 6, 7}, {0, 4, 5, 7}, {0, 4, 6, 7}};
+
+static void corner_xyz(int a, const double h[3], double x[3]) {
+  x[0] = (a & 1) * h[0];
+  x[1] = ((a >> 1) & 1) * h[1];
+  x[2] = ((a >> 2) & 1) * h[2];
+}
+
+/* Barycentric gradients of a tetrahedron with vertices X[4][3] and its volume:
+ * grad l_k for k = 1..3 are the rows of J^-1 with J = [X1-X0, X2-X0, X3-X0]
+ * (columns), grad l_0 = -(sum of the others). */
+static double tet_gradients(const double X[4][3], double G[4][3]) {
+  double J[3][3];
+  for (int d = 0; d < 3; ++d)
+    for (int k = 0; k < 3; ++k) J[d][k] = X[k + 1][d] - X[0][d];
+  const double det = J[0][0] * (J[1][1] * J[2][2] - J[1][2] * J[2][1]) -
+                     J[0][1] * (J[1][0] * J[2][2] - J[1][2] * J[2][0]) +
+                     J[0][2] * (J[1][0] * J[2][1] - J[1][1] * J[2][0]);
+  double inv[3][3];
+  inv[0][0] = (J[1][1] * J[2][2] - J[1][2] * J[2][1]) / det;
+  inv[0][1] = (J[0][2] * J[2][1] - J[0][1] * J[2][2]) / det;
+  inv[0][2] = (J[0][1] * J[1][2] - J[0][2] * J[1][1]) / det;
+  inv[1][0] = (J[1][2] * J[2][0] - J[1][0] * J[2][2]) / det;
+  inv[1][1] = (J[0][0] * J[2][2] - J[0][2] * J[2][0]) / det;
+  inv[1][2] = (J[0][2] * J[1][0] - J[0][0] * J[1][2]) / det;
+  inv[2][0] = (J[1][0] * J[2][1] - J[1][1] * J[2][0]) / det;
+  inv[2][1] = (J[0][1] * J[2][0] - J[0][0] * J[2][1]) / det;
+  inv[2][2] = (J[0][0] * J[1][1] - J[0][1] * J[1][0]) / det;
+  for (int d = 0; d < 3; ++d) {
+    G[0][d] = 0.0;
+    for (int k = 0; k < 3; ++k) {
+      G[k + 1][d] = inv[k][d];
+      G[0][d] -= inv[k][d];
+    }
+  }
+  return fabs(det) / 6.0;
+}
+
+/* 8x8 box matrices of the six-tetrahedron split: the sum of the 4x4
+ * tetrahedron matrices M_t = int l_i l_j (4-point Gauss rule, exact for
+ * quadratics) and K_t = int grad l_i . grad l_j (constant gradients). */
+void oracle_tet6_matrices(double hx, double hy, double hz, double *M, double *K) {
+  const double h[3] = {hx, hy, hz};
+  const double qa = 0.5854101966249685, qb = 0.1381966011250105; /* (5 +- 3 sqrt 5)/20 */
+  memset(M, 0, 64 * sizeof(double));
+  memset(K, 0, 64 * sizeof(double));
+  for (int t = 0; t < 6; ++t) {
+    double X[4][3], G[4][3];
+    for (int k = 0; k < 4; ++k) corner_xyz(kTet6[t][k], h, X[k]);
+    const double V = tet_gradients(X, G);
+    for (int q = 0; q < 4; ++q) {
+      double l[4];
+      for (int k = 0; k < 4; ++k) l[k] = (k == q) ? qa : qb;
+      for (int i = 0; i < 4; ++i)
+        for (int j = 0; j < 4; ++j) M[kTet6[t][i] * 8 + kTet6[t][j]] += 0.25 * V * l[i] * l[j];
+    }
+    for (int i = 0; i < 4; ++i)
+      for (int j = 0; j < 4; ++j)
+        K[kTet6[t][i] * 8 + kTet6[t][j]] += V * (G[i][0] * G[j][0] + G[i][1] * G[j][1] + G[i][2] * G[j][2]);
+  }
+}
+
+/* The 8x8 blocks of one box of the problem's element kind. */
+static void box_matrices(const oracle_problem *p, double *M, double *K) {
+  if (p->element == ORACLE_ELEM_TET6)
+    oracle_tet6_matrices(p->hx, p->hy, p->hz, M, K);
+  else
+    oracle_element_matrices(p->hx, p->hy, p->hz, M, K);
+}
+
 /* ------------------------------------------------------------------------- */
 /* assembly into CSR (Sec. 3.2, the assembly operator)                        */
 /* ------------------------------------------------------------------------- */
@@ -113,7 +189,7 @@ int oracle_assemble(const oracle_problem *p, double cm, double ck, oracle_csr *o
   const int nx = p->nx, ny = p->ny, nz = p->nz;
   const int64_t N = n_nodes(p);
   double M[64], K[64];
-  oracle_element_matrices(p->hx, p->hy, p->hz, M, K);
+  box_matrices(p, M, K);
   int64_t *rowptr = (int64_t *)malloc((size_t)(N + 1) * sizeof(int64_t));
   if (!rowptr) return ORACLE_ENOMEM;
   rowptr[0] = 0;
@@ -194,7 +270,7 @@ void oracle_spmv(const oracle_csr *a, const double *x, double *y, int nthreads) 
 
 void oracle_element_loop(const oracle_problem *p, double cm, double ck, const double *x, double *y) {
   double M[64], K[64];
-  oracle_element_matrices(p->hx, p->hy, p->hz, M, K);
+  box_matrices(p, M, K);
   memset(y, 0, (size_t)n_nodes(p) * sizeof(double));
   for (int ez = 0; ez < p->nz; ++ez)
     for (int ey = 0; ey < p->ny; ++ey)
@@ -227,6 +303,31 @@ void oracle_load_vector(const oracle_problem *p, double *F) {
     const int u = (d + 1) % 3, v = (d + 2) % 3; /* in-face axes */
     const int fixed = (f % 2) ? n[d] : 0;
     const double area = h[u] * h[v];
+    if (p->element == ORACLE_ELEM_TET6) {
+      /* the faces of the tetrahedra on a box face: two triangles split by the
+       * diagonal from its low corner (0,0) to its high corner (1,1) in the two
+       * in-face axes; each vertex gets the integral of its linear function by
+       * the 3-point edge-midpoint rule (exact for quadratics) */
+      const int tri[2][3][2] = {{{0, 0}, {1, 0}, {1, 1}}, {{0, 0}, {0, 1}, {1, 1}}};
+      for (int eu = 0; eu < n[u]; ++eu)
+        for (int ev = 0; ev < n[v]; ++ev)
+          for (int t = 0; t < 2; ++t)
+            for (int k = 0; k < 3; ++k) {
+              double s = 0.0;
+              for (int m = 0; m < 3; ++m) { /* midpoint of the edge opposite to vertex m */
+                double lk = 0.0;
+                for (int j = 0; j < 3; ++j)
+                  if (j != m) lk += (j == k) ? 0.5 : 0.0;
+                s += (0.5 * area / 3.0) * lk;
+              }
+              int idx[3];
+              idx[d] = fixed;
+              idx[u] = eu + tri[t][k][0];
+              idx[v] = ev + tri[t][k][1];
+              F[node_id(p, idx[0], idx[1], idx[2])] += q * s;
+            }
+      continue;
+    }
     for (int eu = 0; eu < n[u]; ++eu)
       for (int ev = 0; ev < n[v]; ++ev)
         for (int c = 0; c < 4; ++c) {
@@ -278,9 +379,33 @@ void oracle_sensors(const oracle_problem *p, const double *T, const double *xyz,
       xi[d] = loc;
     }
     double v = 0.0;
-    for (int a = 0; a < 8; ++a) {
-      const int ax = a & 1, ay = (a >> 1) & 1, az = (a >> 2) & 1;
-      v += phi(ax, xi[0]) * phi(ay, xi[1]) * phi(az, xi[2]) * T[node_id(p, e[0] + ax, e[1] + ay, e[2] + az)];
+    if (p->element == ORACLE_ELEM_TET6) {
+      /* the tetrahedron whose barycentric coordinates of the point are all
+       * >= 0 (the first one, on shared faces), the field linear in it */
+      const double hu[3] = {1.0, 1.0, 1.0};
+      int found = 0;
+      for (int t = 0; t < 6 && !found; ++t) {
+        double X[4][3], G[4][3], l[4];
+        for (int k = 0; k < 4; ++k) corner_xyz(kTet6[t][k], hu, X[k]);
+        (void)tet_gradients(X, G);
+        double mn = 1.0;
+        for (int k = 1; k < 4; ++k) {
+          l[k] = G[k][0] * (xi[0] - X[0][0]) + G[k][1] * (xi[1] - X[0][1]) + G[k][2] * (xi[2] - X[0][2]);
+        }
+        l[0] = 1.0 - l[1] - l[2] - l[3];
+        for (int k = 0; k < 4; ++k) mn = l[k] < mn ? l[k] : mn;
+        if (mn < -1e-12) continue;
+        found = 1;
+        for (int k = 0; k < 4; ++k) {
+          const int a = kTet6[t][k];
+          v += l[k] * T[node_id(p, e[0] + (a & 1), e[1] + ((a >> 1) & 1), e[2] + ((a >> 2) & 1))];
+        }
+      }
+    } else {
+      for (int a = 0; a < 8; ++a) {
+        const int ax = a & 1, ay = (a >> 1) & 1, az = (a >> 2) & 1;
+        v += phi(ax, xi[0]) * phi(ay, xi[1]) * phi(az, xi[2]) * T[node_id(p, e[0] + ax, e[1] + ay, e[2] + az)];
+      }
     }
     out[s] = v;
   }
@@ -487,6 +612,8 @@ int oracle_pcg(const oracle_csr *A, const double *b, double *x, int32_t max_iter
 
 static int valid(const oracle_problem *p, const oracle_controls *c) {
   if (p->nx < 1 || p->ny < 1 || p->nz < 1) return 0;
+  if (p->element != ORACLE_ELEM_HEX8 && p->element != ORACLE_ELEM_TET6) return 0;
+  if (c && c->precond == ORACLE_PRECOND_CHEBYSHEV && p->element != ORACLE_ELEM_HEX8) return 0;
   if (!(p->hx > 0) || !(p->hy > 0) || !(p->hz > 0)) return 0;
   if ((p->dirichlet_mask | p->flux_mask) >= 64u || (p->dirichlet_mask & p->flux_mask)) return 0;
   for (int64_t e = 0; e < n_elems(p); ++e) {

@@ -38,6 +38,7 @@ enum {
 
 enum { ORACLE_GUESS_EXTRAP = 0, ORACLE_GUESS_PREV = 1 };
 enum { ORACLE_STOP_RHS = 0, ORACLE_STOP_INITIAL = 1 };
+enum { ORACLE_ELEM_HEX8 = 0, ORACLE_ELEM_TET6 = 1 };
 enum { ORACLE_PRECOND_JACOBI = 0, ORACLE_PRECOND_CHEBYSHEV = 1 };
 
 /* A preconditioner for oracle_pcg_prec: Jacobi (Sec. 3.3), or the Chebyshev
@@ -59,6 +60,8 @@ typedef struct {
   double flux[6];          /* inward flux q per face */
   const double *flux_schedule; /* s_m for global step m = 1..n_schedule; NULL: s = 1 */
   int32_t n_schedule;
+  int32_t element;         /* ORACLE_ELEM_HEX8: one trilinear hexahedron per box; ORACLE_ELEM_TET6: six
+                              linear tetrahedra per box around its 0-7 diagonal (Sec. 4.1) */
 } oracle_problem;
 
 typedef struct {
@@ -98,6 +101,10 @@ typedef struct {
 /* Element mass and stiffness matrices (8x8, row-major) of the trilinear
  * hexahedron hx*hy*hz by 2x2x2 Gauss-Legendre quadrature (Sec. 3.2). */
 void oracle_element_matrices(double hx, double hy, double hz, double *M, double *K);
+
+/* 8x8 box matrices of the six-tetrahedron split (sum of the six linear
+ * tetrahedra of the box, mass by a 4-point Gauss rule). */
+void oracle_tet6_matrices(double hx, double hy, double hz, double *M, double *K);
 
 /* Assembled CSR of  sum_e (cm*rhoc_e*M_e + ck*k_e*K_e)  (no boundary rows
  * modified).  Returns ORACLE_OK or ORACLE_ENOMEM. */

@@ -23,6 +23,7 @@ OK, EINVAL, ENOMEM, ENOCONV, EBREAKDOWN = 0, -1, -2, -3, -4
 GUESS_EXTRAP, GUESS_PREV = 0, 1
 STOP_RHS, STOP_INITIAL = 0, 1
 PRECOND_JACOBI, PRECOND_CHEBYSHEV = 0, 1
+ELEM_HEX8, ELEM_TET6 = 0, 1
 
 _dp = ctypes.POINTER(ctypes.c_double)
 _ip = ctypes.POINTER(ctypes.c_int32)
@@ -43,7 +44,7 @@ class _Problem(ctypes.Structure):
                 ("k_e", _dp), ("rhoc_e", _dp),
                 ("dirichlet_mask", ctypes.c_uint32), ("dirichlet_value", ctypes.c_double * 6),
                 ("flux_mask", ctypes.c_uint32), ("flux", ctypes.c_double * 6),
-                ("flux_schedule", _dp), ("n_schedule", ctypes.c_int32)]
+                ("flux_schedule", _dp), ("n_schedule", ctypes.c_int32), ("element", ctypes.c_int32)]
 
 
 class _Controls(ctypes.Structure):
@@ -81,6 +82,7 @@ def lib():
             build()
         L = ctypes.CDLL(LIB_PATH)
         L.oracle_element_matrices.argtypes = [ctypes.c_double] * 3 + [_dp, _dp]
+        L.oracle_tet6_matrices.argtypes = [ctypes.c_double] * 3 + [_dp, _dp]
         L.oracle_assemble.argtypes = [ctypes.POINTER(_Problem), ctypes.c_double, ctypes.c_double,
                                       ctypes.POINTER(_CSR), ctypes.c_int]
         L.oracle_csr_free.argtypes = [ctypes.POINTER(_CSR)]
@@ -134,6 +136,7 @@ class _ProblemRef:
         s.flux = (ctypes.c_double * 6)(*[float(v) for v in prob.flux])
         s.flux_schedule = _ptr(self.sched)
         s.n_schedule = 0 if self.sched is None else len(self.sched)
+        s.element = getattr(prob, "element", ELEM_HEX8)
         self.s = s
         self.N = prob.n_nodes
 
@@ -146,6 +149,13 @@ def element_matrices(hx: float, hy: float, hz: float):
     M = np.zeros(64)
     K = np.zeros(64)
     lib().oracle_element_matrices(hx, hy, hz, _ptr(M), _ptr(K))
+    return M.reshape(8, 8), K.reshape(8, 8)
+
+
+def tet6_matrices(hx: float, hy: float, hz: float):
+    M = np.zeros(64)
+    K = np.zeros(64)
+    lib().oracle_tet6_matrices(hx, hy, hz, _ptr(M), _ptr(K))
     return M.reshape(8, 8), K.reshape(8, 8)
 
 

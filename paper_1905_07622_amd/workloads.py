@@ -62,6 +62,7 @@ class Problem:
     flux_schedule: Optional[np.ndarray] = None   # s_n for n = 1..len; None means 1 always
     sensors: Optional[np.ndarray] = None         # (S, 3) float64 points
     seed: Optional[int] = None
+    element: int = 0                             # 0: trilinear hexahedra; 1: six linear tetrahedra per box
 
     @property
     def n_nodes(self) -> int:
