@@ -504,6 +504,72 @@ def bench_served(args, torch):
             "p99_ratio_plain_over_served": round((plain_loose or plain)["p99_s"] / served["p99_s"], 3)}
 
 
+def bench_cheb(args, torch, p, k, rc, T0, jac_ms, jac_iters, T_jac):
+    """The headline workload with the Chebyshev-accelerated Jacobi preconditioner (degree m: m - 1 extra
+    gathers per PCG iteration) against the Jacobi runs of the headline: iterations, run time and the time-to-
+    solution ratio, and the final field against the Jacobi field (both stop at rtol 1e-8 in their own norm)."""
+    from paper_1905_07622_amd import femheat as fh
+    stream = torch.cuda.current_stream().cuda_stream
+    out = {"workload": "the headline workload (FP64) with the Chebyshev preconditioner on [hi/30, hi]",
+           "jacobi": {"ms_per_run": round(jac_ms, 2), "iterations_per_run": int(jac_iters)}}
+    for m in args.cheb_degrees:
+        h = fh.Heat(p.nx, p.ny, p.nz, p.hx, p.hy, p.hz, k, rc, dirichlet_mask=p.dirichlet_mask, flux_mask=p.flux_mask,
+                    flux=p.flux, device_ptrs=True, stream=stream, precond=fh.FEM_PRECOND_CHEBYSHEV, cheb_degree=m,
+                    tune_cache=getattr(args, "tune_cache_path", None))
+        kw = dict(dt=p.dt, theta=p.theta, nsteps=p.nsteps, rtol=p.rtol)
+        h.run(T0, **kw)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r = h.run(T0, **kw)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3
+        h.close()
+        its = int(r["total_iters"])
+        out[f"degree_{m}"] = {"ms_per_run": round(ms, 2), "iterations_per_run": its,
+                              "gathers_per_run": its * m, "speedup_vs_jacobi": round(jac_ms / ms, 3),
+                              "MDOF_iter_per_s": round(p.n_nodes * its / ms / 1e3, 1),
+                              "rel_l2_vs_jacobi_field": _rel(r["T_final"], T_jac, torch)}
+        print(f"chebyshev m={m}: {its} iterations, {ms:.1f} ms (Jacobi {jac_iters}, {jac_ms:.1f} ms)",
+              file=sys.stderr, flush=True)
+    return out
+
+
+def bench_laminate(args, torch):
+    """The paper's own performance workload (Sec. 5.1, Table 2): the two-layer laminate, 50 Crank-Nicolson
+    steps, rtol 1e-6, with the paper's element (six tetrahedra per cube) at the paper's mesh sizes, FP64:
+    PCG iterations over the 50 steps beside the paper's totals (its stop rule and guess may differ from the
+    readings here), time per iteration and MDOF*iter/s; the hexahedral element on the same grids for
+    comparison."""
+    from paper_1905_07622_amd import femheat as fh
+    from paper_1905_07622_amd import workloads as wl
+    stream = torch.cuda.current_stream().cuda_stream
+    paper_iters = {30: 287, 60: 344, 90: 567, 120: 780, 150: 1047, 180: 1278}
+    rows = []
+    for n in args.laminate_sizes:
+        row = {"n": n}
+        for name, el in (("tet6", fh.FEM_ELEM_TET6), ("hex8", fh.FEM_ELEM_HEX8)):
+            p = _to_device(wl.laminate(n, element=el), torch)
+            with fh.Heat.from_problem(p, device_ptrs=True, stream=stream) as h:
+                kw = dict(dt=p.dt, theta=p.theta, nsteps=p.nsteps, rtol=p.rtol)
+                h.run(p.T0, **dict(kw, nsteps=2))
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                r = h.run(p.T0, **kw)
+                torch.cuda.synchronize()
+                secs = time.perf_counter() - t0
+            its = int(r["total_iters"])
+            row["dof"] = p.n_nodes
+            row[name] = {"iterations": its, "ms_total": round(secs * 1e3, 2),
+                         "us_per_iteration": round(secs * 1e6 / max(its, 1), 2),
+                         "MDOF_iter_per_s": round(p.n_nodes * its / secs / 1e6, 1)}
+        row["paper_fg_dbd_iterations"] = paper_iters.get(n)
+        rows.append(row)
+        print(f"laminate n={n}: tet6 {row['tet6']['iterations']} it, hex8 {row['hex8']['iterations']} it "
+              f"(paper {row['paper_fg_dbd_iterations']})", file=sys.stderr, flush=True)
+    return {"workload": "two-layer laminate [-15,15]^2 x [0,10] mm, steel/oxide at x3 = 5, unit flux on x3 = 0, "
+                        "50 CN steps dt 0.01, rtol 1e-6, FP64 Jacobi-PCG", "sizes": rows}
+
+
 def slab_oracle(nthreads):
     """The FP64 oracle over the whole defect-slab run, every step and the
     surface traces kept (run on the host while the GPU does other work)."""
@@ -595,6 +661,8 @@ def main():
     ap.add_argument("--serve-probe", type=int, default=20, help="requests that choose the loose plain rtol")
     ap.add_argument("--serve-oracle", type=int, default=6, help="served requests of edge <= 64 checked by the oracle")
     ap.add_argument("--no-slab", action="store_true", help="skip the defect-slab run and its oracle")
+    ap.add_argument("--cheb-degrees", type=int, nargs="*", default=[2, 3, 4])
+    ap.add_argument("--laminate-sizes", type=int, nargs="*", default=[30, 60, 90, 120, 150])
     ap.add_argument("--no-tune", action="store_true", help="use the library's tile rule (no autotuning)")
     ap.add_argument("--tune-cache", default=os.path.join(ROOT, "gpurun_out", "femheat_tune.json"))
     ap.add_argument("--copy-calibration", action="store_true",
@@ -726,6 +794,11 @@ def main():
         extra["inverse"] = bench_inverse(args, torch)
     if args.precision == "fp64" and not args.no_apply_ab:
         extra["context"] = bench_context(torch, per_iter["gather"])
+    if args.precision == "fp64" and args.cheb_degrees:
+        extra["chebyshev"] = bench_cheb(args, torch, p, k, rc, T0, float(np.median(run_ms)), int(last["total_iters"]),
+                                        last["T_final"])
+    if args.laminate_sizes:
+        extra["laminate_tet6"] = bench_laminate(args, torch)
     if not args.no_batched:
         extra["batched"] = bench_batched(args, torch)
     if not args.no_served:

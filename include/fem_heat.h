@@ -61,6 +61,26 @@ extern "C" {
 #define FEM_STOP_RHS 0       /* continue while r^T P^-1 r > rtol^2 b^T P^-1 b      */
 #define FEM_STOP_INITIAL 1   /* continue while r^T P^-1 r > rtol^2 r0^T P^-1 r0    */
 
+#define FEM_ELEM_HEX8 0         /* one 8-node trilinear hexahedron per box of the grid */
+#define FEM_ELEM_TET6 1         /* the paper's element (Sec. 4.1): every box split into six linear
+                                   tetrahedra 0, e_i, e_i + e_j, 7 (one per order of the axes; the
+                                   split around the box's 0-7 diagonal, conforming between boxes).
+                                   Cubic boxes only (hx = hy = hz).  Face loads come from the
+                                   faces' triangles, sensors are linear in their tetrahedron.
+                                   Not with FEM_OP_ELEMENTWISE / FEM_OP_ROWWAVE or the Chebyshev
+                                   preconditioner (FEM_EINVAL) */
+
+#define FEM_PRECOND_JACOBI 0    /* P = diag(A) (Sec. 3.3)                            */
+#define FEM_PRECOND_CHEBYSHEV 1 /* M^-1 = q(D^-1 A) D^-1, D = diag(A), with 1 - lambda q(lambda) the
+                                   Chebyshev polynomial of degree m = cheb_degree on
+                                   [hi/cheb_ratio, hi], scaled to 1 at 0; hi bounds the spectrum of
+                                   D^-1 A for every coefficient field (27/8 for cubic elements).
+                                   Applied matrix-free as m steps of the Chebyshev iteration from 0
+                                   (m - 1 gathers per application).  Not in the paper, whose GPU
+                                   method uses Jacobi only.  The stop rule's norm (P^-1 above) is
+                                   M^-1.  FP64 two-kernel form only (FEM_EINVAL with the mixed form
+                                   or FEM_ONE_REDUCTION) */
+
 #define FEM_DEVICE_PTRS 0x1u /* array arguments are device pointers               */
 #define FEM_TIMING 0x2u      /* time iteration kernels with HIP events (every 64th iteration and every
                                 8th residual replacement launched, counted across solves, so the
@@ -152,6 +172,10 @@ typedef struct {
                              fit two staging slots per thread: FEM_EINVAL otherwise            */
   const fem_allocator *allocator; /* device memory (NULL: see fem_allocator); must outlive
                              every handle and server created with these options          */
+  int32_t precond;        /* FEM_PRECOND_* (default Jacobi)                                  */
+  int32_t cheb_degree;    /* Chebyshev: 2 .. 8 (default 3)                                   */
+  double cheb_ratio;      /* Chebyshev: hi / lo of the interval, > 1 (default 30)            */
+  int32_t element;        /* FEM_ELEM_* (default FEM_ELEM_HEX8)                              */
   const char *tune_cache; /* path of the autotuner's tile cache (JSON), or NULL.  When set and no
                              tile override is given, a handle takes the gather tile recorded
                              there for its node grid, precision, element class and launch kind

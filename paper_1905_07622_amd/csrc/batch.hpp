@@ -65,6 +65,14 @@ struct SimDev {
   int32_t exc;         // mixed form: e buffer of the last inner solution
   int32_t sweep;       // mixed form: this sweep runs an inner solve and a correction
   double inner_rtol;   // mixed form: floor of the inner relative tolerance
+  // Chebyshev preconditioner (FP64 solves): the preconditioned residual s,
+  // the chain's residual and direction ping-pong, 1/c and the coefficients
+  // a_k = rho_k rho_{k-1}, b_k = 2 rho_k / w of its steps k = 1 .. m-1
+  double* s64;
+  double* cr64;
+  double* cd64[2];
+  double ch_inv_c;
+  double ch_a[kChebMaxDegree], ch_b[kChebMaxDegree];
 };
 
 // What the update kernel of a launch with a single simulation needs, passed
@@ -95,6 +103,9 @@ struct BatchArgs {
   int32_t next_xc;     // next-step launches: iterate buffer the current solve is assumed to end in
   int32_t next_R;      //                     replacement period (< 0: mixed form, buffer known)
   double next_fs;      //                     dt * s of the next step
+  int32_t cheb_k;      // Chebyshev chain: step k (1 .. m-1) of this launch
+  int32_t cheb_last;   //                  the chain's last step (it publishes r_in^T s)
+  int32_t cheb_rhs;    //                  the chain preconditions the lifted right-hand side (else r)
 };
 
 __device__ inline Relay outer_relay(const SimDev& s, const BatchArgs& a, int32_t mode, bool partials) {
@@ -278,6 +289,60 @@ struct RoleCorr {  // mixed form: x64 += e, r64 = b - A x64, FP64 residual norm 
   }
 };
 
+// Search direction from the Chebyshev-preconditioned residual s (a6 + a4).
+struct RoleDirS {
+  using V = double;
+  using Pro = ProDirectionS<double>;
+  using Epi = EpiQDot<double>;
+  static __device__ const GatherArgs<V>& ga(const SimDev& s) { return s.A64; }
+  static __device__ Pro pro(const SimDev& s, const BatchArgs& a) {
+    return Pro{s.s64, s.d64[dir_in(a)], s.d64[dir_out(a)], s.X[a.xpar], a.corr, 0.0, 0.0};
+  }
+  static __device__ Epi epi(const SimDev& s, const BatchArgs&) { return Epi{s.q64}; }
+  static __device__ Relay relay(const SimDev& s, const BatchArgs& a) { return outer_relay(s, a, M_DIR, true); }
+};
+
+// The Chebyshev preconditioner s = q(D^-1 A) D^-1 r_in as a chain of gathers
+// relayed with M_PASS; the last one publishes r_in^T s, which completes the
+// scalar update pending before the chain (delta_b of a right-hand side, or
+// the delta of an initial residual, an update or a replacement).
+__device__ inline const double* cheb_rin(const SimDev& s, const BatchArgs& a) { return a.cheb_rhs ? s.b64 : s.r64; }
+__device__ inline const double* cheb_lift(const SimDev& s, const BatchArgs& a) {
+  return a.cheb_rhs ? s.lift64 : nullptr;
+}
+
+struct RoleChebFirst {  // step 1: gathers d_0 = P^-1 (r_in - lift) / c
+  using V = double;
+  using Pro = ProChebStart<double>;
+  using Epi = EpiCheb<double>;
+  static __device__ const GatherArgs<V>& ga(const SimDev& s) { return s.A64; }
+  static __device__ Pro pro(const SimDev& s, const BatchArgs& a) {
+    return Pro{cheb_rin(s, a), cheb_lift(s, a), s.pinv64, s.ch_inv_c};
+  }
+  static __device__ Epi epi(const SimDev& s, const BatchArgs& a) {
+    return Epi{cheb_rin(s, a), cheb_lift(s, a), s.pinv64, nullptr, cheb_rin(s, a), cheb_lift(s, a), s.cr64,
+               s.cd64[1], s.s64, s.ch_a[0], s.ch_b[0], a.cheb_last};
+  }
+  static __device__ Relay relay(const SimDev& s, const BatchArgs& a) {
+    return outer_relay(s, a, M_PASS, a.cheb_last != 0);
+  }
+};
+
+struct RoleChebNext {  // step k >= 2: gathers d_{k-1}
+  using V = double;
+  using Pro = ProPlain<double>;
+  using Epi = EpiCheb<double>;
+  static __device__ const GatherArgs<V>& ga(const SimDev& s) { return s.A64; }
+  static __device__ Pro pro(const SimDev& s, const BatchArgs& a) { return Pro{s.cd64[(a.cheb_k - 1) & 1]}; }
+  static __device__ Epi epi(const SimDev& s, const BatchArgs& a) {
+    return Epi{s.cr64, nullptr, s.pinv64, s.s64, cheb_rin(s, a), cheb_lift(s, a), s.cr64, s.cd64[a.cheb_k & 1],
+               s.s64, s.ch_a[a.cheb_k - 1], s.ch_b[a.cheb_k - 1], a.cheb_last};
+  }
+  static __device__ Relay relay(const SimDev& s, const BatchArgs& a) {
+    return outer_relay(s, a, M_PASS, a.cheb_last != 0);
+  }
+};
+
 // ---- kernels -----------------------------------------------------------------
 
 // Whether a role's kernel may follow a one-reduction direction kernel (and so
@@ -299,14 +364,14 @@ __device__ inline void work_item(const BatchArgs& a, uint32_t w, uint32_t& sim, 
 
 // One gather role over every simulation of a launch group (grid = the sum
 // of the group's per-simulation block counts, each a multiple of 8).
-template <bool CUBIC, class Role>
+template <int KIND, class Role>
 __global__ void __launch_bounds__(256, 2) gather_batch_kernel(BatchArgs a) {
   uint32_t sim, local;
   work_item(a, xcd_work_item(blockIdx.x, gridDim.x), sim, local);
   const SimDev& s = a.sims[sim];
   const GatherArgs<typename Role::V> ga = Role::ga(s);
   using Pro = typename Role::Pro;
-  gather_tile<typename Role::V, CUBIC, Pro, typename Role::Epi, reads_four<Role>(0) || AdvancesResidual<Pro>::value>(
+  gather_tile<typename Role::V, KIND, Pro, typename Role::Epi, reads_four<Role>(0) || AdvancesResidual<Pro>::value>(
       ga, Role::pro(s, a), Role::epi(s, a), Role::relay(s, a), local);
 }
 

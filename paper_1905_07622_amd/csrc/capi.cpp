@@ -42,6 +42,16 @@ int check_opts(const fem_opts* opts, fem_opts& o, std::string& why) {
   if (o.guess != FEM_GUESS_EXTRAP && o.guess != FEM_GUESS_PREV) return bad("unknown guess rule");
   if (o.stop_rule != FEM_STOP_RHS && o.stop_rule != FEM_STOP_INITIAL) return bad("unknown stop rule");
   if (o.precision == FEM_FP32_FP64DOT && !finite_pos(o.inner_rtol)) return bad("inner_rtol must be > 0");
+  if (o.element != FEM_ELEM_HEX8 && o.element != FEM_ELEM_TET6) return bad("unknown element");
+  if (o.element == FEM_ELEM_TET6 && o.precond != FEM_PRECOND_JACOBI)
+    return bad("the tetrahedral element runs with the Jacobi preconditioner");
+  if (o.precond != FEM_PRECOND_JACOBI && o.precond != FEM_PRECOND_CHEBYSHEV) return bad("unknown preconditioner");
+  if (o.precond == FEM_PRECOND_CHEBYSHEV) {
+    if (o.precision != FEM_FP64 || (o.flags & FEM_ONE_REDUCTION))
+      return bad("the Chebyshev preconditioner runs in the FP64 two-kernel form only");
+    if (o.cheb_degree < 2 || o.cheb_degree > femheat::kChebMaxDegree) return bad("cheb_degree must be in 2..8");
+    if (!(o.cheb_ratio > 1.0) || !std::isfinite(o.cheb_ratio)) return bad("cheb_ratio must be finite and > 1");
+  }
   if (o.tile_x < 0 || o.tile_y < 0 || o.tile_z < 0 || o.tile_x > 256 || o.tile_x * std::max(o.tile_y, 1) > 256)
     return bad("tile overrides out of range");
   // each thread of a gather block stages two entries of the (tx+2) x (ty+2)
@@ -70,6 +80,8 @@ int check_problem(const fem_grid* grid, const double* k_e, const double* rhoc_e,
   const double N = (double)(grid->nx + 1) * (grid->ny + 1) * (grid->nz + 1);
   if (N >= 2147483647.0) return bad("grid too large (N must fit in 31 bits)");
   if (!finite_pos(grid->hx) || !finite_pos(grid->hy) || !finite_pos(grid->hz)) return bad("h must be finite and > 0");
+  if (o.element == FEM_ELEM_TET6 && !(grid->hx == grid->hy && grid->hy == grid->hz))
+    return bad("the tetrahedral element needs cubic boxes (hx = hy = hz)");
   if (bc) {
     if ((bc->dirichlet_mask | bc->flux_mask) >= 64u) return bad("face masks have 6 bits");
     if (bc->dirichlet_mask & bc->flux_mask) return bad("a face is both Dirichlet and flux");
@@ -147,6 +159,9 @@ void fem_heat_default_opts(fem_opts* o) {
   o->stop_rule = FEM_STOP_RHS;
   o->max_refine = 4;
   o->inner_rtol = 1e-5;
+  o->precond = FEM_PRECOND_JACOBI;
+  o->cheb_degree = 3;
+  o->cheb_ratio = 30.0;
 }
 
 const char* fem_strerror(int status) {
@@ -284,7 +299,7 @@ int fem_heat_apply(fem_heat* h, int32_t which, double dt, double theta, const do
   }
   const int32_t form = which & (FEM_OP_ELEMENTWISE | FEM_OP_ROWWAVE);
   if (form && (form == (FEM_OP_ELEMENTWISE | FEM_OP_ROWWAVE) || (which & FEM_OP_FP32) ||
-               (op != FEM_OP_A && op != FEM_OP_L))) {
+               (op != FEM_OP_A && op != FEM_OP_L) || h->opts.element != FEM_ELEM_HEX8)) {
     h->err = "the element-by-element and row-wavefront applies take one of FEM_OP_A, FEM_OP_L in FP64";
     return FEM_EINVAL;
   }

@@ -18,6 +18,7 @@ struct Geom {
   double dir_val[6];
   uint32_t flux_mask;
   double flux[6];
+  int32_t tet6;        // 1: every box is six linear tetrahedra (cubes only), else a trilinear hexahedron
 };
 
 // State of one PCG solve (Algorithm 1), all scalars in FP64, relayed from
@@ -75,10 +76,17 @@ enum Mode : int32_t {
   // the next step's right-hand side and initial residual, launched before the
   // host knows whether the current solve has finished: they run only if it has
   M_RHS_NEXT = 13,   // as M_RHS if the solve ended well with the iterate buffer predicted
-  M_INIT_NEXT = 14   // as M_INIT if the M_RHS_NEXT before it ran
+  M_INIT_NEXT = 14,  // as M_INIT if the M_RHS_NEXT before it ran
+  // a kernel of the preconditioner chain (Chebyshev): relays the state
+  // unchanged, leaves the pending update for the kernel after the chain
+  // (whose partials, from the chain's last kernel, complete it); idle once done
+  M_PASS = 15
 };
 
 constexpr int32_t kStatusBreakdown = -4;
+
+// Highest degree of the Chebyshev preconditioner (m - 1 gathers per application).
+constexpr int kChebMaxDegree = 8;
 
 // Launch shape of the gather apply: a block owns a TX x TY column tile of
 // nodes and marches TZ planes in z.

@@ -84,7 +84,7 @@ namespace {
 // A set of simulations launched together: one kernel per gather for the
 // cubic and one for the general-element members.
 struct Group {
-  bool cubic = true;
+  int kind = kElemCubic;  // element kind of the group's simulations (the gather's template argument)
   uint32_t off = 0, nwork = 0, nthreads = 64;
   size_t smem64 = 0, smem32 = 0, smem64f = 0;  // smem64f: one-reduction direction kernel (three planes)
 };
@@ -92,7 +92,7 @@ struct Group {
 // Work-table layout of a batched launch: where each kernel kind's entries
 // start in the table and how many there are.
 struct Layout {
-  Group groups[2];
+  Group groups[3];
   int ngroups = 0;
   uint32_t off_upd64 = 0, n_upd64 = 0, off_upd32 = 0, n_upd32 = 0, off_start = 0, n_start = 0, off_one = 0,
            n_one = 0;
@@ -106,6 +106,7 @@ class Engine {
     mixed_ = o.precision == FEM_FP32_FP64DOT;
     timing_ = (o.flags & FEM_TIMING) != 0;
     fused_ = !mixed_ && (o.flags & FEM_ONE_REDUCTION) != 0;
+    cheb_ = !mixed_ && !fused_ && o.precond == FEM_PRECOND_CHEBYSHEV;
     R_ = o.replace_every;
   }
   ~Engine() {
@@ -195,6 +196,27 @@ class Engine {
   fem_heat* h_;  // receives error messages
   bool mixed_ = false, timing_ = false;
   bool fused_ = false;  // FP64 PCG in the one-reduction form
+  bool cheb_ = false;   // FP64 PCG with the Chebyshev preconditioner
+  // The preconditioner chain behind the kernel that made a residual (or the
+  // right-hand side): m - 1 gathers computing s = M^-1 r_in, the last one
+  // publishing r_in^T s for the scalar update that kernel left pending.
+  int cheb_chain(bool rhs) {
+    if (!cheb_) return FEM_OK;
+    const int m = opts_.cheb_degree;
+    for (int k = 1; k <= m - 1; ++k) {
+      BatchArgs a = args(ocur_, oprev_, 0, 0);
+      a.cheb_k = k;
+      a.cheb_last = k == m - 1 ? 1 : 0;
+      a.cheb_rhs = rhs ? 1 : 0;
+      if (k == 1)
+        RC_TRY(gather<RoleChebFirst>(a));
+      else
+        RC_TRY(gather<RoleChebNext>(a));
+      ocur_ ^= 1;
+      oprev_ = PK_GATHER;
+    }
+    return FEM_OK;
+  }
   int R_ = 50;
   uint64_t sample_ctr_ = 0;         // iterations launched with timing, across solves
   uint64_t replace_ctr_ = 0;        // residual replacements launched with timing
@@ -381,6 +403,15 @@ void Engine::fill_simdev(const Sim& s, SimDev& d) const {
   // start kernel (see inner_start_batch_kernel): one sweep then usually suffices
   d.ictl = Ctl{-1.0, opts_.max_iter, FEM_STOP_INITIAL};
   d.inner_rtol = opts_.inner_rtol;
+  d.s64 = h->s64;
+  d.cr64 = h->cr64;
+  d.cd64[0] = h->cd64[0];
+  d.cd64[1] = h->cd64[1];
+  d.ch_inv_c = h->ch_inv_c;
+  for (int k = 0; k < kChebMaxDegree; ++k) {
+    d.ch_a[k] = h->ch_a[k];
+    d.ch_b[k] = h->ch_b[k];
+  }
   d.N = h->g.N;
   d.nblk[PK_GATHER] = h->shape.nblocks;
   d.nblk[PK_UPD64] = h->upd_blocks64;
@@ -473,13 +504,13 @@ int Engine::compose() {
 void Engine::build_layout(const std::vector<char>& live, std::vector<uint2>& tab, Layout& L) const {
   const size_t n = act_.size();
   L = Layout{};
-  for (int cls = 0; cls < 2; ++cls) {
+  for (int cls : {kElemCubic, kElemBox, kElemTet6}) {
     Group g;
-    g.cubic = cls == 0;
+    g.kind = cls;
     g.off = (uint32_t)tab.size();
     for (size_t k = 0; k < n; ++k) {
       const fem_heat* sh = act_[k]->rq.h;
-      if (sh->cubic != g.cubic) continue;
+      if (sh->kind != g.kind) continue;
       // launch parameters from every member of the class, live or not, so a
       // compaction launches the same block shape and LDS size
       g.nthreads = std::max<uint32_t>(g.nthreads, (uint32_t)sh->shape.nthreads);
@@ -545,12 +576,15 @@ int Engine::gather(BatchArgs a, hipEvent_t e0, hipEvent_t e1) {
                         : sizeof(typename Role::V) == 8        ? g.smem64
                                                                : g.smem32;
     hipEvent_t s0 = gi == 0 ? e0 : nullptr, s1 = gi == lay_.ngroups - 1 ? e1 : nullptr;
-    if (g.cubic)
-      hipExtLaunchKernelGGL((gather_batch_kernel<true, Role>), dim3(g.nwork), dim3(g.nthreads), smem, stream_, s0, s1,
-                            0, a);
+    if (g.kind == kElemCubic)
+      hipExtLaunchKernelGGL((gather_batch_kernel<kElemCubic, Role>), dim3(g.nwork), dim3(g.nthreads), smem, stream_,
+                            s0, s1, 0, a);
+    else if (g.kind == kElemTet6)
+      hipExtLaunchKernelGGL((gather_batch_kernel<kElemTet6, Role>), dim3(g.nwork), dim3(g.nthreads), smem, stream_,
+                            s0, s1, 0, a);
     else
-      hipExtLaunchKernelGGL((gather_batch_kernel<false, Role>), dim3(g.nwork), dim3(g.nthreads), smem, stream_, s0, s1,
-                            0, a);
+      hipExtLaunchKernelGGL((gather_batch_kernel<kElemBox, Role>), dim3(g.nwork), dim3(g.nthreads), smem, stream_,
+                            s0, s1, 0, a);
   }
   HIP_TRY(hipGetLastError());
   return FEM_OK;
@@ -707,6 +741,8 @@ int Engine::pcg(int first_chunk) {
       const int xpar = replacements_before(jj, R_) & 1;
       if (one_red) {
         RC_TRY(gather<RoleFused>(args(cur, prev, jj, xpar, deferred(jj) ? 1 : 0), e0, e1));
+      } else if (cheb_ && !inner) {
+        RC_TRY(gather<RoleDirS>(args(cur, prev, jj, xpar, deferred(jj) ? 1 : 0), e0, e1));
       } else {
         RC_TRY(gather<RoleDir<V>>(args(cur, prev, jj, xpar, !inner && deferred(jj) ? 1 : 0), e0, e1));
       }
@@ -724,10 +760,12 @@ int Engine::pcg(int first_chunk) {
         prev = upd_kind;
         cur ^= 1;
       }
+      if (cheb_ && !inner) RC_TRY(cheb_chain(false));  // s = M^-1 r and its delta for the next direction
     }
     // the GPU is busy with this chunk: read the earlier chunks' samples now
     if (timing_) RC_TRY(flush_timing());
-    const bool launch_next = !inner && !mixed_ && act_.size() == 1 && act_[0]->step + 1 < act_[0]->rq.nsteps;
+    const bool launch_next =
+        !inner && !mixed_ && !cheb_ && act_.size() == 1 && act_[0]->step + 1 < act_[0]->rq.nsteps;
     RC_TRY(decide(inner, j + k, launch_next));
     bool all_done = true;
     int most = j;
@@ -876,9 +914,11 @@ int Engine::epoch() {
     RC_TRY(gather<RoleRhs>(args(ocur_, oprev_, 0, 0)));
     ocur_ ^= 1;
     oprev_ = PK_GATHER;
+    RC_TRY(cheb_chain(true));  // delta_b in the preconditioner's norm
     RC_TRY(gather<RoleInit>(args(ocur_, oprev_, 0, 0)));
     ocur_ ^= 1;
     oprev_ = PK_GATHER;
+    RC_TRY(cheb_chain(false));  // s_0 = M^-1 r_0 and delta_0
   }
   if (mixed_) {
     RC_TRY(mixed_sweeps());
@@ -1074,7 +1114,7 @@ int Engine::tune(fem_heat* h, double dt, double theta, bool batch, fem_tune_resu
   int rec = 0;
   if (h->opts.tune_cache) {
     const int t[3] = {b.tx, b.ty, b.tz};
-    rec = tune_store(h->opts.tune_cache, tune_key(h->opts.device, mixed_, h->cubic, batch, h->g.px, h->g.py, h->g.pz),
+    rec = tune_store(h->opts.tune_cache, tune_key(h->opts.device, mixed_, h->kind, batch, h->g.px, h->g.py, h->g.pz),
                      t, best, rule, (int)cands.size())
               ? 1
               : 0;

@@ -44,13 +44,32 @@
 
 namespace femheat {
 
+// Element kinds of the gather (template argument KIND): a trilinear
+// hexahedron on a general box (8 class entries), on a cube (4 popcount
+// classes), or a cube split into six linear tetrahedra (the paper's element).
+constexpr int kElemBox = 0, kElemCubic = 1, kElemTet6 = 2;
+
+// Box matrices of the six-tetrahedron split of a cube of side h (tetrahedra
+// 0, e_i, e_i + e_j, 7 for each order of the axes: the split around the 0-7
+// diagonal, conforming across boxes).  From the linear tetrahedron's closed
+// forms M_t = V/20 (1 + delta_ij) and K_t = V grad l_i . grad l_j with
+// V = h^3/6: M = h^3/120 * kTetM and K = h/6 * kTetK (corner a = ax + 2ay + 4az).
+// Pairs joined by no tetrahedron edge are 0, and K reduces to the 7-point
+// Laplacian stencil once assembled.
+constexpr int kTetM[8][8] = {{12, 2, 2, 2, 2, 2, 2, 6}, {2, 4, 0, 1, 0, 1, 0, 2}, {2, 0, 4, 1, 0, 0, 1, 2},
+                             {2, 1, 1, 4, 0, 0, 0, 2}, {2, 0, 0, 0, 4, 1, 1, 2}, {2, 1, 0, 0, 1, 4, 0, 2},
+                             {2, 0, 1, 0, 1, 0, 4, 2}, {6, 2, 2, 2, 2, 2, 2, 12}};
+constexpr int kTetK[8][8] = {{6, -2, -2, 0, -2, 0, 0, 0}, {-2, 4, 0, -1, 0, -1, 0, 0}, {-2, 0, 4, -1, 0, 0, -1, 0},
+                             {0, -1, -1, 4, 0, 0, 0, -2}, {-2, 0, 0, 0, 4, -1, -1, 0}, {0, -1, 0, 0, -1, 4, 0, -2},
+                             {0, 0, -1, 0, -1, 0, 4, -2}, {0, 0, 0, -2, 0, -2, -2, 6}};
+
 template <typename V>
 struct GatherArgs {
   Geom g;
   GatherShape s;
   const V* rhoc;   // per-element rho*C
   const V* kc;     // per-element k
-  V sa, sb;        // cubic: cm*h^3/216, ck*h/12 ; general: cm, ck
+  V sa, sb;        // cubic: cm*h^3/216, ck*h/12 ; tetrahedra: cm*h^3/120, ck*h/6 ; general: cm, ck
   V Mc[8], Kc[8];  // general elements: class entries M[c], K[c]
   V* sink;         // >= 256 scratch values: stores of lanes without a node land here
 };
@@ -115,7 +134,7 @@ struct AdvancesResidual {
 // stored at index `logical`, and tile 0 publishes the relayed state.
 // kD: prefetch depth in layers.  The one-reduction direction kernel stages a fourth vector and keeps
 // four accumulators; with one layer of prefetch it fits 164 VGPRs instead of 256 with a spill.
-template <typename V, bool CUBIC, class Pro, class Epi, bool kFour = AdvancesResidual<Pro>::value,
+template <typename V, int KIND, class Pro, class Epi, bool kFour = AdvancesResidual<Pro>::value,
           int kD = (AdvancesResidual<Pro>::value ? 1 : kDepth)>
 __device__ inline void gather_tile(const GatherArgs<V>& ga, Pro pro, Epi epi, const Relay& R, uint32_t logical) {
   const StageIn in = stage_load<sizeof(V) == 8>(R);
@@ -271,6 +290,14 @@ __device__ inline void gather_tile(const GatherArgs<V>& ga, Pro pro, Epi epi, co
     // coefficients serve both nodes and are then dead.
     auto contributions = [&](const PlaneQ<V>& lp, const PlaneQ<V>& hp, const V* C, V& lo_sum, V& hi_sum) {
       V plo[4], phi[4];
+      // the tetrahedra are not symmetric under z-reflection: their corners
+      // are taken on the physical bottom and top planes of the layer (which
+      // are hp and lp when the chunk marches down)
+      PlaneQ<V> bot, top;
+      if constexpr (KIND == kElemTet6) {
+        bot = down ? hp : lp;
+        top = down ? lp : hp;
+      }
 #pragma unroll
       for (int sy = 0; sy < 2; ++sy) {
 #pragma unroll
@@ -279,7 +306,35 @@ __device__ inline void gather_tile(const GatherArgs<V>& ga, Pro pro, Epi epi, co
           const int ci = (lty + sy) * CW + ltx + sx;
           const V xl = sx ? lp.xp : lp.xm, yl = sy ? lp.yp : lp.ym, bl = lp.b[e];
           const V xh = sx ? hp.xp : hp.xm, yh = sy ? hp.yp : hp.ym, bh = hp.b[e];
-          if (CUBIC) {
+          if constexpr (KIND == kElemTet6) {
+            // rows of the bottom node (corner ax + 2ay) and the top node (+4)
+            // of this element against its 8 corner values, zero entries skipped
+            const V a = C[ci], bk = C[CS + ci];
+            const int ax = 1 - sx, ay = 1 - sy;
+            V val[8];
+#pragma unroll
+            for (int b = 0; b < 8; ++b) {
+              const PlaneQ<V>& P = (b >> 2) ? top : bot;
+              const bool dx = (b & 1) != ax, dy = ((b >> 1) & 1) != ay;
+              val[b] = dx ? (dy ? P.b[e] : (sx ? P.xp : P.xm)) : (dy ? (sy ? P.yp : P.ym) : P.c);
+            }
+            V rows[2];
+#pragma unroll
+            for (int r = 0; r < 2; ++r) {
+              const int arow = ax + 2 * ay + 4 * r;
+              V acc = V(0);
+#pragma unroll
+              for (int b = 0; b < 8; ++b) {
+                const int m = kTetM[arow][b], kk = kTetK[arow][b];
+                if (m == 0 && kk == 0) continue;
+                const V c = m == 0 ? bk * V(kk) : (kk == 0 ? a * V(m) : fma(a, V(m), bk * V(kk)));
+                acc = fma(c, val[b], acc);
+              }
+              rows[r] = acc;
+            }
+            plo[e] = down ? rows[1] : rows[0];
+            phi[e] = down ? rows[0] : rows[1];
+          } else if constexpr (KIND == kElemCubic) {
             // classes by popcount: c0 = 8a+4b, c1 = 4a, c2 = 2a-b, c3 = a-b
             const V a = C[ci], bk = C[CS + ci];
             const V c0 = fma(V(8), a, V(4) * bk), c1 = V(4) * a, c2 = fma(V(2), a, -bk), c3 = a - bk;
@@ -411,9 +466,9 @@ __device__ inline void gather_tile(const GatherArgs<V>& ga, Pro pro, Epi epi, co
 }
 
 // A gather of one solve: one block per tile (grid = ga.s.nblocks).
-template <typename V, bool CUBIC, class Pro, class Epi>
+template <typename V, int KIND, class Pro, class Epi>
 __global__ void __launch_bounds__(256) gather_kernel(GatherArgs<V> ga, Pro pro, Epi epi, Relay R) {
-  gather_tile<V, CUBIC>(ga, pro, epi, R, xcd_work_item(blockIdx.x, ga.s.nblocks));
+  gather_tile<V, KIND>(ga, pro, epi, R, xcd_work_item(blockIdx.x, ga.s.nblocks));
 }
 
 // ---------------------------------------------------------------------------
@@ -517,6 +572,88 @@ struct CarriesIterate<ProFused<V>> {
 template <typename V>
 struct AdvancesResidual<ProFused<V>> {
   static constexpr bool value = true;
+};
+
+// Search direction from a preconditioned residual held as a vector (the
+// Chebyshev preconditioner): d_new = s + beta d_old, with the deferred
+// x += alpha d_old at own nodes as in ProDirection.
+template <typename V>
+struct ProDirectionS {
+  const V* s;
+  const V* dold;
+  V* dnew;
+  V* x;
+  int32_t corr;
+  V beta;
+  V alpha;
+  struct Raw {
+    V s, d;
+  };
+  __device__ void init(const Scalars& S) {
+    beta = (V)S.beta;
+    alpha = (V)S.alpha;
+  }
+  __device__ Raw fetch(uint32_t i) const { return Raw{s[i], dold[i]}; }
+  __device__ V finish(const Raw& w) const { return fma(beta, w.d, w.s); }
+  __device__ void write(uint32_t i, V v, bool live, V* sink) const { *(live ? dnew + i : sink + threadIdx.x) = v; }
+};
+
+template <>
+struct CarriesIterate<ProDirectionS<double>> {
+  static constexpr bool value = true;
+};
+
+// First step of the Chebyshev preconditioner applied to r_in (minus the
+// Dirichlet lifting when given): the gathered vector is d_0 = P^-1 (r_in -
+// lift) / c, c the centre of the interval.
+template <typename V>
+struct ProChebStart {
+  const V* r;
+  const V* lift;  // or nullptr
+  const V* pinv;
+  V inv_c;
+  struct Raw {
+    V r, l, p;
+  };
+  __device__ void init(const Scalars&) {}
+  __device__ Raw fetch(uint32_t i) const { return Raw{r[i], lift ? lift[i] : V(0), pinv[i]}; }
+  __device__ V finish(const Raw& w) const { return (w.p * (w.r - w.l)) * inv_c; }
+  __device__ void write(uint32_t, V, bool, V*) const {}
+};
+
+// Step k of the Chebyshev preconditioner, at own nodes, after the gather
+// formed (A d_{k-1})_i: res_k = res_{k-1} - A d_{k-1}, z = P^-1 res_k,
+// d_k = a_k d_{k-1} + b_k z, y_{k+1} = y_k + d_k (y_1 = d_0).  The last step
+// writes only y (= s, the preconditioned vector) and returns the node's
+// contribution r_in_i s_i; the others carry res, d and y to the next step.
+template <typename V>
+struct EpiCheb {
+  const V* rprev;  // res_{k-1}: r_in (k = 1) or the chain's residual
+  const V* lift;   // k = 1 with a lifted right-hand side, or nullptr
+  const V* pinv;
+  const V* yprev;  // y_k, or nullptr for k = 1 (y_1 = d_0, the gathered value)
+  const V* rin;    // the chain's input (for the last step's dot product)
+  const V* rlift;  // its lifting, or nullptr
+  V* rnext;        // res_k (not on the last step)
+  V* dnext;        // d_k (not on the last step)
+  V* y;            // y_{k+1}
+  V a, b;
+  int32_t last;
+  __device__ void init(const Scalars&) {}
+  __device__ double store(uint32_t i, V acc, V v, bool live, V* sink) const {
+    const V rp = lift ? rprev[i] - lift[i] : rprev[i];
+    const V rk = rp - acc;
+    const V dk = fma(a, v, b * (pinv[i] * rk));
+    const V yk = (yprev ? yprev[i] : v) + dk;
+    *(live ? y + i : sink + threadIdx.x) = yk;
+    if (last) {
+      const V ri = rlift ? rin[i] - rlift[i] : rin[i];
+      return live ? (double)ri * (double)yk : 0.0;
+    }
+    *(live ? rnext + i : sink + threadIdx.x) = rk;
+    *(live ? dnext + i : sink + threadIdx.x) = dk;
+    return 0.0;
+  }
 };
 
 template <typename V, typename W>

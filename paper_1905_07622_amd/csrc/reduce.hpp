@@ -255,7 +255,7 @@ __device__ inline StageIn stage_load(const Relay& R) {
 // A search-direction or update kernel of a finished solve has no work and
 // leaves the state unchanged: only the writer relays it.  Uniform.
 __device__ inline bool stage_idle(const Relay& R, const StageIn& in, bool writer) {
-  if ((R.mode == M_DIR || R.mode == M_UPD || is_fused_mode(R.mode)) && in.t.done) {
+  if ((R.mode == M_DIR || R.mode == M_UPD || R.mode == M_PASS || is_fused_mode(R.mode)) && in.t.done) {
     if (writer && threadIdx.x == 0 && R.sout) *R.sout = in.t;
     return true;
   }
@@ -363,6 +363,9 @@ __device__ inline bool stage_finish(const Relay& R, const StageIn& in, Scalars& 
         break;
       case M_SKIP:
         g = 0;
+        break;
+      case M_PASS:  // state unchanged (done solves returned in stage_idle)
+        g = 1;
         break;
       case M_IDLE:  // settled: done with zero iterations, nothing pending
         t.done = 1;

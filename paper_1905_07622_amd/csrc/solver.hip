@@ -54,23 +54,23 @@ int lds_pitch(int tx, int ty, int nthreads, int width, bool plane) {
 // Blocks of the hot gather (search direction fused with the apply) that one
 // CU holds at once for a block of `nthreads` threads: occupancy is bounded by
 // the kernel's registers and LDS, so it is asked of the runtime.
-int resident_blocks(bool cubic, bool fp32, int nthreads, size_t smem) {
+template <typename V, int KIND>
+hipError_t occupancy_of(int* n, int nthreads, size_t smem) {
+  return hipOccupancyMaxActiveBlocksPerMultiprocessor(
+      n, reinterpret_cast<const void*>(&gather_kernel<V, KIND, ProDirection<V>, EpiQDot<V>>), nthreads, smem);
+}
+
+int resident_blocks(int kind, bool fp32, int nthreads, size_t smem) {
   int n = 0;
   hipError_t e;
   if (fp32)
-    e = cubic ? hipOccupancyMaxActiveBlocksPerMultiprocessor(
-                    &n, reinterpret_cast<const void*>(&gather_kernel<float, true, ProDirection<float>, EpiQDot<float>>),
-                    nthreads, smem)
-              : hipOccupancyMaxActiveBlocksPerMultiprocessor(
-                    &n, reinterpret_cast<const void*>(&gather_kernel<float, false, ProDirection<float>, EpiQDot<float>>),
-                    nthreads, smem);
+    e = kind == kElemCubic ? occupancy_of<float, kElemCubic>(&n, nthreads, smem)
+        : kind == kElemTet6 ? occupancy_of<float, kElemTet6>(&n, nthreads, smem)
+                            : occupancy_of<float, kElemBox>(&n, nthreads, smem);
   else
-    e = cubic ? hipOccupancyMaxActiveBlocksPerMultiprocessor(
-                    &n, reinterpret_cast<const void*>(&gather_kernel<double, true, ProDirection<double>, EpiQDot<double>>),
-                    nthreads, smem)
-              : hipOccupancyMaxActiveBlocksPerMultiprocessor(
-                    &n, reinterpret_cast<const void*>(&gather_kernel<double, false, ProDirection<double>, EpiQDot<double>>),
-                    nthreads, smem);
+    e = kind == kElemCubic ? occupancy_of<double, kElemCubic>(&n, nthreads, smem)
+        : kind == kElemTet6 ? occupancy_of<double, kElemTet6>(&n, nthreads, smem)
+                            : occupancy_of<double, kElemBox>(&n, nthreads, smem);
   if (e != hipSuccess) {
     (void)hipGetLastError();
     return 2;
@@ -139,11 +139,14 @@ GatherShape choose_shape(const Geom& g, const fem_opts& o, int capacity) {
 }
 
 template <typename V>
-void fill_classes(const Geom& g, GatherArgs<V>& ga, double cm, double ck, bool cubic) {
-  if (cubic) {
+void fill_classes(const Geom& g, GatherArgs<V>& ga, double cm, double ck, int kind) {
+  if (kind == kElemCubic || kind == kElemTet6) {
+    // cube of side h: hexahedron classes h^3/216 {8,4,2,1}, h/12 {4,0,-1,-1};
+    // tetrahedra h^3/120 kTetM, h/6 kTetK
     const double h = g.hx;
-    ga.sa = (V)(cm * h * h * h / 216.0);
-    ga.sb = (V)(ck * h / 12.0);
+    const bool tet = kind == kElemTet6;
+    ga.sa = (V)(cm * h * h * h / (tet ? 120.0 : 216.0));
+    ga.sb = (V)(ck * h / (tet ? 6.0 : 12.0));
     for (int c = 0; c < 8; ++c) ga.Mc[c] = ga.Kc[c] = V(0);
     return;
   }
@@ -167,6 +170,52 @@ void fill_classes(const Geom& g, GatherArgs<V>& ga, double cm, double ck, bool c
 
 Relay no_relay() { return Relay{nullptr, nullptr, nullptr, 0, nullptr, M_NONE, Ctl{0.0, 0, 0}, 0}; }
 
+// Upper end of the Chebyshev interval: a bound of the spectrum of D^-1 A for
+// every coefficient field on this element box.  x^T A x / x^T D x is a
+// weighted mean of element quotients, each at most the larger of
+// lambda_max(diag(M_e)^-1 M_e) and lambda_max(diag(K_e)^-1 K_e).  Both blocks
+// have a constant diagonal (V/27 and (V/9) sum_d 1/h_d^2) and the eigenvectors
+// of the tensor products of the 1-D blocks: per axis, the even mode gives the
+// mass entry h/2 and stiffness 0, the odd mode h/6 and 2/h.  So the mass
+// block's top is (V/8)/(V/27) = 27/8 and the stiffness block's the largest of
+// sum_d s_d prod_{d' != d} m_d' over the 8 parity patterns.
+double chebyshev_upper(const Geom& g) {
+  const double h[3] = {g.hx, g.hy, g.hz};
+  const double V = g.hx * g.hy * g.hz;
+  const double kdiag = V / 9.0 * (1.0 / (h[0] * h[0]) + 1.0 / (h[1] * h[1]) + 1.0 / (h[2] * h[2]));
+  double ktop = 0.0;
+  for (int o = 0; o < 8; ++o) {
+    double lam = 0.0;
+    for (int d = 0; d < 3; ++d) {
+      if (!((o >> d) & 1)) continue;  // even mode along d: the stiffness factor is 0
+      double t = 2.0 / h[d];
+      for (int e = 0; e < 3; ++e)
+        if (e != d) t *= ((o >> e) & 1) ? h[e] / 6.0 : h[e] / 2.0;
+      lam += t;
+    }
+    ktop = std::max(ktop, lam);
+  }
+  return std::max(27.0 / 8.0, ktop / kdiag);
+}
+
+// The Chebyshev preconditioner of degree m on [hi/ratio, hi]: with centre c,
+// half-width w and sigma = c/w, rho_0 = 1/sigma, rho_k = 1/(2 sigma - rho_{k-1});
+// step k of the chain forms d_k = rho_k rho_{k-1} d_{k-1} + (2 rho_k / w) P^-1 res_k.
+void chebyshev_coefficients(fem_heat* h) {
+  const double hi = chebyshev_upper(h->g), lo = hi / h->opts.cheb_ratio;
+  const double c = 0.5 * (hi + lo), w = 0.5 * (hi - lo), sigma = c / w;
+  h->ch_hi = hi;
+  h->ch_lo = lo;
+  h->ch_inv_c = 1.0 / c;
+  double rho = 1.0 / sigma;
+  for (int k = 1; k < h->opts.cheb_degree && k <= kChebMaxDegree; ++k) {
+    const double rn = 1.0 / (2.0 * sigma - rho);
+    h->ch_a[k - 1] = rn * rho;
+    h->ch_b[k - 1] = 2.0 * rn / w;
+    rho = rn;
+  }
+}
+
 }  // namespace
 
 template <typename V>
@@ -182,7 +231,7 @@ GatherArgs<V> gather_args(const fem_heat* h, double cm, double ck) {
     ga.kc = h->k32;
   }
   ga.sink = reinterpret_cast<V*>(h->sink);
-  fill_classes(h->g, ga, cm, ck, h->cubic);
+  fill_classes(h->g, ga, cm, ck, h->kind);
   return ga;
 }
 template GatherArgs<double> gather_args<double>(const fem_heat*, double, double);
@@ -197,11 +246,14 @@ int launch_gather(fem_heat* h, double cm, double ck, Pro pro, Epi epi, const Rel
   GatherArgs<V> ga = gather_args<V>(h, cm, ck);
   if (sink) ga.sink = sink;
   const size_t smem = h->shape.smem_bytes(sizeof(V));
-  if (h->cubic)
-    hipLaunchKernelGGL((gather_kernel<V, true, Pro, Epi>), dim3(h->shape.nblocks), dim3(h->shape.nthreads), smem,
-                       h->stream, ga, pro, epi, R);
+  if (h->kind == kElemCubic)
+    hipLaunchKernelGGL((gather_kernel<V, kElemCubic, Pro, Epi>), dim3(h->shape.nblocks), dim3(h->shape.nthreads),
+                       smem, h->stream, ga, pro, epi, R);
+  else if (h->kind == kElemTet6)
+    hipLaunchKernelGGL((gather_kernel<V, kElemTet6, Pro, Epi>), dim3(h->shape.nblocks), dim3(h->shape.nthreads),
+                       smem, h->stream, ga, pro, epi, R);
   else
-    hipLaunchKernelGGL((gather_kernel<V, false, Pro, Epi>), dim3(h->shape.nblocks), dim3(h->shape.nthreads), smem,
+    hipLaunchKernelGGL((gather_kernel<V, kElemBox, Pro, Epi>), dim3(h->shape.nblocks), dim3(h->shape.nthreads), smem,
                        h->stream, ga, pro, epi, R);
   HIP_TRY(hipGetLastError());
   return FEM_OK;
@@ -305,6 +357,8 @@ int solver_init(fem_heat* h, const fem_grid* grid, const double* k_e, const doub
   if (bc && bc->flux_schedule && bc->n_schedule > 0)
     h->sched.assign(bc->flux_schedule, bc->flux_schedule + bc->n_schedule);
   h->cubic = (g.hx == g.hy && g.hy == g.hz);
+  g.tet6 = h->opts.element == FEM_ELEM_TET6 ? 1 : 0;
+  h->kind = g.tet6 ? kElemTet6 : (h->cubic ? kElemCubic : kElemBox);
   HIP_TRY(hipSetDevice(h->opts.device));
   {
     // a tile the autotuner recorded for this grid, precision, element class
@@ -312,7 +366,7 @@ int solver_init(fem_heat* h, const fem_grid* grid, const double* k_e, const doub
     fem_opts so = h->opts;
     if (so.tune_cache && so.tile_x == 0 && so.tile_y == 0 && so.tile_z == 0) {
       int t[3];
-      if (tune_lookup(so.tune_cache, tune_key(so.device, so.precision == FEM_FP32_FP64DOT, h->cubic, h->batched,
+      if (tune_lookup(so.tune_cache, tune_key(so.device, so.precision == FEM_FP32_FP64DOT, h->kind, h->batched,
                                               g.px, g.py, g.pz),
                       t)) {
         fem_opts probe_o = so;
@@ -333,7 +387,7 @@ int solver_init(fem_heat* h, const fem_grid* grid, const double* k_e, const doub
     // at most two blocks per CU: beyond that, the shorter z-marches pay the
     // plane pipeline's fill more often than the extra blocks hide latency
     // (measured for the FP32 gather, which could hold four)
-    const int per_cu = std::min(2, resident_blocks(h->cubic, fp32, probe.nthreads, probe.smem_bytes(fp32 ? 4 : 8)));
+    const int per_cu = std::min(2, resident_blocks(h->kind, fp32, probe.nthreads, probe.smem_bytes(fp32 ? 4 : 8)));
     h->shape = choose_shape(g, so, h->batched ? 0 : std::max(1, cus) * per_cu);
     h->capacity = std::max(1, cus) * per_cu;
   }
@@ -383,6 +437,13 @@ int solver_init(fem_heat* h, const fem_grid* grid, const double* k_e, const doub
       HIP_TRY(hipMemsetAsync(c->S[k], 0, sizeof(Scalars), h->stream));
       HIP_TRY(hipMemsetAsync(c->P[k], 0, ncomp * h->n_partials * sizeof(double), h->stream));
     }
+  if (h->opts.precond == FEM_PRECOND_CHEBYSHEV && h->opts.precision == FEM_FP64) {
+    RC_TRY(dalloc(h, &h->s64, N));
+    RC_TRY(dalloc(h, &h->cr64, N));
+    RC_TRY(dalloc(h, &h->cd64[0], N));
+    RC_TRY(dalloc(h, &h->cd64[1], N));
+    chebyshev_coefficients(h);
+  }
   RC_TRY(copy_in(h, h->rhoc64, rhoc_e, E));
   RC_TRY(copy_in(h, h->k64, k_e, E));
   hipLaunchKernelGGL(load_vector_kernel, dim3(nblk(N)), dim3(kT), 0, h->stream, g, h->F64);
@@ -414,7 +475,7 @@ int solver_apply(fem_heat* h, int32_t which, double dt, double theta, const doub
   } else if ((op == FEM_OP_A || op == FEM_OP_L) && rows) {
     const double ck = op == FEM_OP_A ? theta * dt : -(1.0 - theta) * dt;
     GatherArgs<double> ga{};
-    fill_classes(h->g, ga, 1.0, ck, false);
+    fill_classes(h->g, ga, 1.0, ck, kElemBox);
     RowArgs ra{};
     ra.nx = h->g.nx;
     ra.ny = h->g.ny;
@@ -598,6 +659,7 @@ size_t handle_device_bytes(const fem_grid& grid, const fem_opts& opts, const fem
   const bool one_red = (opts.flags & FEM_ONE_REDUCTION) != 0;
   size_t bytes = 8 * (2 * E + (11 + (lift ? 1 : 0) + (one_red ? 2 : 0)) * N);
   if (opts.precision == FEM_FP32_FP64DOT) bytes += 4 * (2 * E + 8 * N);  // FP32 set
+  if (opts.precond == FEM_PRECOND_CHEBYSHEV && opts.precision == FEM_FP64) bytes += 8 * 4 * N;  // s, chain
   // relay state and partials (at most max(tiles, update blocks) per buffer) and the sink
   const size_t tiles_bound = N / 32 + 1024;
   bytes += 4 * (sizeof(Scalars) + 8 * tiles_bound * (one_red ? 4 : 1)) + 8 * 256;
@@ -633,6 +695,9 @@ void solver_free(fem_heat* h) {
       dfree(h, c->S[k]);
       dfree(h, c->P[k]);
     }
+  dfree(h, h->s64);
+  dfree(h, h->cr64);
+  for (auto& p : h->cd64) dfree(h, p);
   dfree(h, h->xyz_dev);
   dfree(h, h->traces_dev);
   dfree(h, h->ebe_part);

@@ -29,6 +29,7 @@ struct fem_heat {
 
   femheat::Geom g{};
   bool cubic = false;
+  int kind = 0;  // gather element kind: kElemBox, kElemCubic or kElemTet6
   bool nonzero_dirichlet = false;
   std::vector<double> sched;
 
@@ -51,6 +52,14 @@ struct fem_heat {
   double* lift64 = nullptr;   // A_fD g (only with non-zero Dirichlet values)
   double* sink = nullptr;     // 256 scratch values for stores of lanes without a node
   double ck_cached = -1.0;    // theta*dt of pinv/lift; < 0: none
+
+  // Chebyshev preconditioner (FP64 solves): s = M^-1 r, the chain's residual
+  // and direction ping-pong, 1/c and the step coefficients a_k, b_k
+  double* s64 = nullptr;
+  double* cr64 = nullptr;
+  double* cd64[2] = {nullptr, nullptr};
+  double ch_inv_c = 0.0, ch_hi = 0.0, ch_lo = 0.0;
+  double ch_a[femheat::kChebMaxDegree] = {}, ch_b[femheat::kChebMaxDegree] = {};
 
   // node vectors, FP32 (mixed form)
   float* pinv32 = nullptr;

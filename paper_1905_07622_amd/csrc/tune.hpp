@@ -12,7 +12,7 @@ struct fem_heat;
 namespace femheat {
 
 // Cache key of a launch shape (see tune_cache.cpp).
-std::string tune_key(int device, bool mixed, bool cubic, bool batched, int px, int py, int pz);
+std::string tune_key(int device, bool mixed, int kind, bool batched, int px, int py, int pz);
 // Tile recorded for `key` in the cache file `path` (false: none).
 bool tune_lookup(const char* path, const std::string& key, int tile[3]);
 // Records (or replaces) the tile of `key`; false if the file cannot be written.

@@ -1,5 +1,5 @@
 // Tile cache of the autotuner: one JSON file of records
-//   {"key": "<arch>|hip<version>|<fp64|mixed>|<cubic|box>|<single|batch>|<px>x<py>x<pz>",
+//   {"key": "<arch>|hip<version>|<fp64|mixed>|<box|cubic|tet6>|<single|batch>|<px>x<py>x<pz>",
 //    "tile": [tx, ty, tz], "best_us": t, "rule_us": t0, "candidates": n}
 // one record per line inside {"femheat_tune": 1, "entries": [ ... ]}.  The
 // key names what the launch shape depends on: the GPU architecture, the HIP
@@ -56,7 +56,7 @@ std::map<std::string, Record> read_all(const char* path) {
 
 }  // namespace
 
-std::string tune_key(int device, bool mixed, bool cubic, bool batched, int px, int py, int pz) {
+std::string tune_key(int device, bool mixed, int kind, bool batched, int px, int py, int pz) {
   static std::mutex mu;
   static std::map<int, std::string> arch;
   std::string a;
@@ -80,7 +80,7 @@ std::string tune_key(int device, bool mixed, bool cubic, bool batched, int px, i
   int ver = 0;
   if (hipRuntimeGetVersion(&ver) != hipSuccess) (void)hipGetLastError();
   std::ostringstream k;
-  k << a << "|hip" << ver << "|" << (mixed ? "mixed" : "fp64") << "|" << (cubic ? "cubic" : "box") << "|"
+  k << a << "|hip" << ver << "|" << (mixed ? "mixed" : "fp64") << "|" << (kind == 2 ? "tet6" : kind == 1 ? "cubic" : "box") << "|"
     << (batched ? "batch" : "single") << "|" << px << "x" << py << "x" << pz;
   return k.str();
 }

@@ -5,6 +5,7 @@
 #pragma once
 
 #include "common.hpp"
+#include "gather.hpp"
 #include "reduce.hpp"
 
 namespace femheat {
@@ -210,7 +211,12 @@ __global__ void jacobi_kernel(Geom g, const double* __restrict__ rhoc, const dou
         const int ex = ix - 1 + ox, ey = iy - 1 + oy, ez = iz - 1 + oz;
         if (ex < 0 || ex >= g.nx || ey < 0 || ey >= g.ny || ez < 0 || ez >= g.nz) continue;
         const uint32_t e = (uint32_t)ex + (uint32_t)g.nx * ((uint32_t)ey + (uint32_t)g.ny * (uint32_t)ez);
-        P += rhoc[e] * md + ck * kc[e] * kd;
+        if (g.tet6) {  // the node is corner a of this box; the tetrahedra's diagonal entries differ by corner
+          const int a = (1 - ox) + 2 * (1 - oy) + 4 * (1 - oz);
+          P += rhoc[e] * (g.hx * g.hx * g.hx / 120.0 * kTetM[a][a]) + ck * kc[e] * (g.hx / 6.0 * kTetK[a][a]);
+        } else {
+          P += rhoc[e] * md + ck * kc[e] * kd;
+        }
       }
   pinv[i] = (V)(1.0 / P);
 }
@@ -230,6 +236,19 @@ __global__ void jacobi_kernel(Geom g, const double* __restrict__ rhoc, const dou
     const int d = face >> 1;
     if (idx[d] != ((face & 1) ? n[d] : 0)) continue;
     const int u = (d + 1) % 3, v = (d + 2) % 3;
+    if (g.tet6) {
+      // the face's triangles split every face square along its (0,0)-(1,1)
+      // diagonal: a node at that diagonal of a square gets q hu hv / 3 from
+      // it (two triangles), at the other diagonal q hu hv / 6 (one)
+      double w = 0.0;
+      for (int su = idx[u] - 1; su <= idx[u]; ++su)
+        for (int sv = idx[v] - 1; sv <= idx[v]; ++sv) {
+          if (su < 0 || su >= n[u] || sv < 0 || sv >= n[v]) continue;
+          w += ((idx[u] - su) == (idx[v] - sv)) ? 1.0 / 3.0 : 1.0 / 6.0;
+        }
+      f += g.flux[face] * h[u] * h[v] * w;
+      continue;
+    }
     const int cu = (idx[u] > 0) + (idx[u] < n[u]);
     const int cv = (idx[v] > 0) + (idx[v] < n[v]);
     f += g.flux[face] * 0.25 * h[u] * h[v] * (double)(cu * cv);
@@ -302,6 +321,28 @@ __global__ void scale_kernel(const V* __restrict__ a, const V* __restrict__ x, d
     xi[d] = loc;
   }
   double v = 0.0;
+  if (g.tet6) {
+    // the tetrahedron 0, e_p, e_p + e_q, 7 with xi_p >= xi_q >= xi_r contains
+    // the point; barycentrics 1 - xi_p, xi_p - xi_q, xi_q - xi_r, xi_r
+    int o[3] = {0, 1, 2};
+    for (int i = 0; i < 2; ++i)
+      for (int j = 0; j < 2 - i; ++j)
+        if (xi[o[j]] < xi[o[j + 1]]) {
+          const int t = o[j];
+          o[j] = o[j + 1];
+          o[j + 1] = t;
+        }
+    const double lam[4] = {1.0 - xi[o[0]], xi[o[0]] - xi[o[1]], xi[o[1]] - xi[o[2]], xi[o[2]]};
+    int a = 0;
+    for (int k = 0; k < 4; ++k) {
+      if (k > 0) a |= 1 << o[k - 1];
+      const uint32_t i = (uint32_t)(e[0] + (a & 1)) +
+                         (uint32_t)g.px * ((uint32_t)(e[1] + ((a >> 1) & 1)) + (uint32_t)g.py * (uint32_t)(e[2] + (a >> 2)));
+      v += lam[k] * T[i];
+    }
+    out[s] = v;
+    return;
+  }
   for (int a = 0; a < 8; ++a) {
     const int ax = a & 1, ay = (a >> 1) & 1, az = (a >> 2) & 1;
     const double w = (ax ? xi[0] : 1.0 - xi[0]) * (ay ? xi[1] : 1.0 - xi[1]) * (az ? xi[2] : 1.0 - xi[2]);

@@ -21,6 +21,8 @@ FEM_OK, FEM_EINVAL, FEM_ENOMEM, FEM_ENOCONV, FEM_EBREAKDOWN, FEM_EDEVICE, FEM_EB
 FEM_FP64, FEM_FP32_FP64DOT = 0, 1
 FEM_GUESS_EXTRAP, FEM_GUESS_PREV = 0, 1
 FEM_STOP_RHS, FEM_STOP_INITIAL = 0, 1
+FEM_PRECOND_JACOBI, FEM_PRECOND_CHEBYSHEV = 0, 1
+FEM_ELEM_HEX8, FEM_ELEM_TET6 = 0, 1
 FEM_DEVICE_PTRS, FEM_TIMING, FEM_ONE_REDUCTION = 0x1, 0x2, 0x4
 FEM_OP_A, FEM_OP_L, FEM_OP_JACOBI, FEM_OP_LOAD, FEM_OP_FP32, FEM_OP_ELEMENTWISE, FEM_OP_ROWWAVE = (
     0, 1, 2, 3, 0x100, 0x200, 0x400)
@@ -47,7 +49,8 @@ class fem_opts(ctypes.Structure):
                 ("inner_rtol", ctypes.c_double), ("flags", ctypes.c_uint32),
                 ("hip_stream", ctypes.c_void_p), ("device", ctypes.c_int32),
                 ("tile_x", ctypes.c_int32), ("tile_y", ctypes.c_int32), ("tile_z", ctypes.c_int32),
-                ("allocator", ctypes.c_void_p), ("tune_cache", ctypes.c_char_p)]
+                ("allocator", ctypes.c_void_p), ("precond", ctypes.c_int32), ("cheb_degree", ctypes.c_int32),
+                ("cheb_ratio", ctypes.c_double), ("element", ctypes.c_int32), ("tune_cache", ctypes.c_char_p)]
 
 
 class fem_out(ctypes.Structure):
@@ -298,8 +301,10 @@ class _Arrays:
 
 def make_opts(*, precision=FEM_FP64, max_iter=10000, replace_every=50, guess=FEM_GUESS_EXTRAP,
               stop_rule=FEM_STOP_RHS, max_refine=4, inner_rtol=1e-5, device_ptrs=False, timing=False,
-              one_reduction=False, tile=(0, 0, 0), stream=None, device=0, tune_cache=None) -> fem_opts:
+              one_reduction=False, tile=(0, 0, 0), stream=None, device=0, tune_cache=None,
+              precond=FEM_PRECOND_JACOBI, cheb_degree=3, cheb_ratio=30.0, element=FEM_ELEM_HEX8) -> fem_opts:
     o = fem_heat_default_opts()
+    o.precond, o.cheb_degree, o.cheb_ratio, o.element = precond, cheb_degree, cheb_ratio, element
     o.precision, o.max_iter, o.replace_every = precision, max_iter, replace_every
     o.guess, o.stop_rule, o.max_refine, o.inner_rtol = guess, stop_rule, max_refine, inner_rtol
     o.flags = ((FEM_DEVICE_PTRS if device_ptrs else 0) | (FEM_TIMING if timing else 0)
@@ -353,6 +358,8 @@ def run_batch(problems, *, save_every=0, sensors=False, T_prev=None, check=True,
     keyword options (precision, tile, device_ptrs, ...) apply to all.
     Returns (status, list of per-simulation result dicts)."""
     device = bool(opt_kw.get("device_ptrs", False))
+    if problems:
+        opt_kw.setdefault("element", getattr(problems[0], "element", FEM_ELEM_HEX8))
     a = _Arrays(device)
     n = len(problems)
     reqs = (fem_request * max(n, 1))()
@@ -471,7 +478,8 @@ class Heat:
                  flux_mask=0, flux=None, flux_schedule=None, precision=FEM_FP64, max_iter=10000,
                  replace_every=50, guess=FEM_GUESS_EXTRAP, stop_rule=FEM_STOP_RHS, max_refine=4,
                  inner_rtol=1e-5, device_ptrs=False, timing=False, one_reduction=False, tile=(0, 0, 0), stream=None,
-                 device=0, tune_cache=None):
+                 device=0, tune_cache=None, precond=FEM_PRECOND_JACOBI, cheb_degree=3, cheb_ratio=30.0,
+                 element=FEM_ELEM_HEX8):
         self.h = None
         self.device_ptrs = device_ptrs
         self.N = (nx + 1) * (ny + 1) * (nz + 1)
@@ -488,6 +496,7 @@ class Heat:
         o = fem_heat_default_opts()
         o.precision, o.max_iter, o.replace_every = precision, max_iter, replace_every
         o.guess, o.stop_rule, o.max_refine, o.inner_rtol = guess, stop_rule, max_refine, inner_rtol
+        o.precond, o.cheb_degree, o.cheb_ratio, o.element = precond, cheb_degree, cheb_ratio, element
         o.flags = ((FEM_DEVICE_PTRS if device_ptrs else 0) | (FEM_TIMING if timing else 0)
                    | (FEM_ONE_REDUCTION if one_reduction else 0))
         o.hip_stream = stream
@@ -504,6 +513,7 @@ class Heat:
 
     @classmethod
     def from_problem(cls, p, **kw):
+        kw.setdefault("element", getattr(p, "element", FEM_ELEM_HEX8))
         return cls(p.nx, p.ny, p.nz, p.hx, p.hy, p.hz, p.k_e, p.rhoc_e,
                    dirichlet_mask=p.dirichlet_mask, dirichlet_value=p.dirichlet_value,
                    flux_mask=p.flux_mask, flux=p.flux, flux_schedule=p.flux_schedule, **kw)

@@ -215,6 +215,34 @@ def defect_slab(nx: int = 200, ny: int = 200, nz: int = 25, seed: int = 3,
                    flux_schedule=sched, sensors=sensor_grid(n_sensor, lx, ly, lz), seed=seed)
 
 
+# The paper's performance workload (Sec. 5.1): a two-layer laminate
+# [-15,15] x [-15,15] x [0,10] (mm), unit flux on the face x3 = 0, the other
+# faces insulated, T0 = 0; layer x3 <= 5 mild steel, above it iron oxide,
+# with the heat capacities and conductivities as printed; 50 Crank-Nicolson
+# steps of dt = 0.01, rtol 1e-6.  Its mesh sizes give 10.5k to 2.00M nodes
+# for n = 30 to 180 divisions across (n/3 through the thickness).
+LAMINATE_RHOC = (3.724e6, 1.65e6)
+LAMINATE_K = (4.9e8, 4e6)
+
+
+def laminate(n: int = 30, nsteps: int = 50, element: int = 1) -> Problem:
+    """The two-layer laminate on an n x n x n/3 grid of cubes of side 30/n
+    (origin at the prism's corner), material by element centroid
+    (x3 <= 5: steel), six tetrahedra per cube by default (the paper's element)."""
+    assert n % 3 == 0
+    nz = n // 3
+    h = 30.0 / n
+    _, _, cz = element_centroids(n, n, nz, h, h, h)
+    steel = cz <= 5.0
+    k = np.where(steel, LAMINATE_K[0], LAMINATE_K[1]).ravel().astype(np.float64)
+    rhoc = np.where(steel, LAMINATE_RHOC[0], LAMINATE_RHOC[1]).ravel().astype(np.float64)
+    flux = np.zeros(6)
+    flux[FACE_ZM] = 1.0
+    return Problem(name=f"laminate{n}", nx=n, ny=n, nz=nz, hx=h, hy=h, hz=h, k_e=k, rhoc_e=rhoc,
+                   T0=np.zeros((n + 1) * (n + 1) * (nz + 1)), dt=0.01, theta=0.5, nsteps=nsteps, rtol=1e-6,
+                   dirichlet_mask=0, flux_mask=face_bit(FACE_ZM), flux=flux, element=element)
+
+
 def sphere_proposal(s: int, n: int = 48, nsteps: int = 100) -> Problem:
     """One simulation of the batched proposal workload: n^3 unit cube,
     random-sphere two-phase field from seed 4000+s, T0=1, T=0 on z=0,
