@@ -1,17 +1,22 @@
 """The autotuner (fem_heat_tune) and its tile cache.
 
-Tuning changes only the launch shape of the gather: the sums of every node
-are formed in a fixed order whatever the tile, so runs with the tuned tile
-must be bit-identical to runs with the library's rule -- alone, in a batch,
-in FP64 and in the mixed form.  The cache makes later handles (single,
-batch members) take the recorded tile.
+Tuning changes only the launch shape of the gather.  The operator's value at
+every node is formed in a fixed order whatever the tile (the apply is
+bit-identical across tiles), but the PCG dot products are summed per block,
+so another tile partitions them differently and rounds them differently.
+Runs with the tuned tile are therefore checked against the oracle locked to
+their own iteration counts (FP64: relative L2 1e-10) or against the FP64
+oracle (mixed form: 1e-5), and against the untuned run to rounding; a
+handle that takes the tile from the cache repeats the tuned run bit for bit.
+The cache makes later handles (single, batch members) take the recorded tile.
 """
 import json
 
 import numpy as np
 import pytest
 
-from _util import say
+from _util import rel_l2, say
+from oracle import oracle
 from paper_1905_07622_amd import femheat as fh
 from paper_1905_07622_amd import workloads as wl
 
@@ -37,7 +42,17 @@ def test_tuned_single_run_bitwise_equal_and_cached(gpu, tmp_path, precision):
         st = h1.stats()
         assert [st["tile_x"], st["tile_y"], st["tile_z"]] == [res["tile_x"], res["tile_y"], res["tile_z"]]
         out = _run(h1, p)
-    assert np.array_equal(out["T_final"], ref["T_final"]) and np.array_equal(out["iters"], ref["iters"])
+    assert out["status"] == 0
+    gate = 1e-10 if precision == fh.FEM_FP64 else 1e-5
+    if precision == fh.FEM_FP64:
+        want = oracle.run(p, nsteps=4, locked_iters=out["iters"])
+    else:
+        want = oracle.run(p, nsteps=4)
+    err = rel_l2(out["T_final"], want["T_final"])
+    say(f"  tuned run vs oracle: rel L2 {err:.2e}; vs untuned run {rel_l2(out['T_final'], ref['T_final']):.2e}")
+    assert err <= gate
+    assert rel_l2(out["T_final"], ref["T_final"]) <= gate
+    assert np.abs(out["iters"].astype(int) - ref["iters"].astype(int)).max() <= 1
     rec = json.load(open(cache))["entries"]
     assert len(rec) == 1 and rec[0]["tile"] == [res["tile_x"], res["tile_y"], res["tile_z"]]
     assert "|single|37x37x37" in rec[0]["key"]
@@ -46,10 +61,10 @@ def test_tuned_single_run_bitwise_equal_and_cached(gpu, tmp_path, precision):
         st = h2.stats()
         assert [st["tile_x"], st["tile_y"], st["tile_z"]] == rec[0]["tile"]
         again = _run(h2, p)
-    assert np.array_equal(again["T_final"], ref["T_final"])
+    assert np.array_equal(again["T_final"], out["T_final"]) and np.array_equal(again["iters"], out["iters"])
 
 
-def test_tuned_batch_members_bitwise_equal(gpu, tmp_path):
+def test_tuned_batch_members_match(gpu, tmp_path):
     cache = str(tmp_path / "tune.json")
     probs = [wl.sphere_proposal(s, n=20, nsteps=3) for s in range(5)]
     st0, ref = fh.run_batch(probs, precision=fh.FEM_FP32_FP64DOT)
@@ -65,7 +80,14 @@ def test_tuned_batch_members_bitwise_equal(gpu, tmp_path):
     assert "|batch|21x21x21" in json.load(open(cache))["entries"][0]["key"]
     st1, out = fh.run_batch(probs, precision=fh.FEM_FP32_FP64DOT, tune_cache=cache)
     assert st0 == st1 == fh.FEM_OK
-    for a, b in zip(out, ref):
+    for q, a, b in zip(probs, out, ref):
+        want = oracle.run(q, nsteps=3)
+        assert rel_l2(a["T_final"], want["T_final"]) <= 1e-5
+        assert rel_l2(a["T_final"], b["T_final"]) <= 1e-5
+    # the same cache gives the same tiles, so a second batch repeats the first bit for bit
+    st2, again = fh.run_batch(probs, precision=fh.FEM_FP32_FP64DOT, tune_cache=cache)
+    assert st2 == fh.FEM_OK
+    for a, b in zip(again, out):
         assert np.array_equal(a["T_final"], b["T_final"]) and np.array_equal(a["iters"], b["iters"])
 
 
