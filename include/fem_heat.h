@@ -246,6 +246,24 @@ int fem_heat_run(fem_heat *h, const double *T0, const double *T_prev, double dt,
  * dt and theta: y = op(x).  x and y are N-vectors. */
 int fem_heat_apply(fem_heat *h, int32_t which, double dt, double theta, const double *x, double *y);
 
+/* fem_heat_apply for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * which is FEM_OP_A or FEM_OP_L, optionally OR-ed with FEM_OP_ELEMENTWISE
+ * (hexahedra only), in FP64.  x and y are DEVICE pointers to N doubles on
+ * the handle's device whatever the handle's flags (y must not overlap x).
+ * The call only enqueues kernels on the handle's stream and returns: no
+ * allocation, copy, event or synchronisation; the caller synchronises the
+ * stream before reading y.  The kernels' scratch (the element-by-element
+ * form's 4 N partial sums and the gather's sink for lanes without a node) is
+ * a static array of the library, one per GPU (32 MiB + 2 KiB, held until the
+ * process ends): the element-by-element form takes at most 2^20 nodes
+ * (FEM_EINVAL beyond).  Every call on one GPU shares that array, so calls
+ * that overlap on one GPU (two streams, two threads) race; calls in one
+ * stream's order do not.  Results are bit-identical to fem_heat_apply with
+ * the same operator and form.  Returns FEM_EINVAL for other operators, FP32
+ * or row-wavefront forms, missing pointers or bad dt/theta. */
+int fem_heat_apply_noalloc(fem_heat *h, int32_t which, double dt, double theta, const double *x, double *y);
+
 /* One simulation of a batch: a problem as for fem_heat_create and a run as
  * for fem_heat_run (same meanings, validation and outputs). */
 typedef struct {

@@ -319,6 +319,34 @@ int fem_heat_apply(fem_heat* h, int32_t which, double dt, double theta, const do
   }
 }
 
+int fem_heat_apply_noalloc(fem_heat* h, int32_t which, double dt, double theta, const double* x, double* y) {
+  if (!h) return FEM_EINVAL;
+  h->err.clear();
+  const int op = which & 0xff;
+  if ((which & ~(0xff | FEM_OP_ELEMENTWISE)) || (op != FEM_OP_A && op != FEM_OP_L)) {
+    h->err = "fem_heat_apply_noalloc takes FEM_OP_A or FEM_OP_L, optionally with FEM_OP_ELEMENTWISE";
+    return FEM_EINVAL;
+  }
+  if ((which & FEM_OP_ELEMENTWISE) && h->opts.element != FEM_ELEM_HEX8) {
+    h->err = "the element-by-element apply takes the hexahedral element";
+    return FEM_EINVAL;
+  }
+  if (!x || !y) {
+    h->err = "x and y are required";
+    return FEM_EINVAL;
+  }
+  if (!finite_pos(dt) || !(theta >= 0.0 && theta <= 1.0)) {
+    h->err = "dt must be > 0 and theta in [0, 1]";
+    return FEM_EINVAL;
+  }
+  try {
+    return femheat::solver_apply_noalloc(h, which, dt, theta, x, y);
+  } catch (...) {
+    h->err = "unexpected exception";
+    return FEM_EDEVICE;
+  }
+}
+
 int fem_heat_tune(fem_heat* h, double dt, double theta, uint32_t flags, fem_tune_result* out) {
   if (!h) return FEM_EINVAL;
   h->err.clear();

@@ -6,9 +6,11 @@
 // (Sec. 3.1); the time stepping itself lives in engine.hip, which drives one
 // handle or a batch of them.
 #include <algorithm>
+#include <array>
 #include <new>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 
 #include "ebe.hpp"
 #include "engine.hpp"
@@ -17,8 +19,23 @@
 #include "tune.hpp"
 #include "vector_kernels.hpp"
 
+// Scratch of fem_heat_apply_noalloc, for callers that cannot allocate: the
+// element-by-element form's 4 N partial sums (N <= kNoallocMaxNodes) and a
+// 256-value sink for the gather's stores of lanes without a node.  One copy
+// per GPU, held until the process ends.  Host code never passes this name to
+// a kernel (on the host it is only a stand-in); it uses the device address
+// that hipGetSymbolAddress returns for the current device.
+constexpr size_t kNoallocMaxNodes = size_t(1) << 20;
+constexpr size_t kNoallocSink = 256;
+static __device__ __align__(256) double scratch[4 * kNoallocMaxNodes + kNoallocSink];
+
 namespace femheat {
 namespace {
+
+// Device address of `scratch` per device ordinal, looked up once per device.
+constexpr int kMaxDevices = 64;
+std::mutex scratch_mu;
+std::array<double*, kMaxDevices> scratch_dev{};
 
 // LDS row pitch (in values) of a tile of width `width`: the smallest pitch
 // for which the 64 lanes of every wave, split into half-waves of 32 lanes,
@@ -288,6 +305,45 @@ void launch_ebe(fem_heat* h, double ck, const double* x, double* part, double* y
 
 }  // namespace
 
+// Looks up the device address of `scratch` on the handle's device (current)
+// the first time a handle is created there, and gives it to the handle.
+int noalloc_scratch_setup(fem_heat* h) {
+  const int dev = h->opts.device;
+  if (dev < 0 || dev >= kMaxDevices) return fail(h, FEM_EINVAL, "device ordinal out of range");
+  std::lock_guard<std::mutex> lk(scratch_mu);
+  if (!scratch_dev[(size_t)dev]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) {
+      (void)hipGetLastError();
+      return fail(h, FEM_EDEVICE, "hipGetSymbolAddress(scratch) failed");
+    }
+    scratch_dev[(size_t)dev] = static_cast<double*>(p);
+  }
+  h->noalloc_scratch = scratch_dev[(size_t)dev];
+  return FEM_OK;
+}
+
+int solver_apply_noalloc(fem_heat* h, int32_t which, double dt, double theta, const double* x, double* y) {
+  const uint32_t N = h->g.N;
+  const bool ebe = (which & FEM_OP_ELEMENTWISE) != 0;
+  const int op = which & 0xff;
+  if (ebe && (size_t)N > kNoallocMaxNodes)
+    return fail(h, FEM_EINVAL, "the element-by-element form without allocation takes at most 2^20 nodes");
+  double* part = h->noalloc_scratch;
+  double* sink = h->noalloc_scratch + 4 * kNoallocMaxNodes;
+  if (!part) return fail(h, FEM_EDEVICE, "scratch address not set up");
+  HIP_TRY(hipSetDevice(h->opts.device));
+  const double ck = op == FEM_OP_A ? theta * dt : -(1.0 - theta) * dt;
+  if (ebe) {
+    launch_ebe(h, ck, x, part, y);
+  } else {
+    RC_TRY(launch_gather<double>(h, 1.0, ck, ProPlain<double>{x}, EpiStore<double>{y}, no_relay(), sink));
+  }
+  HIP_TRY(hipGetLastError());
+  return FEM_OK;
+}
+
 int ensure_fp32(fem_heat* h) {
   if (h->pinv32) return FEM_OK;
   const uint32_t N = h->g.N, E = h->g.E;
@@ -360,6 +416,7 @@ int solver_init(fem_heat* h, const fem_grid* grid, const double* k_e, const doub
   g.tet6 = h->opts.element == FEM_ELEM_TET6 ? 1 : 0;
   h->kind = g.tet6 ? kElemTet6 : (h->cubic ? kElemCubic : kElemBox);
   HIP_TRY(hipSetDevice(h->opts.device));
+  RC_TRY(noalloc_scratch_setup(h));
   {
     // a tile the autotuner recorded for this grid, precision, element class
     // and launch kind (alone or in a batch) replaces the rule

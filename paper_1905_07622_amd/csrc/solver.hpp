@@ -51,6 +51,7 @@ struct fem_heat {
   double* pool[4] = {nullptr, nullptr, nullptr, nullptr};  // T^{n-1}, T^{n-2}, x ping-pong
   double* lift64 = nullptr;   // A_fD g (only with non-zero Dirichlet values)
   double* sink = nullptr;     // 256 scratch values for stores of lanes without a node
+  double* noalloc_scratch = nullptr;  // device address of the library's static scratch on this device
   double ck_cached = -1.0;    // theta*dt of pinv/lift; < 0: none
 
   // Chebyshev preconditioner (FP64 solves): s = M^-1 r, the chain's residual
@@ -101,6 +102,10 @@ int solver_init(fem_heat* h, const fem_grid* grid, const double* k_e, const doub
 int make_handle(const fem_grid* grid, const double* k_e, const double* rhoc_e, const fem_bc* bc, const fem_opts& o,
                 bool batched, fem_heat** out, std::string* why);
 int solver_apply(fem_heat* h, int32_t which, double dt, double theta, const double* x, double* y);
+// fem_heat_apply for device pointers with the library's static scratch: only
+// kernel launches on the handle's stream (no allocation, copy or wait).
+int solver_apply_noalloc(fem_heat* h, int32_t which, double dt, double theta, const double* x, double* y);
+int noalloc_scratch_setup(fem_heat* h);
 void solver_free(fem_heat* h);
 
 // Time stepping (engine.hip): one handle, or a batch of handles advanced

@@ -111,7 +111,8 @@ class FemError(RuntimeError):
         self.status = status
 
 
-EXPORTS = ("fem_heat_create", "fem_heat_run", "fem_heat_apply", "fem_heat_stats", "fem_heat_tune",
+EXPORTS = ("fem_heat_create", "fem_heat_run", "fem_heat_apply", "fem_heat_apply_noalloc", "fem_heat_stats",
+           "fem_heat_tune",
            "fem_heat_destroy",
            "fem_heat_default_opts", "fem_strerror", "fem_last_error", "fem_heat_run_batch",
            "fem_server_create", "fem_server_submit", "fem_server_poll", "fem_server_wait", "fem_server_cancel",
@@ -133,6 +134,7 @@ def lib():
         L.fem_heat_run.argtypes = [vp, _dp, _dp, ctypes.c_double, ctypes.c_double, ctypes.c_int32,
                                    ctypes.c_double, ctypes.POINTER(fem_out)]
         L.fem_heat_apply.argtypes = [vp, ctypes.c_int32, ctypes.c_double, ctypes.c_double, _dp, _dp]
+        L.fem_heat_apply_noalloc.argtypes = [vp, ctypes.c_int32, ctypes.c_double, ctypes.c_double, vp, vp]
         L.fem_heat_stats.argtypes = [vp, ctypes.POINTER(fem_stats)]
         L.fem_heat_tune.argtypes = [vp, ctypes.c_double, ctypes.c_double, ctypes.c_uint32,
                                     ctypes.POINTER(fem_tune_result)]
@@ -157,7 +159,8 @@ def lib():
         L.fem_strerror.restype = ctypes.c_char_p
         L.fem_last_error.argtypes = [vp]
         L.fem_last_error.restype = ctypes.c_char_p
-        for n in ("fem_heat_create", "fem_heat_run", "fem_heat_apply", "fem_heat_stats", "fem_heat_tune"):
+        for n in ("fem_heat_create", "fem_heat_run", "fem_heat_apply", "fem_heat_apply_noalloc", "fem_heat_stats",
+                  "fem_heat_tune"):
             getattr(L, n).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -196,6 +199,11 @@ def fem_heat_run(h, T0_ptr, T_prev_ptr, dt, theta, nsteps, rtol, out: Optional[f
 
 def fem_heat_apply(h, which, dt, theta, x_ptr, y_ptr) -> int:
     return lib().fem_heat_apply(h, which, dt, theta, x_ptr, y_ptr)
+
+
+def fem_heat_apply_noalloc(h, which, dt, theta, x_dev_ptr, y_dev_ptr) -> int:
+    """Device pointers (ints) in and out; enqueues on the handle's stream and returns."""
+    return lib().fem_heat_apply_noalloc(h, which, dt, theta, x_dev_ptr, y_dev_ptr)
 
 
 def fem_heat_tune(h, dt, theta, flags=0):

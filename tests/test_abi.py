@@ -91,6 +91,7 @@ def test_create_rejects_invalid_arguments_before_device_work(lib, case):
 def test_null_handle_calls_are_rejected(lib):
     assert lib.fem_heat_run(None, None, None, 1.0, 1.0, 1, 1.0, None) == fh.FEM_EINVAL
     assert lib.fem_heat_apply(None, 0, 1.0, 1.0, None, None) == fh.FEM_EINVAL
+    assert lib.fem_heat_apply_noalloc(None, 0, 1.0, 1.0, None, None) == fh.FEM_EINVAL
     lib.fem_heat_destroy(None)
     assert lib.fem_heat_stats(None, None) == fh.FEM_EINVAL
 
