@@ -91,8 +91,8 @@ extern "C" {
                                   test are Algorithm 1's, beta uses r'^T P^-1 r' = delta - 2 alpha
                                   q^T P^-1 r + alpha^2 q^T P^-1 q (restarted from the summed delta every
                                   iteration), so the iterates agree with Algorithm 1 to rounding.  One
-                                  extra direction kernel per solve; the inner FP32 solves of the mixed
-                                  form keep two kernels per iteration */
+                                  extra direction kernel per solve.  With FEM_FP32_FP64DOT the FP32
+                                  inner solves take this form (sums and scalars in FP64) */
 
 /* Operators for fem_heat_apply */
 #define FEM_OP_A 0           /* y = (M + theta*dt*K) x                              */
@@ -180,7 +180,7 @@ typedef struct {
                              tile override is given, a handle takes the gather tile recorded
                              there for its node grid, precision, element class and launch kind
                              (alone or batch member) on this GPU architecture and HIP runtime;
-                             fem_heat_tune records into it.  Results do not depend on the tile. */
+                             fem_heat_tune records into it (see fem_heat_tune on results). */
 } fem_opts;
 
 /* Outputs of a run (inputs marked "in").  Every pointer may be NULL.
@@ -222,7 +222,7 @@ typedef struct {
 /* Create a solver for one grid, coefficient field and set of boundary
  * conditions (Sec. 3.2: the element data are prepared once, only the
  * coefficients change between solves).  Validates (FEM_EINVAL): nx,ny,nz >= 1,
- * h* > 0 and finite, k_e >= 0 and finite, rho*c_e > 0 and finite, masks in 6
+ * fewer than 2^29 nodes, h* > 0 and finite, k_e >= 0 and finite, rho*c_e > 0 and finite, masks in 6
  * bits and disjoint, finite boundary values.  Copies k_e, rho*c_e and the
  * schedule to the device, builds the load vector F (a1 kernel).  opts may be
  * NULL (defaults).  On success *out owns the device state. */
@@ -381,8 +381,10 @@ void fem_server_destroy(fem_server *s);
  * handle's options name a tune_cache, the result is recorded there under
  * the key of this grid, precision, element class and launch kind, and later
  * handles (fem_heat_create, fem_heat_run_batch, servers) with the same
- * options take it.  Results of a run do not depend on the tile (the gather's
- * sums are formed in a fixed order).  The handle's vectors are overwritten:
+ * options take it.  The operator's value at every node does not depend on
+ * the tile (its sums are formed in a fixed order), but a run's dot products
+ * are summed per block, so another tile changes results at rounding level;
+ * the same tile repeats a run bit for bit.  The handle's vectors are overwritten:
  * tune before a run, not between the two halves of a resumed run.  out may
  * be NULL. */
 #define FEM_TUNE_BATCH 0x1

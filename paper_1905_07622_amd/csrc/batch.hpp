@@ -48,6 +48,8 @@ struct SimDev {
   const float* pinv32;
   float* r32;
   float* q32;
+  float* r32b;  // one-reduction form of the inner solves: second residual and apply buffers
+  float* q32b;
   float* d32[2];
   float* e32[2];
   float* rhs32;
@@ -108,19 +110,19 @@ struct BatchArgs {
   int32_t cheb_rhs;    //                  the chain preconditions the lifted right-hand side (else r)
 };
 
-__device__ inline Relay outer_relay(const SimDev& s, const BatchArgs& a, int32_t mode, bool partials) {
+__host__ __device__ inline Relay outer_relay(const SimDev& s, const BatchArgs& a, int32_t mode, bool partials) {
   return Relay{s.oS[a.cur], s.oS[a.cur ^ 1], s.oP[a.cur], s.nblk[a.prev], partials ? s.oP[a.cur ^ 1] : nullptr,
                mode, s.octl, s.ldp};
 }
-__device__ inline Relay inner_relay(const SimDev& s, const BatchArgs& a, int32_t mode, bool partials) {
+__host__ __device__ inline Relay inner_relay(const SimDev& s, const BatchArgs& a, int32_t mode, bool partials) {
   return Relay{s.iS[a.cur], s.iS[a.cur ^ 1], s.iP[a.cur], s.nblk[a.prev], partials ? s.iP[a.cur ^ 1] : nullptr,
                mode, s.ictl, s.ldp};
 }
 
 // The direction ping-pongs every iteration: iteration j reads d[j&1] and
 // writes d[(j+1)&1], which the update of iteration j then uses.
-__device__ inline int dir_in(const BatchArgs& a) { return a.j & 1; }
-__device__ inline int dir_out(const BatchArgs& a) { return (a.j + 1) & 1; }
+__host__ __device__ inline int dir_in(const BatchArgs& a) { return a.j & 1; }
+__host__ __device__ inline int dir_out(const BatchArgs& a) { return (a.j + 1) & 1; }
 
 // ---- gather roles: operator, prologue, epilogue and relay of each gather ----
 
@@ -128,22 +130,22 @@ struct RoleRhs {  // b = L T^{n-1} + dt*s_n*F, with b^T P^-1 b (a2)
   using V = double;
   using Pro = ProPlain<double>;
   using Epi = EpiRhs<double>;
-  static __device__ const GatherArgs<V>& ga(const SimDev& s) { return s.L64; }
-  static __device__ Pro pro(const SimDev& s, const BatchArgs&) { return Pro{s.T1}; }
-  static __device__ Epi epi(const SimDev& s, const BatchArgs&) { return Epi{s.b64, s.F64, s.pinv64, s.lift64, s.fs}; }
-  static __device__ Relay relay(const SimDev& s, const BatchArgs& a) { return outer_relay(s, a, M_RHS, true); }
+  static __host__ __device__ const GatherArgs<V>& ga(const SimDev& s) { return s.L64; }
+  static __host__ __device__ Pro pro(const SimDev& s, const BatchArgs&) { return Pro{s.T1}; }
+  static __host__ __device__ Epi epi(const SimDev& s, const BatchArgs&) { return Epi{s.b64, s.F64, s.pinv64, s.lift64, s.fs}; }
+  static __host__ __device__ Relay relay(const SimDev& s, const BatchArgs& a) { return outer_relay(s, a, M_RHS, true); }
 };
 
 struct RoleInit {  // x0 by the guess rule, r = b - A x0, r^T P^-1 r (a3)
   using V = double;
   using Pro = ProGuess<double>;
   using Epi = EpiResidual<double>;
-  static __device__ const GatherArgs<V>& ga(const SimDev& s) { return s.A64; }
-  static __device__ Pro pro(const SimDev& s, const BatchArgs&) {
+  static __host__ __device__ const GatherArgs<V>& ga(const SimDev& s) { return s.A64; }
+  static __host__ __device__ Pro pro(const SimDev& s, const BatchArgs&) {
     return Pro{s.T1, s.T2, s.pinv64, s.X[0], s.guess_prev, 0};
   }
-  static __device__ Epi epi(const SimDev& s, const BatchArgs&) { return Epi{s.b64, s.pinv64, s.r64}; }
-  static __device__ Relay relay(const SimDev& s, const BatchArgs& a) { return outer_relay(s, a, M_INIT, true); }
+  static __host__ __device__ Epi epi(const SimDev& s, const BatchArgs&) { return Epi{s.b64, s.pinv64, s.r64}; }
+  static __host__ __device__ Relay relay(const SimDev& s, const BatchArgs& a) { return outer_relay(s, a, M_INIT, true); }
 };
 
 // The next step's RHS and initial residual, launched right after a decide
@@ -152,7 +154,7 @@ struct RoleInit {  // x0 by the guess rule, r = b - A x0, r^T P^-1 r (a3)
 // rotate them -- T^n = X[next_xc], T^{n-1} = T1, the guess into T2's buffer --
 // and run only if the solve has ended well in X[next_xc]; otherwise they
 // pass the state through and the host carries on (see M_RHS_NEXT).
-__device__ inline Relay next_relay(const SimDev& s, const BatchArgs& a, int32_t mode) {
+__host__ __device__ inline Relay next_relay(const SimDev& s, const BatchArgs& a, int32_t mode) {
   Relay R = outer_relay(s, a, mode, true);
   R.next_xc = a.next_xc;
   R.next_R = a.next_R;
@@ -163,24 +165,24 @@ struct RoleRhsNext {
   using V = double;
   using Pro = ProPlain<double>;
   using Epi = EpiRhs<double>;
-  static __device__ const GatherArgs<V>& ga(const SimDev& s) { return s.L64; }
-  static __device__ Pro pro(const SimDev& s, const BatchArgs& a) { return Pro{s.X[a.next_xc]}; }
-  static __device__ Epi epi(const SimDev& s, const BatchArgs& a) {
+  static __host__ __device__ const GatherArgs<V>& ga(const SimDev& s) { return s.L64; }
+  static __host__ __device__ Pro pro(const SimDev& s, const BatchArgs& a) { return Pro{s.X[a.next_xc]}; }
+  static __host__ __device__ Epi epi(const SimDev& s, const BatchArgs& a) {
     return Epi{s.b64, s.F64, s.pinv64, s.lift64, a.next_fs};
   }
-  static __device__ Relay relay(const SimDev& s, const BatchArgs& a) { return next_relay(s, a, M_RHS_NEXT); }
+  static __host__ __device__ Relay relay(const SimDev& s, const BatchArgs& a) { return next_relay(s, a, M_RHS_NEXT); }
 };
 
 struct RoleInitNext {
   using V = double;
   using Pro = ProGuess<double>;
   using Epi = EpiResidual<double>;
-  static __device__ const GatherArgs<V>& ga(const SimDev& s) { return s.A64; }
-  static __device__ Pro pro(const SimDev& s, const BatchArgs& a) {
+  static __host__ __device__ const GatherArgs<V>& ga(const SimDev& s) { return s.A64; }
+  static __host__ __device__ Pro pro(const SimDev& s, const BatchArgs& a) {
     return Pro{s.X[a.next_xc], s.T1, s.pinv64, const_cast<double*>(s.T2), s.guess_prev, 0};
   }
-  static __device__ Epi epi(const SimDev& s, const BatchArgs&) { return Epi{s.b64, s.pinv64, s.r64}; }
-  static __device__ Relay relay(const SimDev& s, const BatchArgs& a) { return next_relay(s, a, M_INIT_NEXT); }
+  static __host__ __device__ Epi epi(const SimDev& s, const BatchArgs&) { return Epi{s.b64, s.pinv64, s.r64}; }
+  static __host__ __device__ Relay relay(const SimDev& s, const BatchArgs& a) { return next_relay(s, a, M_INIT_NEXT); }
 };
 
 template <typename V>
@@ -191,12 +193,12 @@ struct RoleDir<double> {
   using V = double;
   using Pro = ProDirection<double>;
   using Epi = EpiQDot<double>;
-  static __device__ const GatherArgs<V>& ga(const SimDev& s) { return s.A64; }
-  static __device__ Pro pro(const SimDev& s, const BatchArgs& a) {
+  static __host__ __device__ const GatherArgs<V>& ga(const SimDev& s) { return s.A64; }
+  static __host__ __device__ Pro pro(const SimDev& s, const BatchArgs& a) {
     return Pro{s.r64, s.pinv64, s.d64[dir_in(a)], s.d64[dir_out(a)], s.X[a.xpar], a.corr, 0.0, 0.0};
   }
-  static __device__ Epi epi(const SimDev& s, const BatchArgs&) { return Epi{s.q64}; }
-  static __device__ Relay relay(const SimDev& s, const BatchArgs& a) { return outer_relay(s, a, M_DIR, true); }
+  static __host__ __device__ Epi epi(const SimDev& s, const BatchArgs&) { return Epi{s.q64}; }
+  static __host__ __device__ Relay relay(const SimDev& s, const BatchArgs& a) { return outer_relay(s, a, M_DIR, true); }
 };
 
 template <>
@@ -204,12 +206,12 @@ struct RoleDir<float> {
   using V = float;
   using Pro = ProDirection<float>;
   using Epi = EpiQDot<float>;
-  static __device__ const GatherArgs<V>& ga(const SimDev& s) { return s.A32; }
-  static __device__ Pro pro(const SimDev& s, const BatchArgs& a) {
+  static __host__ __device__ const GatherArgs<V>& ga(const SimDev& s) { return s.A32; }
+  static __host__ __device__ Pro pro(const SimDev& s, const BatchArgs& a) {
     return Pro{s.r32, s.pinv32, s.d32[dir_in(a)], s.d32[dir_out(a)], s.e32[a.xpar], a.corr, 0.0f, 0.0f};
   }
-  static __device__ Epi epi(const SimDev& s, const BatchArgs&) { return Epi{s.q32}; }
-  static __device__ Relay relay(const SimDev& s, const BatchArgs& a) { return inner_relay(s, a, M_DIR, true); }
+  static __host__ __device__ Epi epi(const SimDev& s, const BatchArgs&) { return Epi{s.q32}; }
+  static __host__ __device__ Relay relay(const SimDev& s, const BatchArgs& a) { return inner_relay(s, a, M_DIR, true); }
 };
 
 template <typename V>
@@ -220,12 +222,12 @@ struct RoleRepl<double> {
   using V = double;
   using Pro = ProAxpy<double, double>;
   using Epi = EpiResidual<double>;
-  static __device__ const GatherArgs<V>& ga(const SimDev& s) { return s.A64; }
-  static __device__ Pro pro(const SimDev& s, const BatchArgs& a) {
+  static __host__ __device__ const GatherArgs<V>& ga(const SimDev& s) { return s.A64; }
+  static __host__ __device__ Pro pro(const SimDev& s, const BatchArgs& a) {
     return Pro{s.X[a.xpar], s.d64[dir_out(a)], s.X[a.xpar ^ 1], 0, 0.0};
   }
-  static __device__ Epi epi(const SimDev& s, const BatchArgs&) { return Epi{s.b64, s.pinv64, s.r64}; }
-  static __device__ Relay relay(const SimDev& s, const BatchArgs& a) { return outer_relay(s, a, M_UPD, true); }
+  static __host__ __device__ Epi epi(const SimDev& s, const BatchArgs&) { return Epi{s.b64, s.pinv64, s.r64}; }
+  static __host__ __device__ Relay relay(const SimDev& s, const BatchArgs& a) { return outer_relay(s, a, M_UPD, true); }
 };
 
 template <>
@@ -233,31 +235,31 @@ struct RoleRepl<float> {
   using V = float;
   using Pro = ProAxpy<float, float>;
   using Epi = EpiResidual<float>;
-  static __device__ const GatherArgs<V>& ga(const SimDev& s) { return s.A32; }
-  static __device__ Pro pro(const SimDev& s, const BatchArgs& a) {
+  static __host__ __device__ const GatherArgs<V>& ga(const SimDev& s) { return s.A32; }
+  static __host__ __device__ Pro pro(const SimDev& s, const BatchArgs& a) {
     return Pro{s.e32[a.xpar], s.d32[dir_out(a)], s.e32[a.xpar ^ 1], 0, 0.0f};
   }
-  static __device__ Epi epi(const SimDev& s, const BatchArgs&) { return Epi{s.rhs32, s.pinv32, s.r32}; }
-  static __device__ Relay relay(const SimDev& s, const BatchArgs& a) { return inner_relay(s, a, M_UPD, true); }
+  static __host__ __device__ Epi epi(const SimDev& s, const BatchArgs&) { return Epi{s.rhs32, s.pinv32, s.r32}; }
+  static __host__ __device__ Relay relay(const SimDev& s, const BatchArgs& a) { return inner_relay(s, a, M_UPD, true); }
 };
 
 // One-reduction form (FP64): iteration j's residual lives in buffer j&1 of
 // (r64, r64b) and its q = A d in buffer j&1 of (q64, q64b); the initial
 // residual is in r64 (buffer 0).
-__device__ inline double* rbuf(const SimDev& s, int k) { return (k & 1) ? s.r64b : s.r64; }
-__device__ inline double* qbuf(const SimDev& s, int k) { return (k & 1) ? s.q64b : s.q64; }
+__host__ __device__ inline double* rbuf(const SimDev& s, int k) { return (k & 1) ? s.r64b : s.r64; }
+__host__ __device__ inline double* qbuf(const SimDev& s, int k) { return (k & 1) ? s.q64b : s.q64; }
 
 struct RoleFused {  // (r -= alpha q, x += alpha d_old,) d = P^-1 r + beta d, q = A d, four sums (a4-a6)
   using V = double;
   using Pro = ProFused<double>;
   using Epi = EpiQ<double>;
-  static __device__ const GatherArgs<V>& ga(const SimDev& s) { return s.A64; }
-  static __device__ Pro pro(const SimDev& s, const BatchArgs& a) {
+  static __host__ __device__ const GatherArgs<V>& ga(const SimDev& s) { return s.A64; }
+  static __host__ __device__ Pro pro(const SimDev& s, const BatchArgs& a) {
     return Pro{rbuf(s, a.corr ? a.j + 1 : a.j), qbuf(s, a.j + 1), s.pinv64, s.d64[dir_in(a)], s.d64[dir_out(a)],
                s.X[a.xpar], rbuf(s, a.j), a.corr, 0.0, 0.0};
   }
-  static __device__ Epi epi(const SimDev& s, const BatchArgs& a) { return Epi{qbuf(s, a.j)}; }
-  static __device__ Relay relay(const SimDev& s, const BatchArgs& a) {
+  static __host__ __device__ Epi epi(const SimDev& s, const BatchArgs& a) { return Epi{qbuf(s, a.j)}; }
+  static __host__ __device__ Relay relay(const SimDev& s, const BatchArgs& a) {
     return outer_relay(s, a, a.corr ? M_FUPD : M_FDIR, true);
   }
 };
@@ -267,24 +269,60 @@ struct RoleReplFused {  // one-reduction form: x += alpha d, r = b - A x into th
   static constexpr bool kFour = true;  // follows a one-reduction direction kernel
   using Pro = ProAxpy<double, double>;
   using Epi = EpiResidual<double>;
-  static __device__ const GatherArgs<V>& ga(const SimDev& s) { return s.A64; }
-  static __device__ Pro pro(const SimDev& s, const BatchArgs& a) {
+  static __host__ __device__ const GatherArgs<V>& ga(const SimDev& s) { return s.A64; }
+  static __host__ __device__ Pro pro(const SimDev& s, const BatchArgs& a) {
     return Pro{s.X[a.xpar], s.d64[dir_out(a)], s.X[a.xpar ^ 1], 0, 0.0};
   }
-  static __device__ Epi epi(const SimDev& s, const BatchArgs& a) { return Epi{s.b64, s.pinv64, rbuf(s, a.j + 1)}; }
-  static __device__ Relay relay(const SimDev& s, const BatchArgs& a) { return outer_relay(s, a, M_FREPL, true); }
+  static __host__ __device__ Epi epi(const SimDev& s, const BatchArgs& a) { return Epi{s.b64, s.pinv64, rbuf(s, a.j + 1)}; }
+  static __host__ __device__ Relay relay(const SimDev& s, const BatchArgs& a) { return outer_relay(s, a, M_FREPL, true); }
+};
+
+// The one-reduction form of the FP32 inner solves of the mixed form: the
+// same kernels on the FP32 set (r32, r32b; q32, q32b; the inner iterate e)
+// with the inner relay (FP64 sums and scalars).
+__host__ __device__ inline float* rbuf32(const SimDev& s, int k) { return (k & 1) ? s.r32b : s.r32; }
+__host__ __device__ inline float* qbuf32(const SimDev& s, int k) { return (k & 1) ? s.q32b : s.q32; }
+
+struct RoleFused32 {
+  using V = float;
+  using Pro = ProFused<float>;
+  using Epi = EpiQ<float>;
+  static __host__ __device__ const GatherArgs<V>& ga(const SimDev& s) { return s.A32; }
+  static __host__ __device__ Pro pro(const SimDev& s, const BatchArgs& a) {
+    return Pro{rbuf32(s, a.corr ? a.j + 1 : a.j), qbuf32(s, a.j + 1), s.pinv32, s.d32[dir_in(a)], s.d32[dir_out(a)],
+               s.e32[a.xpar], rbuf32(s, a.j), a.corr, 0.0f, 0.0f};
+  }
+  static __host__ __device__ Epi epi(const SimDev& s, const BatchArgs& a) { return Epi{qbuf32(s, a.j)}; }
+  static __host__ __device__ Relay relay(const SimDev& s, const BatchArgs& a) {
+    return inner_relay(s, a, a.corr ? M_FUPD : M_FDIR, true);
+  }
+};
+
+struct RoleReplFused32 {  // e += alpha d, r = rhs - A e into the next residual buffer
+  using V = float;
+  static constexpr bool kFour = true;
+  using Pro = ProAxpy<float, float>;
+  using Epi = EpiResidual<float>;
+  static __host__ __device__ const GatherArgs<V>& ga(const SimDev& s) { return s.A32; }
+  static __host__ __device__ Pro pro(const SimDev& s, const BatchArgs& a) {
+    return Pro{s.e32[a.xpar], s.d32[dir_out(a)], s.e32[a.xpar ^ 1], 0, 0.0f};
+  }
+  static __host__ __device__ Epi epi(const SimDev& s, const BatchArgs& a) {
+    return Epi{s.rhs32, s.pinv32, rbuf32(s, a.j + 1)};
+  }
+  static __host__ __device__ Relay relay(const SimDev& s, const BatchArgs& a) { return inner_relay(s, a, M_FREPL, true); }
 };
 
 struct RoleCorr {  // mixed form: x64 += e, r64 = b - A x64, FP64 residual norm (a9)
   using V = double;
   using Pro = ProAxpy<double, float>;
   using Epi = EpiResidual<double>;
-  static __device__ const GatherArgs<V>& ga(const SimDev& s) { return s.A64; }
-  static __device__ Pro pro(const SimDev& s, const BatchArgs&) {
+  static __host__ __device__ const GatherArgs<V>& ga(const SimDev& s) { return s.A64; }
+  static __host__ __device__ Pro pro(const SimDev& s, const BatchArgs&) {
     return Pro{s.X[s.xc], s.e32[s.exc], s.X[s.xc ^ 1], 1, 0.0};
   }
-  static __device__ Epi epi(const SimDev& s, const BatchArgs&) { return Epi{s.b64, s.pinv64, s.r64}; }
-  static __device__ Relay relay(const SimDev& s, const BatchArgs& a) {
+  static __host__ __device__ Epi epi(const SimDev& s, const BatchArgs&) { return Epi{s.b64, s.pinv64, s.r64}; }
+  static __host__ __device__ Relay relay(const SimDev& s, const BatchArgs& a) {
     return outer_relay(s, a, s.sweep ? M_CORR : M_SKIP, true);
   }
 };
@@ -294,20 +332,20 @@ struct RoleDirS {
   using V = double;
   using Pro = ProDirectionS<double>;
   using Epi = EpiQDot<double>;
-  static __device__ const GatherArgs<V>& ga(const SimDev& s) { return s.A64; }
-  static __device__ Pro pro(const SimDev& s, const BatchArgs& a) {
+  static __host__ __device__ const GatherArgs<V>& ga(const SimDev& s) { return s.A64; }
+  static __host__ __device__ Pro pro(const SimDev& s, const BatchArgs& a) {
     return Pro{s.s64, s.d64[dir_in(a)], s.d64[dir_out(a)], s.X[a.xpar], a.corr, 0.0, 0.0};
   }
-  static __device__ Epi epi(const SimDev& s, const BatchArgs&) { return Epi{s.q64}; }
-  static __device__ Relay relay(const SimDev& s, const BatchArgs& a) { return outer_relay(s, a, M_DIR, true); }
+  static __host__ __device__ Epi epi(const SimDev& s, const BatchArgs&) { return Epi{s.q64}; }
+  static __host__ __device__ Relay relay(const SimDev& s, const BatchArgs& a) { return outer_relay(s, a, M_DIR, true); }
 };
 
 // The Chebyshev preconditioner s = q(D^-1 A) D^-1 r_in as a chain of gathers
 // relayed with M_PASS; the last one publishes r_in^T s, which completes the
 // scalar update pending before the chain (delta_b of a right-hand side, or
 // the delta of an initial residual, an update or a replacement).
-__device__ inline const double* cheb_rin(const SimDev& s, const BatchArgs& a) { return a.cheb_rhs ? s.b64 : s.r64; }
-__device__ inline const double* cheb_lift(const SimDev& s, const BatchArgs& a) {
+__host__ __device__ inline const double* cheb_rin(const SimDev& s, const BatchArgs& a) { return a.cheb_rhs ? s.b64 : s.r64; }
+__host__ __device__ inline const double* cheb_lift(const SimDev& s, const BatchArgs& a) {
   return a.cheb_rhs ? s.lift64 : nullptr;
 }
 
@@ -315,15 +353,15 @@ struct RoleChebFirst {  // step 1: gathers d_0 = P^-1 (r_in - lift) / c
   using V = double;
   using Pro = ProChebStart<double>;
   using Epi = EpiCheb<double>;
-  static __device__ const GatherArgs<V>& ga(const SimDev& s) { return s.A64; }
-  static __device__ Pro pro(const SimDev& s, const BatchArgs& a) {
+  static __host__ __device__ const GatherArgs<V>& ga(const SimDev& s) { return s.A64; }
+  static __host__ __device__ Pro pro(const SimDev& s, const BatchArgs& a) {
     return Pro{cheb_rin(s, a), cheb_lift(s, a), s.pinv64, s.ch_inv_c};
   }
-  static __device__ Epi epi(const SimDev& s, const BatchArgs& a) {
+  static __host__ __device__ Epi epi(const SimDev& s, const BatchArgs& a) {
     return Epi{cheb_rin(s, a), cheb_lift(s, a), s.pinv64, nullptr, cheb_rin(s, a), cheb_lift(s, a), s.cr64,
                s.cd64[1], s.s64, s.ch_a[0], s.ch_b[0], a.cheb_last};
   }
-  static __device__ Relay relay(const SimDev& s, const BatchArgs& a) {
+  static __host__ __device__ Relay relay(const SimDev& s, const BatchArgs& a) {
     return outer_relay(s, a, M_PASS, a.cheb_last != 0);
   }
 };
@@ -332,13 +370,13 @@ struct RoleChebNext {  // step k >= 2: gathers d_{k-1}
   using V = double;
   using Pro = ProPlain<double>;
   using Epi = EpiCheb<double>;
-  static __device__ const GatherArgs<V>& ga(const SimDev& s) { return s.A64; }
-  static __device__ Pro pro(const SimDev& s, const BatchArgs& a) { return Pro{s.cd64[(a.cheb_k - 1) & 1]}; }
-  static __device__ Epi epi(const SimDev& s, const BatchArgs& a) {
+  static __host__ __device__ const GatherArgs<V>& ga(const SimDev& s) { return s.A64; }
+  static __host__ __device__ Pro pro(const SimDev& s, const BatchArgs& a) { return Pro{s.cd64[(a.cheb_k - 1) & 1]}; }
+  static __host__ __device__ Epi epi(const SimDev& s, const BatchArgs& a) {
     return Epi{s.cr64, nullptr, s.pinv64, s.s64, cheb_rin(s, a), cheb_lift(s, a), s.cr64, s.cd64[a.cheb_k & 1],
                s.s64, s.ch_a[a.cheb_k - 1], s.ch_b[a.cheb_k - 1], a.cheb_last};
   }
-  static __device__ Relay relay(const SimDev& s, const BatchArgs& a) {
+  static __host__ __device__ Relay relay(const SimDev& s, const BatchArgs& a) {
     return outer_relay(s, a, M_PASS, a.cheb_last != 0);
   }
 };
@@ -373,6 +411,18 @@ __global__ void __launch_bounds__(256, 2) gather_batch_kernel(BatchArgs a) {
   using Pro = typename Role::Pro;
   gather_tile<typename Role::V, KIND, Pro, typename Role::Epi, reads_four<Role>(0) || AdvancesResidual<Pro>::value>(
       ga, Role::pro(s, a), Role::epi(s, a), Role::relay(s, a), local);
+}
+
+// One gather role of a single simulation, its operator, functors and relay
+// passed by value in the launch: the first plane loads need no dependent
+// read of the simulation's record (the same code as gather_batch_kernel on
+// the same data, so the same bits).
+template <int KIND, class Role>
+__global__ void __launch_bounds__(256, 2)
+    gather_one_kernel(GatherArgs<typename Role::V> ga, typename Role::Pro pro, typename Role::Epi epi, Relay R) {
+  using Pro = typename Role::Pro;
+  gather_tile<typename Role::V, KIND, Pro, typename Role::Epi, reads_four<Role>(0) || AdvancesResidual<Pro>::value>(
+      ga, pro, epi, R, xcd_work_item(blockIdx.x, gridDim.x));
 }
 
 // Residual update and preconditioned residual norm (a5), FP64 outer solve
@@ -415,7 +465,7 @@ static __global__ void __launch_bounds__(256) inner_start_batch_kernel(BatchArgs
   const SimDev& s = a.sims[sim];
   Relay R = inner_relay(s, a, M_IDLE, true);
   if (s.sweep) {
-    const Scalars& o = *s.oS[a.ocur];
+    const Scalars o = gld_at(s.oS[a.ocur]);
     if (!o.done && o.status == 0) {
       const double ref = s.octl.stop_rule == 1 ? o.delta0 : o.delta_b;
       const double need = o.delta > 0.0 ? 0.5 * sqrt(s.octl.rtol2 * ref / o.delta) : 1.0;
@@ -443,7 +493,7 @@ __global__ void __launch_bounds__(256) decide_batch_kernel(BatchArgs a) {
   const StageIn in = stage_load(R);
   Scalars st;
   (void)stage_finish<kFour>(R, in, st, local == 0);
-  if (local == 0 && threadIdx.x == 0) a.snap[sim] = st;
+  if (local == 0 && threadIdx.x == 0) gst_at(a.snap + sim, st);
   if (a.corr && in.pending && st.done && st.status == 0) {
     if constexpr (inner)
       axpy_body<float>(s.e32[a.xpar], s.d32[dir_out(a)], (float)st.alpha, s.N, local, s.nblk[PK_UPD32]);

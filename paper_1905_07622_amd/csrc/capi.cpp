@@ -78,7 +78,8 @@ int check_problem(const fem_grid* grid, const double* k_e, const double* rhoc_e,
   if (!grid || !k_e || !rhoc_e) return bad("grid, k_e and rhoc_e are required");
   if (grid->nx < 1 || grid->ny < 1 || grid->nz < 1) return bad("nx, ny, nz must be >= 1");
   const double N = (double)(grid->nx + 1) * (grid->ny + 1) * (grid->nz + 1);
-  if (N >= 2147483647.0) return bad("grid too large (N must fit in 31 bits)");
+  // kernels address FP64 node vectors with 32-bit byte offsets
+  if (N >= 536870912.0) return bad("grid too large (N must be below 2^29 nodes)");
   if (!finite_pos(grid->hx) || !finite_pos(grid->hy) || !finite_pos(grid->hz)) return bad("h must be finite and > 0");
   if (o.element == FEM_ELEM_TET6 && !(grid->hx == grid->hy && grid->hy == grid->hz))
     return bad("the tetrahedral element needs cubic boxes (hx = hy = hz)");

@@ -86,7 +86,7 @@ namespace {
 struct Group {
   int kind = kElemCubic;  // element kind of the group's simulations (the gather's template argument)
   uint32_t off = 0, nwork = 0, nthreads = 64;
-  size_t smem64 = 0, smem32 = 0, smem64f = 0;  // smem64f: one-reduction direction kernel (three planes)
+  size_t smem64 = 0, smem32 = 0, smem64f = 0, smem32f = 0;  // *f: one-reduction direction kernels (three planes)
 };
 
 // Work-table layout of a batched launch: where each kernel kind's entries
@@ -106,6 +106,7 @@ class Engine {
     mixed_ = o.precision == FEM_FP32_FP64DOT;
     timing_ = (o.flags & FEM_TIMING) != 0;
     fused_ = !mixed_ && (o.flags & FEM_ONE_REDUCTION) != 0;
+    ifused_ = mixed_ && (o.flags & FEM_ONE_REDUCTION) != 0;
     cheb_ = !mixed_ && !fused_ && o.precond == FEM_PRECOND_CHEBYSHEV;
     R_ = o.replace_every;
   }
@@ -195,7 +196,8 @@ class Engine {
   fem_opts opts_;
   fem_heat* h_;  // receives error messages
   bool mixed_ = false, timing_ = false;
-  bool fused_ = false;  // FP64 PCG in the one-reduction form
+  bool fused_ = false;   // FP64 PCG in the one-reduction form
+  bool ifused_ = false;  // the FP32 inner solves of the mixed form in the one-reduction form
   bool cheb_ = false;   // FP64 PCG with the Chebyshev preconditioner
   // The preconditioner chain behind the kernel that made a residual (or the
   // right-hand side): m - 1 gathers computing s = M^-1 r_in, the last one
@@ -387,6 +389,8 @@ void Engine::fill_simdev(const Sim& s, SimDev& d) const {
   d.pinv32 = h->pinv32;
   d.r32 = h->r32;
   d.q32 = h->q32;
+  d.r32b = h->r32b ? h->r32b : h->r32;
+  d.q32b = h->q32b ? h->q32b : h->q32;
   d.d32[0] = h->d32[0];
   d.d32[1] = h->d32[1];
   d.e32[0] = h->e32[0];
@@ -517,6 +521,7 @@ void Engine::build_layout(const std::vector<char>& live, std::vector<uint2>& tab
       g.smem64 = std::max(g.smem64, sh->shape.smem_bytes(8));
       g.smem32 = std::max(g.smem32, sh->shape.smem_bytes(4));
       g.smem64f = std::max(g.smem64f, sh->shape.smem_bytes(8, 3));
+      g.smem32f = std::max(g.smem32f, sh->shape.smem_bytes(4, 3));
       if (!live[k]) continue;
       for (uint32_t b = 0; b < sh->shape.nblocks; ++b) tab.push_back(make_uint2((uint32_t)k, b));
     }
@@ -572,10 +577,27 @@ int Engine::gather(BatchArgs a, hipEvent_t e0, hipEvent_t e1) {
   for (int gi = 0; gi < lay_.ngroups; ++gi) {
     const Group& g = lay_.groups[gi];
     a.table = multi_ ? tab_cur_ + g.off : nullptr;
-    const size_t smem = std::is_same<Role, RoleFused>::value ? g.smem64f
-                        : sizeof(typename Role::V) == 8        ? g.smem64
-                                                               : g.smem32;
+    const size_t smem = std::is_same<Role, RoleFused>::value     ? g.smem64f
+                        : std::is_same<Role, RoleFused32>::value ? g.smem32f
+                        : sizeof(typename Role::V) == 8          ? g.smem64
+                                                                 : g.smem32;
     hipEvent_t s0 = gi == 0 ? e0 : nullptr, s1 = gi == lay_.ngroups - 1 ? e1 : nullptr;
+    if (!multi_) {  // one simulation: its record (sd_one_, as uploaded) goes into the launch
+      const auto ga = Role::ga(sd_one_);
+      const auto pro = Role::pro(sd_one_, a);
+      const auto epi = Role::epi(sd_one_, a);
+      const Relay R = Role::relay(sd_one_, a);
+      if (g.kind == kElemCubic)
+        hipExtLaunchKernelGGL((gather_one_kernel<kElemCubic, Role>), dim3(g.nwork), dim3(g.nthreads), smem, stream_,
+                              s0, s1, 0, ga, pro, epi, R);
+      else if (g.kind == kElemTet6)
+        hipExtLaunchKernelGGL((gather_one_kernel<kElemTet6, Role>), dim3(g.nwork), dim3(g.nthreads), smem, stream_,
+                              s0, s1, 0, ga, pro, epi, R);
+      else
+        hipExtLaunchKernelGGL((gather_one_kernel<kElemBox, Role>), dim3(g.nwork), dim3(g.nthreads), smem, stream_,
+                              s0, s1, 0, ga, pro, epi, R);
+      continue;
+    }
     if (g.kind == kElemCubic)
       hipExtLaunchKernelGGL((gather_batch_kernel<kElemCubic, Role>), dim3(g.nwork), dim3(g.nthreads), smem, stream_,
                             s0, s1, 0, a);
@@ -637,7 +659,8 @@ int Engine::decide(bool inner, int j_end, bool launch_next, bool wait, int slot)
   const int jl = std::max(0, j_end - 1);
   // (nothing is owed by the one-reduction form, whose direction kernel
   // completes each update before the stop test, nor by the FP32 inner
-  // solves, whose update kernel applies x += alpha d itself)
+  // solves of the two-kernel form, whose update kernel applies x += alpha d
+  // itself)
   BatchArgs a = args(cur, prev, jl, replacements_before(jl, R_) & 1,
                      !inner && !fused_ && j_end > 0 && deferred(j_end) ? 1 : 0);
   if (slot) a.snap += act_.size();
@@ -651,7 +674,9 @@ int Engine::decide(bool inner, int j_end, bool launch_next, bool wait, int slot)
     a.table = multi_ ? tab_cur_ + lay_.off_one : nullptr;
     grid = lay_.n_one;
   }
-  if (inner)
+  if (inner && ifused_)
+    hipLaunchKernelGGL((decide_batch_kernel<float, true>), dim3(grid), dim3(kT), 0, stream_, a);
+  else if (inner)
     hipLaunchKernelGGL((decide_batch_kernel<float, false>), dim3(grid), dim3(kT), 0, stream_, a);
   else if (fused_)
     hipLaunchKernelGGL((decide_batch_kernel<double, true>), dim3(grid), dim3(kT), 0, stream_, a);
@@ -701,7 +726,7 @@ int Engine::pcg(int first_chunk) {
   int& cur = inner ? icur_ : ocur_;
   int& prev = inner ? iprev_ : oprev_;
   const int upd_kind = inner ? PK_UPD32 : PK_UPD64;
-  const bool one_red = fused_ && !inner;  // one kernel per iteration (plus replacements)
+  const bool one_red = inner ? ifused_ : fused_;  // one kernel per iteration (plus replacements)
   // Timing samples one iteration in kSampleEvery and one residual replacement
   // in kReplaceEvery, counted across solves so that the sample holds the
   // forms of the direction kernel (with or without the deferred update) in
@@ -740,7 +765,10 @@ int Engine::pcg(int first_chunk) {
       hipEvent_t e2 = tr ? tr->e[2] : nullptr, e3 = tr ? tr->e[3] : nullptr;
       const int xpar = replacements_before(jj, R_) & 1;
       if (one_red) {
-        RC_TRY(gather<RoleFused>(args(cur, prev, jj, xpar, deferred(jj) ? 1 : 0), e0, e1));
+        if constexpr (inner)
+          RC_TRY(gather<RoleFused32>(args(cur, prev, jj, xpar, deferred(jj) ? 1 : 0), e0, e1));
+        else
+          RC_TRY(gather<RoleFused>(args(cur, prev, jj, xpar, deferred(jj) ? 1 : 0), e0, e1));
       } else if (cheb_ && !inner) {
         RC_TRY(gather<RoleDirS>(args(cur, prev, jj, xpar, deferred(jj) ? 1 : 0), e0, e1));
       } else {
@@ -749,7 +777,9 @@ int Engine::pcg(int first_chunk) {
       cur ^= 1;
       prev = PK_GATHER;
       if (rep) {
-        if (one_red)
+        if (one_red && inner)
+          RC_TRY(gather<RoleReplFused32>(args(cur, prev, jj, xpar), e2, e3));
+        else if (one_red)
           RC_TRY(gather<RoleReplFused>(args(cur, prev, jj, xpar), e2, e3));
         else
           RC_TRY(gather<RoleRepl<V>>(args(cur, prev, jj, xpar), e2, e3));

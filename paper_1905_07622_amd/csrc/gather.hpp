@@ -40,6 +40,7 @@
 #include <type_traits>
 
 #include "common.hpp"
+#include "gmem.hpp"
 #include "reduce.hpp"
 
 namespace femheat {
@@ -129,13 +130,37 @@ struct AdvancesResidual {
   static constexpr bool value = false;
 };
 
+// An epilogue that reads per-node inputs (b, P^-1, F, ...) declares them as
+// its Raw and loads them in fetch(i); the march issues that load for the own
+// node two layers ahead, like the plane loads, and hands the values to
+// store().  (Loads issued inside a layer and used at once would make the
+// wave wait for every load before them, the prefetched planes included.)
+template <class E, class = void>
+struct EpiFetches {
+  static constexpr bool value = false;
+};
+template <class E>
+struct EpiFetches<E, std::void_t<typename E::Raw>> {
+  static constexpr bool value = true;
+};
+struct NoRaw {};
+template <class E, bool = EpiFetches<E>::value>
+struct EpiRawOf {
+  using type = NoRaw;
+};
+template <class E>
+struct EpiRawOf<E, true> {
+  using type = typename E::Raw;
+};
+
 // One block's share of a gather: tile `logical` of the solve that `ga`, the
 // functors and the relay describe.  The block's dot-product partial is
 // stored at index `logical`, and tile 0 publishes the relayed state.
-// kD: prefetch depth in layers.  The one-reduction direction kernel stages a fourth vector and keeps
-// four accumulators; with one layer of prefetch it fits 164 VGPRs instead of 256 with a spill.
+// kD: prefetch depth in layers.  The FP64 one-reduction direction kernel stages a fourth vector and
+// keeps four accumulators; with one layer of prefetch it fits 164 VGPRs instead of 256 with a spill
+// (in FP32 two layers fit in 169).
 template <typename V, int KIND, class Pro, class Epi, bool kFour = AdvancesResidual<Pro>::value,
-          int kD = (AdvancesResidual<Pro>::value ? 1 : kDepth)>
+          int kD = (AdvancesResidual<Pro>::value && sizeof(V) == 8 ? 1 : kDepth)>
 __device__ inline void gather_tile(const GatherArgs<V>& ga, Pro pro, Epi epi, const Relay& R, uint32_t logical) {
   const StageIn in = stage_load<sizeof(V) == 8>(R);
   if (stage_idle(R, in, logical == 0)) return;  // uniform: a finished solve
@@ -222,6 +247,7 @@ __device__ inline void gather_tile(const GatherArgs<V>& ga, Pro pro, Epi epi, co
     // Two register sets hold the planes l+1 and l+2 (and coefficient layers
     // l and l+1) while layer l computes.
     constexpr bool XI = CarriesIterate<Pro>::value;
+    constexpr bool EF = EpiFetches<Epi>::value;
     struct Stage {
       typename Pro::Raw p[kSlots];
       V a[kSlots], b[kSlots];
@@ -233,13 +259,13 @@ __device__ inline void gather_tile(const GatherArgs<V>& ga, Pro pro, Epi epi, co
 #pragma unroll
       for (int k = 0; k < kSlots; ++k) {
         S.p[k] = pro.fetch(pxy[k] + zo);
-        S.a[k] = ga.rhoc[cxy[k] + lo_];
-        S.b[k] = ga.kc[cxy[k] + lo_];
+        S.a[k] = gld(ga.rhoc, cxy[k] + lo_);
+        S.b[k] = gld(ga.kc, cxy[k] + lo_);
       }
       if constexpr (XI) {
         const uint32_t io = col_xy + pstride * (uint32_t)min(max(zown, 0), pz - 1);
-        S.xo = pro.x[io];
-        S.dold = pro.dold[io];
+        S.xo = gld(pro.x, io);
+        S.dold = gld(pro.dold, io);
       }
     };
     auto store = [&](const Stage& S, int l, int buf) {  // LDS only
@@ -371,7 +397,25 @@ __device__ inline void gather_tile(const GatherArgs<V>& ga, Pro pro, Epi epi, co
     // here (clamped to the march: past its end they re-read the last ones).
     auto layer = [&](int k, int buf, Stage& S, auto emit) {
       store(S, lay(k), buf);
-      const V xo_k = S.xo, dold_k = S.dold;  // node vis(k), fetched with this stage
+      if constexpr (XI) {
+        // The deferred x += alpha d_old at node vis(k), whose x and d_old came
+        // with this stage: stored before the stage's registers take the next
+        // loads, so no value of a load still in flight has to be kept (a copy
+        // of it would make the wave wait for that load).
+        if (decltype(emit)::value && pro.corr) {
+          const uint32_t i = col_xy + pstride * (uint32_t)vis(k);
+          const V xn = fma(pro.alpha, S.dold, S.xo);
+          gst_at(col_ok ? pro.x + i : ga.sink + threadIdx.x, xn);
+        }
+      }
+      // The epilogue's inputs at node vis(k) are requested before the next
+      // planes, so the wait for them at the end of the layer leaves those
+      // planes in flight.  (Carried over from an earlier layer in registers,
+      // they would cross the loop's back edge as copies of loads still in
+      // flight, which wait for every load.)
+      typename EpiRawOf<Epi>::type eo{};
+      if constexpr (EF)
+        if (decltype(emit)::value) eo = epi.fetch(col_xy + pstride * (uint32_t)vis(k));
       __syncthreads();
       fetch(S, vis(min(k + 1 + kD, n)), lay(min(k + kD, n - 1)), vis(min(k + kD, n)));
       read_plane(plane + buf * PW * PH, PW, ltx, lty, hi);
@@ -385,18 +429,18 @@ __device__ inline void gather_tile(const GatherArgs<V>& ga, Pro pro, Epi epi, co
       if (decltype(emit)::value) {  // node vis(k) is owned by this block
         const uint32_t i = col_xy + pstride * (uint32_t)vis(k);
         pro.write(i, lo.c, col_ok, ga.sink);
-        if constexpr (XI)
-          if (pro.corr) *(col_ok ? pro.x + i : ga.sink + threadIdx.x) = fma(pro.alpha, dold_k, xo_k);
         if constexpr (FU) {
-          if (pro.corr) *(col_ok ? pro.rnew + i : ga.sink + threadIdx.x) = rn_lo;
+          if (pro.corr) gst_at(col_ok ? pro.rnew + i : ga.sink + threadIdx.x, rn_lo);
           const V qv = carry + p_lo;
-          *(col_ok ? epi.q + i : ga.sink + threadIdx.x) = qv;
+          gst_at(col_ok ? epi.q + i : ga.sink + threadIdx.x, qv);
           if (col_ok) {
             dots[0] += (double)lo.c * (double)qv;
             dots[1] += (double)qv * (double)(pp_lo * rn_lo);
             dots[2] += (double)qv * (double)(pp_lo * qv);
             dots[3] += (double)rn_lo * (double)(pp_lo * rn_lo);
           }
+        } else if constexpr (EF) {
+          dot += epi.store(i, carry + p_lo, lo.c, col_ok, ga.sink, eo);
         } else {
           dot += epi.store(i, carry + p_lo, lo.c, col_ok, ga.sink);
         }
@@ -427,7 +471,8 @@ __device__ inline void gather_tile(const GatherArgs<V>& ga, Pro pro, Epi epi, co
             const V al = (V)st.alpha;
             for (int z = z0; z < z1; ++z) {
               const uint32_t i = col_xy + pstride * (uint32_t)z;
-              pro.x[i] = fma(al, pro.dold[i], pro.x[i]);
+              const V xn = fma(al, gld(pro.dold, i), gld(pro.x, i));
+              gst(pro.x, i, xn);
             }
           }
         }
@@ -487,7 +532,7 @@ struct ProPlain {  // v = src
     V a;
   };
   __device__ void init(const Scalars&) {}
-  __device__ Raw fetch(uint32_t i) const { return Raw{src[i]}; }
+  __device__ Raw fetch(uint32_t i) const { return Raw{gld(src, i)}; }
   __device__ V finish(const Raw& w) const { return w.a; }
   __device__ void write(uint32_t, V, bool, V*) const {}
 };
@@ -514,9 +559,9 @@ struct ProDirection {  // d_new = P^-1 r + beta d_old   (Algorithm 1: s <- P^-1 
     beta = (V)S.beta;
     alpha = (V)S.alpha;
   }
-  __device__ Raw fetch(uint32_t i) const { return Raw{r[i], pinv[i], dold[i]}; }
+  __device__ Raw fetch(uint32_t i) const { return Raw{gld(r, i), gld(pinv, i), gld(dold, i)}; }
   __device__ V finish(const Raw& w) const { return fma(beta, w.d, w.p * w.r); }
-  __device__ void write(uint32_t i, V v, bool live, V* sink) const { *(live ? dnew + i : sink + threadIdx.x) = v; }
+  __device__ void write(uint32_t i, V v, bool live, V* sink) const { gst_at(live ? dnew + i : sink + threadIdx.x, v); }
 };
 
 // Only the FP64 direction kernel carries the iterate: in the FP32 inner
@@ -553,7 +598,7 @@ struct ProFused {
     beta = (V)S.beta;
     alpha = (V)S.alpha;
   }
-  __device__ Raw fetch(uint32_t i) const { return Raw{r[i], qold[i], pinv[i], dold[i]}; }
+  __device__ Raw fetch(uint32_t i) const { return Raw{gld(r, i), gld(qold, i), gld(pinv, i), gld(dold, i)}; }
   __device__ V residual(const Raw& w) const {
     if (!corr) return w.r;
     const V rr = fma(-alpha, w.q, w.r);
@@ -561,7 +606,7 @@ struct ProFused {
   }
   __device__ V direction(const Raw& w, V rn) const { return fma(beta, w.d, w.p * rn); }
   __device__ V finish(const Raw& w) const { return direction(w, residual(w)); }
-  __device__ void write(uint32_t i, V v, bool live, V* sink) const { *(live ? dnew + i : sink + threadIdx.x) = v; }
+  __device__ void write(uint32_t i, V v, bool live, V* sink) const { gst_at(live ? dnew + i : sink + threadIdx.x, v); }
 };
 
 template <typename V>
@@ -593,9 +638,9 @@ struct ProDirectionS {
     beta = (V)S.beta;
     alpha = (V)S.alpha;
   }
-  __device__ Raw fetch(uint32_t i) const { return Raw{s[i], dold[i]}; }
+  __device__ Raw fetch(uint32_t i) const { return Raw{gld(s, i), gld(dold, i)}; }
   __device__ V finish(const Raw& w) const { return fma(beta, w.d, w.s); }
-  __device__ void write(uint32_t i, V v, bool live, V* sink) const { *(live ? dnew + i : sink + threadIdx.x) = v; }
+  __device__ void write(uint32_t i, V v, bool live, V* sink) const { gst_at(live ? dnew + i : sink + threadIdx.x, v); }
 };
 
 template <>
@@ -616,7 +661,7 @@ struct ProChebStart {
     V r, l, p;
   };
   __device__ void init(const Scalars&) {}
-  __device__ Raw fetch(uint32_t i) const { return Raw{r[i], lift ? lift[i] : V(0), pinv[i]}; }
+  __device__ Raw fetch(uint32_t i) const { return Raw{gld(r, i), lift ? gld(lift, i) : V(0), gld(pinv, i)}; }
   __device__ V finish(const Raw& w) const { return (w.p * (w.r - w.l)) * inv_c; }
   __device__ void write(uint32_t, V, bool, V*) const {}
 };
@@ -639,19 +684,32 @@ struct EpiCheb {
   V* y;            // y_{k+1}
   V a, b;
   int32_t last;
+  struct Raw {  // loaded values only: the arithmetic waits for them in store()
+    V rp, l, p, y, ri, rl;
+  };
   __device__ void init(const Scalars&) {}
-  __device__ double store(uint32_t i, V acc, V v, bool live, V* sink) const {
-    const V rp = lift ? rprev[i] - lift[i] : rprev[i];
+  __device__ Raw fetch(uint32_t i) const {
+    Raw w;
+    w.rp = gld(rprev, i);
+    w.l = lift ? gld(lift, i) : V(0);
+    w.p = gld(pinv, i);
+    w.y = yprev ? gld(yprev, i) : V(0);
+    w.ri = last ? gld(rin, i) : V(0);
+    w.rl = (last && rlift) ? gld(rlift, i) : V(0);
+    return w;
+  }
+  __device__ double store(uint32_t i, V acc, V v, bool live, V* sink, const Raw& w) const {
+    const V rp = lift ? w.rp - w.l : w.rp;
     const V rk = rp - acc;
-    const V dk = fma(a, v, b * (pinv[i] * rk));
-    const V yk = (yprev ? yprev[i] : v) + dk;
-    *(live ? y + i : sink + threadIdx.x) = yk;
+    const V dk = fma(a, v, b * (w.p * rk));
+    const V yk = (yprev ? w.y : v) + dk;
+    gst_at(live ? y + i : sink + threadIdx.x, yk);
     if (last) {
-      const V ri = rlift ? rin[i] - rlift[i] : rin[i];
+      const V ri = rlift ? w.ri - w.rl : w.ri;
       return live ? (double)ri * (double)yk : 0.0;
     }
-    *(live ? rnext + i : sink + threadIdx.x) = rk;
-    *(live ? dnext + i : sink + threadIdx.x) = dk;
+    gst_at(live ? rnext + i : sink + threadIdx.x, rk);
+    gst_at(live ? dnext + i : sink + threadIdx.x, dk);
     return 0.0;
   }
 };
@@ -668,9 +726,9 @@ struct ProAxpy {  // x_new = x + alpha d  (alpha from the solve's scalars, or 1 
     W d;
   };
   __device__ void init(const Scalars& S) { alpha = unit_alpha ? V(1) : (V)S.alpha; }
-  __device__ Raw fetch(uint32_t i) const { return Raw{x[i], d[i]}; }
+  __device__ Raw fetch(uint32_t i) const { return Raw{gld(x, i), gld(d, i)}; }
   __device__ V finish(const Raw& w) const { return fma(alpha, (V)w.d, w.x); }
-  __device__ void write(uint32_t i, V v, bool live, V* sink) const { *(live ? xnew + i : sink + threadIdx.x) = v; }
+  __device__ void write(uint32_t i, V v, bool live, V* sink) const { gst_at(live ? xnew + i : sink + threadIdx.x, v); }
 };
 
 template <typename V>
@@ -685,13 +743,13 @@ struct ProGuess {  // x0 = 2 T1 - T2 (u0_update, App. A.2) or T1; 0 on free node
     V a, b, p;
   };
   __device__ void init(const Scalars& S) { zero = S.zero_rhs; }
-  __device__ Raw fetch(uint32_t i) const { return Raw{t1[i], t2[i], pinv[i]}; }
+  __device__ Raw fetch(uint32_t i) const { return Raw{gld(t1, i), gld(t2, i), gld(pinv, i)}; }
   __device__ V finish(const Raw& w) const {
     V v = prev ? w.a : fma(V(2), w.a, -w.b);
     if (zero) v = (w.p == V(0)) ? w.a : V(0);
     return v;
   }
-  __device__ void write(uint32_t i, V v, bool live, V* sink) const { *(live ? x + i : sink + threadIdx.x) = v; }
+  __device__ void write(uint32_t i, V v, bool live, V* sink) const { gst_at(live ? x + i : sink + threadIdx.x, v); }
 };
 
 // ---------------------------------------------------------------------------
@@ -706,7 +764,7 @@ struct EpiStore {  // y = A v
   V* y;
   __device__ void init(const Scalars&) {}
   __device__ double store(uint32_t i, V acc, V, bool live, V* sink) const {
-    *(live ? y + i : sink + threadIdx.x) = acc;
+    gst_at(live ? y + i : sink + threadIdx.x, acc);
     return 0.0;
   }
 };
@@ -716,7 +774,7 @@ struct EpiQDot {  // q = A d ; contribution d_i q_i to d^T q
   V* q;
   __device__ void init(const Scalars&) {}
   __device__ double store(uint32_t i, V acc, V v, bool live, V* sink) const {
-    *(live ? q + i : sink + threadIdx.x) = acc;
+    gst_at(live ? q + i : sink + threadIdx.x, acc);
     return live ? (double)v * (double)acc : 0.0;
   }
 };
@@ -732,12 +790,15 @@ struct EpiResidual {  // r = b - A x (0 on Dirichlet rows); contribution r_i P^-
   const V* b;
   const V* pinv;
   V* r;
+  struct Raw {
+    V b, p;
+  };
   __device__ void init(const Scalars&) {}
-  __device__ double store(uint32_t i, V acc, V, bool live, V* sink) const {
-    const V p = pinv[i];
-    const V rr = (p == V(0)) ? V(0) : b[i] - acc;
-    *(live ? r + i : sink + threadIdx.x) = rr;
-    return live ? (double)rr * (double)(p * rr) : 0.0;
+  __device__ Raw fetch(uint32_t i) const { return Raw{gld(b, i), gld(pinv, i)}; }
+  __device__ double store(uint32_t i, V acc, V, bool live, V* sink, const Raw& w) const {
+    const V rr = (w.p == V(0)) ? V(0) : w.b - acc;
+    gst_at(live ? r + i : sink + threadIdx.x, rr);
+    return live ? (double)rr * (double)(w.p * rr) : 0.0;
   }
 };
 
@@ -748,12 +809,16 @@ struct EpiRhs {  // b = L T + dt*s*F ; contribution (b - lift)_i P^-1_i (b - lif
   const V* pinv;
   const V* lift;  // A_fD g for non-zero Dirichlet values, or nullptr
   V fs;           // dt * s_n
+  struct Raw {
+    V F, p, l;
+  };
   __device__ void init(const Scalars&) {}
-  __device__ double store(uint32_t i, V acc, V, bool live, V* sink) const {
-    const V bb = fma(fs, F[i], acc);
-    *(live ? b + i : sink + threadIdx.x) = bb;
-    const V bh = lift ? bb - lift[i] : bb;
-    return live ? (double)bh * (double)(pinv[i] * bh) : 0.0;
+  __device__ Raw fetch(uint32_t i) const { return Raw{gld(F, i), gld(pinv, i), lift ? gld(lift, i) : V(0)}; }
+  __device__ double store(uint32_t i, V acc, V, bool live, V* sink, const Raw& w) const {
+    const V bb = fma(fs, w.F, acc);
+    gst_at(live ? b + i : sink + threadIdx.x, bb);
+    const V bh = lift ? bb - w.l : bb;
+    return live ? (double)bh * (double)(w.p * bh) : 0.0;
   }
 };
 

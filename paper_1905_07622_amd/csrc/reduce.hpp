@@ -23,6 +23,7 @@
 #pragma once
 
 #include "common.hpp"
+#include "gmem.hpp"
 
 namespace femheat {
 
@@ -52,12 +53,12 @@ __device__ inline double canonical_sum(const double* p, uint32_t n, double* red4
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
       const uint32_t k = slot + 256u * u;
-      v[u] = k < n ? p[k] : 0.0;
+      v[u] = k < n ? gld(p, k) : 0.0;
     }
     double s = v[0];
 #pragma unroll
     for (int u = 1; u < 8; ++u) s += v[u];
-    for (uint32_t k = slot + 2048u; k < n; k += 256u) s += p[k];
+    for (uint32_t k = slot + 2048u; k < n; k += 256u) s += gld(p, k);
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
     if (lane == 0) red4[vw] = s;
@@ -75,7 +76,7 @@ __device__ inline double canonical_sum_pre(const double* p, uint32_t n, const do
     double s = v[0];
 #pragma unroll
     for (int u = 1; u < 8; ++u) s += v[u];
-    for (uint32_t k = slot + 2048u; k < n; k += 256u) s += p[k];
+    for (uint32_t k = slot + 2048u; k < n; k += 256u) s += gld(p, k);
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
     if (lane == 0) red4[wid] = s;
@@ -96,14 +97,14 @@ __device__ inline void canonical_sum4(const double* p, uint32_t ld, uint32_t n, 
 #pragma unroll
       for (int u = 0; u < 8; ++u) {
         const uint32_t k = slot + 256u * u;
-        v[c][u] = k < n ? p[c * ld + k] : 0.0;
+        v[c][u] = k < n ? femheat::gld(p, c * ld + k) : 0.0;
       }
 #pragma unroll
     for (int c = 0; c < 4; ++c) {
       double s = v[c][0];
 #pragma unroll
       for (int u = 1; u < 8; ++u) s += v[c][u];
-      for (uint32_t k = slot + 2048u; k < n; k += 256u) s += p[c * ld + k];
+      for (uint32_t k = slot + 2048u; k < n; k += 256u) s += femheat::gld(p, c * ld + k);
 #pragma unroll
       for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
       if (lane == 0) red16[c * 4 + vw] = s;
@@ -241,11 +242,11 @@ __device__ inline StageIn stage_load(const Relay& R) {
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
       const uint32_t k = slot + 256u * u;
-      in.pv[u] = (slot < 256u && k < R.npin) ? R.pin[k] : 0.0;
+      in.pv[u] = (slot < 256u && k < R.npin) ? gld(R.pin, k) : 0.0;
     }
   }
   in.t = Scalars{};
-  if (R.sin) in.t = *R.sin;
+  if (R.sin) in.t = gld_at(R.sin);
   in.pending = !in.t.done && in.t.phase != PH_DECIDED && in.t.phase != PH_NONE;
   in.need = R.mode == M_INIT || R.mode == M_INIT_NEXT || (R.mode == M_UPD && !in.t.done) ||
             ((R.mode == M_DIR || R.mode == M_DECIDE || is_fused_mode(R.mode)) && in.pending);
@@ -256,7 +257,7 @@ __device__ inline StageIn stage_load(const Relay& R) {
 // leaves the state unchanged: only the writer relays it.  Uniform.
 __device__ inline bool stage_idle(const Relay& R, const StageIn& in, bool writer) {
   if ((R.mode == M_DIR || R.mode == M_UPD || R.mode == M_PASS || is_fused_mode(R.mode)) && in.t.done) {
-    if (writer && threadIdx.x == 0 && R.sout) *R.sout = in.t;
+    if (writer && threadIdx.x == 0 && R.sout) gst_at(R.sout, in.t);
     return true;
   }
   return false;
@@ -379,7 +380,7 @@ __device__ inline bool stage_finish(const Relay& R, const StageIn& in, Scalars& 
     }
     sh = t;
     go = g;
-    if (writer && R.sout) *R.sout = t;
+    if (writer && R.sout) gst_at(R.sout, t);
   }
   __syncthreads();
   out = sh;
@@ -397,7 +398,7 @@ __device__ inline bool stage_entry(const Relay& R, Scalars& out, bool writer) {
 __device__ inline void publish_partial(const Relay& R, double v, uint32_t slot) {
   __shared__ double wsum[16];
   const double bs = block_sum(v, wsum);
-  if (threadIdx.x == 0 && R.pout) R.pout[slot] = bs;
+  if (threadIdx.x == 0 && R.pout) gst(R.pout, slot, bs);
 }
 
 // Four partials per block (component c at pout[c*ld + slot]), each summed in
@@ -417,7 +418,7 @@ __device__ inline void publish_partial4(const Relay& R, const double* v, uint32_
     const int c = threadIdx.x, nw = blockDim.x >> 6;
     double s = 0.0;
     for (int w = 0; w < nw; ++w) s += wsum4[c][w];
-    R.pout[c * R.ld + slot] = s;
+    gst(R.pout, c * R.ld + slot, s);
   }
 }
 

@@ -357,6 +357,10 @@ int ensure_fp32(fem_heat* h) {
   RC_TRY(dalloc(h, &h->d32[0], N));
   RC_TRY(dalloc(h, &h->d32[1], N));
   RC_TRY(dalloc(h, &h->rhs32, N));
+  if (h->opts.flags & FEM_ONE_REDUCTION) {
+    RC_TRY(dalloc(h, &h->r32b, N));
+    RC_TRY(dalloc(h, &h->q32b, N));
+  }
   hipLaunchKernelGGL((cast_kernel<double, float>), dim3(nblk(E)), dim3(kT), 0, h->stream, h->rhoc64, h->rhoc32, E);
   hipLaunchKernelGGL((cast_kernel<double, float>), dim3(nblk(E)), dim3(kT), 0, h->stream, h->k64, h->k32, E);
   HIP_TRY(hipGetLastError());
@@ -476,7 +480,7 @@ int solver_init(fem_heat* h, const fem_grid* grid, const double* k_e, const doub
   RC_TRY(dalloc(h, &h->r64, N));
   RC_TRY(dalloc(h, &h->q64, N));
   const bool one_red = (h->opts.flags & FEM_ONE_REDUCTION) != 0;
-  if (one_red) {
+  if (one_red && h->opts.precision == FEM_FP64) {  // (the mixed form's FP32 set has its own, below)
     RC_TRY(dalloc(h, &h->r64b, N));
     RC_TRY(dalloc(h, &h->q64b, N));
   }
@@ -714,8 +718,9 @@ size_t handle_device_bytes(const fem_grid& grid, const fem_opts& opts, const fem
   // FP64: coefficients; F, pinv, b, r, q, two directions, four fields (+ lift; + r, q ping-pong buffers of
   // the one-reduction form)
   const bool one_red = (opts.flags & FEM_ONE_REDUCTION) != 0;
-  size_t bytes = 8 * (2 * E + (11 + (lift ? 1 : 0) + (one_red ? 2 : 0)) * N);
-  if (opts.precision == FEM_FP32_FP64DOT) bytes += 4 * (2 * E + 8 * N);  // FP32 set
+  const bool mixed = opts.precision == FEM_FP32_FP64DOT;
+  size_t bytes = 8 * (2 * E + (11 + (lift ? 1 : 0) + (one_red && !mixed ? 2 : 0)) * N);
+  if (mixed) bytes += 4 * (2 * E + (8 + (one_red ? 2 : 0)) * N);  // FP32 set
   if (opts.precond == FEM_PRECOND_CHEBYSHEV && opts.precision == FEM_FP64) bytes += 8 * 4 * N;  // s, chain
   // relay state and partials (at most max(tiles, update blocks) per buffer) and the sink
   const size_t tiles_bound = N / 32 + 1024;
@@ -745,6 +750,8 @@ void solver_free(fem_heat* h) {
   for (auto& p : h->e32) dfree(h, p);
   dfree(h, h->r32);
   dfree(h, h->q32);
+  dfree(h, h->r32b);
+  dfree(h, h->q32b);
   for (auto& p : h->d32) dfree(h, p);
   dfree(h, h->rhs32);
   for (RelayCtx* c : {&h->outer, &h->inner})

@@ -67,6 +67,8 @@ struct fem_heat {
   float* e32[2] = {nullptr, nullptr};
   float* r32 = nullptr;
   float* q32 = nullptr;
+  float* r32b = nullptr;  // one-reduction form of the inner solves: second residual and apply buffers
+  float* q32b = nullptr;
   float* d32[2] = {nullptr, nullptr};
   float* rhs32 = nullptr;
 

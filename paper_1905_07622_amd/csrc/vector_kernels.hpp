@@ -73,12 +73,12 @@ __device__ inline void update_body(V* __restrict__ r, const V* __restrict__ q, c
     for (int u = 0; u < kU; ++u) {
       const uint32_t j = base + (uint32_t)u * stride;
       if (j < nvec) {
-        rr[u] = rv[j];
-        qq[u] = qv[j];
-        pp[u] = pv[j];
+        rr[u] = gld(rv, j);
+        qq[u] = gld(qv, j);
+        pp[u] = gld(pv, j);
         if (withx) {
-          xx[u] = xv[j];
-          dd[u] = dv[j];
+          xx[u] = gld(xv, j);
+          dd[u] = gld(dv, j);
         }
       }
     }
@@ -107,7 +107,7 @@ __device__ inline void update_body(V* __restrict__ r, const V* __restrict__ q, c
           upd1(rr[u].z, qq[u].z, pp[u].z, alpha, acc);
           upd1(rr[u].w, qq[u].w, pp[u].w, alpha, acc);
         }
-        rv[j] = rr[u];
+        gst(rv, j, rr[u]);
         if (withx) {
           if constexpr (W == 2) {
             xx[u].x = fma(alpha, dd[u].x, xx[u].x);
@@ -118,16 +118,16 @@ __device__ inline void update_body(V* __restrict__ r, const V* __restrict__ q, c
             xx[u].z = fma(alpha, dd[u].z, xx[u].z);
             xx[u].w = fma(alpha, dd[u].w, xx[u].w);
           }
-          xv[j] = xx[u];
+          gst(xv, j, xx[u]);
         }
       }
     }
   }
   for (uint32_t i = nvec * W + tid; i < N; i += stride) {
-    V rs = r[i];
-    upd1(rs, q[i], pinv[i], alpha, acc);
-    r[i] = rs;
-    if (withx) x[i] = fma(alpha, d[i], x[i]);
+    V rs = gld(r, i);
+    upd1(rs, gld(q, i), gld(pinv, i), alpha, acc);
+    gst(r, i, rs);
+    if (withx) gst(x, i, fma(alpha, gld(d, i), gld(x, i)));
   }
   publish_partial(R, acc, blk);
 }
@@ -138,7 +138,7 @@ template <typename V>
 __device__ inline void axpy_body(V* __restrict__ x, const V* __restrict__ d, V alpha, uint32_t N, uint32_t blk,
                                  uint32_t nblk) {
   const uint32_t stride = nblk * blockDim.x;
-  for (uint32_t i = blk * blockDim.x + threadIdx.x; i < N; i += stride) x[i] = fma(alpha, d[i], x[i]);
+  for (uint32_t i = blk * blockDim.x + threadIdx.x; i < N; i += stride) gst(x, i, fma(alpha, gld(d, i), gld(x, i)));
 }
 
 // Start of an inner (FP32) solve of A e = r64 by block `blk` of `nblk`:
@@ -153,11 +153,11 @@ __device__ inline void inner_start_body(const double* __restrict__ r64, float* _
   double acc = 0.0;
   const uint32_t stride = nblk * blockDim.x;
   for (uint32_t i = blk * blockDim.x + threadIdx.x; i < N; i += stride) {
-    const float v = (float)r64[i];
-    rhs[i] = v;
-    r[i] = v;
-    e[i] = 0.0f;
-    acc += (double)v * (double)(pinv[i] * v);
+    const float v = (float)gld(r64, i);
+    gst(rhs, i, v);
+    gst(r, i, v);
+    gst(e, i, 0.0f);
+    acc += (double)v * (double)(gld(pinv, i) * v);
   }
   publish_partial(R, acc, blk);
 }
