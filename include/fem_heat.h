@@ -94,6 +94,18 @@ extern "C" {
                                   extra direction kernel per solve.  With FEM_FP32_FP64DOT the FP32
                                   inner solves take this form (sums and scalars in FP64) */
 
+#define FEM_ONE_KERNEL 0x8u /* fem_heat_run: each iteration of Algorithm 1 in one kernel instead of two
+                               (direction gather, then the x/r update): the gather's blocks publish
+                               d^T q, meet at a grid-wide barrier, and each updates r (and x in FP32)
+                               at its own nodes from values it kept on chip.  Used when the gather's
+                               blocks all fit the device at once (else two kernels).  The barrier
+                               needs all of them resident: work that other streams or processes run
+                               on the device at the same time can hold CUs, and then its bounded wait
+                               runs out and the run fails with FEM_EDEVICE.  Results agree with the
+                               two-kernel form to rounding (the r^T P^-1 r partials are summed per
+                               gather block).  Batches and servers always use two kernels, so a
+                               simulation's results do not depend on its co-runners */
+
 /* Operators for fem_heat_apply */
 #define FEM_OP_A 0           /* y = (M + theta*dt*K) x                              */
 #define FEM_OP_L 1           /* y = (M - (1-theta)*dt*K) x                          */
@@ -217,6 +229,8 @@ typedef struct {
   int64_t apply_calls;       /* fem_heat_apply calls on a handle created with FEM_TIMING,  */
   double apply_ms;           /* and the device time of their operator kernels (HIP events;
                                 the copies of x and y are outside)                          */
+  int64_t one_kernel_launches; /* of the sampled direction kernels above, those that also did the
+                                x/r update (FEM_ONE_KERNEL) */
 } fem_stats;
 
 /* Create a solver for one grid, coefficient field and set of boundary

@@ -37,6 +37,7 @@
 #include <hip/hip_ext.h>
 
 #include "batch.hpp"
+#include "dirupd.hpp"
 #include "engine.hpp"
 #include "runtime.hpp"
 #include "tune.hpp"
@@ -109,9 +110,13 @@ class Engine {
     ifused_ = mixed_ && (o.flags & FEM_ONE_REDUCTION) != 0;
     cheb_ = !mixed_ && !fused_ && o.precond == FEM_PRECOND_CHEBYSHEV;
     R_ = o.replace_every;
+    dirupd_ = false;
   }
+  void allow_one_kernel(bool on) { dirupd_ = on && (opts_.flags & FEM_ONE_KERNEL) != 0; }
   ~Engine() {
     (void)hipStreamSynchronize(stream_);
+    efree(bar_count_);
+    efree(bar_fail_);
     efree(sd_dev_);
     efree(tab_dev_);
     for (auto& p : sd_host_)
@@ -169,6 +174,12 @@ class Engine {
   int gather(BatchArgs a, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
   template <typename V>
   int update(BatchArgs a, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
+  // One iteration in one kernel with a grid-wide barrier (dirupd.hpp): a
+  // single simulation whose gather fits the device at once.  *done = false:
+  // not possible here (the caller launches the two kernels).
+  template <typename V>
+  int dirupd(BatchArgs a, hipEvent_t e0, hipEvent_t e1, bool* done);
+  int check_barrier();
   int decide(bool inner, int j_end = 0, bool launch_next = false, bool wait = true, int slot = 0);
   // The next step's RHS and initial residual launched behind a decide (one
   // simulation): set when they ran, so the next epoch does not launch them.
@@ -187,6 +198,7 @@ class Engine {
     hipEvent_t e[4];  // direction kernel start/end, update or replacement start/end
     bool gather;      // the direction kernel is in the sample
     int kind;         // 0: no second kernel timed, 1: update, 2: replacement
+    bool one;         // the direction kernel also did the update (one-kernel iteration)
   };
   hipEvent_t take_event();
   int flush_timing();
@@ -230,6 +242,16 @@ class Engine {
 
   SimDev* sd_dev_ = nullptr;
   SimDev sd_one_{};  // host copy of the uploaded SimDev when the batch holds one simulation
+  // one-kernel iterations (FEM_ONE_KERNEL, runs of one handle); the grid-wide
+  // barrier's arrival counter followed by one flag per block (bar_blocks_ of
+  // them), its failure flag, and the arrivals so far
+  bool dirupd_ = false;
+  unsigned long long* bar_count_ = nullptr;
+  uint32_t bar_blocks_ = 0;
+  int32_t* bar_fail_ = nullptr;
+  unsigned long long bar_total_ = 0;
+  int dirupd_cap_[2] = {-1, -1};  // blocks the device holds at once (FP64, FP32), -1: not yet asked
+  size_t dirupd_cap_smem_[2] = {0, 0};
   SimDev* sd_host_[2] = {nullptr, nullptr};  // pinned staging, used alternately
   int sd_flip_ = 0;
   size_t sd_cap_ = 0;
@@ -284,6 +306,7 @@ int Engine::flush_timing() {
       HIP_TRY(hipEventElapsedTime(&ms, t.e[0], t.e[1]));
       stats.gather_launches += 1;
       stats.gather_ms += ms;
+      if (t.one) stats.one_kernel_launches += 1;
     }
     if (t.kind != 0) {
       HIP_TRY(hipEventElapsedTime(&ms, t.e[2], t.e[3]));
@@ -613,6 +636,91 @@ int Engine::gather(BatchArgs a, hipEvent_t e0, hipEvent_t e1) {
 }
 
 template <typename V>
+int Engine::dirupd(BatchArgs a, hipEvent_t e0, hipEvent_t e1, bool* done) {
+  fem_heat* h = h_;
+  *done = false;
+  if (lay_.ngroups != 1) return FEM_OK;
+  const Group& g = lay_.groups[0];
+  constexpr bool f64 = sizeof(V) == 8;
+  const int kind = g.kind;
+  const void* fn = kind == kElemCubic  ? reinterpret_cast<const void*>(&dirupd_kernel<kElemCubic, V>)
+                   : kind == kElemTet6 ? reinterpret_cast<const void*>(&dirupd_kernel<kElemTet6, V>)
+                                       : reinterpret_cast<const void*>(&dirupd_kernel<kElemBox, V>);
+  const SimDev& s = sd_one_;
+  using Role = RoleDir<V>;
+  GatherArgs<V> ga = Role::ga(s);
+  // LDS: the gather's planes and coefficient tiles, then q, r and P^-1 (and,
+  // in FP32, d and x) at the block's own nodes
+  const uint32_t lds_base = (uint32_t)((f64 ? g.smem64 : g.smem32) + 255) / 256 * 256;
+  const size_t smem = lds_base + (size_t)ga.s.tz * g.nthreads * sizeof(V) * (f64 ? 3 : 5);
+  int& cap = dirupd_cap_[f64 ? 0 : 1];
+  if (cap < 0 || dirupd_cap_smem_[f64 ? 0 : 1] != smem) {
+    int per_cu = 0, cus = 0;
+    HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, (int)g.nthreads, smem));
+    HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, h->opts.device));
+    cap = per_cu * cus;
+    dirupd_cap_smem_[f64 ? 0 : 1] = smem;
+  }
+  if ((int)g.nwork > cap || smem > 160 * 1024) return FEM_OK;  // not every block at once: two kernels
+  if (bar_blocks_ < g.nwork) {  // (re)start the barrier: counter and flags at 0
+    efree(bar_count_);
+    bar_count_ = nullptr;
+    bar_blocks_ = 0;
+    const size_t words = (size_t)kBarFlagStride * (1 + g.nwork);
+    RC_TRY(ealloc(&bar_count_, words));
+    if (!bar_fail_) RC_TRY(ealloc(&bar_fail_, 1));
+    HIP_TRY(hipMemsetAsync(bar_count_, 0, words * sizeof(unsigned long long), stream_));
+    HIP_TRY(hipMemsetAsync(bar_fail_, 0, sizeof(int32_t), stream_));
+    bar_blocks_ = g.nwork;
+    bar_total_ = 0;
+  }
+  ProDirection<V> pro = Role::pro(s, a);
+  Relay R = Role::relay(s, a);
+  UpdHalf<V> u{};
+  const V* pinv = nullptr;
+  if constexpr (f64) {
+    u = UpdHalf<V>{s.r64, nullptr, s.oS[a.cur], s.oP[a.cur]};
+    pinv = s.pinv64;
+  } else {
+    u = UpdHalf<V>{s.r32, s.e32[a.xpar], s.iS[a.cur], s.iP[a.cur]};
+    pinv = s.pinv32;
+  }
+  bar_total_ += g.nwork;
+  GridBar gb{bar_count_, bar_count_ + kBarFlagStride, bar_fail_, bar_total_};
+  uint32_t lb = lds_base;
+  void* kargs[] = {&ga, &pro, &R, &u, &pinv, &gb, &lb};
+  if (e0) HIP_TRY(hipEventRecord(e0, stream_));
+  // A plain launch: a cooperative one would guarantee that every block is
+  // resident, but costs about 14 us more per launch here (measured).  The
+  // grid was checked against the device's occupancy above; work that other
+  // streams or processes run at the same time can still hold CUs, and then
+  // the barrier's bounded wait runs out and the run fails (FEM_ONE_KERNEL
+  // is an option for that reason).
+  HIP_TRY(hipLaunchKernel(fn, dim3(g.nwork), dim3(g.nthreads), kargs, (unsigned int)smem, stream_));
+  if (e1) HIP_TRY(hipEventRecord(e1, stream_));
+  *done = true;
+  return FEM_OK;
+}
+
+// A grid-wide barrier that ran out of time leaves its launch's results void:
+// the run fails, and the counter starts over.
+int Engine::check_barrier() {
+  fem_heat* h = h_;
+  if (!bar_fail_) return FEM_OK;
+  int32_t f = 0;
+  HIP_TRY(hipMemcpyAsync(&f, bar_fail_, sizeof(f), hipMemcpyDeviceToHost, stream_));
+  HIP_TRY(hipStreamSynchronize(stream_));
+  if (!f) return FEM_OK;
+  HIP_TRY(hipMemsetAsync(bar_count_, 0, (size_t)kBarFlagStride * (1 + bar_blocks_) * sizeof(unsigned long long), stream_));
+  HIP_TRY(hipMemsetAsync(bar_fail_, 0, sizeof(int32_t), stream_));
+  HIP_TRY(hipStreamSynchronize(stream_));
+  bar_total_ = 0;
+  return fail(h, FEM_EDEVICE,
+              "a grid-wide barrier of the one-kernel iteration timed out (other work on the device held "
+              "some of its blocks back)");
+}
+
+template <typename V>
 int Engine::update(BatchArgs a, hipEvent_t e0, hipEvent_t e1) {
   fem_heat* h = h_;
   const bool f64 = sizeof(V) == 8;
@@ -750,7 +858,7 @@ int Engine::pcg(int first_chunk) {
       const bool pick = timing_ && (sample_ctr_++ % kSampleEvery) == 0;
       const bool rep = replacing(jj);
       const bool pick_rep = rep && timing_ && (replace_ctr_++ % kReplaceEvery) == 0;
-      Timed t{{nullptr, nullptr, nullptr, nullptr}, pick, pick_rep ? 2 : (pick && !rep && !one_red ? 1 : 0)};
+      Timed t{{nullptr, nullptr, nullptr, nullptr}, pick, pick_rep ? 2 : (pick && !rep && !one_red ? 1 : 0), false};
       if (timing_ && (t.gather || t.kind != 0)) {
         for (int q = 0; q < 4; ++q)
           if ((q < 2 && t.gather) || (q >= 2 && t.kind != 0)) {
@@ -771,6 +879,26 @@ int Engine::pcg(int first_chunk) {
           RC_TRY(gather<RoleFused>(args(cur, prev, jj, xpar, deferred(jj) ? 1 : 0), e0, e1));
       } else if (cheb_ && !inner) {
         RC_TRY(gather<RoleDirS>(args(cur, prev, jj, xpar, deferred(jj) ? 1 : 0), e0, e1));
+      } else if (!rep && dirupd_ && !multi_) {
+        // direction, apply and update in one kernel; the state and partials
+        // it leaves are in the buffers the gather read (cur)
+        bool one = false;
+        RC_TRY(dirupd<V>(args(cur, prev, jj, xpar, !inner && deferred(jj) ? 1 : 0), e0, e1, &one));
+        if (one) {
+          prev = PK_GATHER;
+          if (tr) {  // the sample has no separate update kernel
+            Timed& rt = recs.back();
+            for (int q = 2; q < 4; ++q)
+              if (rt.e[q]) {
+                ev_.push_back(rt.e[q]);
+                rt.e[q] = nullptr;
+              }
+            rt.kind = 0;
+            rt.one = true;
+          }
+          continue;
+        }
+        RC_TRY(gather<RoleDir<V>>(args(cur, prev, jj, xpar, !inner && deferred(jj) ? 1 : 0), e0, e1));
       } else {
         RC_TRY(gather<RoleDir<V>>(args(cur, prev, jj, xpar, !inner && deferred(jj) ? 1 : 0), e0, e1));
       }
@@ -1052,6 +1180,7 @@ int Engine::run() {
   }
   HIP_TRY(hipEventRecord(ev_run_[1], stream_));
   HIP_TRY(hipEventSynchronize(ev_run_[1]));
+  RC_TRY(check_barrier());
   RC_TRY(flush_timing());
   float ms = 0.f;
   HIP_TRY(hipEventElapsedTime(&ms, ev_run_[0], ev_run_[1]));
@@ -1191,16 +1320,19 @@ int solver_run(fem_heat* h, const double* T0, const double* T_prev, double dt, d
   RunRequest r{h, T0, T_prev, dt, theta, rtol, nsteps, out};
   int32_t st = FEM_OK;
   std::string err;
-  RC_TRY(engine_run(&r, 1, h->stream, h->opts, &st, &err));
+  RC_TRY(engine_run(&r, 1, h->stream, h->opts, &st, &err, true));
   return st;
 }
 
 int engine_run(const RunRequest* reqs, int32_t n, hipStream_t stream, const fem_opts& opts, int32_t* status,
-               std::string* err) {
+               std::string* err, bool one_kernel) {
   fem_heat* h = n == 1 ? reqs[0].h : nullptr;
   fem_heat scratch;
   if (!h) h = &scratch;
   Engine e(stream, opts, h);
+  // a run of one handle may iterate in one kernel; batches (and servers)
+  // keep two, so a simulation's bits do not depend on what it runs with
+  e.allow_one_kernel(one_kernel && n == 1);
   for (int32_t i = 0; i < n; ++i) {
     const int rc = e.add(reqs[i]);
     if (rc != FEM_OK) {

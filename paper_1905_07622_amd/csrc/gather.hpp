@@ -131,10 +131,11 @@ struct AdvancesResidual {
 };
 
 // An epilogue that reads per-node inputs (b, P^-1, F, ...) declares them as
-// its Raw and loads them in fetch(i); the march issues that load for the own
-// node two layers ahead, like the plane loads, and hands the values to
-// store().  (Loads issued inside a layer and used at once would make the
-// wave wait for every load before them, the prefetched planes included.)
+// its Raw and loads them in fetch(i); the march requests them at the start of
+// the layer that completes the own node, before that layer issues the next
+// planes' loads, and hands the values to store() (or keep()).  (Loads issued
+// after the planes' and used in the same layer would make the wave wait for
+// every load before them, the prefetched planes included.)
 template <class E, class = void>
 struct EpiFetches {
   static constexpr bool value = false;
@@ -153,6 +154,28 @@ struct EpiRawOf<E, true> {
   using type = typename E::Raw;
 };
 
+// An epilogue that keeps the result at the block's own nodes on chip (in
+// LDS, for a later phase of the same kernel) instead of storing it: it has
+// keep(zl, acc, v, live, raw), zl the node's plane within the block's
+// z-chunk, raw what its fetch(i) read at the node (see EpiFetches).
+template <class E, class = void>
+struct EpiKeeps {
+  static constexpr bool value = false;
+};
+template <class E>
+struct EpiKeeps<E, std::void_t<decltype(E::kKeeps)>> {
+  static constexpr bool value = E::kKeeps;
+};
+
+// What a gather leaves for a later phase of the same kernel (out-parameter
+// of gather_tile): the state it evaluated (valid when `settled`) and, when
+// the relay has no partial buffer, the thread's share of the dot product.
+struct TileOut {
+  Scalars st;
+  double dot;
+  bool settled;
+};
+
 // One block's share of a gather: tile `logical` of the solve that `ga`, the
 // functors and the relay describe.  The block's dot-product partial is
 // stored at index `logical`, and tile 0 publishes the relayed state.
@@ -161,8 +184,14 @@ struct EpiRawOf<E, true> {
 // (in FP32 two layers fit in 169).
 template <typename V, int KIND, class Pro, class Epi, bool kFour = AdvancesResidual<Pro>::value,
           int kD = (AdvancesResidual<Pro>::value && sizeof(V) == 8 ? 1 : kDepth)>
-__device__ inline void gather_tile(const GatherArgs<V>& ga, Pro pro, Epi epi, const Relay& R, uint32_t logical) {
+__device__ inline void gather_tile(const GatherArgs<V>& ga, Pro pro, Epi epi, const Relay& R, uint32_t logical,
+                                   TileOut* out = nullptr) {
   const StageIn in = stage_load<sizeof(V) == 8>(R);
+  if (out) {
+    out->st = in.t;
+    out->dot = 0.0;
+    out->settled = false;
+  }
   if (stage_idle(R, in, logical == 0)) return;  // uniform: a finished solve
   Scalars st;
 
@@ -185,7 +214,12 @@ __device__ inline void gather_tile(const GatherArgs<V>& ga, Pro pro, Epi epi, co
   const uint32_t pstride = (uint32_t)px * (uint32_t)py, lstride = (uint32_t)nx * (uint32_t)ny;
 
   if (logical >= ga.s.ntiles) {  // a padding block: partial 0 (never the writer)
-    if (stage_finish<kFour>(R, in, st, false) && R.pout) {
+    const bool go = stage_finish<kFour>(R, in, st, false);
+    if (out) {
+      out->st = st;
+      out->settled = true;
+    }
+    if (go && R.pout) {
       if constexpr (AdvancesResidual<Pro>::value) {
         const double z[4] = {0.0, 0.0, 0.0, 0.0};
         publish_partial4(R, z, logical);
@@ -439,6 +473,8 @@ __device__ inline void gather_tile(const GatherArgs<V>& ga, Pro pro, Epi epi, co
             dots[2] += (double)qv * (double)(pp_lo * qv);
             dots[3] += (double)rn_lo * (double)(pp_lo * rn_lo);
           }
+        } else if constexpr (EpiKeeps<Epi>::value) {
+          dot += epi.keep(vis(k) - z0, carry + p_lo, lo.c, col_ok, eo);
         } else if constexpr (EF) {
           dot += epi.store(i, carry + p_lo, lo.c, col_ok, ga.sink, eo);
         } else {
@@ -463,7 +499,12 @@ __device__ inline void gather_tile(const GatherArgs<V>& ga, Pro pro, Epi epi, co
       fetch(S0, vis(0), lay(0), vis(0));
       fetch(SB, vis(1), lay(0), vis(0));
       if constexpr (kD == 2) fetch(SA, vis(min(2, n)), lay(min(1, n - 1)), vis(1));
-      if (!stage_finish<kFour>(R, in, st, logical == 0)) {  // uniform
+      const bool go = stage_finish<kFour>(R, in, st, logical == 0);
+      if (out) {
+        out->st = st;
+        out->settled = true;
+      }
+      if (!go) {  // uniform
         if constexpr (XI) {
           // the solve finished in this kernel's evaluation: the last
           // iteration's deferred iterate update is still due at own nodes
@@ -507,6 +548,7 @@ __device__ inline void gather_tile(const GatherArgs<V>& ga, Pro pro, Epi epi, co
     if (R.pout) publish_partial4(R, dots, logical);
   } else {
     if (R.pout) publish_partial(R, dot, logical);
+    if (out) out->dot = dot;
   }
 }
 

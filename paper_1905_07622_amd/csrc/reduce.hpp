@@ -216,6 +216,23 @@ __device__ inline void evaluate_pending(Scalars& s, const double* xs, const Ctl&
 
 __device__ inline bool is_fused_mode(int32_t m) { return m == M_FDIR || m == M_FUPD || m == M_FREPL; }
 
+// The scalar step of the x/r update (Algorithm 1's alpha = delta / d^T q),
+// given x = d^T q; returns whether the update has work.
+__device__ inline bool settle_update(Scalars& t, double x) {
+  if (t.done) return false;
+  const double a = t.delta / x;
+  t.dq = x;
+  if (!(x > 0.0) || !isfinite(x) || !isfinite(a)) {
+    t.status = kStatusBreakdown;
+    t.done = 1;
+    return false;
+  }
+  t.alpha = a;
+  t.iter += 1;
+  t.phase = PH_AFTER_UPD;
+  return true;
+}
+
 // The relayed state as a kernel finds it, before the pending update.
 struct StageIn {
   Scalars t;
@@ -342,21 +359,7 @@ __device__ inline bool stage_finish(const Relay& R, const StageIn& in, Scalars& 
         if (g) t.phase = PH_AFTER_UPD;
         break;
       case M_UPD:
-        if (t.done) {
-          g = 0;
-        } else {
-          const double a = t.delta / x;
-          t.dq = x;
-          if (!(x > 0.0) || !isfinite(x) || !isfinite(a)) {
-            t.status = kStatusBreakdown;
-            t.done = 1;
-            g = 0;
-          } else {
-            t.alpha = a;
-            t.iter += 1;
-            t.phase = PH_AFTER_UPD;
-          }
-        }
+        g = settle_update(t, x) ? 1 : 0;
         break;
       case M_CORR:
         t.phase = PH_AFTER_CHECK;

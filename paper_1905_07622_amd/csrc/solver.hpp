@@ -123,6 +123,6 @@ struct RunRequest {
 int solver_run(fem_heat* h, const double* T0, const double* T_prev, double dt, double theta, int32_t nsteps,
                double rtol, fem_out* out);
 int engine_run(const RunRequest* reqs, int32_t n, hipStream_t stream, const fem_opts& opts, int32_t* status,
-               std::string* err);
+               std::string* err, bool one_kernel = false);
 
 }  // namespace femheat

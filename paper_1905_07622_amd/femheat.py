@@ -23,7 +23,7 @@ FEM_GUESS_EXTRAP, FEM_GUESS_PREV = 0, 1
 FEM_STOP_RHS, FEM_STOP_INITIAL = 0, 1
 FEM_PRECOND_JACOBI, FEM_PRECOND_CHEBYSHEV = 0, 1
 FEM_ELEM_HEX8, FEM_ELEM_TET6 = 0, 1
-FEM_DEVICE_PTRS, FEM_TIMING, FEM_ONE_REDUCTION = 0x1, 0x2, 0x4
+FEM_DEVICE_PTRS, FEM_TIMING, FEM_ONE_REDUCTION, FEM_ONE_KERNEL = 0x1, 0x2, 0x4, 0x8
 FEM_OP_A, FEM_OP_L, FEM_OP_JACOBI, FEM_OP_LOAD, FEM_OP_FP32, FEM_OP_ELEMENTWISE, FEM_OP_ROWWAVE = (
     0, 1, 2, 3, 0x100, 0x200, 0x400)
 
@@ -67,7 +67,8 @@ class fem_stats(ctypes.Structure):
                 ("replace_launches", ctypes.c_int64), ("replace_ms", ctypes.c_double),
                 ("grid_blocks", ctypes.c_int32), ("tile_x", ctypes.c_int32),
                 ("tile_y", ctypes.c_int32), ("tile_z", ctypes.c_int32),
-                ("apply_calls", ctypes.c_int64), ("apply_ms", ctypes.c_double)]
+                ("apply_calls", ctypes.c_int64), ("apply_ms", ctypes.c_double),
+                ("one_kernel_launches", ctypes.c_int64)]
 
 
 FEM_TUNE_BATCH = 0x1
@@ -487,7 +488,7 @@ class Heat:
                  replace_every=50, guess=FEM_GUESS_EXTRAP, stop_rule=FEM_STOP_RHS, max_refine=4,
                  inner_rtol=1e-5, device_ptrs=False, timing=False, one_reduction=False, tile=(0, 0, 0), stream=None,
                  device=0, tune_cache=None, precond=FEM_PRECOND_JACOBI, cheb_degree=3, cheb_ratio=30.0,
-                 element=FEM_ELEM_HEX8):
+                 element=FEM_ELEM_HEX8, one_kernel=False):
         self.h = None
         self.device_ptrs = device_ptrs
         self.N = (nx + 1) * (ny + 1) * (nz + 1)
@@ -506,7 +507,7 @@ class Heat:
         o.guess, o.stop_rule, o.max_refine, o.inner_rtol = guess, stop_rule, max_refine, inner_rtol
         o.precond, o.cheb_degree, o.cheb_ratio, o.element = precond, cheb_degree, cheb_ratio, element
         o.flags = ((FEM_DEVICE_PTRS if device_ptrs else 0) | (FEM_TIMING if timing else 0)
-                   | (FEM_ONE_REDUCTION if one_reduction else 0))
+                   | (FEM_ONE_REDUCTION if one_reduction else 0) | (FEM_ONE_KERNEL if one_kernel else 0))
         o.hip_stream = stream
         o.device = device
         o.tile_x, o.tile_y, o.tile_z = tile

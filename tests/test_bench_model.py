@@ -36,8 +36,22 @@ def test_byte_model_per_node():
 
 def test_byte_model_one_reduction():
     N, E = 1000, 729
-    ab0 = bench.algorithmic_bytes(N, E, 8, 0.0, True)
-    ab1 = bench.algorithmic_bytes(N, E, 8, 1.0, True)
+    ab0 = bench.algorithmic_bytes(N, E, 8, 0.0, "one-reduction")
+    ab1 = bench.algorithmic_bytes(N, E, 8, 1.0, "one-reduction")
     assert ab0["gather"] == (5 * N + 2 * E) * 8  # as the two-kernel direction kernel
     assert ab1["gather"] - ab0["gather"] == 32 * N  # + q read, r written, x read and written
     assert ab1["update"] == 0
+
+
+def test_byte_model_one_kernel():
+    """Both halves of the iteration in one launch: the two kernels' bytes
+    minus q written and read and r and P^-1 read again (q, r and P^-1 at the
+    own nodes stay on chip), so the direction kernel's bytes with r written
+    in place of q; the deferred x as before."""
+    N, E = 1000, 729
+    for f in (0.0, 0.5, 1.0):
+        two = bench.algorithmic_bytes(N, E, 8, f)
+        one = bench.algorithmic_bytes(N, E, 8, f, "one-kernel")
+        assert one["update"] == 0
+        assert one["gather"] == two["gather"]
+        assert one["gather"] == two["gather"] + two["update"] - 4 * N * 8
