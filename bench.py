@@ -654,7 +654,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-timing", action="store_true", help="time without per-kernel HIP events")
     ap.add_argument("--tile", type=int, nargs=3, default=(0, 0, 0))
-    ap.add_argument("--pcg-form", choices=["one-kernel", "two-kernel", "one-reduction"], default="one-kernel",
+    ap.add_argument("--pcg-form", choices=["one-kernel", "two-kernel", "one-reduction"], default="two-kernel",
                     help="Algorithm 1 in one kernel per iteration with a grid-wide barrier (FEM_ONE_KERNEL), "
                          "in two kernels (the library's default), or the one-reduction form")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched-proposals measurement")
