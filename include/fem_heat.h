@@ -193,6 +193,13 @@ typedef struct {
                              there for its node grid, precision, element class and launch kind
                              (alone or batch member) on this GPU architecture and HIP runtime;
                              fem_heat_tune records into it (see fem_heat_tune on results). */
+  int32_t batch_groups;   /* fem_heat_run_batch: run the simulations as this many batches at once,
+                             dealt round-robin, each on its own stream and host thread, so that one
+                             batch's last iterations (its slowest members) overlap the others'
+                             work; results do not change.  0 = automatic (1; 2 from 16
+                             simulations on, 3 from 48); with a caller's stream the batches
+                             start after its earlier work.  Handles and servers ignore it
+                             (server lanes already overlap) */
 } fem_opts;
 
 /* Outputs of a run (inputs marked "in").  Every pointer may be NULL.
@@ -299,7 +306,8 @@ typedef struct {
  * own data, with its own reductions), they advance one time step per epoch
  * in lockstep, and each leaves the batch after its last step.  A
  * simulation's results do not depend on the others in the batch: they are
- * bit-identical to those of a batch holding it alone.  opts (may be NULL)
+ * bit-identical to those of a batch holding it alone.  Large batches run as
+ * a few such batches at once (fem_opts.batch_groups).  opts (may be NULL)
  * apply to all: precision, iteration controls, flags (FEM_DEVICE_PTRS covers
  * every array of every request), stream, device and tile overrides; without
  * a tile_z override every simulation marches z-chunks of at most 32 planes.
@@ -390,8 +398,12 @@ void fem_server_destroy(fem_server *s);
  * heights, z-chunk lengths for 1 to 4 resident blocks per CU), each with
  * device events over repeated launches, and installs the fastest on the
  * handle.  With FEM_TUNE_BATCH the candidates and the timing are those of a
- * batch member: chunks of 8 to 32 planes, timed with enough copies of the
- * simulation in one launch to fill the device, per simulation.  When the
+ * batch member: chunks of 8 to 32 planes or the node column cut into 1 to 6
+ * equal chunks, each scored by its time per simulation in a launch with
+ * enough copies of the simulation to fill the device plus a sixteenth of a
+ * launch holding the simulation alone (a lockstep batch ends each step with
+ * launches serving only its slowest members, where the tile's latency
+ * counts); the tile is recorded, not installed.  When the
  * handle's options name a tune_cache, the result is recorded there under
  * the key of this grid, precision, element class and launch kind, and later
  * handles (fem_heat_create, fem_heat_run_batch, servers) with the same
@@ -405,7 +417,7 @@ void fem_server_destroy(fem_server *s);
 typedef struct {
   int32_t tile_x, tile_y, tile_z; /* installed tile                                         */
   int32_t candidates;             /* tiles timed                                            */
-  double best_us;                 /* its time per launch (per simulation with FEM_TUNE_BATCH) */
+  double best_us;                 /* its time per launch (with FEM_TUNE_BATCH: its score, in us) */
   double rule_us;                 /* the same for the tile the handle had before            */
   int32_t recorded;               /* 1: written to the tune_cache                           */
 } fem_tune_result;

@@ -8,6 +8,7 @@
 #include <cstring>
 #include <new>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "engine.hpp"
@@ -52,6 +53,7 @@ int check_opts(const fem_opts* opts, fem_opts& o, std::string& why) {
     if (o.cheb_degree < 2 || o.cheb_degree > femheat::kChebMaxDegree) return bad("cheb_degree must be in 2..8");
     if (!(o.cheb_ratio > 1.0) || !std::isfinite(o.cheb_ratio)) return bad("cheb_ratio must be finite and > 1");
   }
+  if (o.batch_groups < 0) return bad("batch_groups must be >= 0");
   if (o.tile_x < 0 || o.tile_y < 0 || o.tile_z < 0 || o.tile_x > 256 || o.tile_x * std::max(o.tile_y, 1) > 256)
     return bad("tile overrides out of range");
   // each thread of a gather block stages two entries of the (tx+2) x (ty+2)
@@ -247,29 +249,100 @@ int fem_heat_run_batch(const fem_request* reqs, int32_t n, const fem_opts* opts,
     if (status) std::copy(st.begin(), st.end(), status);
     return first_bad;
   }
-  hipStream_t stream = reinterpret_cast<hipStream_t>(o.hip_stream);
-  bool own = false;
   if (hipSetDevice(o.device) != hipSuccess) {
     g_create_error = "hipSetDevice failed";
     return FEM_EDEVICE;
   }
-  if (!stream) {
-    if (hipStreamCreateWithFlags(&stream, hipStreamNonBlocking) != hipSuccess) {
-      g_create_error = "hipStreamCreate failed";
-      return FEM_EDEVICE;
+  // G concurrent batches, simulations dealt round-robin, each batch on its
+  // own stream and host thread: while one batch runs the last iterations of
+  // its slowest member (few blocks), the others fill the device.  A
+  // simulation's results do not depend on its batch, so the grouping changes
+  // no result.
+  // Automatic: two batches from 16 simulations on, three from 48 (measured
+  // on 64 x 48^3 in the mixed form, medians of three: 92 solves/s as one
+  // batch, 105 as two, 108 as three, 92 as four, where the streams with the
+  // caller's outnumber the four hardware queues a process gets by default).
+  const int G = std::max(
+      1, std::min<int>(n, o.batch_groups > 0 ? o.batch_groups : (n >= 48 ? 3 : (n >= 16 ? 2 : 1))));
+  hipStream_t caller = reinterpret_cast<hipStream_t>(o.hip_stream);
+  std::vector<hipStream_t> gs((size_t)G, nullptr);
+  std::vector<bool> own((size_t)G, false);
+  hipEvent_t start = nullptr;
+  for (int g = 0; g < G && rc == FEM_OK; ++g) {
+    if (G == 1 && caller) {
+      gs[0] = caller;
+      break;
     }
-    own = true;
-    o.hip_stream = stream;
+    if (hipStreamCreateWithFlags(&gs[(size_t)g], hipStreamNonBlocking) != hipSuccess) {
+      g_create_error = "hipStreamCreate failed";
+      rc = FEM_EDEVICE;
+      break;
+    }
+    own[(size_t)g] = true;
+  }
+  // the batches start after the work the caller enqueued on its stream
+  if (rc == FEM_OK && caller && G > 1) {
+    if (hipEventCreateWithFlags(&start, hipEventDisableTiming) != hipSuccess || hipEventRecord(start, caller) != hipSuccess) {
+      g_create_error = "hipEventRecord failed";
+      rc = FEM_EDEVICE;
+    }
+    for (int g = 0; g < G && rc == FEM_OK; ++g)
+      if (hipStreamWaitEvent(gs[(size_t)g], start, 0) != hipSuccess) {
+        g_create_error = "hipStreamWaitEvent failed";
+        rc = FEM_EDEVICE;
+      }
   }
   std::vector<fem_heat*> hs((size_t)n, nullptr);
-  std::vector<femheat::RunRequest> rq((size_t)n);
+  std::vector<std::vector<femheat::RunRequest>> rq((size_t)G);
+  std::vector<std::vector<int32_t>> idx((size_t)G), gst((size_t)G);
+  std::vector<int> grc((size_t)G, FEM_OK);
+  std::vector<std::string> gerr((size_t)G);
   try {
     for (int32_t i = 0; i < n && rc == FEM_OK; ++i) {
       const fem_request& r = reqs[i];
-      rc = femheat::make_handle(&r.grid, r.k_e, r.rhoc_e, &r.bc, o, true, &hs[(size_t)i], &g_create_error);
-      rq[(size_t)i] = femheat::RunRequest{hs[(size_t)i], r.T0, r.T_prev, r.dt, r.theta, r.rtol, r.nsteps, r.out};
+      const size_t g = (size_t)(i % G);
+      fem_opts og = o;
+      og.hip_stream = gs[g];
+      rc = femheat::make_handle(&r.grid, r.k_e, r.rhoc_e, &r.bc, og, true, &hs[(size_t)i], &g_create_error);
+      rq[g].push_back(femheat::RunRequest{hs[(size_t)i], r.T0, r.T_prev, r.dt, r.theta, r.rtol, r.nsteps, r.out});
+      idx[g].push_back(i);
     }
-    if (rc == FEM_OK) rc = femheat::engine_run(rq.data(), n, stream, o, st.data(), &g_create_error);
+    auto run_group = [&](size_t g) {
+      fem_opts og = o;
+      og.hip_stream = gs[g];
+      gst[g].assign(rq[g].size(), FEM_OK);
+      try {
+        if (G > 1 && hipSetDevice(o.device) != hipSuccess) {
+          gerr[g] = "hipSetDevice failed";
+          grc[g] = FEM_EDEVICE;
+          return;
+        }
+        grc[g] = femheat::engine_run(rq[g].data(), (int32_t)rq[g].size(), gs[g], og, gst[g].data(), &gerr[g]);
+      } catch (const std::bad_alloc&) {
+        gerr[g] = "host allocation failed";
+        grc[g] = FEM_ENOMEM;
+      } catch (...) {
+        gerr[g] = "unexpected exception";
+        grc[g] = FEM_EDEVICE;
+      }
+    };
+    if (rc == FEM_OK) {
+      if (G == 1) {
+        run_group(0);
+      } else {
+        std::vector<std::thread> th;
+        for (int g = 1; g < G; ++g) th.emplace_back(run_group, (size_t)g);
+        run_group(0);
+        for (auto& t : th) t.join();
+      }
+      for (int g = 0; g < G && rc == FEM_OK; ++g)
+        if (grc[(size_t)g] != FEM_OK) {
+          rc = grc[(size_t)g];
+          g_create_error = gerr[(size_t)g];
+        }
+      for (int g = 0; g < G; ++g)
+        for (size_t q = 0; q < idx[(size_t)g].size(); ++q) st[(size_t)idx[(size_t)g][q]] = gst[(size_t)g][q];
+    }
   } catch (const std::bad_alloc&) {
     g_create_error = "host allocation failed";
     rc = FEM_ENOMEM;
@@ -282,7 +355,12 @@ int fem_heat_run_batch(const fem_request* reqs, int32_t n, const fem_opts* opts,
     femheat::solver_free(h);
     delete h;
   }
-  if (own) (void)hipStreamDestroy(stream);
+  for (int g = 0; g < G; ++g)
+    if (own[(size_t)g]) {
+      (void)hipStreamSynchronize(gs[(size_t)g]);
+      (void)hipStreamDestroy(gs[(size_t)g]);
+    }
+  if (start) (void)hipEventDestroy(start);
   if (rc != FEM_OK) return rc;
   if (status) std::copy(st.begin(), st.end(), status);
   for (int32_t v : st)

@@ -1223,11 +1223,9 @@ int Engine::tune(fem_heat* h, double dt, double theta, bool batch, fem_tune_resu
   double best = 0.0, rule = 0.0;
   size_t bi = 0;
   int rc = FEM_OK;
-  for (size_t i = 0; i < cands.size() && rc == FEM_OK; ++i) {
-    const GatherShape& c = cands[i];
-    rc = set_shape(h, c);
-    if (rc != FEM_OK) break;
-    const int copies = batch ? std::min<int>(64, std::max<int>(1, (4 * cus + (int)c.nblocks - 1) / (int)c.nblocks)) : 1;
+  // Time per launch and copy of the candidate installed on h, with `copies`
+  // copies of the simulation in each launch.
+  auto time_copies = [&](int copies, double* us) -> int {
     sims_.clear();
     for (int q = 0; q < copies; ++q) {
       auto sp = std::make_unique<Sim>();
@@ -1239,20 +1237,44 @@ int Engine::tune(fem_heat* h, double dt, double theta, bool batch, fem_tune_resu
       sims_.push_back(std::move(sp));
     }
     dirty_ = true;
-    if ((rc = compose()) != FEM_OK || (rc = upload_simdev()) != FEM_OK) break;
+    int r = compose();
+    if (r == FEM_OK) r = upload_simdev();
     auto launch = [&]() {
       return mixed_ ? gather<RoleDir<float>>(args(0, PK_GATHER, 1, 0, 0))
                     : gather<RoleDir<double>>(args(0, PK_GATHER, 1, 0, 1));
     };
-    for (int w = 0; w < 2 && rc == FEM_OK; ++w) rc = launch();
-    if (rc == FEM_OK && hipEventRecord(ev[0], stream_) != hipSuccess) rc = fail(eh, FEM_EDEVICE, "hipEventRecord");
-    for (int r = 0; r < kReps && rc == FEM_OK; ++r) rc = launch();
-    if (rc == FEM_OK && (hipEventRecord(ev[1], stream_) != hipSuccess || hipEventSynchronize(ev[1]) != hipSuccess))
-      rc = fail(eh, FEM_EDEVICE, "timing events failed");
+    for (int w = 0; w < 2 && r == FEM_OK; ++w) r = launch();
+    if (r == FEM_OK && hipEventRecord(ev[0], stream_) != hipSuccess) r = fail(eh, FEM_EDEVICE, "hipEventRecord");
+    for (int k = 0; k < kReps && r == FEM_OK; ++k) r = launch();
+    if (r == FEM_OK && (hipEventRecord(ev[1], stream_) != hipSuccess || hipEventSynchronize(ev[1]) != hipSuccess))
+      r = fail(eh, FEM_EDEVICE, "timing events failed");
     float ms = 0.f;
-    if (rc == FEM_OK && hipEventElapsedTime(&ms, ev[0], ev[1]) != hipSuccess) rc = fail(eh, FEM_EDEVICE, "hipEventElapsedTime");
+    if (r == FEM_OK && hipEventElapsedTime(&ms, ev[0], ev[1]) != hipSuccess) r = fail(eh, FEM_EDEVICE, "hipEventElapsedTime");
+    *us = (double)ms * 1e3 / kReps / copies;
+    return r;
+  };
+  for (size_t i = 0; i < cands.size() && rc == FEM_OK; ++i) {
+    const GatherShape& c = cands[i];
+    rc = set_shape(h, c);
     if (rc != FEM_OK) break;
-    const double us = (double)ms * 1e3 / kReps / copies;
+    double us = 0.0;
+    if (!batch) {
+      rc = time_copies(1, &us);
+    } else {
+      // A batch member's score: its share of a launch that fills the device,
+      // plus a sixteenth of a launch holding it alone.  In a lockstep batch
+      // the last iterations of a step serve only its slowest members, and
+      // then a tile's latency (the length of its z-march) is what counts:
+      // measured on 64 x 48^3, whole 49-plane columns per block were the
+      // fastest full launches and the slowest batch (95 against 108 solves/s
+      // with two-chunk columns).
+      const int copies = std::min<int>(64, std::max<int>(1, (4 * cus + (int)c.nblocks - 1) / (int)c.nblocks));
+      double full = 0.0, alone = 0.0;
+      rc = time_copies(copies, &full);
+      if (rc == FEM_OK) rc = time_copies(1, &alone);
+      us = full + alone / 16.0;
+    }
+    if (rc != FEM_OK) break;
     if (i == 0) rule = us;
     if (i == 0 || us < best) {
       best = us;

@@ -649,7 +649,8 @@ std::vector<GatherShape> tune_candidates(const fem_heat* h, int cus) {
       const int cols = ((px + tx - 1) / tx) * ((py + ty - 1) / ty);
       std::vector<int> tzs;
       if (h->batched) {
-        tzs = {8, 12, 16, 24, 32, pz};
+        tzs = {8, 12, 16, 24, 32};
+        for (int c : {1, 2, 3, 4, 6}) tzs.push_back((pz + c - 1) / c);  // the column in c equal chunks
       } else {
         for (int per_cu = 1; per_cu <= 4; ++per_cu) {
           const int ntz = std::max(1, per_cu * cus / cols);

@@ -50,7 +50,8 @@ class fem_opts(ctypes.Structure):
                 ("hip_stream", ctypes.c_void_p), ("device", ctypes.c_int32),
                 ("tile_x", ctypes.c_int32), ("tile_y", ctypes.c_int32), ("tile_z", ctypes.c_int32),
                 ("allocator", ctypes.c_void_p), ("precond", ctypes.c_int32), ("cheb_degree", ctypes.c_int32),
-                ("cheb_ratio", ctypes.c_double), ("element", ctypes.c_int32), ("tune_cache", ctypes.c_char_p)]
+                ("cheb_ratio", ctypes.c_double), ("element", ctypes.c_int32), ("tune_cache", ctypes.c_char_p),
+                ("batch_groups", ctypes.c_int32)]
 
 
 class fem_out(ctypes.Structure):
@@ -311,8 +312,10 @@ class _Arrays:
 def make_opts(*, precision=FEM_FP64, max_iter=10000, replace_every=50, guess=FEM_GUESS_EXTRAP,
               stop_rule=FEM_STOP_RHS, max_refine=4, inner_rtol=1e-5, device_ptrs=False, timing=False,
               one_reduction=False, tile=(0, 0, 0), stream=None, device=0, tune_cache=None,
-              precond=FEM_PRECOND_JACOBI, cheb_degree=3, cheb_ratio=30.0, element=FEM_ELEM_HEX8) -> fem_opts:
+              precond=FEM_PRECOND_JACOBI, cheb_degree=3, cheb_ratio=30.0, element=FEM_ELEM_HEX8,
+              batch_groups=0) -> fem_opts:
     o = fem_heat_default_opts()
+    o.batch_groups = batch_groups
     o.precond, o.cheb_degree, o.cheb_ratio, o.element = precond, cheb_degree, cheb_ratio, element
     o.precision, o.max_iter, o.replace_every = precision, max_iter, replace_every
     o.guess, o.stop_rule, o.max_refine, o.inner_rtol = guess, stop_rule, max_refine, inner_rtol

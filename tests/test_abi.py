@@ -141,6 +141,8 @@ def test_run_batch_argument_checks(lib):
     reqs = (fh.fem_request * 1)()
     bad_opts = fh.make_opts(precision=7)
     assert fh.fem_heat_run_batch(reqs, 1, bad_opts, None) == fh.FEM_EINVAL
+    assert fh.fem_heat_run_batch(reqs, 1, fh.make_opts(batch_groups=-1), None) == fh.FEM_EINVAL
+    assert "batch_groups" in fh.fem_last_error(None)
 
 
 STRUCTS = ("fem_grid", "fem_bc", "fem_opts", "fem_out", "fem_stats", "fem_tune_result", "fem_request",

@@ -100,6 +100,46 @@ def test_batch_mixed_matches_oracle_and_alone(gpu):
         same_bits(r, alone[0])
 
 
+@pytest.mark.parametrize("precision", [fh.FEM_FP64, fh.FEM_FP32_FP64DOT])
+def test_batch_groups_change_no_bits(gpu, precision):
+    """The same batch run as one, two, three or seven concurrent batches
+    (fem_opts.batch_groups, each on its own stream and host thread): every
+    simulation's outputs bit for bit the same, also with device pointers
+    on a caller's stream."""
+    import torch
+    probs = uneven_batch()
+    st, one = fh.run_batch(probs, save_every=1, precision=precision, batch_groups=1)
+    assert st == fh.FEM_OK
+    for g in (2, 3, 7):
+        st, res = fh.run_batch(probs, save_every=1, precision=precision, batch_groups=g)
+        assert st == fh.FEM_OK
+        for a, b in zip(res, one):
+            same_bits(a, b)
+    stream = torch.cuda.Stream()
+    dev_probs = [p.replace(k_e=torch.tensor(p.k_e, device="cuda"), rhoc_e=torch.tensor(p.rhoc_e, device="cuda"),
+                           T0=torch.tensor(p.T0, device="cuda")) for p in probs]
+    torch.cuda.synchronize()
+    with torch.cuda.stream(stream):
+        st, dev = fh.run_batch(dev_probs, precision=precision, device_ptrs=True, stream=stream.cuda_stream,
+                               batch_groups=3)
+    stream.synchronize()
+    assert st == fh.FEM_OK
+    for a, b in zip(dev, one):
+        assert np.array_equal(a["T_final"].cpu().numpy(), b["T_final"])
+        assert np.array_equal(a["iters"].cpu().numpy() if hasattr(a["iters"], "cpu") else a["iters"], b["iters"])
+
+
+def test_batch_groups_keep_statuses_per_simulation(gpu):
+    easy = wl.random_problem(8, 8, 8, seed=41, nsteps=2, rtol=1e-6)
+    hard = wl.random_problem(12, 12, 12, seed=42, nsteps=2, rtol=1e-30)  # below FP64 reach
+    st, res = fh.run_batch([easy, hard, easy], max_iter=40, check=False, batch_groups=2)
+    assert st == fh.FEM_ENOCONV
+    assert [r["status"] for r in res] == [fh.FEM_OK, fh.FEM_ENOCONV, fh.FEM_OK]
+    _, alone = fh.run_batch([easy], max_iter=40)
+    same_bits(res[0], alone[0])
+    same_bits(res[2], alone[0])
+
+
 def test_batch_sensors_and_device_pointers(gpu):
     import torch
     probs = [wl.defect_slab(30, 24, 5, seed=3, n_defects=3, nsteps=6, pulse_steps=2, n_sensor=4),
