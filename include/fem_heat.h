@@ -179,9 +179,11 @@ typedef struct {
   uint32_t flags;         /* FEM_DEVICE_PTRS | FEM_TIMING                          */
   void *hip_stream;       /* hipStream_t to run on; NULL = the library's own stream */
   int32_t device;         /* HIP device ordinal                                    */
-  int32_t tile_x, tile_y, tile_z; /* gather tile overrides; 0 = automatic.  tile_x <= 256,
-                             tile_x*tile_y <= 256, and the (tile_x+2)*(tile_y+2) plane tile must
-                             fit two staging slots per thread: FEM_EINVAL otherwise            */
+  int32_t tile_x, tile_y, tile_z; /* gather tile overrides; 0 = automatic.  tile_x*tile_y <= 512
+                             for a handle's own runs (blocks of up to 512 threads), <= 256 for
+                             batch members and served simulations, and the (tile_x+2)*(tile_y+2)
+                             plane tile must fit two staging slots per thread: FEM_EINVAL
+                             otherwise                                                        */
   const fem_allocator *allocator; /* device memory (NULL: see fem_allocator); must outlive
                              every handle and server created with these options          */
   int32_t precond;        /* FEM_PRECOND_* (default Jacobi)                                  */

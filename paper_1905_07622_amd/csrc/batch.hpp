@@ -418,7 +418,7 @@ __global__ void __launch_bounds__(256, 2) gather_batch_kernel(BatchArgs a) {
 // read of the simulation's record (the same code as gather_batch_kernel on
 // the same data, so the same bits).
 template <int KIND, class Role>
-__global__ void __launch_bounds__(256, 2)
+__global__ void __launch_bounds__(kMaxBlockThreads)
     gather_one_kernel(GatherArgs<typename Role::V> ga, typename Role::Pro pro, typename Role::Epi epi, Relay R) {
   using Pro = typename Role::Pro;
   gather_tile<typename Role::V, KIND, Pro, typename Role::Epi, reads_four<Role>(0) || AdvancesResidual<Pro>::value>(

@@ -54,7 +54,8 @@ int check_opts(const fem_opts* opts, fem_opts& o, std::string& why) {
     if (!(o.cheb_ratio > 1.0) || !std::isfinite(o.cheb_ratio)) return bad("cheb_ratio must be finite and > 1");
   }
   if (o.batch_groups < 0) return bad("batch_groups must be >= 0");
-  if (o.tile_x < 0 || o.tile_y < 0 || o.tile_z < 0 || o.tile_x > 256 || o.tile_x * std::max(o.tile_y, 1) > 256)
+  if (o.tile_x < 0 || o.tile_y < 0 || o.tile_z < 0 || o.tile_x > femheat::kMaxBlockThreads ||
+      o.tile_x * std::max(o.tile_y, 1) > femheat::kMaxBlockThreads)
     return bad("tile overrides out of range");
   // each thread of a gather block stages two entries of the (tx+2) x (ty+2)
   // plane tile and of the (tx+1) x (ty+1) coefficient tile; with tile_x given

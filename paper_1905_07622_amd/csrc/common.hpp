@@ -88,6 +88,14 @@ constexpr int32_t kStatusBreakdown = -4;
 // Highest degree of the Chebyshev preconditioner (m - 1 gathers per application).
 constexpr int kChebMaxDegree = 8;
 
+// Threads of a gather block: up to 512 for a simulation alone (one block of
+// eight waves per CU holds a whole x-row of a 101-node grid in 101 x 5
+// tiles: every wave of the CU then marches in step with the others, where
+// two blocks of four waves drift apart, the older one issuing first), up to
+// 256 for batch members (two or more per CU).
+constexpr int kMaxBlockThreads = 512;
+constexpr int kMaxBatchThreads = 256;
+
 // Launch shape of the gather apply: a block owns a TX x TY column tile of
 // nodes and marches TZ planes in z.
 struct GatherShape {

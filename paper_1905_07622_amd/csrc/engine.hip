@@ -661,7 +661,8 @@ int Engine::dirupd(BatchArgs a, hipEvent_t e0, hipEvent_t e1, bool* done) {
     cap = per_cu * cus;
     dirupd_cap_smem_[f64 ? 0 : 1] = smem;
   }
-  if ((int)g.nwork > cap || smem > 160 * 1024) return FEM_OK;  // not every block at once: two kernels
+  // not every block at once, or blocks wider than the kernel's bounds: two kernels
+  if ((int)g.nwork > cap || smem > 160 * 1024 || g.nthreads > kMaxBatchThreads) return FEM_OK;
   if (bar_blocks_ < g.nwork) {  // (re)start the barrier: counter and flags at 0
     efree(bar_count_);
     bar_count_ = nullptr;

@@ -72,7 +72,7 @@ struct GatherArgs {
   const V* kc;     // per-element k
   V sa, sb;        // cubic: cm*h^3/216, ck*h/12 ; tetrahedra: cm*h^3/120, ck*h/6 ; general: cm, ck
   V Mc[8], Kc[8];  // general elements: class entries M[c], K[c]
-  V* sink;         // >= 256 scratch values: stores of lanes without a node land here
+  V* sink;         // >= kMaxBlockThreads scratch values: stores of lanes without a node land here
 };
 
 // 3x3 neighbourhood of one plane around a column: centre, x-/x+, y-/y+, and
@@ -554,7 +554,7 @@ __device__ inline void gather_tile(const GatherArgs<V>& ga, Pro pro, Epi epi, co
 
 // A gather of one solve: one block per tile (grid = ga.s.nblocks).
 template <typename V, int KIND, class Pro, class Epi>
-__global__ void __launch_bounds__(256) gather_kernel(GatherArgs<V> ga, Pro pro, Epi epi, Relay R) {
+__global__ void __launch_bounds__(kMaxBlockThreads) gather_kernel(GatherArgs<V> ga, Pro pro, Epi epi, Relay R) {
   gather_tile<V, KIND>(ga, pro, epi, R, xcd_work_item(blockIdx.x, ga.s.nblocks));
 }
 

@@ -21,12 +21,13 @@
 
 // Scratch of fem_heat_apply_noalloc, for callers that cannot allocate: the
 // element-by-element form's 4 N partial sums (N <= kNoallocMaxNodes) and a
-// 256-value sink for the gather's stores of lanes without a node.  One copy
+// sink for the gather's stores of lanes without a node (one value per thread
+// of a block).  One copy
 // per GPU, held until the process ends.  Host code never passes this name to
 // a kernel (on the host it is only a stand-in); it uses the device address
 // that hipGetSymbolAddress returns for the current device.
 constexpr size_t kNoallocMaxNodes = size_t(1) << 20;
-constexpr size_t kNoallocSink = 256;
+constexpr size_t kNoallocSink = femheat::kMaxBlockThreads;
 static __device__ __align__(256) double scratch[4 * kNoallocMaxNodes + kNoallocSink];
 
 namespace femheat {
@@ -96,7 +97,8 @@ int resident_blocks(int kind, bool fp32, int nthreads, size_t smem) {
 }
 
 // Launch shape of the gather: TX spans the x-row of nodes in as few equal
-// pieces of at most 64 as possible, TY fills the block to <= 256 threads.
+// pieces of at most 64 as possible, TY fills the block to <= 256 threads
+// (tile overrides of a simulation alone may take up to kMaxBlockThreads).
 // Unless given, TZ splits the columns of a simulation that has the GPU to
 // itself into as many z-chunks as the chip holds blocks at once
 // (`capacity`): the gather is latency-bound, so the launch should fill every
@@ -108,7 +110,8 @@ GatherShape choose_shape(const Geom& g, const fem_opts& o, int capacity) {
   GatherShape s{};
   const int px = g.px, py = g.py, pz = g.pz;
   int tx = o.tile_x > 0 ? o.tile_x : (px + (px + 63) / 64 - 1) / ((px + 63) / 64);
-  tx = std::max(1, std::min(tx, 256));
+  const int lim = capacity > 0 ? kMaxBlockThreads : kMaxBatchThreads;
+  tx = std::max(1, std::min(tx, lim));
   int ty;
   if (o.tile_y > 0) {
     ty = o.tile_y;
@@ -117,7 +120,7 @@ GatherShape choose_shape(const Geom& g, const fem_opts& o, int capacity) {
     const int nty = (py + tymax - 1) / tymax;
     ty = (py + nty - 1) / nty;
   }
-  ty = std::max(1, std::min(ty, 256 / tx));
+  ty = std::max(1, std::min(ty, lim / tx));
   // every thread stages at most kSlots entries of the plane and coefficient tiles
   auto fits = [](int a, int b) {
     const int nt = ((a * b + 63) / 64) * 64;
@@ -257,7 +260,7 @@ template GatherArgs<float> gather_args<float>(const fem_heat*, double, double);
 namespace {
 
 // One gather of one handle outside the time stepping (set-up, test hook);
-// `sink` (>= 256 values) replaces the handle's sink when given.
+// `sink` (>= kMaxBlockThreads values) replaces the handle's sink when given.
 template <typename V, class Pro, class Epi>
 int launch_gather(fem_heat* h, double cm, double ck, Pro pro, Epi epi, const Relay& R, V* sink = nullptr) {
   GatherArgs<V> ga = gather_args<V>(h, cm, ck);
@@ -421,6 +424,8 @@ int solver_init(fem_heat* h, const fem_grid* grid, const double* k_e, const doub
   h->kind = g.tet6 ? kElemTet6 : (h->cubic ? kElemCubic : kElemBox);
   HIP_TRY(hipSetDevice(h->opts.device));
   RC_TRY(noalloc_scratch_setup(h));
+  if (h->batched && h->opts.tile_x * std::max(h->opts.tile_y, 1) > kMaxBatchThreads)
+    return fail(h, FEM_EINVAL, "tile overrides of batch members and served simulations: tile_x * tile_y <= 256");
   {
     // a tile the autotuner recorded for this grid, precision, element class
     // and launch kind (alone or in a batch) replaces the rule
@@ -488,7 +493,7 @@ int solver_init(fem_heat* h, const fem_grid* grid, const double* k_e, const doub
   RC_TRY(dalloc(h, &h->d64[1], N));
   for (auto& p : h->pool) RC_TRY(dalloc(h, &p, N));
   if (h->nonzero_dirichlet) RC_TRY(dalloc(h, &h->lift64, N));
-  RC_TRY(dalloc(h, &h->sink, 256));
+  RC_TRY(dalloc(h, &h->sink, kMaxBlockThreads));
   h->n_partials = std::max({h->shape.nblocks, h->upd_blocks64, h->upd_blocks32, h->start_blocks});
   const size_t ncomp = one_red ? 4 : 1;  // the one-reduction direction kernel publishes four sums per block
   for (RelayCtx* c : {&h->outer, &h->inner})
@@ -599,7 +604,7 @@ int solver_apply(fem_heat* h, int32_t which, double dt, double theta, const doub
 // launch shapes for the autotuner
 
 bool shape_stages(const GatherShape& s) {
-  return s.tx >= 1 && s.ty >= 1 && s.tz >= 1 && s.tx * s.ty <= 256 &&
+  return s.tx >= 1 && s.ty >= 1 && s.tz >= 1 && s.tx * s.ty <= kMaxBlockThreads &&
          (s.tx + 2) * (s.ty + 2) <= kSlots * s.nthreads && (s.tx + 1) * (s.ty + 1) <= kSlots * s.nthreads;
 }
 
@@ -612,8 +617,9 @@ GatherShape shape_with_tile(const fem_heat* h, int tx, int ty, int tz) {
 }
 
 // Candidates: x pieces of the node row (1 to 4 equal pieces, and 16/32/64
-// wide), block heights that the staging scheme holds (the largest, the one
-// that splits the y-rows evenly, and half of it), and for each x-y tile a
+// wide), block heights that the staging scheme holds in 256 threads (and,
+// for a simulation alone, in 512: the largest, the one that splits the
+// y-rows evenly, and half of it), and for each x-y tile a
 // z-chunk length per target of resident blocks (1 to 4 per CU for a
 // simulation alone; 8 to 32 planes or the whole column for batch members).
 std::vector<GatherShape> tune_candidates(const fem_heat* h, int cus) {
@@ -632,8 +638,13 @@ std::vector<GatherShape> tune_candidates(const fem_heat* h, int cus) {
       if (o.tx == s.tx && o.ty == s.ty && o.tz == s.tz) return true;
     return false;
   };
+  std::vector<std::pair<int, int>> txl;  // (tx, thread limit)
   for (int tx : txs) {
-    const int tymax = std::max(1, 256 / tx);
+    txl.emplace_back(tx, kMaxBatchThreads);
+    if (!h->batched) txl.emplace_back(tx, kMaxBlockThreads);
+  }
+  for (auto [tx, lim] : txl) {
+    const int tymax = std::max(1, lim / tx);
     int fit = 0;
     for (int ty = std::min(tymax, py); ty >= 1; --ty) {
       const int nt = ((tx * ty + 63) / 64) * 64;
@@ -642,7 +653,7 @@ std::vector<GatherShape> tune_candidates(const fem_heat* h, int cus) {
         break;
       }
     }
-    if (fit == 0) continue;
+    if (fit == 0 || (lim > kMaxBatchThreads && tx * fit <= kMaxBatchThreads)) continue;
     const int even = (py + ((py + fit - 1) / fit) - 1) / ((py + fit - 1) / fit);
     std::vector<int> tys = {fit, even, std::max(1, even / 2)};
     for (int ty : tys) {
@@ -725,7 +736,7 @@ size_t handle_device_bytes(const fem_grid& grid, const fem_opts& opts, const fem
   if (opts.precond == FEM_PRECOND_CHEBYSHEV && opts.precision == FEM_FP64) bytes += 8 * 4 * N;  // s, chain
   // relay state and partials (at most max(tiles, update blocks) per buffer) and the sink
   const size_t tiles_bound = N / 32 + 1024;
-  bytes += 4 * (sizeof(Scalars) + 8 * tiles_bound * (one_red ? 4 : 1)) + 8 * 256;
+  bytes += 4 * (sizeof(Scalars) + 8 * tiles_bound * (one_red ? 4 : 1)) + 8 * kMaxBlockThreads;
   if (n_sensors > 0) bytes += 8 * (3 * (size_t)n_sensors + (size_t)std::max(nsteps, 1) * n_sensors);
   return bytes;
 }

@@ -193,7 +193,7 @@ def test_server_rejects_invalid_options_before_device_work(lib):
     assert fh.fem_server_submit(None, r)[0] == fh.FEM_EINVAL
 
 
-@pytest.mark.parametrize("tile", [(128, 2, 4), (1, 64, 4), (200, 0, 0), (0, 4, 0), (257, 1, 1), (64, 5, 1)])
+@pytest.mark.parametrize("tile", [(128, 2, 4), (1, 64, 4), (200, 0, 0), (0, 4, 0), (257, 1, 1), (64, 9, 1), (513, 1, 1)])
 def test_create_rejects_tiles_the_gather_cannot_stage(lib, tile):
     """Tile overrides whose (tx+2)(ty+2) plane tile needs more than two staging
     slots per thread (or out of range) are refused before any device work."""

@@ -97,3 +97,42 @@ def test_tune_rejects_bad_arguments(gpu):
         assert fh.fem_heat_tune(h.h, -1.0, 1.0)[0] == fh.FEM_EINVAL
         assert fh.fem_heat_tune(h.h, 1e-3, 2.0)[0] == fh.FEM_EINVAL
         assert fh.fem_heat_tune(h.h, 1e-3, 1.0, 0x8)[0] == fh.FEM_EINVAL
+
+
+@pytest.mark.parametrize("precision", [fh.FEM_FP64, fh.FEM_FP32_FP64DOT])
+@pytest.mark.parametrize("tile", [(41, 12, 5), (101, 5, 9), (37, 13, 4)])
+def test_wide_blocks_of_a_simulation_alone(gpu, precision, tile):
+    """Blocks of up to 512 threads (eight waves), which a simulation alone may
+    take: the run against the oracle (FP64 locked to its own counts at 1e-10,
+    mixed against the FP64 oracle at 1e-5), ragged tiles at every edge and a
+    block with idle lanes (41 x 12 = 492 of 512 threads); the operator apply
+    with such a tile is bit-identical to the default tile's."""
+    p = wl.random_problem(40, 23, 17, seed=71, nsteps=4, rtol=1e-10) if tile[0] != 101 else \
+        wl.lognormal_cube(100, seed=2, nsteps=2)
+    with fh.Heat.from_problem(p, precision=precision, tile=tile, timing=True) as h:
+        out = h.run(p.T0, dt=p.dt, theta=p.theta, nsteps=p.nsteps, rtol=p.rtol, save_every=1)
+        st = h.stats()
+        x = np.random.default_rng(3).standard_normal(p.n_nodes)
+        y_wide = h.apply(fh.FEM_OP_A, x, dt=p.dt, theta=p.theta)
+    assert [st["tile_x"], st["tile_y"], st["tile_z"]] == list(tile)
+    assert out["status"] == fh.FEM_OK
+    if precision == fh.FEM_FP64:
+        ref = oracle.run(p, save_every=1, locked_iters=out["iters"], nthreads=16)
+        gate = 1e-10
+    else:
+        ref = oracle.run(p, save_every=1, nthreads=16)
+        gate = 1e-5
+    errs = [rel_l2(out["T_saved"][n], ref["T_saved"][n]) for n in range(p.nsteps)]
+    say(f"  tile {tile} ({st['grid_blocks']} blocks): iters {list(out['iters'])}, rel L2 max {max(errs):.2e}")
+    assert max(errs) <= gate
+    assert np.all(out["relres"] <= p.rtol)
+    with fh.Heat.from_problem(p, precision=precision) as h0:
+        y_rule = h0.apply(fh.FEM_OP_A, x, dt=p.dt, theta=p.theta)
+    assert np.array_equal(y_wide, y_rule)
+
+
+def test_wide_blocks_refused_for_batch_members(gpu):
+    p = wl.random_problem(12, 10, 9, seed=72, nsteps=1)
+    st, _ = fh.run_batch([p, p], tile=(41, 12, 5), check=False)
+    assert st == fh.FEM_EINVAL
+    assert "256" in fh.fem_last_error(None)
