@@ -167,15 +167,17 @@ def bench_mixed(args, torch, p, k, rc, T0, T_fp64):
     stream = torch.cuda.current_stream().cuda_stream
     h = fh.Heat(p.nx, p.ny, p.nz, p.hx, p.hy, p.hz, k, rc, dirichlet_mask=p.dirichlet_mask,
                 flux_mask=p.flux_mask, flux=p.flux, precision=fh.FEM_FP32_FP64DOT, device_ptrs=True,
-                stream=stream, one_kernel=args.pcg_form == "one-kernel")
+                stream=stream, one_kernel=args.pcg_form == "one-kernel",
+                tune_cache=getattr(args, "tune_cache_path", None))
     run_kw = dict(dt=p.dt, theta=p.theta, nsteps=p.nsteps, rtol=p.rtol)
+    tuned = h.tune(dt=p.dt, theta=p.theta) if getattr(args, "tune_cache_path", None) else None
     rate, its, last = _timed_runs(h, T0, run_kw, 2)
     h.close()
     diff = torch.linalg.vector_norm(last["T_final"] - T_fp64) / torch.linalg.vector_norm(T_fp64)
     print(f"mixed: {rate * p.n_nodes:.1f} MDOF*iter/s", file=sys.stderr, flush=True)
     return {"workload": "the headline workload in the mixed form", "value": round(rate * p.n_nodes, 1),
             "unit": "MDOF*iter/s", "iterations_per_run": int(its),
-            "sweeps_per_step_max": int(last["refine_sweeps"].max()),
+            "sweeps_per_step_max": int(last["refine_sweeps"].max()), "autotuned": tuned,
             "rel_l2_vs_fp64_final_field": float(diff)}
 
 

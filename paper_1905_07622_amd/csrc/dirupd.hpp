@@ -146,7 +146,7 @@ struct UpdHalf {
 };
 
 template <int KIND, typename V>
-__global__ void __launch_bounds__(256, 2)
+__global__ void __launch_bounds__(kMaxBlockThreads)
     dirupd_kernel(GatherArgs<V> ga, ProDirection<V> pro, Relay R, UpdHalf<V> u, const V* pinv, GridBar gb,
                   uint32_t lds_base) {
   const uint32_t logical = xcd_work_item(blockIdx.x, gridDim.x);

@@ -504,6 +504,12 @@ int Engine::compose() {
   }
   std::vector<uint2> tab;
   build_layout(std::vector<char>(n, 1), tab, full_);
+  // the batched kernels are built for blocks of at most 256 threads (the
+  // wider blocks of a simulation alone run only in the one-simulation kernels)
+  if (multi_)
+    for (int gi = 0; gi < full_.ngroups; ++gi)
+      if (full_.groups[gi].nthreads > (uint32_t)kMaxBatchThreads)
+        return fail(h_, FEM_EINVAL, "a batched launch with blocks of more than 256 threads");
   lay_ = full_;
   live_count_ = n;
   if (multi_) {
@@ -661,8 +667,7 @@ int Engine::dirupd(BatchArgs a, hipEvent_t e0, hipEvent_t e1, bool* done) {
     cap = per_cu * cus;
     dirupd_cap_smem_[f64 ? 0 : 1] = smem;
   }
-  // not every block at once, or blocks wider than the kernel's bounds: two kernels
-  if ((int)g.nwork > cap || smem > 160 * 1024 || g.nthreads > kMaxBatchThreads) return FEM_OK;
+  if ((int)g.nwork > cap || smem > 160 * 1024) return FEM_OK;  // not every block at once: two kernels
   if (bar_blocks_ < g.nwork) {  // (re)start the barrier: counter and flags at 0
     efree(bar_count_);
     bar_count_ = nullptr;

@@ -97,26 +97,29 @@ int resident_blocks(int kind, bool fp32, int nthreads, size_t smem) {
 }
 
 // Launch shape of the gather: TX spans the x-row of nodes in as few equal
-// pieces of at most 64 as possible, TY fills the block to <= 256 threads
-// (tile overrides of a simulation alone may take up to kMaxBlockThreads).
-// Unless given, TZ splits the columns of a simulation that has the GPU to
-// itself into as many z-chunks as the chip holds blocks at once
-// (`capacity`): the gather is latency-bound, so the launch should fill every
-// CU to its occupancy limit in a single round -- a second, partial round of
-// blocks costs a whole extra block time -- and longer z-marches pay the
-// start-up of the plane pipeline less often.  capacity <= 0 selects the rule
-// for members of a batch.
+// pieces as possible, TY fills the block: pieces of at most 128 and blocks of
+// at most 512 threads for a simulation alone (one block of eight waves per
+// CU), of at most 64 and 256 threads for a batch member.  Unless given, TZ
+// splits the columns of a simulation that has the GPU to itself into as
+// many z-chunks as the chip holds blocks at once (`capacity`): the gather is
+// latency-bound, so the launch should fill every CU to its occupancy limit
+// in a single round -- a second, partial round of blocks costs a whole
+// extra block time -- and longer z-marches pay the start-up of the plane
+// pipeline less often.  capacity <= 0 selects the rule for members of a
+// batch.
 GatherShape choose_shape(const Geom& g, const fem_opts& o, int capacity) {
   GatherShape s{};
   const int px = g.px, py = g.py, pz = g.pz;
-  int tx = o.tile_x > 0 ? o.tile_x : (px + (px + 63) / 64 - 1) / ((px + 63) / 64);
-  const int lim = capacity > 0 ? kMaxBlockThreads : kMaxBatchThreads;
+  const bool alone = capacity > 0;
+  const int piece = alone ? 128 : 64;
+  int tx = o.tile_x > 0 ? o.tile_x : (px + (px + piece - 1) / piece - 1) / ((px + piece - 1) / piece);
+  const int lim = alone ? kMaxBlockThreads : kMaxBatchThreads;
   tx = std::max(1, std::min(tx, lim));
   int ty;
   if (o.tile_y > 0) {
     ty = o.tile_y;
   } else {
-    const int tymax = std::max(1, 256 / tx);
+    const int tymax = std::max(1, lim / tx);
     const int nty = (py + tymax - 1) / tymax;
     ty = (py + nty - 1) / nty;
   }
@@ -452,8 +455,10 @@ int solver_init(fem_heat* h, const fem_grid* grid, const double* k_e, const doub
     HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, h->opts.device));
     // at most two blocks per CU: beyond that, the shorter z-marches pay the
     // plane pipeline's fill more often than the extra blocks hide latency
-    // (measured for the FP32 gather, which could hold four)
-    const int per_cu = std::min(2, resident_blocks(h->kind, fp32, probe.nthreads, probe.smem_bytes(fp32 ? 4 : 8)));
+    // (measured for the FP32 gather, which could hold four); one block of
+    // eight waves (blocks sharing a CU drift apart, the older one first)
+    const int per_cu = std::min(probe.nthreads > kMaxBatchThreads ? 1 : 2,
+                                resident_blocks(h->kind, fp32, probe.nthreads, probe.smem_bytes(fp32 ? 4 : 8)));
     h->shape = choose_shape(g, so, h->batched ? 0 : std::max(1, cus) * per_cu);
     h->capacity = std::max(1, cus) * per_cu;
   }
@@ -624,7 +629,11 @@ GatherShape shape_with_tile(const fem_heat* h, int tx, int ty, int tz) {
 // simulation alone; 8 to 32 planes or the whole column for batch members).
 std::vector<GatherShape> tune_candidates(const fem_heat* h, int cus) {
   std::vector<GatherShape> out;
-  out.push_back(h->shape);  // the rule's (or the cached) shape first
+  // first the shape the launch kind gets without tuning: the handle's own
+  // (the rule's, or the cached one) for a simulation alone, the batch rule's
+  // for a batch member (a handle alone may have blocks wider than a batched
+  // launch takes)
+  out.push_back(h->batched ? choose_shape(h->g, h->opts, 0) : h->shape);
   const int px = h->g.px, py = h->g.py, pz = h->g.pz;
   std::vector<int> txs;
   for (int pieces = 1; pieces <= 4; ++pieces) {
