@@ -106,14 +106,15 @@ int resident_blocks(int kind, bool fp32, int nthreads, size_t smem) {
 // in a single round -- a second, partial round of blocks costs a whole
 // extra block time -- and longer z-marches pay the start-up of the plane
 // pipeline less often.  capacity <= 0 selects the rule for members of a
-// batch.
-GatherShape choose_shape(const Geom& g, const fem_opts& o, int capacity) {
+// batch; wide = false the narrow blocks for a simulation alone too (the
+// rule of a grid too small to give every CU a wide block).
+GatherShape choose_shape(const Geom& g, const fem_opts& o, int capacity, bool wide = true) {
   GatherShape s{};
   const int px = g.px, py = g.py, pz = g.pz;
   const bool alone = capacity > 0;
-  const int piece = alone ? 128 : 64;
+  const int piece = alone && wide ? 128 : 64;
   int tx = o.tile_x > 0 ? o.tile_x : (px + (px + piece - 1) / piece - 1) / ((px + piece - 1) / piece);
-  const int lim = alone ? kMaxBlockThreads : kMaxBatchThreads;
+  const int lim = alone && (wide || o.tile_x > 0) ? kMaxBlockThreads : kMaxBatchThreads;
   tx = std::max(1, std::min(tx, lim));
   int ty;
   if (o.tile_y > 0) {
@@ -448,19 +449,30 @@ int solver_init(fem_heat* h, const fem_grid* grid, const double* k_e, const doub
         }
       }
     }
-    // the x-y tiling does not depend on the capacity: size the block first
-    const GatherShape probe = choose_shape(g, so, 1);
     const bool fp32 = h->opts.precision == FEM_FP32_FP64DOT;
     int cus = 0;
     HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, h->opts.device));
-    // at most two blocks per CU: beyond that, the shorter z-marches pay the
-    // plane pipeline's fill more often than the extra blocks hide latency
-    // (measured for the FP32 gather, which could hold four); one block of
-    // eight waves (blocks sharing a CU drift apart, the older one first)
-    const int per_cu = std::min(probe.nthreads > kMaxBatchThreads ? 1 : 2,
-                                resident_blocks(h->kind, fp32, probe.nthreads, probe.smem_bytes(fp32 ? 4 : 8)));
-    h->shape = choose_shape(g, so, h->batched ? 0 : std::max(1, cus) * per_cu);
-    h->capacity = std::max(1, cus) * per_cu;
+    cus = std::max(1, cus);
+    auto rule = [&](bool wide, int* capacity) {
+      // the x-y tiling does not depend on the capacity: size the block first
+      const GatherShape probe = choose_shape(g, so, 1, wide);
+      // at most two blocks per CU: beyond that, the shorter z-marches pay the
+      // plane pipeline's fill more often than the extra blocks hide latency
+      // (measured for the FP32 gather, which could hold four); one block of
+      // eight waves (blocks sharing a CU drift apart, the older one first)
+      const int per_cu = std::min(probe.nthreads > kMaxBatchThreads ? 1 : 2,
+                                  resident_blocks(h->kind, fp32, probe.nthreads, probe.smem_bytes(fp32 ? 4 : 8)));
+      *capacity = cus * std::max(per_cu, 1);
+      return choose_shape(g, so, h->batched ? 0 : *capacity, wide);
+    };
+    int cap = 0;
+    h->shape = rule(true, &cap);
+    // wide blocks only where they give (nearly) every CU one: a small grid
+    // keeps narrow blocks, twice as many (measured at 49^3 nodes: 65 wide
+    // blocks 13.0 us, 130 narrow ones 10.7 us per direction gather)
+    if (!h->batched && so.tile_x == 0 && h->shape.nthreads > kMaxBatchThreads && 10 * h->shape.ntiles < 9u * cus)
+      h->shape = rule(false, &cap);
+    h->capacity = cap;
   }
   {
     const GatherShape& s = h->shape;

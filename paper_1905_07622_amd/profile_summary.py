@@ -70,6 +70,31 @@ def working_durations(d: str):
     return out
 
 
+def dispatch_gaps(d: str):
+    """Idle time of the device between consecutive dispatches (any stream, in
+    start order; overlapping dispatches count no gap): gaps under 50 us are
+    the launch-to-launch cost inside a run, longer ones host phases (set-up,
+    a host round trip, the end of the program)."""
+    try:
+        rows = list(csv.DictReader(open(find_csv(d, "kernel_trace.csv"))))
+    except FileNotFoundError:
+        return None
+    iv = sorted((int(r["Start_Timestamp"]), int(r["End_Timestamp"])) for r in rows)
+    gaps, end = [], None
+    for s0, e0 in iv:
+        if end is not None:
+            gaps.append(max(0, s0 - end) / 1e3)
+        end = e0 if end is None else max(end, e0)
+    if not gaps:
+        return None
+    short = sorted(g for g in gaps if g < 50.0)
+    return {"dispatches": len(iv), "short_gaps": len(short),
+            "short_gap_median_us": short[len(short) // 2] if short else 0.0,
+            "short_gap_mean_us": sum(short) / len(short) if short else 0.0,
+            "short_gap_total_ms": sum(short) / 1e3,
+            "busy_ms": sum(e0 - s0 for s0, e0 in iv) / 1e6}
+
+
 def stats(d: str, out: str, commands):
     rows = list(csv.DictReader(open(find_csv(d, "kernel_stats.csv"))))
     work = working_durations(d)
@@ -86,6 +111,12 @@ def stats(d: str, out: str, commands):
         lines.append(f"{name[:70]:70s} {int(r['Calls']):7d} {float(r['AverageNs']) / 1e3:9.3f} "
                      f"{float(r['MinNs']) / 1e3:8.3f} {float(r['MaxNs']) / 1e3:8.3f} {float(r['Percentage']):7.2f} "
                      f"{len(w):8d} {wa}")
+    g = dispatch_gaps(d)
+    if g:
+        lines += ["", f"dispatch gaps (device idle between consecutive dispatches, {g['dispatches']} dispatches): "
+                      f"{g['short_gaps']} gaps under 50 us, median {g['short_gap_median_us']:.2f} us, "
+                      f"mean {g['short_gap_mean_us']:.2f} us, total {g['short_gap_total_ms']:.2f} ms "
+                      f"against {g['busy_ms']:.1f} ms of dispatches"]
     with open(out, "w") as f:
         f.write("\n".join(lines) + "\n")
     print("\n".join(lines))
