@@ -344,7 +344,7 @@ def bench_batched(args, torch):
            "seconds_of_three_runs": [round(t, 3) for t in times],
            "nodes_per_sim": probs[0].n_nodes, "iterations_per_sim_mean": float(np.mean([r["total_iters"] for r in res])),
            "autotuned_member_tile": tuned,
-           "concurrent_batches": 3 if len(probs) >= 48 else (2 if len(probs) >= 16 else 1)}
+           "concurrent_batches": max(1, min(3, len(probs) // 16, sum(p.n_nodes for p in probs) >> 21))}
     plain = {}
     refs = {}
     for rtol in (1e-8,) + tuple(args.loose_rtols):

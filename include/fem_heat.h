@@ -198,10 +198,10 @@ typedef struct {
   int32_t batch_groups;   /* fem_heat_run_batch: run the simulations as this many batches at once,
                              dealt round-robin, each on its own stream and host thread, so that one
                              batch's last iterations (its slowest members) overlap the others'
-                             work; results do not change.  0 = automatic (1; 2 from 16
-                             simulations on, 3 from 48); with a caller's stream the batches
-                             start after its earlier work.  Handles and servers ignore it
-                             (server lanes already overlap) */
+                             work; results do not change.  0 = automatic (one batch per 16
+                             simulations and per 2^21 nodes in all, at most 3, at least 1);
+                             with a caller's stream the batches start after its earlier work.
+                             Handles and servers ignore it (server lanes already overlap) */
 } fem_opts;
 
 /* Outputs of a run (inputs marked "in").  Every pointer may be NULL.

@@ -259,12 +259,18 @@ int fem_heat_run_batch(const fem_request* reqs, int32_t n, const fem_opts* opts,
   // its slowest member (few blocks), the others fill the device.  A
   // simulation's results do not depend on its batch, so the grouping changes
   // no result.
-  // Automatic: two batches from 16 simulations on, three from 48 (measured
-  // on 64 x 48^3 in the mixed form, medians of three: 92 solves/s as one
-  // batch, 105 as two, 108 as three, 92 as four, where the streams with the
-  // caller's outnumber the four hardware queues a process gets by default).
-  const int G = std::max(
-      1, std::min<int>(n, o.batch_groups > 0 ? o.batch_groups : (n >= 48 ? 3 : (n >= 16 ? 2 : 1))));
+  // Automatic: one batch per 16 simulations and per 2^21 nodes, at most
+  // three.  Measured on 64 x 48^3 in the mixed form (7.5M nodes), medians of
+  // three: 92 solves/s as one batch, 105 as two, 108 as three, 92 as four
+  // (the streams with the caller's then outnumber the four hardware queues a
+  // process gets by default).  Batches of small simulations are bound by
+  // launches, not by their tails, and stay whole: 32 x 19k nodes ran 20%
+  // slower as two.
+  uint64_t nodes = 0;
+  for (int32_t i = 0; i < n; ++i)
+    nodes += (uint64_t)(reqs[i].grid.nx + 1) * (uint64_t)(reqs[i].grid.ny + 1) * (uint64_t)(reqs[i].grid.nz + 1);
+  const int auto_g = (int)std::min<uint64_t>({3u, (uint64_t)n / 16u, nodes >> 21});
+  const int G = std::max(1, std::min<int>(n, o.batch_groups > 0 ? o.batch_groups : auto_g));
   hipStream_t caller = reinterpret_cast<hipStream_t>(o.hip_stream);
   std::vector<hipStream_t> gs((size_t)G, nullptr);
   std::vector<bool> own((size_t)G, false);
