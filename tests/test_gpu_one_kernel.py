@@ -31,6 +31,8 @@ def problems():
                           dirichlet_mask=(1 << wl.FACE_ZM) | (1 << wl.FACE_XP),
                           dirichlet_value=[0, 1.5, 0, 0, -0.5, 0]),
         wl.two_phase_sphere_cube().replace(nsteps=6),
+        # the paper's element (six tetrahedra per box)
+        wl.random_problem(12, 10, 14, seed=65, nsteps=4, rtol=1e-10).replace(element=fh.FEM_ELEM_TET6),
     ]
 
 
