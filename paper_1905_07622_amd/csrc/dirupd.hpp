@@ -30,17 +30,19 @@ namespace femheat {
 // memory channel: measured, that slowed the march of the blocks still
 // gathering by half and the barrier by microseconds.)  `count` and the flags
 // only grow (target = the arrivals of every earlier launch plus this grid),
-// so nothing is reset between launches.  A wait that runs out (all blocks of
-// the launch are resident, so it should not) sets `fail`, and the blocks
-// leave without the update: the host reports the run as failed.
+// so nothing is reset between launches.  A wait that runs out after
+// `spin_limit` polls (all blocks of the launch are resident, so it should
+// not) sets `fail`, and the blocks leave without the update: the host stops
+// the run at the end of the chunk and reports it as failed.
 struct GridBar {
   unsigned long long* count;
   unsigned long long* flags;  // one per block, kBarFlagStride apart
   int32_t* fail;
   unsigned long long target;
+  uint32_t spin_limit;
 };
 
-constexpr uint32_t kBarSpinLimit = 1u << 20;
+constexpr uint32_t kBarSpinLimit = 1u << 20;  // about a second of polls
 constexpr uint32_t kBarFlagStride = 16;  // 128 bytes: one flag per cache line
 
 // Keeps, at the block's own nodes, q (and r, P^-1, and in FP32 also d and x)
@@ -122,8 +124,8 @@ __device__ inline bool grid_barrier(const GridBar& gb) {
     int good = 1;
     uint32_t spins = 0;
     while (__hip_atomic_load(gb.flags + kBarFlagStride * blockIdx.x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < gb.target) {
-      if (++spins > kBarSpinLimit) {
-        __hip_atomic_store(gb.fail, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      if (++spins > gb.spin_limit) {
+        __hip_atomic_store(gb.fail, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);  // host memory
         good = 0;
         break;
       }

@@ -29,6 +29,7 @@
 // batch of one.  Between epochs, finished simulations leave the batch.
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <memory>
 #include <type_traits>
@@ -112,11 +113,14 @@ class Engine {
     R_ = o.replace_every;
     dirupd_ = false;
   }
-  void allow_one_kernel(bool on) { dirupd_ = on && (opts_.flags & FEM_ONE_KERNEL) != 0; }
+  void allow_one_kernel(bool on) {
+    dirupd_ = on && (opts_.flags & FEM_ONE_KERNEL) != 0;
+    if (const char* v = std::getenv("FEMHEAT_BARRIER_SPIN_LIMIT")) bar_spin_ = (uint32_t)std::strtoul(v, nullptr, 10);
+  }
   ~Engine() {
     (void)hipStreamSynchronize(stream_);
     efree(bar_count_);
-    efree(bar_fail_);
+    if (bar_fail_host_) (void)hipHostFree(bar_fail_host_);
     efree(sd_dev_);
     efree(tab_dev_);
     for (auto& p : sd_host_)
@@ -248,8 +252,14 @@ class Engine {
   bool dirupd_ = false;
   unsigned long long* bar_count_ = nullptr;
   uint32_t bar_blocks_ = 0;
+  // the failure flag in mapped pinned host memory: the host reads it after
+  // every chunk's decide without a copy (bar_fail_: its device address)
+  int32_t* bar_fail_host_ = nullptr;
   int32_t* bar_fail_ = nullptr;
   unsigned long long bar_total_ = 0;
+  // polls before a barrier wait gives up: kBarSpinLimit, or
+  // FEMHEAT_BARRIER_SPIN_LIMIT from the environment (tests of the failure path)
+  uint32_t bar_spin_ = kBarSpinLimit;
   int dirupd_cap_[2] = {-1, -1};  // blocks the device holds at once (FP64, FP32), -1: not yet asked
   size_t dirupd_cap_smem_[2] = {0, 0};
   SimDev* sd_host_[2] = {nullptr, nullptr};  // pinned staging, used alternately
@@ -674,9 +684,13 @@ int Engine::dirupd(BatchArgs a, hipEvent_t e0, hipEvent_t e1, bool* done) {
     bar_blocks_ = 0;
     const size_t words = (size_t)kBarFlagStride * (1 + g.nwork);
     RC_TRY(ealloc(&bar_count_, words));
-    if (!bar_fail_) RC_TRY(ealloc(&bar_fail_, 1));
+    if (!bar_fail_host_) {
+      HIP_TRY(hipHostMalloc(reinterpret_cast<void**>(&bar_fail_host_), sizeof(int32_t),
+                            hipHostMallocMapped | hipHostMallocCoherent));
+      *bar_fail_host_ = 0;
+      HIP_TRY(hipHostGetDevicePointer(reinterpret_cast<void**>(&bar_fail_), bar_fail_host_, 0));
+    }
     HIP_TRY(hipMemsetAsync(bar_count_, 0, words * sizeof(unsigned long long), stream_));
-    HIP_TRY(hipMemsetAsync(bar_fail_, 0, sizeof(int32_t), stream_));
     bar_blocks_ = g.nwork;
     bar_total_ = 0;
   }
@@ -692,7 +706,7 @@ int Engine::dirupd(BatchArgs a, hipEvent_t e0, hipEvent_t e1, bool* done) {
     pinv = s.pinv32;
   }
   bar_total_ += g.nwork;
-  GridBar gb{bar_count_, bar_count_ + kBarFlagStride, bar_fail_, bar_total_};
+  GridBar gb{bar_count_, bar_count_ + kBarFlagStride, bar_fail_, bar_total_, bar_spin_};
   uint32_t lb = lds_base;
   void* kargs[] = {&ga, &pro, &R, &u, &pinv, &gb, &lb};
   if (e0) HIP_TRY(hipEventRecord(e0, stream_));
@@ -709,17 +723,15 @@ int Engine::dirupd(BatchArgs a, hipEvent_t e0, hipEvent_t e1, bool* done) {
 }
 
 // A grid-wide barrier that ran out of time leaves its launch's results void:
-// the run fails, and the counter starts over.
+// the run fails (checked after every chunk's decide, when the stream has
+// drained up to it), and the counter starts over.
 int Engine::check_barrier() {
   fem_heat* h = h_;
-  if (!bar_fail_) return FEM_OK;
-  int32_t f = 0;
-  HIP_TRY(hipMemcpyAsync(&f, bar_fail_, sizeof(f), hipMemcpyDeviceToHost, stream_));
+  if (!bar_fail_host_ || *reinterpret_cast<volatile int32_t*>(bar_fail_host_) == 0) return FEM_OK;
   HIP_TRY(hipStreamSynchronize(stream_));
-  if (!f) return FEM_OK;
   HIP_TRY(hipMemsetAsync(bar_count_, 0, (size_t)kBarFlagStride * (1 + bar_blocks_) * sizeof(unsigned long long), stream_));
-  HIP_TRY(hipMemsetAsync(bar_fail_, 0, sizeof(int32_t), stream_));
   HIP_TRY(hipStreamSynchronize(stream_));
+  *bar_fail_host_ = 0;
   bar_total_ = 0;
   return fail(h, FEM_EDEVICE,
               "a grid-wide barrier of the one-kernel iteration timed out (other work on the device held "
@@ -931,6 +943,7 @@ int Engine::pcg(int first_chunk) {
     const bool launch_next =
         !inner && !mixed_ && !cheb_ && act_.size() == 1 && act_[0]->step + 1 < act_[0]->rq.nsteps;
     RC_TRY(decide(inner, j + k, launch_next));
+    if (dirupd_) RC_TRY(check_barrier());  // a failed barrier left this chunk's results void
     bool all_done = true;
     int most = j;
     for (size_t q = 0; q < act_.size(); ++q) {

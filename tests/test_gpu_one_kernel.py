@@ -85,3 +85,23 @@ def test_headline_grid_first_steps_locked(gpu):
     mixed, _ = _run(p, precision=fh.FEM_FP32_FP64DOT)
     free = oracle.run(p, save_every=1, nthreads=16)
     assert max(rel_l2(mixed["T_saved"][n], free["T_saved"][n]) for n in range(3)) <= 1e-5
+
+
+def test_barrier_timeout_fails_the_run_and_the_handle_recovers(gpu, monkeypatch):
+    """A grid-barrier wait made to give up at once (a spin limit of 0 set from
+    the host): every kernel still exits, the run stops with FEM_EDEVICE at
+    the end of its first chunk instead of iterating on void results, and
+    the next run on the same handle, with the normal limit, matches the
+    two-kernel form."""
+    p = problems()[3]
+    two, _ = _run(p, one_kernel=False)
+    with fh.Heat.from_problem(p, one_kernel=True) as h:
+        monkeypatch.setenv("FEMHEAT_BARRIER_SPIN_LIMIT", "0")
+        bad = h.run(p.T0, dt=p.dt, theta=p.theta, nsteps=p.nsteps, rtol=p.rtol, check=False)
+        assert bad["status"] == fh.FEM_EDEVICE
+        assert "barrier" in fh.fem_last_error(h.h)
+        monkeypatch.delenv("FEMHEAT_BARRIER_SPIN_LIMIT")
+        good = h.run(p.T0, dt=p.dt, theta=p.theta, nsteps=p.nsteps, rtol=p.rtol)
+    assert good["status"] == fh.FEM_OK
+    assert np.abs(good["iters"].astype(int) - two["iters"].astype(int)).max() <= 1
+    assert rel_l2(good["T_final"], two["T_final"]) <= 1e-10
