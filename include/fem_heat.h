@@ -278,7 +278,7 @@ int fem_heat_apply(fem_heat *h, int32_t which, double dt, double theta, const do
  * allocation, copy, event or synchronisation; the caller synchronises the
  * stream before reading y.  The kernels' scratch (the element-by-element
  * form's 4 N partial sums and the gather's sink for lanes without a node) is
- * a static array of the library, one per GPU (32 MiB + 2 KiB, held until the
+ * a static array of the library, one per GPU (32 MiB + 4 KiB, held until the
  * process ends): the element-by-element form takes at most 2^20 nodes
  * (FEM_EINVAL beyond).  Every call on one GPU shares that array, so calls
  * that overlap on one GPU (two streams, two threads) race; calls in one
