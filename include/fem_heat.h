@@ -322,13 +322,18 @@ int fem_heat_run_batch(const fem_request *reqs, int32_t n, const fem_opts *opts,
 
 /* ---- serving: continuous batching of forward simulations ------------------
  *
- * A server owns one HIP stream and a worker thread that advances every
- * admitted simulation one time step per epoch with the batched launches of
- * fem_heat_run_batch.  Submitted requests wait in a FIFO queue; at each epoch
- * boundary finished simulations retire (outputs written, device memory
- * released, completion stamped) and queued ones are admitted in order while
+ * A server groups requests into size classes (the binary order of magnitude
+ * of their node count); each class has a lane, a worker thread with its own
+ * HIP stream, that advances every admitted simulation of the class one time
+ * step per epoch with the batched launches of fem_heat_run_batch, so the
+ * classes run concurrently and a small request never waits for the epochs of
+ * a large one.  Submitted requests wait in one FIFO queue; at each of its
+ * epoch boundaries a lane retires its finished simulations (outputs written,
+ * device memory released to the server's stream-ordered pool, completion
+ * stamped) and admits queued requests of its class in arrival order while
  * their device footprint fits the free part of the HBM budget and a slot is
- * free (the head of the queue is never overtaken).  An admitted simulation
+ * free (a request that does not fit blocks every later one, so large
+ * requests cannot starve).  An admitted simulation
  * keeps its whole PCG state resident until it finishes, and joins the
  * launches at the next epoch while the others continue: its results are
  * bit-identical to those of a batch holding it alone.  The use case is the
