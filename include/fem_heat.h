@@ -247,7 +247,7 @@ typedef struct {
  * coefficients change between solves).  Validates (FEM_EINVAL): nx,ny,nz >= 1,
  * fewer than 2^29 nodes, h* > 0 and finite, k_e >= 0 and finite, rho*c_e > 0 and finite, masks in 6
  * bits and disjoint, finite boundary values.  Copies k_e, rho*c_e and the
- * schedule to the device, builds the load vector F (a1 kernel).  opts may be
+ * schedule to the device, builds the load vector F.  opts may be
  * NULL (defaults).  On success *out owns the device state. */
 int fem_heat_create(const fem_grid *grid, const double *k_e, const double *rhoc_e,
                     const fem_bc *bc, const fem_opts *opts, fem_heat **out);

@@ -126,7 +126,7 @@ __host__ __device__ inline int dir_out(const BatchArgs& a) { return (a.j + 1) & 
 
 // ---- gather roles: operator, prologue, epilogue and relay of each gather ----
 
-struct RoleRhs {  // b = L T^{n-1} + dt*s_n*F, with b^T P^-1 b (a2)
+struct RoleRhs {  // b = L T^{n-1} + dt*s_n*F, with b^T P^-1 b
   using V = double;
   using Pro = ProPlain<double>;
   using Epi = EpiRhs<double>;
@@ -136,7 +136,7 @@ struct RoleRhs {  // b = L T^{n-1} + dt*s_n*F, with b^T P^-1 b (a2)
   static __host__ __device__ Relay relay(const SimDev& s, const BatchArgs& a) { return outer_relay(s, a, M_RHS, true); }
 };
 
-struct RoleInit {  // x0 by the guess rule, r = b - A x0, r^T P^-1 r (a3)
+struct RoleInit {  // x0 by the guess rule, r = b - A x0, r^T P^-1 r
   using V = double;
   using Pro = ProGuess<double>;
   using Epi = EpiResidual<double>;
@@ -186,7 +186,7 @@ struct RoleInitNext {
 };
 
 template <typename V>
-struct RoleDir;  // d = P^-1 r + beta d, q = A d, d^T q (a6 + a4); deferred x += alpha d_old (a5)
+struct RoleDir;  // d = P^-1 r + beta d, q = A d, d^T q; deferred x += alpha d_old
 
 template <>
 struct RoleDir<double> {
@@ -215,7 +215,7 @@ struct RoleDir<float> {
 };
 
 template <typename V>
-struct RoleRepl;  // residual replacement: x += alpha d, r = b - A x (a5, i mod 50 == 0)
+struct RoleRepl;  // residual replacement: x += alpha d, r = b - A x (i mod 50 == 0)
 
 template <>
 struct RoleRepl<double> {
@@ -249,7 +249,7 @@ struct RoleRepl<float> {
 __host__ __device__ inline double* rbuf(const SimDev& s, int k) { return (k & 1) ? s.r64b : s.r64; }
 __host__ __device__ inline double* qbuf(const SimDev& s, int k) { return (k & 1) ? s.q64b : s.q64; }
 
-struct RoleFused {  // (r -= alpha q, x += alpha d_old,) d = P^-1 r + beta d, q = A d, four sums (a4-a6)
+struct RoleFused {  // (r -= alpha q, x += alpha d_old,) d = P^-1 r + beta d, q = A d, four sums
   using V = double;
   using Pro = ProFused<double>;
   using Epi = EpiQ<double>;
@@ -313,7 +313,7 @@ struct RoleReplFused32 {  // e += alpha d, r = rhs - A e into the next residual 
   static __host__ __device__ Relay relay(const SimDev& s, const BatchArgs& a) { return inner_relay(s, a, M_FREPL, true); }
 };
 
-struct RoleCorr {  // mixed form: x64 += e, r64 = b - A x64, FP64 residual norm (a9)
+struct RoleCorr {  // mixed form: x64 += e, r64 = b - A x64, FP64 residual norm
   using V = double;
   using Pro = ProAxpy<double, float>;
   using Epi = EpiResidual<double>;
@@ -327,7 +327,7 @@ struct RoleCorr {  // mixed form: x64 += e, r64 = b - A x64, FP64 residual norm 
   }
 };
 
-// Search direction from the Chebyshev-preconditioned residual s (a6 + a4).
+// Search direction from the Chebyshev-preconditioned residual s.
 struct RoleDirS {
   using V = double;
   using Pro = ProDirectionS<double>;
@@ -425,7 +425,7 @@ __global__ void __launch_bounds__(kMaxBlockThreads)
       ga, pro, epi, R, xcd_work_item(blockIdx.x, gridDim.x));
 }
 
-// Residual update and preconditioned residual norm (a5), FP64 outer solve
+// Residual update and preconditioned residual norm, FP64 outer solve
 // or FP32 inner solve; kOne: the launch serves one simulation (UpdView).
 template <typename V, bool kOne>
 __global__ void __launch_bounds__(256) update_batch_kernel(BatchArgs a) {
@@ -452,17 +452,14 @@ __global__ void __launch_bounds__(256) update_batch_kernel(BatchArgs a) {
   }
 }
 
-// Start of the inner solves of a refinement sweep (a9).  A simulation sweeps
+// Start of the inner solves of a refinement sweep.  A simulation sweeps
 // if the host asked for it and its settled outer state (read here, so the
 // host need not have seen it) is neither done nor broken down; the others get
 // an idle, already finished inner solve.  The inner tolerance is half the
 // reduction the FP64 stop rule still needs, never tighter than inner_rtol
 // (FP32 arithmetic bounds what the inner solve can reach) nor looser than
 // 0.5; it goes to the first evaluation with the relayed state.
-static __global__ void __launch_bounds__(256) inner_start_batch_kernel(BatchArgs a) {
-  uint32_t sim, local;
-  work_item(a, blockIdx.x, sim, local);
-  const SimDev& s = a.sims[sim];
+__device__ inline void inner_start_sim(const SimDev& s, const BatchArgs& a, uint32_t local) {
   Relay R = inner_relay(s, a, M_IDLE, true);
   if (s.sweep) {
     const Scalars o = gld_at(s.oS[a.ocur]);
@@ -477,6 +474,18 @@ static __global__ void __launch_bounds__(256) inner_start_batch_kernel(BatchArgs
   inner_start_body(s.r64, s.rhs32, s.r32, s.e32[0], s.pinv32, s.N, R, local, s.nblk[PK_START]);
 }
 
+static __global__ void __launch_bounds__(256) inner_start_batch_kernel(BatchArgs a) {
+  uint32_t sim, local;
+  work_item(a, blockIdx.x, sim, local);
+  inner_start_sim(a.sims[sim], a, local);
+}
+
+// The same for a launch with one simulation, whose record comes with the
+// launch (so it is never copied to device memory; the bits are the same).
+static __global__ void __launch_bounds__(256) inner_start_one_kernel(BatchArgs a, SimDev s) {
+  inner_start_sim(s, a, blockIdx.x);
+}
+
 // Settles the pending decision of every simulation and copies the settled
 // state to snap[sim] for the host.  Blocks follow the update kernel's layout
 // (every block settles the same state; block 0 of a simulation writes it):
@@ -484,11 +493,8 @@ static __global__ void __launch_bounds__(256) inner_start_batch_kernel(BatchArgs
 // x += alpha d, which the simulation's blocks apply.  V selects the relay
 // and vectors: double the outer (FP64) solve, float the inner one.
 template <typename V, bool kFour>
-__global__ void __launch_bounds__(256) decide_batch_kernel(BatchArgs a) {
+__device__ inline void decide_sim(const SimDev& s, const BatchArgs& a, uint32_t sim, uint32_t local) {
   constexpr bool inner = sizeof(V) == 4;
-  uint32_t sim, local;
-  work_item(a, blockIdx.x, sim, local);
-  const SimDev& s = a.sims[sim];
   const Relay R = inner ? inner_relay(s, a, M_DECIDE, false) : outer_relay(s, a, M_DECIDE, false);
   const StageIn in = stage_load(R);
   Scalars st;
@@ -500,6 +506,19 @@ __global__ void __launch_bounds__(256) decide_batch_kernel(BatchArgs a) {
     else
       axpy_body<double>(s.X[a.xpar], s.d64[dir_out(a)], st.alpha, s.N, local, s.nblk[PK_UPD64]);
   }
+}
+
+template <typename V, bool kFour>
+__global__ void __launch_bounds__(256) decide_batch_kernel(BatchArgs a) {
+  uint32_t sim, local;
+  work_item(a, blockIdx.x, sim, local);
+  decide_sim<V, kFour>(a.sims[sim], a, sim, local);
+}
+
+// One simulation, its record in the launch arguments.
+template <typename V, bool kFour>
+__global__ void __launch_bounds__(256) decide_one_kernel(BatchArgs a, SimDev s) {
+  decide_sim<V, kFour>(s, a, 0, blockIdx.x);
 }
 
 }  // namespace femheat

@@ -1,6 +1,6 @@
 // One PCG iteration of one simulation in one kernel (gfx950): the
-// search-direction gather with q = A d and d^T q (a4, a6), a grid-wide
-// barrier, then alpha and the x/r update with r^T P^-1 r (a5).
+// search-direction gather with q = A d and d^T q, a grid-wide
+// barrier, then alpha and the x/r update with r^T P^-1 r (Algorithm 1).
 //
 // Algorithm 1 needs the whole d^T q before any r can be updated, so the two
 // halves normally run as two kernels (gather_batch_kernel with RoleDir, then

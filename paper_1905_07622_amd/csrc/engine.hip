@@ -463,9 +463,15 @@ void Engine::fill_simdev(const Sim& s, SimDev& d) const {
 
 // Copies the SimDev array of the current epoch to the device.  Callers only
 // do so after waiting for a decide launched after the previous copy, so the
-// staging buffer being written is never still in use.
+// staging buffer being written is never still in use.  A batch of one
+// simulation needs no copy: every kernel launched for it takes its record
+// (sd_one_, as filled here) with the launch arguments.
 int Engine::upload_simdev() {
   fem_heat* h = h_;
+  if (!multi_ && act_.size() == 1) {
+    fill_simdev(*act_[0], sd_one_);
+    return FEM_OK;
+  }
   SimDev* stage = sd_host_[sd_flip_];
   sd_flip_ ^= 1;
   for (size_t k = 0; k < act_.size(); ++k) fill_simdev(*act_[k], stage[k]);
@@ -800,14 +806,24 @@ int Engine::decide(bool inner, int j_end, bool launch_next, bool wait, int slot)
     a.table = multi_ ? tab_cur_ + lay_.off_one : nullptr;
     grid = lay_.n_one;
   }
-  if (inner && ifused_)
+  if (!multi_) {  // one simulation: its record goes into the launch
+    if (inner && ifused_)
+      hipLaunchKernelGGL((decide_one_kernel<float, true>), dim3(grid), dim3(kT), 0, stream_, a, sd_one_);
+    else if (inner)
+      hipLaunchKernelGGL((decide_one_kernel<float, false>), dim3(grid), dim3(kT), 0, stream_, a, sd_one_);
+    else if (fused_)
+      hipLaunchKernelGGL((decide_one_kernel<double, true>), dim3(grid), dim3(kT), 0, stream_, a, sd_one_);
+    else
+      hipLaunchKernelGGL((decide_one_kernel<double, false>), dim3(grid), dim3(kT), 0, stream_, a, sd_one_);
+  } else if (inner && ifused_) {
     hipLaunchKernelGGL((decide_batch_kernel<float, true>), dim3(grid), dim3(kT), 0, stream_, a);
-  else if (inner)
+  } else if (inner) {
     hipLaunchKernelGGL((decide_batch_kernel<float, false>), dim3(grid), dim3(kT), 0, stream_, a);
-  else if (fused_)
+  } else if (fused_) {
     hipLaunchKernelGGL((decide_batch_kernel<double, true>), dim3(grid), dim3(kT), 0, stream_, a);
-  else
+  } else {
     hipLaunchKernelGGL((decide_batch_kernel<double, false>), dim3(grid), dim3(kT), 0, stream_, a);
+  }
   HIP_TRY(hipGetLastError());
   cur ^= 1;
   if (!ev_decide_) HIP_TRY(hipEventCreateWithFlags(&ev_decide_, hipEventDisableTiming));
@@ -1020,7 +1036,10 @@ int Engine::mixed_sweeps() {
     RC_TRY(upload_simdev());
     BatchArgs a = args(icur_, iprev_, 0, 0);
     a.table = multi_ ? tab_cur_ + lay_.off_start : nullptr;
-    hipLaunchKernelGGL(inner_start_batch_kernel, dim3(lay_.n_start), dim3(kT), 0, stream_, a);
+    if (multi_)
+      hipLaunchKernelGGL(inner_start_batch_kernel, dim3(lay_.n_start), dim3(kT), 0, stream_, a);
+    else
+      hipLaunchKernelGGL(inner_start_one_kernel, dim3(lay_.n_start), dim3(kT), 0, stream_, a, sd_one_);
     HIP_TRY(hipGetLastError());
     icur_ ^= 1;
     iprev_ = PK_START;

@@ -375,7 +375,7 @@ int ensure_fp32(fem_heat* h) {
   return FEM_OK;
 }
 
-// Jacobi preconditioner (a0) and, for non-zero Dirichlet values, the lifting
+// Jacobi preconditioner (Sec. 3.3) and, for non-zero Dirichlet values, the lifting
 // A_fD g, for the system matrix with stiffness scale ck = theta*dt.
 int prepare_operator(fem_heat* h, double ck, bool need32) {
   if (need32) RC_TRY(ensure_fp32(h));
