@@ -108,6 +108,8 @@ struct BatchArgs {
   int32_t cheb_k;      // Chebyshev chain: step k (1 .. m-1) of this launch
   int32_t cheb_last;   //                  the chain's last step (it publishes r_in^T s)
   int32_t cheb_rhs;    //                  the chain preconditions the lifted right-hand side (else r)
+  uint32_t* seq;       // decide of one simulation whose host polls: sequence word per simulation (else nullptr)
+  uint32_t seq_val;    //                                         the value this decide writes there
 };
 
 __host__ __device__ inline Relay outer_relay(const SimDev& s, const BatchArgs& a, int32_t mode, bool partials) {
@@ -499,7 +501,24 @@ __device__ inline void decide_sim(const SimDev& s, const BatchArgs& a, uint32_t 
   const StageIn in = stage_load(R);
   Scalars st;
   (void)stage_finish<kFour>(R, in, st, local == 0);
-  if (local == 0 && threadIdx.x == 0) gst_at(a.snap + sim, st);
+  if (local == 0 && threadIdx.x == 0) {
+    if (a.seq) {
+      // the host polls a.seq instead of waiting for the end of the kernel:
+      // the state goes to host memory at system scope first, and once those
+      // stores have completed, the sequence word that tells the host so
+      static_assert(sizeof(Scalars) % 8 == 0, "the state moves as 8-byte words");
+      uint64_t w[sizeof(Scalars) / 8];
+      __builtin_memcpy(w, &st, sizeof(Scalars));
+      uint64_t* p = reinterpret_cast<uint64_t*>(a.snap + sim);
+#pragma unroll
+      for (int k = 0; k < (int)(sizeof(Scalars) / 8); ++k)
+        __hip_atomic_store(p + k, w[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+      __builtin_amdgcn_s_waitcnt(0);
+      __hip_atomic_store(a.seq + sim, a.seq_val, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    } else {
+      gst_at(a.snap + sim, st);
+    }
+  }
   if (a.corr && in.pending && st.done && st.status == 0) {
     if constexpr (inner)
       axpy_body<float>(s.e32[a.xpar], s.d32[dir_out(a)], (float)st.alpha, s.N, local, s.nblk[PK_UPD32]);

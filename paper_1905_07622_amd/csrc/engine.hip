@@ -28,6 +28,7 @@
 // all simulations, each block working for one of them.  A single run is the
 // batch of one.  Between epochs, finished simulations leave the batch.
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
@@ -268,6 +269,13 @@ class Engine {
   Scalars* snap_host_ = nullptr;  // pinned, coherent: the decide kernel writes it directly
   Scalars* snap_map_ = nullptr;   // its device address
   size_t snap_cap_ = 0;
+  // after the snapshots, in the same allocation: one sequence word per
+  // snapshot, which a decide of one simulation writes once its snapshot is in
+  // host memory (the host polls it: see wait_decide)
+  uint32_t* seq_host_ = nullptr;
+  uint32_t* seq_map_ = nullptr;
+  uint32_t dseq_ = 0;  // the last sequence number given to a decide
+  int wait_decide(const volatile uint32_t* seq, uint32_t want);
   uint2* tab_dev_ = nullptr;
   uint2* tab_host_ = nullptr;
   size_t tab_cap_ = 0;
@@ -512,10 +520,14 @@ int Engine::compose() {
     const size_t cap = grow(snap_cap_, n);
     if (snap_host_) (void)hipHostFree(snap_host_);
     snap_host_ = snap_map_ = nullptr;
+    seq_host_ = seq_map_ = nullptr;
     snap_cap_ = 0;
-    HIP_TRY(hipHostMalloc(reinterpret_cast<void**>(&snap_host_), 2 * cap * sizeof(Scalars),
-                          hipHostMallocMapped | hipHostMallocCoherent));
+    const size_t bytes = 2 * cap * (sizeof(Scalars) + sizeof(uint32_t));
+    HIP_TRY(hipHostMalloc(reinterpret_cast<void**>(&snap_host_), bytes, hipHostMallocMapped | hipHostMallocCoherent));
     HIP_TRY(hipHostGetDevicePointer(reinterpret_cast<void**>(&snap_map_), snap_host_, 0));
+    std::memset(static_cast<void*>(snap_host_), 0, bytes);  // sequence numbers start above 0
+    seq_host_ = reinterpret_cast<uint32_t*>(snap_host_ + 2 * cap);
+    seq_map_ = reinterpret_cast<uint32_t*>(snap_map_ + 2 * cap);
     snap_cap_ = cap;
   }
   std::vector<uint2> tab;
@@ -796,6 +808,10 @@ int Engine::decide(bool inner, int j_end, bool launch_next, bool wait, int slot)
   BatchArgs a = args(cur, prev, jl, replacements_before(jl, R_) & 1,
                      !inner && !fused_ && j_end > 0 && deferred(j_end) ? 1 : 0);
   if (slot) a.snap += act_.size();
+  // one simulation: the host polls the decide's sequence word (wait_decide)
+  const bool poll = wait && !multi_;
+  a.seq = poll ? seq_map_ + (slot ? act_.size() : 0) : nullptr;
+  a.seq_val = ++dseq_;
   // a decide that may owe x += alpha d runs over the update kernel's blocks,
   // which then share that work; otherwise one block per simulation settles it
   uint32_t grid;
@@ -850,12 +866,38 @@ int Engine::decide(bool inner, int j_end, bool launch_next, bool wait, int slot)
     RC_TRY(gather<RoleInitNext>(b));
     ocur_ ^= 1;
   }
-  if (wait) HIP_TRY(hipEventSynchronize(ev_decide_));
+  if (poll)
+    RC_TRY(wait_decide(seq_host_ + (slot ? act_.size() : 0), a.seq_val));
+  else if (wait)
+    HIP_TRY(hipEventSynchronize(ev_decide_));
   if (launch_next) {
     const Scalars& t = snap_host_[0];
     next_ran_ = t.done && t.status == 0 && (mixed_ || (replacements_before(t.iter, R_) & 1) == next_xc);
     next_sim_ = act_[0];
   }
+  return FEM_OK;
+}
+
+// The host's wait for the decide of one simulation.  It polls the sequence
+// word that the decide kernel writes once the snapshot is in host memory
+// (the kernel and everything queued behind it may still be running: the host
+// only reads the snapshot, and every later launch is ordered behind the
+// decide on the stream).  Waiting for the kernel's completion signal instead
+// takes the GPU's end-of-kernel work and the runtime's wake-up on top, while
+// the GPU idles until the host's next launch.  The event is queried now and
+// then, so a device error, or a kernel that ended without writing the word,
+// also ends the wait.
+int Engine::wait_decide(const volatile uint32_t* seq, uint32_t want) {
+  fem_heat* h = h_;
+  for (uint32_t spins = 1; *seq != want; ++spins) {
+    if ((spins & 1023u) == 0) {
+      const hipError_t q = hipEventQuery(ev_decide_);
+      if (q == hipSuccess) break;
+      if (q != hipErrorNotReady) return fail(h, FEM_EDEVICE, std::string("decide kernel failed: ") + hipGetErrorString(q));
+      (void)hipGetLastError();  // "not ready" is no error of a later call
+    }
+  }
+  std::atomic_thread_fence(std::memory_order_acquire);
   return FEM_OK;
 }
 
