@@ -1120,8 +1120,23 @@ int Engine::mixed_sweeps() {
       s.xc ^= 1;
       s.nsw += 1;
     }
-    // with one simulation, the next step's RHS and initial residual go in
-    // behind this decide (they run if this sweep ended the step)
+    // One simulation whose previous step ran more sweeps than this one has so
+    // far: the next sweep goes in behind this decide before the host has read
+    // it, as the first sweep does (the inner start kernel finds on the device
+    // whether the step has ended and then starts an idle solve; the host
+    // reads the state from the second snapshot slot after the inner solve's
+    // first decide).
+    if (early && act_.size() == 1 && !multi_) {
+      const Sim& s = *act_[0];
+      if (s.sweeping && s.nsw < opts_.max_refine && s.step > 0 && s.sweeps[s.step - 1] > s.nsw) {
+        RC_TRY(decide(false, 0, false, false, 1));
+        first = true;
+        continue;
+      }
+    }
+    // otherwise the host waits for the decide; with one simulation, the next
+    // step's RHS and initial residual go in behind it (they run if this sweep
+    // ended the step)
     const bool launch_next = act_.size() == 1 && act_[0]->step + 1 < act_[0]->rq.nsteps;
     RC_TRY(decide(false, 0, launch_next));
     for (size_t q = 0; q < act_.size(); ++q) {

@@ -210,6 +210,36 @@ def test_single_simulation_overlap_matches_batch(gpu, replace_every, rtol):
     assert max(rel_l2(one["T_saved"][n], ref["T_saved"][n]) for n in range(p.nsteps)) <= GATE64
 
 
+def test_mixed_early_sweep_start_matches_batch(gpu):
+    """A simulation alone starts a refinement sweep behind the previous
+    sweep's decide, before the host has read it, when its previous step ran
+    more sweeps; a step that then needs fewer runs that sweep's inner solve
+    idle and ends.  Flux pulses and random initial fields make the sweep
+    count per step fall as well as rise.  Alone and in a batch of two (which
+    never starts a sweep early) must give the same bits, and the fields must
+    match the FP64 oracle."""
+    kw = dict(save_every=1, precision=fh.FEM_FP32_FP64DOT, max_refine=6, inner_rtol=1e-3, check=False)
+    falls = 0
+    for seed, theta, dt, pulse in [(41, 1.0, 1e-3, 3), (42, 0.5, 5e-3, 2), (43, 1.0, 2e-2, 4)]:
+        base = wl.random_problem(12, 10, 9, seed=seed, nsteps=9, rtol=1e-11, theta=theta, dt=dt)
+        flux = np.zeros(6)
+        flux[wl.FACE_ZP] = 50.0
+        sched = np.zeros(base.nsteps)
+        sched[:pulse] = 1.0
+        p = base.replace(flux_mask=wl.face_bit(wl.FACE_ZP), flux=flux, flux_schedule=sched)
+        partner = wl.random_problem(6, 6, 6, seed=seed + 100, nsteps=9)
+        _, alone = fh.run_batch([p], **kw)
+        _, pair = fh.run_batch([p, partner], **kw)
+        sw = np.asarray(alone[0]["refine_sweeps"])
+        say(f"  seed {seed}: sweeps {list(sw)} iters {list(alone[0]['iters'])} status {alone[0]['status']}")
+        assert alone[0]["status"] == fh.FEM_OK == pair[0]["status"]
+        same_bits(alone[0], pair[0])
+        falls += int(np.sum(np.diff(sw) < 0))
+        ref = oracle.run(p, save_every=1)
+        assert max(rel_l2(alone[0]["T_saved"][n], ref["T_saved"][n]) for n in range(p.nsteps)) <= GATE_MIXED
+    assert falls > 0, "no step ran fewer sweeps than the one before it: the idle early sweep went untested"
+
+
 @pytest.mark.parametrize("rtol,max_refine,inner_rtol", [(1e-8, 4, 1e-5), (1e-11, 4, 1e-3), (1e-11, 1, 1e-3),
                                                         (0.5, 4, 1e-5)])
 def test_mixed_single_simulation_overlap_matches_batch(gpu, rtol, max_refine, inner_rtol):
