@@ -19,6 +19,7 @@ from __future__ import annotations
 import argparse
 import json
 import os
+import tempfile
 import sys
 import time
 
@@ -690,7 +691,8 @@ def main():
     ap.add_argument("--cheb-degrees", type=int, nargs="*", default=[2, 3, 4])
     ap.add_argument("--laminate-sizes", type=int, nargs="*", default=[30, 60, 90, 120, 150])
     ap.add_argument("--no-tune", action="store_true", help="use the library's tile rule (no autotuning)")
-    ap.add_argument("--tune-cache", default=os.path.join(ROOT, "gpurun_out", "femheat_tune.json"))
+    ap.add_argument("--tune-cache", default=os.path.join(tempfile.gettempdir(), "femheat_tune.json"),
+                    help="tile cache file of the autotuner (tuned on first use of each shape)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 256 MiB device copy 3 times (scale for rocprof FETCH/WRITE_SIZE)")
     args = ap.parse_args()

@@ -67,7 +67,7 @@ struct fem_server {
   // server (or the caller's allocator).  Each lane allocates and releases on
   // its own stream, so a retirement never synchronises the device -- hipFree
   // would wait for every lane's kernels -- and released blocks are reused by
-  // later admissions without returning to the driver.
+  // later admissions without going back to the HIP runtime.
   hipMemPool_t pool = nullptr;
   fem_allocator pool_alloc{};
   std::string tune_cache;  // own copy of the options' tile-cache path
